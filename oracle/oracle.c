@@ -1,0 +1,283 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, brute-force CPU point/polygon join used to check the GPU
+ * library. Only tests, the smoke check and the benchmark's CPU-baseline leg
+ * load it; the product path never does. It shares no code with the library.
+ *
+ * What it computes (the plain definition the paper's join reaches exactly):
+ *   for every point p and every polygon P, whether P covers p under the
+ *   ST_Covers predicate (Section "Background": points on edges or vertices
+ *   lie within the polygon). Geometry model: the plane x = longitude,
+ *   y = latitude in degrees, straight edges, closed polygons; holes are
+ *   rings of the same polygon and their edges are boundary too; inside-ness
+ *   is the even-odd crossing number of the ray tracing test the paper names
+ *   for refinement (Section "Background", PIP paragraph).
+ *
+ * All predicates are evaluated exactly on the given fp64 coordinates:
+ *   orientation sign = sign of (bx-ax)(py-ay) - (by-ay)(px-ax), first with
+ *   fp64 and the static error bound (3 + 16 eps) eps (|l| + |r|) from
+ *   Shewchuk, "Adaptive Precision Floating-Point Arithmetic and Fast Robust
+ *   Geometric Predicates" (1997), and when that bound does not decide, from
+ *   an exact floating-point expansion of the determinant (error-free
+ *   TwoSum / TwoProduct transformations, Knuth and Dekker; expansion growth
+ *   per Shewchuk Theorem 10). Exact as long as no product underflows, i.e.
+ *   nonzero coordinate differences above 2^-450.
+ *
+ * Points that are non-finite or outside |lat| <= 90, |lng| <= 180 match no
+ * polygon.
+ *
+ * Built with gcc -O2 -fopenmp -ffp-contract=off (no FMA contraction: the
+ * error-free transformations need exactly rounded products and sums).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_EPS 1.1102230246251565e-16 /* 2^-53, unit roundoff of fp64 */
+
+/* ---- error-free transformations ---------------------------------------- */
+
+/* s + e == a + b exactly (Knuth's TwoSum). */
+static void or_two_sum(double a, double b, double *s, double *e) {
+  double x = a + b;
+  double bv = x - a;
+  double av = x - bv;
+  *e = (a - av) + (b - bv);
+  *s = x;
+}
+
+/* p + e == a * b exactly (fused multiply-add gives the rounding error). */
+static void or_two_prod(double a, double b, double *p, double *e) {
+  double x = a * b;
+  *e = fma(a, b, -x);
+  *p = x;
+}
+
+/* Add one double to a nonoverlapping expansion h[0..n) (increasing
+ * magnitude); result is again nonoverlapping, length n + 1. */
+static int or_grow(double *h, int n, double b) {
+  double q = b;
+  for (int i = 0; i < n; i++) {
+    double s, e;
+    or_two_sum(q, h[i], &s, &e);
+    h[i] = e;
+    q = s;
+  }
+  h[n] = q;
+  return n + 1;
+}
+
+/* Exact sign of (bx-ax)(py-ay) - (by-ay)(px-ax). */
+static int or_orient_exact(double ax, double ay, double bx, double by,
+                           double px, double py) {
+  double d[4][2];
+  /* each difference as an exact pair hi + lo */
+  or_two_sum(bx, -ax, &d[0][0], &d[0][1]);
+  or_two_sum(py, -ay, &d[1][0], &d[1][1]);
+  or_two_sum(by, -ay, &d[2][0], &d[2][1]);
+  or_two_sum(px, -ax, &d[3][0], &d[3][1]);
+  double h[40];
+  int n = 0;
+  for (int i = 0; i < 2; i++)
+    for (int j = 0; j < 2; j++) {
+      double p, e;
+      or_two_prod(d[0][i], d[1][j], &p, &e);
+      n = or_grow(h, n, e);
+      n = or_grow(h, n, p);
+      or_two_prod(d[2][i], d[3][j], &p, &e);
+      n = or_grow(h, n, -e);
+      n = or_grow(h, n, -p);
+    }
+  /* nonoverlapping expansion: the sign of the sum is the sign of its most
+   * significant nonzero component */
+  for (int i = n - 1; i >= 0; i--) {
+    if (h[i] > 0) return 1;
+    if (h[i] < 0) return -1;
+  }
+  return 0;
+}
+
+int oracle_orient_sign(double ax, double ay, double bx, double by, double px,
+                       double py) {
+  double l = (bx - ax) * (py - ay);
+  double r = (by - ay) * (px - ax);
+  double det = l - r;
+  double bound = (3.0 + 16.0 * OR_EPS) * OR_EPS * (fabs(l) + fabs(r));
+  if (det > bound) return 1;
+  if (-det > bound) return -1;
+  return or_orient_exact(ax, ay, bx, by, px, py);
+}
+
+/* Exact-only variant (no filter); used by tests to show the filter changes
+ * nothing. */
+int oracle_orient_sign_exact(double ax, double ay, double bx, double by,
+                             double px, double py) {
+  return or_orient_exact(ax, ay, bx, by, px, py);
+}
+
+/* ---- point in polygon ---------------------------------------------------- */
+
+/* verts: interleaved (lat, lng). Returns 1 if polygon p covers (lat, lng).
+ * use_bbox = 0 skips the bounding-box prefilter (a test shows it changes
+ * nothing). */
+static int or_covers(const double *verts, const int64_t *ring_off,
+                     const int32_t *poly_ring_off, const double *bbox, int p,
+                     double lat, double lng, int use_bbox) {
+  if (use_bbox) {
+    const double *b = bbox + 4 * (size_t)p; /* lat_min lat_max lng_min lng_max */
+    if (lat < b[0] || lat > b[1] || lng < b[2] || lng > b[3]) return 0;
+  }
+  const double px = lng, py = lat;
+  int inside = 0;
+  for (int r = poly_ring_off[p]; r < poly_ring_off[p + 1]; r++) {
+    int64_t k0 = ring_off[r], k1 = ring_off[r + 1];
+    for (int64_t k = k0; k < k1; k++) {
+      int64_t kn = (k + 1 < k1) ? k + 1 : k0; /* closing edge */
+      double ay = verts[2 * k], ax = verts[2 * k + 1];
+      double by = verts[2 * kn], bx = verts[2 * kn + 1];
+      int straddle = (ay > py) != (by > py);
+      int in_box = px >= fmin(ax, bx) && px <= fmax(ax, bx) &&
+                   py >= fmin(ay, by) && py <= fmax(ay, by);
+      if (!straddle && !in_box) continue;
+      int s = oracle_orient_sign(ax, ay, bx, by, px, py);
+      if (in_box && s == 0) return 1; /* on the boundary: covered */
+      if (straddle && ((by > ay) ? (s > 0) : (s < 0))) inside ^= 1;
+    }
+  }
+  return inside;
+}
+
+static int or_valid_point(double lat, double lng) {
+  return isfinite(lat) && isfinite(lng) && fabs(lat) <= 90.0 &&
+         fabs(lng) <= 180.0;
+}
+
+static double *or_bboxes(const double *verts, const int64_t *ring_off,
+                         const int32_t *poly_ring_off, int n_polys) {
+  double *bb = (double *)malloc(sizeof(double) * 4 * (size_t)(n_polys > 0 ? n_polys : 1));
+  for (int p = 0; p < n_polys; p++) {
+    double b[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int r = poly_ring_off[p]; r < poly_ring_off[p + 1]; r++)
+      for (int64_t k = ring_off[r]; k < ring_off[r + 1]; k++) {
+        b[0] = fmin(b[0], verts[2 * k]);
+        b[1] = fmax(b[1], verts[2 * k]);
+        b[2] = fmin(b[2], verts[2 * k + 1]);
+        b[3] = fmax(b[3], verts[2 * k + 1]);
+      }
+    memcpy(bb + 4 * (size_t)p, b, sizeof b);
+  }
+  return bb;
+}
+
+/* Covers test for a single (polygon, point); for tests. */
+int oracle_covers(const double *verts, const int64_t *ring_off,
+                  const int32_t *poly_ring_off, int32_t n_polys, int32_t p,
+                  double lat, double lng, int use_bbox) {
+  if (p < 0 || p >= n_polys || !or_valid_point(lat, lng)) return 0;
+  double *bb = or_bboxes(verts, ring_off, poly_ring_off, n_polys);
+  int c = or_covers(verts, ring_off, poly_ring_off, bb, p, lat, lng, use_bbox);
+  free(bb);
+  return c;
+}
+
+/*
+ * The join. For each point i (interleaved lat, lng):
+ *   out[i]   = lowest id of a covering polygon, or -1;
+ *   cnt[i]   = number of covering polygons.
+ * Pairs beyond out[i] are written, in (point, polygon) ascending order, to
+ * pair_pt / pair_poly up to `capacity`; the total is returned in *n_pairs.
+ * nthreads <= 0 uses the OpenMP default. Returns 0.
+ */
+int oracle_join(const double *verts, const int64_t *ring_off,
+                const int32_t *poly_ring_off, int32_t n_polys,
+                const double *pts, int64_t n, int32_t *out, int32_t *cnt,
+                int64_t *pair_pt, int32_t *pair_poly, int64_t capacity,
+                int64_t *n_pairs, int nthreads, int use_bbox) {
+  double *bb = or_bboxes(verts, ring_off, poly_ring_off, n_polys);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; i++) {
+    double lat = pts[2 * i], lng = pts[2 * i + 1];
+    int32_t first = -1, c = 0;
+    if (or_valid_point(lat, lng))
+      for (int p = 0; p < n_polys; p++)
+        if (or_covers(verts, ring_off, poly_ring_off, bb, p, lat, lng, use_bbox)) {
+          if (first < 0) first = p;
+          c++;
+        }
+    out[i] = first;
+    cnt[i] = c;
+  }
+  /* second pass over the (rare) points with more than one covering polygon */
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++) {
+    if (cnt[i] < 2) continue;
+    double lat = pts[2 * i], lng = pts[2 * i + 1];
+    for (int p = out[i] + 1; p < n_polys; p++)
+      if (or_covers(verts, ring_off, poly_ring_off, bb, p, lat, lng, use_bbox)) {
+        if (m < capacity) {
+          pair_pt[m] = i;
+          pair_poly[m] = p;
+        }
+        m++;
+      }
+  }
+  *n_pairs = m;
+  free(bb);
+  return 0;
+}
+
+/*
+ * Checker for the approximate join: planar distance in metres from (lat, lng)
+ * to the boundary (all ring edges) of polygon p, in the local equirectangular
+ * frame at the point's latitude: X = dlng * cos(lat) * R * pi / 180,
+ * Y = dlat * R * pi / 180, R = 6,371,008.8 m. The paper bounds the error of
+ * the approximate join by the diagonal of the largest covering cell without
+ * naming a metric; this is the reading used to check that bound.
+ */
+double oracle_boundary_dist_m(const double *verts, const int64_t *ring_off,
+                              const int32_t *poly_ring_off, int32_t p,
+                              double lat, double lng) {
+  const double R = 6371008.8;
+  const double k = R * 3.14159265358979323846 / 180.0;
+  const double kx = k * cos(lat * 3.14159265358979323846 / 180.0);
+  double best = INFINITY;
+  for (int r = poly_ring_off[p]; r < poly_ring_off[p + 1]; r++) {
+    int64_t k0 = ring_off[r], k1 = ring_off[r + 1];
+    for (int64_t q = k0; q < k1; q++) {
+      int64_t qn = (q + 1 < k1) ? q + 1 : k0;
+      double ax = (verts[2 * q + 1] - lng) * kx, ay = (verts[2 * q] - lat) * k;
+      double bx = (verts[2 * qn + 1] - lng) * kx, by = (verts[2 * qn] - lat) * k;
+      double dx = bx - ax, dy = by - ay;
+      double len2 = dx * dx + dy * dy;
+      double t = len2 > 0 ? -(ax * dx + ay * dy) / len2 : 0.0;
+      t = t < 0 ? 0 : (t > 1 ? 1 : t);
+      double cx = ax + t * dx, cy = ay + t * dy;
+      double d = sqrt(cx * cx + cy * cy);
+      if (d < best) best = d;
+    }
+  }
+  return best;
+}
+
+/* Batched form of the checker: dist[i] for pairs (pt[i], poly[i]). */
+void oracle_boundary_dist_pairs(const double *verts, const int64_t *ring_off,
+                                const int32_t *poly_ring_off, const double *pts,
+                                const int64_t *pair_pt, const int32_t *pair_poly,
+                                int64_t m, double *dist) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < m; i++) {
+    int64_t q = pair_pt[i];
+    dist[i] = oracle_boundary_dist_m(verts, ring_off, poly_ring_off, pair_poly[i],
+                                     pts[2 * q], pts[2 * q + 1]);
+  }
+}

@@ -1,0 +1,254 @@
+"""Pins for the oracle (CPU): the brute-force join is checked against what the
+paper and plain mathematics fix, never against itself.
+
+* exact orientation sign vs rational arithmetic (fractions.Fraction);
+* hand-built polygons with hand-derived answers under the ST_Covers rule
+  (Section "Background": points on edges and vertices are inside);
+* convex polygons: crossing number == intersection of closed half-planes;
+* Monte Carlo hit fraction vs shoelace area;
+* a Voronoi partition covers each generic point exactly once;
+* invariance under ring reversal / rotation / exact dyadic translation;
+* the bounding-box prefilter changes nothing.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def frac_orient(a, b, p):
+    ax, ay, bx, by, px, py = (Fraction(float(v)) for v in (*a, *b, *p))
+    d = (bx - ax) * (py - ay) - (by - ay) * (px - ax)
+    return (d > 0) - (d < 0)
+
+
+def _adversarial_triples(rng, n):
+    out = []
+    for _ in range(n):
+        kind = rng.integers(0, 5)
+        if kind == 0:  # generic
+            a, b, p = rng.uniform(-180, 180, (3, 2))
+        elif kind == 1:  # point on the line through a, b (rounded), nudged by ulps
+            a, b = rng.uniform(-75, -73, (2, 2))
+            t = rng.uniform(-0.5, 1.5)
+            p = a + t * (b - a)
+            p = p + rng.integers(-3, 4, 2) * np.spacing(p)
+        elif kind == 2:  # exactly collinear dyadic points
+            a = rng.integers(-2**20, 2**20, 2) / 2.0**10
+            d = rng.integers(-2**10, 2**10, 2) / 2.0**12
+            k = rng.integers(-4, 5)
+            b = a + d
+            p = a + k * d
+        elif kind == 3:  # lat/lng-like, tiny offsets from an edge
+            a = np.array([rng.uniform(-74.3, -73.6), rng.uniform(40.4, 41.0)])
+            b = a + rng.uniform(-1e-3, 1e-3, 2)
+            t = rng.uniform(0, 1)
+            p = a + t * (b - a) + rng.uniform(-1e-15, 1e-15, 2)
+        else:  # widely different magnitudes
+            a = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-30, 3, 2)
+            b = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-30, 3, 2)
+            p = a + rng.uniform(0, 1) * (b - a)
+        out.append((tuple(a), tuple(b), tuple(p)))
+    return out
+
+
+def test_orient_sign_matches_rationals():
+    rng = np.random.default_rng(11)
+    cases = _adversarial_triples(rng, 60000)
+    zeros = 0
+    for a, b, p in cases:
+        want = frac_orient(a, b, p)
+        zeros += want == 0
+        assert oracle.orient_sign(a, b, p) == want, (a, b, p)
+        assert oracle.orient_sign(a, b, p, exact_only=True) == want, (a, b, p)
+    assert zeros > 1000  # the adversarial set really exercises the exact path
+
+
+def _P(*rings_xy):
+    """Polygon from rings given as (x=lng, y=lat) pairs."""
+    return [np.asarray(r, dtype=np.float64)[:, ::-1] for r in rings_xy]
+
+
+def _covers(poly_rings, x, y):
+    P = synth.Polygons.from_rings([poly_rings])
+    return oracle.covers(P, 0, lat=y, lng=x)
+
+
+SQUARE = _P([(0, 0), (0, 1), (1, 1), (1, 0)])
+U_SHAPE = _P([(0, 0), (3, 0), (3, 3), (2, 3), (2, 1), (1, 1), (1, 3), (0, 3)])
+HOLED = _P([(0, 0), (4, 0), (4, 4), (0, 4)], [(1, 1), (3, 1), (3, 3), (1, 3)])
+DIAMOND = _P([(0, 1), (1, 0), (2, 1), (1, 2)])
+TRIANGLE = _P([(0, 0), (4, 0), (2, 2)])
+
+E = 2.0 ** -40
+
+HAND = [
+    # unit square
+    (SQUARE, 0.5, 0.5, True), (SQUARE, 1.5, 0.5, False), (SQUARE, 0.5, 0.0, True),
+    (SQUARE, 0.0, 0.0, True), (SQUARE, 1.0, 1.0, True), (SQUARE, 0.5, -E, False),
+    (SQUARE, 0.5, E, True), (SQUARE, 1.0 + E, 0.5, False), (SQUARE, 1.0, 0.5, True),
+    (SQUARE, -E, -E, False),
+    # U shape (concave): notch between the arms is outside
+    (U_SHAPE, 1.5, 2.0, False), (U_SHAPE, 0.5, 2.0, True), (U_SHAPE, 2.5, 2.0, True),
+    (U_SHAPE, 1.5, 0.5, True), (U_SHAPE, 0.5, 1.0, True), (U_SHAPE, 1.5, 1.0, True),
+    (U_SHAPE, 2.5, 1.0, True), (U_SHAPE, 3.5, 1.0, False), (U_SHAPE, -0.5, 1.0, False),
+    (U_SHAPE, 1.5, 3.0, False), (U_SHAPE, 1.0, 3.0, True), (U_SHAPE, 1.5, 1.0 + E, False),
+    # square with a square hole: hole boundary is boundary (covered)
+    (HOLED, 0.5, 0.5, True), (HOLED, 2.0, 2.0, False), (HOLED, 1.0, 2.0, True),
+    (HOLED, 1.0, 1.0, True), (HOLED, 3.5, 2.0, True), (HOLED, 1.0 + E, 2.0, False),
+    (HOLED, 1.0 - E, 2.0, True), (HOLED, 2.0, 3.0, True), (HOLED, 4.0, 4.0, True),
+    # diamond: horizontal rays through vertices
+    (DIAMOND, 0.5, 1.0, True), (DIAMOND, -0.5, 1.0, False), (DIAMOND, 3.0, 1.0, False),
+    (DIAMOND, 1.0, 0.0, True), (DIAMOND, 1.0, -E, False), (DIAMOND, 2.0, 1.0, True),
+    (DIAMOND, 1.5, 1.5, True), (DIAMOND, 1.5 + E, 1.5, False),
+    # triangle with a horizontal edge at the point's latitude
+    (TRIANGLE, -1.0, 0.0, False), (TRIANGLE, 5.0, 0.0, False), (TRIANGLE, 2.0, 0.0, True),
+    (TRIANGLE, 2.0, 1.0, True), (TRIANGLE, 2.0, 2.0, True), (TRIANGLE, 2.0, 2.0 + E, False),
+    (TRIANGLE, 1.0, 1.0, True), (TRIANGLE, 1.0 - E, 1.0, False),
+]
+
+
+@pytest.mark.parametrize("rings,x,y,want", HAND)
+def test_hand_built_polygons(rings, x, y, want):
+    assert _covers(rings, x, y) == want
+    # ring orientation and start vertex do not matter
+    rev = [r[::-1] for r in rings]
+    assert _covers(rev, x, y) == want
+    rot = [np.roll(r, 1, axis=0) for r in rings]
+    assert _covers(rot, x, y) == want
+
+
+def _convex_hull(pts):
+    pts = sorted(map(tuple, pts))
+
+    def cross(o, a, b):
+        return (Fraction(a[0]) - Fraction(o[0])) * (Fraction(b[1]) - Fraction(o[1])) - \
+               (Fraction(a[1]) - Fraction(o[1])) * (Fraction(b[0]) - Fraction(o[0]))
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+            upper.pop()
+        upper.append(p)
+    return lower[:-1] + upper[:-1]  # counter-clockwise
+
+
+def test_convex_equals_halfplane_intersection():
+    """For a convex polygon, covered <=> on the inner closed side of every edge."""
+    rng = np.random.default_rng(5)
+    checked = 0
+    for trial in range(40):
+        c = rng.uniform([-74.2, 40.5], [-73.7, 40.9])
+        hull = _convex_hull(c + rng.normal(0, 0.01, (12, 2)))
+        rings = [np.asarray(hull)[:, ::-1]]
+        P = synth.Polygons.from_rings([rings])
+        lo, hi = np.min(hull, 0), np.max(hull, 0)
+        pts = list(rng.uniform(lo - 0.002, hi + 0.002, (150, 2)))
+        # boundary points: vertices and exact dyadic midpoints of axis-aligned-ish edges
+        pts += [np.array(v) for v in hull[:4]]
+        for (x, y) in pts:
+            want = all(frac_orient(hull[k], hull[(k + 1) % len(hull)], (x, y)) >= 0
+                       for k in range(len(hull)))
+            assert oracle.covers(P, 0, lat=y, lng=x) == want
+            checked += 1
+    assert checked > 5000
+
+
+def test_monte_carlo_area_matches_shoelace():
+    P = synth.workload_polygons("c2")
+    rng = np.random.default_rng(7)
+    for p in [0, 17, 101, 250]:
+        rings = P.rings(p)
+        area = 0.0
+        for r in rings:
+            x, y = r[:, 1], r[:, 0]
+            area_r = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
+            area += area_r if area == 0.0 else -area_r  # holes subtract
+        lo, hi = rings[0].min(0), rings[0].max(0)
+        box_area = (hi[0] - lo[0]) * (hi[1] - lo[1])
+        n = 40000
+        pts = rng.uniform(lo, hi, (n, 2))
+        sub = P.subset([p])
+        res = oracle.join(sub, pts)
+        frac = float((res.out == 0).mean())
+        expect = area / box_area
+        sigma = np.sqrt(expect * (1 - expect) / n)
+        assert abs(frac - expect) < 5 * sigma + 1e-12, (p, frac, expect)
+
+
+def test_partition_covers_generic_points_once():
+    P = synth.workload_polygons("c1")
+    pts = synth.uniform_points(0, 200000, seed=77)
+    res = oracle.join(P, pts)
+    # generic points: exactly one polygon each
+    assert np.all(res.cnt == 1)
+    assert np.all(res.out >= 0)
+
+
+def test_partition_shared_vertices_covered_by_all_neighbours():
+    P = synth.workload_polygons("c1")
+    v = P.verts
+    # count, for each distinct vertex, how many polygons list it
+    owners = {}
+    for p in range(P.n_polys):
+        for r in P.rings(p):
+            for q in map(tuple, r):
+                owners.setdefault(q, set()).add(p)
+    keys = list(owners)
+    pts = np.asarray(keys)
+    res = oracle.join(P, pts)
+    got = {}
+    for i, o in enumerate(res.out):
+        if o >= 0:
+            got.setdefault(i, set()).add(int(o))
+    for i, p in res.pairs:
+        got.setdefault(int(i), set()).add(int(p))
+    for i, k in enumerate(keys):
+        # every polygon that has this vertex covers it (possibly more: a
+        # vertex can also lie on another polygon's straight edge)
+        assert owners[k] <= got.get(i, set()), (k, owners[k], got.get(i))
+    assert v.shape[0] > 0
+
+
+def test_dyadic_translation_invariance():
+    P = synth.workload_polygons("c1")
+    pts = synth.uniform_points(0, 20000, seed=78)
+    base = oracle.join(P, pts)
+    # +0.25 deg lat / +0.125 deg lng keeps every value in its binade: exact
+    sh = np.array([0.25, 0.125])
+    P2 = synth.Polygons(P.verts + sh, P.ring_off, P.poly_ring_off)
+    assert np.array_equal(P2.verts - sh, P.verts)
+    moved = oracle.join(P2, pts + sh)
+    assert np.array_equal(base.out, moved.out)
+    assert np.array_equal(base.pairs, moved.pairs)
+
+
+def test_bbox_prefilter_changes_nothing():
+    P = synth.workload_polygons("c1")
+    pts = np.concatenate([synth.uniform_points(0, 5000, seed=79), P.verts[::3]])
+    a = oracle.join(P, pts, use_bbox=True)
+    b = oracle.join(P, pts, use_bbox=False)
+    assert np.array_equal(a.out, b.out) and np.array_equal(a.pairs, b.pairs)
+
+
+def test_out_of_domain_points_match_nothing():
+    P = synth.Polygons.from_rings([[np.array([[-90, -180], [-90, 180], [90, 180], [90, -180]],
+                                             dtype=float)]])
+    pts = np.array([[np.nan, 0], [0, np.inf], [91, 0], [0, 181], [0, -180.0], [90, 0], [0, 0]])
+    res = oracle.join(P, pts)
+    assert res.out.tolist() == [-1, -1, -1, -1, 0, 0, 0]
+
+
+def test_boundary_distance_checker():
+    # 1 degree of latitude is R*pi/180 metres
+    sq = synth.Polygons.from_rings([[np.array([[0, 0], [0, 1], [1, 1], [1, 0]], float)]])
+    d = oracle.boundary_dist_m(sq, 0, lat=-1.0, lng=0.5)
+    assert abs(d - synth.M_PER_DEG) < 1e-6
+    d = oracle.boundary_dist_m(sq, 0, lat=0.5, lng=0.5)
+    assert abs(d - 0.5 * synth.M_PER_DEG * np.cos(np.radians(0.5))) < 1e-6
