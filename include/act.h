@@ -1,0 +1,267 @@
+/*
+ * act.h -- C ABI of the MI355X Adaptive Cell Trie point/polygon join.
+ *
+ * Method: Kipf et al., "Adaptive Geospatial Joins for Modern Hardware"
+ * (arXiv 1802.09488). The library builds, on the host, a precision-preserving
+ * super covering of a set of polygons (Section III-B), stores it in an
+ * Adaptive Cell Trie plus a lookup table (Section III-C), uploads that image
+ * to HBM once, and probes streaming lat/lng points against it on the GPU
+ * (Section III-E, Listings 2 and 3): point -> 64-bit cube-face/Hilbert cell
+ * id -> trie descent -> true hits / candidate hits -> exact point-in-polygon
+ * refinement of candidates. In approximate mode boundary cells are split
+ * until their diagonal is below the requested precision and refinement is
+ * skipped (Section III-A, approximate approach).
+ *
+ * Conventions shared by every entry point:
+ *   - Coordinates are fp64 degrees, interleaved (lat, lng).
+ *   - Join semantics are ST_Covers (Section II): a polygon covers the points
+ *     on its edges and vertices, hole edges included; the plane is
+ *     x = longitude, y = latitude with straight edges. Points that are not
+ *     finite or lie outside |lat| <= 90, |lng| <= 180 match nothing.
+ *   - Polygon ids are input positions 0 .. n_polys-1 (at most 2^30, the
+ *     width of an inlined payload, Section III-C).
+ *   - "Device pointer" means memory of the index's HIP device, owned by the
+ *     caller; the library never frees it.
+ *   - `stream` is a hipStream_t of the index's device (NULL = the default
+ *     stream) passed as void*. Joins are enqueued asynchronously and never
+ *     synchronise the host.
+ *   - Every function returns ACT_OK (0) or a negative ACT_E_* code; the
+ *     message of the last failure on the calling thread is returned by
+ *     act_last_error(). Arguments are validated before anything is launched;
+ *     on error nothing is launched and no output is written.
+ *   - The index is immutable after act_build: concurrent joins on different
+ *     streams or host threads are safe (Section IV-B1: probes of an
+ *     immutable index need no synchronisation).
+ */
+#ifndef ACT_H
+#define ACT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ACT_OK = 0,
+  ACT_E_ARG = -1,      /* NULL pointer, n < 0, bad mode/precision/options   */
+  ACT_E_POLY = -2,     /* malformed polygon input                            */
+  ACT_E_OOM = -3,      /* host or device allocation failed                   */
+  ACT_E_HIP = -4,      /* HIP runtime / launch error (message has details)   */
+  ACT_E_OVERFLOW = -5, /* more result pairs than the caller's capacity       */
+  ACT_E_DEVICE = -6,   /* no usable device, or index built without a device  */
+  ACT_E_RANGE = -7     /* request beyond a documented limit                  */
+};
+
+enum { ACT_EXACT = 0, ACT_APPROX = 1 };
+
+/* Refinement arithmetic for candidate hits in exact mode. */
+enum {
+  ACT_REFINE_FP32_FILTER = 0, /* fp32 crossing test with a proven error bound,
+                                 fp64 re-test of undecided edges, exact
+                                 expansion arithmetic as the last resort      */
+  ACT_REFINE_FP64 = 1         /* every edge test in fp64 (+ exact fallback)  */
+};
+
+typedef struct act_index act_index;
+
+/* Build options; pass NULL for the defaults given per field. */
+typedef struct {
+  int32_t max_level;   /* exact mode: finest covering level (default 20;
+                          Section V configuration uses 20 for interior
+                          cells); range 1..30                                */
+  int32_t device;      /* HIP device to upload to (default 0); -1 builds a
+                          host-only index (inspection and tests; joins on it
+                          return ACT_E_DEVICE)                               */
+  int32_t threads;     /* host build threads (default 0 = hardware count)   */
+  int32_t reserved;
+  double margin_deg;   /* conservative inflation of every cell's lat/lng box
+                          before classification (default 1e-9 deg, which
+                          covers fp64 projection rounding by >1e3x)          */
+} act_build_opts;
+
+/*
+ * act_build -- build an index over n_polys polygons (Sections III-B, III-C).
+ *
+ * verts_latlng  host, 2*V doubles: (lat, lng) of every vertex.
+ * ring_off      host, R+1 int64: ring r spans vertices ring_off[r] ..
+ *               ring_off[r+1]-1 (at least 3, closed implicitly).
+ * poly_ring_off host, n_polys+1 int32: polygon p owns rings
+ *               poly_ring_off[p] .. poly_ring_off[p+1]-1; the first is the
+ *               outer ring, the rest are holes. Orientation is arbitrary.
+ *               Polygons may overlap (a point then matches several).
+ * mode          ACT_EXACT or ACT_APPROX.
+ * precision_m   approx mode: every reported pair is a true containment or
+ *               the point lies within precision_m metres of the polygon's
+ *               boundary (cells are split until their diagonal is below
+ *               it); must be >= 0.05. Ignored in exact mode.
+ * out           receives the index; release it with act_free.
+ *
+ * Inputs are copied; the caller keeps ownership of its arrays. Polygons must
+ * not cross the antimeridian or contain a pole (planar lat/lng model).
+ * Consecutive duplicate vertices are dropped.
+ * Errors: ACT_E_ARG, ACT_E_POLY (fewer than 3 distinct vertices in a ring,
+ * non-finite or out-of-range coordinates, more than 2^30 polygons),
+ * ACT_E_OOM, ACT_E_HIP, ACT_E_DEVICE.
+ */
+int act_build(const double *verts_latlng, const int64_t *ring_off,
+              const int32_t *poly_ring_off, int32_t n_polys, int32_t mode,
+              double precision_m, const act_build_opts *opts,
+              act_index **out);
+
+/* Release an index and its device memory. NULL is a no-op. The caller must
+ * make sure no join on it is still running. */
+void act_free(act_index *idx);
+
+/*
+ * act_join -- probe n points (Section III-E, Listing 3).
+ *
+ * d_points  device, 2*n doubles (lat, lng).
+ * d_out     device, n int32: lowest id of a polygon that covers the point
+ *           (exact mode) or that the point's cell references (approx mode),
+ *           or -1.
+ * n == 0 is a no-op. Further matches of a point (overlapping polygons,
+ * shared edges and vertices) are not reported here; use act_join_pairs.
+ */
+int act_join(const act_index *idx, const double *d_points, int64_t n,
+             int32_t *d_out, void *stream);
+
+/*
+ * act_join_pairs -- as act_join, plus every match beyond d_out[i] as a
+ * (point index, polygon id) pair (the paper's output is the list of join
+ * pairs, Listing 3).
+ *
+ * d_pair_point, d_pair_poly  device arrays of `capacity` elements.
+ * d_n_pairs  device int64 counter; the call adds the number of pairs it
+ *            found (zero it first). Pairs beyond `capacity` are counted but
+ *            not stored: after the stream completes, *d_n_pairs > capacity
+ *            means the pair list is incomplete (ACT_E_OVERFLOW condition;
+ *            rerun with a larger capacity). Pair order is unspecified.
+ */
+int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
+                   int32_t *d_out, int64_t *d_pair_point, int32_t *d_pair_poly,
+                   int64_t capacity, int64_t *d_n_pairs, void *stream);
+
+/* Join counters (uint64 each), accumulated by act_join_ex when asked. */
+enum {
+  ACT_CNT_POINTS = 0,      /* points probed                                  */
+  ACT_CNT_INVALID,         /* non-finite / out-of-range points               */
+  ACT_CNT_FALSE_HIT,       /* trie returned no cell                          */
+  ACT_CNT_SOLELY_TRUE,     /* cell with true hits only (no refinement)       */
+  ACT_CNT_CAND_POINTS,     /* points with at least one candidate hit         */
+  ACT_CNT_CANDIDATES,      /* candidate (point, polygon) pairs refined       */
+  ACT_CNT_EDGES,           /* edges visited by refinement                    */
+  ACT_CNT_EDGE_FP64,       /* edges the fp32 tier left undecided             */
+  ACT_CNT_EDGE_EXACT,      /* edges the fp64 filter left undecided           */
+  ACT_CNT_NODE_READS,      /* trie entries read (all levels)                 */
+  ACT_CNT_LUT_READS,       /* cells whose references live in the LUT         */
+  ACT_NCOUNTERS = 16
+};
+
+/* Full-control join; act_join / act_join_pairs are shorthands for it. */
+typedef struct {
+  const double *d_points;  /* device, 2*n doubles                            */
+  int64_t n;
+  int32_t *d_out;          /* device, n int32                                */
+  int64_t *d_pair_point;   /* optional (NULL): pair output, see above        */
+  int32_t *d_pair_poly;
+  int64_t pair_capacity;
+  int64_t *d_n_pairs;
+  uint64_t *d_counters;    /* optional (NULL): ACT_NCOUNTERS accumulators    */
+  int32_t refine;          /* ACT_REFINE_*                                   */
+  int32_t block;           /* threads per block (0 = tuned/default; 64..1024,
+                              a multiple of 64)                              */
+  int32_t lds_levels;      /* trie levels staged in LDS (-1 = tuned/default) */
+  int32_t reserved;
+} act_join_args;
+
+int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
+
+/*
+ * act_cell_ids -- level-30 cell ids of n points (Section II, S2 paragraph:
+ * 3 face bits, a Hilbert-ordered bit pair per level, a marker bit). The
+ * projection is lat/lng -> unit sphere -> cube face (u, v) -> quadratic
+ * (s, t) -> 30-bit (i, j) -> Hilbert position, in fp64. Invalid points get
+ * id 0. d_points: device 2*n doubles; d_ids: device n uint64. The points'
+ * device must be the current HIP device.
+ */
+int act_cell_ids(const double *d_points, int64_t n, uint64_t *d_ids,
+                 void *stream);
+
+/* Index metrics (the paper's Table III analogues plus sizes). */
+typedef struct {
+  int64_t n_polys;
+  int64_t n_edges;
+  int64_t n_cells;          /* cells of the super covering                    */
+  int64_t n_cells_interior_only; /* cells whose references are all true hits */
+  int64_t n_nodes;          /* trie nodes (256 x 8 B each), node 0 reserved    */
+  int64_t node_bytes;
+  int64_t lut_words;        /* uint32 words of the lookup table               */
+  int64_t edge_bytes;       /* device polygon store                           */
+  int64_t device_bytes;     /* total HBM held by the index                    */
+  int32_t max_depth;        /* deepest node level (root = 1)                  */
+  int32_t max_refs;         /* most references of one cell                    */
+  int32_t max_cell_level;
+  int32_t n_faces;          /* faces with a trie                              */
+  int32_t face_prefix_level[6]; /* per-face common-prefix level, -1 if none  */
+  int32_t mode;
+  int32_t reserved;
+  double precision_m;
+  double build_seconds;
+} act_stats;
+
+int act_index_stats(const act_index *idx, act_stats *out);
+
+/*
+ * act_lookup_host -- host-side trie lookup of n level-30 cell ids (for
+ * inspection and tests): writes the tagged trie entry each id ends at
+ * (0 = false hit) to entries[i]. Host pointers.
+ */
+int act_lookup_host(const act_index *idx, const uint64_t *ids, int64_t n,
+                    uint64_t *entries);
+
+/*
+ * act_lut_host -- copy of the lookup table (host). If `words` is NULL only
+ * *n_words is set. Encoding per list (Section III-C): number of true hits,
+ * the true-hit ids, number of candidate hits, the candidate ids; ids sorted
+ * ascending within each part. Trie entries with tag 3 hold word offsets.
+ */
+int act_lut_host(const act_index *idx, uint32_t *words, int64_t *n_words);
+
+/*
+ * act_encode_refs_host -- encode one reference list exactly as the builder
+ * does (tests): refs[k] = polygon id << 1 | interior flag. Returns the
+ * tagged entry in *entry and appends to / reuses the LUT held in `lut`
+ * (capacity `lut_cap` words, current length *lut_len) for lists of three or
+ * more references.
+ */
+int act_encode_refs_host(const uint32_t *refs, int32_t n_refs,
+                         uint32_t *lut, int64_t lut_cap, int64_t *lut_len,
+                         uint64_t *entry);
+
+/*
+ * act_orient_fp32_host -- the fp32 refinement tier's decision for one
+ * orientation test, evaluated on the host with the same code the GPU runs
+ * (tests): translates a, b, p by `origin` (x = lng, y = lat), rounds to
+ * fp32, and returns +1 / -1 when the proven error bound decides the sign of
+ * (bx-ax)(py-ay) - (by-ay)(px-ax), 0 when it does not. `m_poly` is the
+ * largest |translated coordinate| of the polygon (as the builder stores it).
+ */
+int act_orient_fp32_host(const double *a, const double *b, const double *p,
+                         const double *origin, float m_poly);
+
+/* Exact orientation sign as used by the builder and the last refinement
+ * tier (host evaluation, tests). */
+int act_orient_exact_host(const double *a, const double *b, const double *p);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *act_last_error(void);
+
+/* Library version string. */
+const char *act_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACT_H */

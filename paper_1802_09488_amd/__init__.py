@@ -1,0 +1,217 @@
+"""MI355X (gfx950) Adaptive Cell Trie point/polygon join.
+
+Kipf et al., "Adaptive Geospatial Joins for Modern Hardware" (arXiv
+1802.09488): polygons are approximated by a precision-preserving super
+covering of cube-face/Hilbert cells stored in an Adaptive Cell Trie
+(Sections III-B, III-C); streaming points are probed against it on the GPU
+(Section III-E) and candidate hits are refined by an exact point-in-polygon
+test. This package is a thin binding of the C ABI in include/act.h.
+
+    idx = build(polys, mode="exact")               # host build + upload
+    out = idx.join(points)                         # (n,) int32 on the GPU
+    out, pairs = idx.join_pairs(points)            # all (point, polygon) pairs
+
+`polys` is any object with .verts (V,2 float64 lat,lng), .ring_off (int64)
+and .poly_ring_off (int32) in the CSR layout of act_build; `points` is an
+(n, 2) float64 (lat, lng) CUDA tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _binding as _b
+from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64,
+                       COUNTER_NAMES, ActError)
+
+__all__ = ["build", "Index", "cell_ids", "ActError", "ACT_EXACT", "ACT_APPROX",
+           "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64", "version", "lib"]
+
+lib = _b.lib
+
+
+def version() -> str:
+    return lib.act_version().decode()
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_points(points):
+    import torch
+    if not isinstance(points, torch.Tensor) or not points.is_cuda:
+        raise TypeError("points must be a CUDA tensor")
+    if points.dtype != torch.float64 or points.dim() != 2 or points.shape[1] != 2:
+        raise TypeError("points must be an (n, 2) float64 tensor of (lat, lng)")
+    if not points.is_contiguous():
+        raise TypeError("points must be contiguous")
+
+
+class Index:
+    """A built index (host structure + HBM image). Immutable; joins on it may
+    run concurrently on different streams."""
+
+    def __init__(self, handle, mode, precision_m, device):
+        self._h = handle
+        self.mode = mode
+        self.precision_m = precision_m
+        self.device = device
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            lib.act_free(h)
+
+    def close(self):
+        self.__del__()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        st = _b.Stats()
+        _b.check(lib.act_index_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def join(self, points, out=None, stream=None):
+        """out[i] = lowest matching polygon id or -1 (int32 CUDA tensor)."""
+        import torch
+        _check_points(points)
+        n = points.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=points.device)
+        _b.check(lib.act_join(self._h, ctypes.c_void_p(points.data_ptr()), n,
+                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def join_ex(self, points, out=None, *, capacity=None, counters=False,
+                refine=ACT_REFINE_FP32_FILTER, block=0, lds_levels=-1, stream=None):
+        """Full-control join. Returns (out, pairs or None, counters dict or None).
+
+        pairs: (m, 2) int64 CUDA tensor of (point, polygon) beyond out[i]
+        when `capacity` is given (ActError ACT_E_OVERFLOW if it was too
+        small)."""
+        import torch
+        _check_points(points)
+        n = points.shape[0]
+        dev = points.device
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=dev)
+        a = _b.JoinArgs()
+        a.d_points = points.data_ptr()
+        a.n = n
+        a.d_out = out.data_ptr()
+        a.refine = refine
+        a.block = block
+        a.lds_levels = lds_levels
+        pp = pq = cnt = ctr = None
+        if capacity is not None:
+            pp = torch.empty(max(1, capacity), dtype=torch.int64, device=dev)
+            pq = torch.empty(max(1, capacity), dtype=torch.int32, device=dev)
+            cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+            a.d_pair_point, a.d_pair_poly, a.d_n_pairs = pp.data_ptr(), pq.data_ptr(), cnt.data_ptr()
+            a.pair_capacity = capacity
+        if counters:
+            ctr = torch.zeros(_b.ACT_NCOUNTERS, dtype=torch.int64, device=dev)
+            a.d_counters = ctr.data_ptr()
+        _b.check(lib.act_join_ex(self._h, ctypes.byref(a), _stream_ptr(stream)))
+        pairs = None
+        if capacity is not None:
+            m = int(cnt.item())
+            if m > capacity:
+                raise ActError(_b.ACT_E_OVERFLOW, "%d pairs exceed capacity %d" % (m, capacity))
+            pairs = torch.stack([pp[:m], pq[:m].to(torch.int64)], 1)
+        cdict = None
+        if counters:
+            c = ctr.cpu().numpy()
+            cdict = {k: int(c[i]) for i, k in enumerate(COUNTER_NAMES)}
+        return out, pairs, cdict
+
+    def join_pairs(self, points, capacity=None, stream=None):
+        """(out, pairs): pairs is (m, 2) int64 of (point, polygon) beyond out[i].
+        Retries once with the exact size if the first capacity was too small."""
+        n = points.shape[0]
+        cap = max(1024, n // 16) if capacity is None else capacity
+        try:
+            out, pairs, _ = self.join_ex(points, capacity=cap, stream=stream)
+        except ActError as e:
+            if e.code != _b.ACT_E_OVERFLOW or capacity is not None:
+                raise
+            need = int(str(e).split()[3])
+            out, pairs, _ = self.join_ex(points, capacity=need, stream=stream)
+        return out, pairs
+
+    def lookup_host(self, ids: np.ndarray) -> np.ndarray:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        ent = np.empty(ids.shape[0], np.uint64)
+        _b.check(lib.act_lookup_host(self._h, _np_ptr(ids), ids.shape[0], _np_ptr(ent)))
+        return ent
+
+    def lut_host(self) -> np.ndarray:
+        n = ctypes.c_int64(0)
+        _b.check(lib.act_lut_host(self._h, None, ctypes.byref(n)))
+        w = np.empty(n.value, np.uint32)
+        _b.check(lib.act_lut_host(self._h, _np_ptr(w), ctypes.byref(n)))
+        return w
+
+
+def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
+          device: int = 0, threads: int = 0, margin_deg: float = 0.0) -> Index:
+    """Build an index (host) and upload it to `device` (-1: host only)."""
+    m = {"exact": ACT_EXACT, "approx": ACT_APPROX}.get(mode, mode)
+    v = np.ascontiguousarray(polys.verts, dtype=np.float64)
+    ro = np.ascontiguousarray(polys.ring_off, dtype=np.int64)
+    pro = np.ascontiguousarray(polys.poly_ring_off, dtype=np.int32)
+    n_polys = pro.shape[0] - 1
+    opts = _b.BuildOpts(max_level=max_level, device=device, threads=threads, reserved=0,
+                        margin_deg=margin_deg)
+    h = ctypes.c_void_p()
+    _b.check(lib.act_build(_np_ptr(v), _np_ptr(ro), _np_ptr(pro), n_polys, m, float(precision_m),
+                           ctypes.byref(opts), ctypes.byref(h)))
+    return Index(h, m, precision_m, device)
+
+
+def cell_ids(points, out=None, stream=None):
+    """Level-30 cell ids (int64 CUDA tensor holding the uint64 bit patterns)."""
+    import torch
+    _check_points(points)
+    n = points.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=points.device)
+    _b.check(lib.act_cell_ids(ctypes.c_void_p(points.data_ptr()), n,
+                              ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def encode_refs_host(refs, lut=None, lut_cap=4096):
+    """Encode a reference list (ids << 1 | interior) as the builder does.
+    Returns (entry, lut words)."""
+    r = np.ascontiguousarray(refs, dtype=np.uint32)
+    buf = np.zeros(lut_cap, np.uint32)
+    n = 0 if lut is None else len(lut)
+    if lut is not None:
+        buf[:n] = lut
+    ln = ctypes.c_int64(n)
+    e = ctypes.c_uint64(0)
+    _b.check(lib.act_encode_refs_host(_np_ptr(r), r.shape[0], _np_ptr(buf), lut_cap,
+                                      ctypes.byref(ln), ctypes.byref(e)))
+    return int(e.value), buf[:ln.value].copy()
+
+
+def orient_fp32_host(a, b, p, origin, m_poly) -> int:
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, p, origin)]
+    return int(lib.act_orient_fp32_host(*[_np_ptr(x) for x in arr], ctypes.c_float(m_poly)))
+
+
+def orient_exact_host(a, b, p) -> int:
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, p)]
+    return int(lib.act_orient_exact_host(*[_np_ptr(x) for x in arr]))

@@ -1,0 +1,101 @@
+"""ctypes binding of libact.so (argument marshalling only).
+
+Every step of the join runs in the HIP library; torch supplies device memory
+(tensors) and streams. If the library is not built, importing this module
+raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libact.so")
+
+ACT_OK, ACT_E_ARG, ACT_E_POLY, ACT_E_OOM, ACT_E_HIP, ACT_E_OVERFLOW, ACT_E_DEVICE, ACT_E_RANGE = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ACT_EXACT, ACT_APPROX = 0, 1
+ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1
+ACT_NCOUNTERS = 16
+COUNTER_NAMES = ["points", "invalid", "false_hit", "solely_true", "cand_points", "candidates",
+                 "edges", "edge_fp64", "edge_exact", "node_reads", "lut_reads"]
+
+EXPORTS = ["act_build", "act_free", "act_join", "act_join_pairs", "act_join_ex", "act_cell_ids",
+           "act_index_stats", "act_lookup_host", "act_lut_host", "act_encode_refs_host",
+           "act_orient_fp32_host", "act_orient_exact_host", "act_last_error", "act_version"]
+
+
+class ActError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("act error %d: %s" % (code, msg))
+        self.code = code
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("max_level", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("margin_deg", ctypes.c_double)]
+
+
+class JoinArgs(ctypes.Structure):
+    _fields_ = [("d_points", ctypes.c_void_p), ("n", ctypes.c_int64), ("d_out", ctypes.c_void_p),
+                ("d_pair_point", ctypes.c_void_p), ("d_pair_poly", ctypes.c_void_p),
+                ("pair_capacity", ctypes.c_int64), ("d_n_pairs", ctypes.c_void_p),
+                ("d_counters", ctypes.c_void_p), ("refine", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_polys", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("n_cells", ctypes.c_int64), ("n_cells_interior_only", ctypes.c_int64),
+                ("n_nodes", ctypes.c_int64), ("node_bytes", ctypes.c_int64),
+                ("lut_words", ctypes.c_int64), ("edge_bytes", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("max_depth", ctypes.c_int32),
+                ("max_refs", ctypes.c_int32), ("max_cell_level", ctypes.c_int32),
+                ("n_faces", ctypes.c_int32), ("face_prefix_level", ctypes.c_int32 * 6),
+                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["face_prefix_level"] = list(self.face_prefix_level)
+        return d
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libact.so is not built (run __graft_entry__.build() or "
+                          "python paper_1802_09488_amd/build_lib.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "act_build": ([p, p, p, i32, i32, d, p, p], ctypes.c_int),
+        "act_free": ([p], None),
+        "act_join": ([p, p, i64, p, p], ctypes.c_int),
+        "act_join_pairs": ([p, p, i64, p, p, p, i64, p, p], ctypes.c_int),
+        "act_join_ex": ([p, p, p], ctypes.c_int),
+        "act_cell_ids": ([p, i64, p, p], ctypes.c_int),
+        "act_index_stats": ([p, p], ctypes.c_int),
+        "act_lookup_host": ([p, p, i64, p], ctypes.c_int),
+        "act_lut_host": ([p, p, p], ctypes.c_int),
+        "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),
+        "act_orient_fp32_host": ([p, p, p, p, ctypes.c_float], ctypes.c_int),
+        "act_orient_exact_host": ([p, p, p], ctypes.c_int),
+        "act_last_error": ([], ctypes.c_char_p),
+        "act_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def check(rc: int):
+    if rc != ACT_OK:
+        raise ActError(rc, lib.act_last_error().decode())
+    return rc

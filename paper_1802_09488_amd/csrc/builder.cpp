@@ -1,0 +1,663 @@
+// builder.cpp -- host construction of the logical and physical index.
+//
+// Logical index (Section III-B): the paper computes per-polygon coverings
+// and interior coverings and merges them into a super covering whose cells
+// never overlap, keeping each cell's (polygon id, interior flag) references
+// (flavour (iii), Listing 1, Fig. 5). Here the coverings of all polygons are
+// computed jointly by one recursive subdivision of the six cube faces: a
+// cell is classified against every polygon that can reach it as INTERIOR
+// (cell inside the polygon), EXTERIOR (disjoint) or BOUNDARY (an edge meets
+// the cell). Recursion stops when no polygon is BOUNDARY, at the maximum
+// covering level (exact mode), or once the cell's diagonal is below the
+// requested precision (approximate mode, Section III-A). The emitted cells
+// are disjoint by construction and carry exactly the references a merge of
+// the individual coverings with precision-preserving conflict resolution
+// would give them.
+//
+// Classification is conservative so that exact-mode output is bit-exact:
+// every cell is represented by a lat/lng box that contains the cell's
+// region on the sphere (corner points plus the latitude extremes of its
+// great-circle edges), inflated by a margin that dominates the GPU's fp64
+// projection rounding. All predicates on that box are exact (geom.hpp).
+//
+// Physical index (Section III-C): cells are denormalised to the node levels
+// of their face (g = 4 levels per node, Fig. 6a), references of fewer than
+// three polygons are inlined into the tagged entry, longer lists are
+// deduplicated into the lookup table (Fig. 6b).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "cellid.hpp"
+#include "geom.hpp"
+#include "index.hpp"
+
+namespace act {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kDeg = 180.0 / kPi;
+constexpr double kEarthR = 6371008.8;
+
+// Lat/lng box. When `wrap` is set the longitude range crosses the
+// antimeridian and consists of the two pieces [lng0, 180] and [-180, lng1].
+struct Box {
+  double lat0, lat1, lng0, lng1;
+  bool wrap = false;
+  int pieces() const { return wrap ? 2 : 1; }
+  double plo(int k) const { return wrap ? (k == 0 ? lng0 : -180.0) : lng0; }
+  double phi(int k) const { return wrap ? (k == 0 ? 180.0 : lng1) : lng1; }
+};
+
+struct Prep {
+  int n_polys = 0;
+  std::vector<int32_t> e_off;    // per polygon edge range
+  std::vector<double> ex;        // edges: ax ay bx by (x = lng, y = lat)
+  std::vector<Box> bbox;         // per polygon
+};
+
+// ---------------------------------------------------------------- geometry
+
+void face_uv_xyz(int face, double u, double v, double c[3]) {
+  int a = face % 3;
+  c[a] = face >= 3 ? -1.0 : 1.0;
+  c[(a + 1) % 3] = u;
+  c[(a + 2) % 3] = v;
+}
+
+double lat_of(const double c[3]) { return std::atan2(c[2], std::hypot(c[0], c[1])) * kDeg; }
+double lng_of(const double c[3]) { return std::atan2(c[1], c[0]) * kDeg; }
+
+void cross3(const double a[3], const double b[3], double o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Lat/lng bounds of the cell's region (no margin). The region is bounded by
+// four great-circle arcs: latitude can peak inside an arc (the point of the
+// arc's circle closest to a pole), longitude is monotone along each arc and
+// sweeps less than 180 degrees, so unless the cell holds a pole its longitude
+// range is the smallest circular interval containing the corners (which may
+// cross the antimeridian). Cells spanning more than 90 degrees of longitude
+// get the full range.
+Box cell_bounds(int face, int level, uint32_t i, uint32_t j) {
+  double inv = std::ldexp(1.0, -level);
+  double u0 = uv_from_st(i * inv), u1 = uv_from_st((i + 1) * inv);
+  double v0 = uv_from_st(j * inv), v1 = uv_from_st((j + 1) * inv);
+  double P[4][3];
+  face_uv_xyz(face, u0, v0, P[0]);
+  face_uv_xyz(face, u1, v0, P[1]);
+  face_uv_xyz(face, u1, v1, P[2]);
+  face_uv_xyz(face, u0, v1, P[3]);
+  Box b{90, -90, 180, -180};
+  double lng[4];
+  for (int k = 0; k < 4; k++) {
+    double la = lat_of(P[k]);
+    lng[k] = lng_of(P[k]);
+    b.lat0 = std::min(b.lat0, la);
+    b.lat1 = std::max(b.lat1, la);
+  }
+  for (int k = 0; k < 4; k++) {
+    const double *A = P[k], *B = P[(k + 1) & 3];
+    double n[3];
+    cross3(A, B, n);
+    double nxy2 = n[0] * n[0] + n[1] * n[1];
+    if (nxy2 <= 0) continue;
+    double m[3] = {-n[0] * n[2], -n[1] * n[2], nxy2};
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+      double q[3] = {sgn * m[0], sgn * m[1], sgn * m[2]};
+      double t1[3], t2[3];
+      cross3(A, q, t1);
+      cross3(q, B, t2);
+      if (dot3(t1, n) >= 0 && dot3(t2, n) >= 0) {
+        double la = lat_of(q);
+        b.lat0 = std::min(b.lat0, la);
+        b.lat1 = std::max(b.lat1, la);
+      }
+    }
+  }
+  bool pole = (face % 3 == 2) && u0 <= 0 && u1 >= 0 && v0 <= 0 && v1 >= 0;
+  if (pole) {
+    if (face == 2) b.lat1 = 90;
+    else b.lat0 = -90;
+    b.lng0 = -180;
+    b.lng1 = 180;
+    return b;
+  }
+  // smallest circular interval holding the four corner longitudes
+  std::sort(lng, lng + 4);
+  double gap = lng[0] + 360.0 - lng[3];
+  int after = 0;  // index of the value right after the largest gap
+  for (int k = 1; k < 4; k++)
+    if (lng[k] - lng[k - 1] > gap) {
+      gap = lng[k] - lng[k - 1];
+      after = k;
+    }
+  if (360.0 - gap > 90.0) {
+    b.lng0 = -180;
+    b.lng1 = 180;
+  } else if (after == 0) {
+    b.lng0 = lng[0];
+    b.lng1 = lng[3];
+  } else {
+    b.lng0 = lng[after];
+    b.lng1 = lng[after - 1];
+    b.wrap = true;
+  }
+  return b;
+}
+
+// Inflate by the margin. A child's box is not clipped to its parent's: the
+// child's region lies inside the parent's, so classifying the child only
+// against the edges that meet the parent box decides the child box's part
+// inside the parent box, which still holds the child region plus nearly the
+// whole margin.
+Box inflate(Box b, double margin) {
+  b.lat0 -= margin;
+  b.lat1 += margin;
+  b.lng0 -= margin;
+  b.lng1 += margin;
+  if (!b.wrap && b.lng1 - b.lng0 >= 360.0) {
+    b.lng0 = -180 - margin;
+    b.lng1 = 180 + margin;
+  }
+  return b;
+}
+
+// Upper bound of the planar distance (local equirectangular frame at any
+// latitude of the box) between two points of the box, in metres.
+double box_diag_m(const Box &b) {
+  double k = kEarthR * kPi / 180.0;
+  double maxcos = (b.lat0 <= 0 && b.lat1 >= 0)
+                      ? 1.0
+                      : std::cos(std::min(std::fabs(b.lat0), std::fabs(b.lat1)) / kDeg);
+  // the planar model does not wrap: a box across the antimeridian is as wide
+  // as the plane
+  double w = b.wrap ? 360.0 : b.lng1 - b.lng0;
+  double dx = w * maxcos, dy = b.lat1 - b.lat0;
+  // small relative slack for rounding in this evaluation
+  return k * std::sqrt(dx * dx + dy * dy) * (1.0 + 1e-12);
+}
+
+// Cell box (possibly wrapped) vs a polygon's bounding box (never wrapped).
+bool boxes_meet(const Box &a, const Box &pb) {
+  if (a.lat1 < pb.lat0 || pb.lat1 < a.lat0) return false;
+  for (int k = 0; k < a.pieces(); k++)
+    if (!(a.phi(k) < pb.lng0 || pb.lng1 < a.plo(k))) return true;
+  return false;
+}
+
+bool segment_meets(const double *q, const Box &b) {
+  for (int k = 0; k < b.pieces(); k++)
+    if (segment_meets_box(q[0], q[1], q[2], q[3], b.plo(k), b.phi(k), b.lat0, b.lat1)) return true;
+  return false;
+}
+
+bool poly_covers(const Prep &P, int p, double x, double y) {
+  int inside = 0;
+  for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) {
+    const double *q = &P.ex[4 * (size_t)e];
+    int r = edge_test_exact(q[0], q[1], q[2], q[3], x, y);
+    if (r == 2) return true;
+    inside ^= r;
+  }
+  return inside != 0;
+}
+
+// ------------------------------------------------------------ subdivision
+
+struct Bref {
+  int32_t poly, off, cnt;  // edges[off .. off+cnt) meet the cell's box
+};
+
+struct Work {
+  int face, level;
+  uint32_t i, j;
+  Box box;
+  std::vector<int32_t> interior;  // polygons containing the cell
+  std::vector<Bref> bnd;
+  std::vector<int32_t> edges;
+};
+
+struct CellOut {
+  uint64_t id;
+  int32_t level;
+  int32_t ref_off, ref_cnt;
+};
+
+struct Sink {
+  std::vector<CellOut> cells;
+  std::vector<uint32_t> refs;  // id << 1 | interior
+};
+
+struct Ctx {
+  const Prep *P;
+  BuildParams bp;
+  const uint16_t *htab;
+  std::atomic<bool> failed{false};
+  std::string err;
+};
+
+// Classify a child box given the parent's candidates.
+void classify(const Ctx &C, const Box &box, const std::vector<int32_t> &pint,
+              const std::vector<Bref> &pbnd, const std::vector<int32_t> &pedges, Work &w) {
+  const Prep &P = *C.P;
+  w.interior = pint;
+  w.bnd.clear();
+  w.edges.clear();
+  for (const Bref &br : pbnd) {
+    if (!boxes_meet(box, P.bbox[br.poly])) continue;
+    int32_t off = (int32_t)w.edges.size();
+    for (int k = 0; k < br.cnt; k++) {
+      int e = pedges[br.off + k];
+      const double *q = &P.ex[4 * (size_t)e];
+      if (segment_meets(q, box)) w.edges.push_back(e);
+    }
+    int32_t cnt = (int32_t)w.edges.size() - off;
+    if (cnt > 0) {
+      w.bnd.push_back({br.poly, off, cnt});
+    } else {
+      // no edge meets the box: each (convex) piece is inside or outside
+      double cy = 0.5 * (box.lat0 + box.lat1);
+      int in = 0;
+      for (int k = 0; k < box.pieces(); k++)
+        in += poly_covers(P, br.poly, 0.5 * (box.plo(k) + box.phi(k)), cy);
+      if (in == box.pieces()) w.interior.push_back(br.poly);
+      else if (in > 0) w.bnd.push_back({br.poly, off, 0});  // undecided: keep as candidate
+    }
+  }
+  std::sort(w.interior.begin(), w.interior.end());
+}
+
+void emit(const Ctx &C, const Work &w, Sink &s) {
+  CellOut c;
+  c.id = cell_id(w.face, w.level, w.i, w.j, C.htab);
+  c.level = w.level;
+  c.ref_off = (int32_t)s.refs.size();
+  size_t a = 0, b = 0;
+  // merge interior (flag 1) and boundary (flag 0) ids in ascending order
+  std::vector<int32_t> bids;
+  bids.reserve(w.bnd.size());
+  for (const Bref &br : w.bnd) bids.push_back(br.poly);
+  std::sort(bids.begin(), bids.end());
+  while (a < w.interior.size() || b < bids.size()) {
+    if (b >= bids.size() || (a < w.interior.size() && w.interior[a] < bids[b]))
+      s.refs.push_back(((uint32_t)w.interior[a++] << 1) | 1u);
+    else
+      s.refs.push_back((uint32_t)bids[b++] << 1);
+  }
+  c.ref_cnt = (int32_t)s.refs.size() - c.ref_off;
+  s.cells.push_back(c);
+}
+
+// Decide a cell: returns true if it must be split further.
+bool settle(Ctx &C, const Work &w, Sink &s) {
+  if (w.bnd.empty()) {
+    if (!w.interior.empty()) emit(C, w, s);
+    return false;
+  }
+  if (C.bp.mode == ACT_EXACT) {
+    if (w.level >= C.bp.max_level) {
+      emit(C, w, s);
+      return false;
+    }
+    return true;
+  }
+  if (box_diag_m(w.box) < C.bp.precision_m) {
+    emit(C, w, s);
+    return false;
+  }
+  if (w.level >= kMaxLevel) {
+    if (w.box.wrap) {  // level-30 cell on the antimeridian: emitted as is
+      emit(C, w, s);
+      return false;
+    }
+    if (!C.failed.exchange(true))
+      C.err = "precision_m is below the diagonal of the finest (level-30) cell";
+    return false;
+  }
+  return true;
+}
+
+void make_child(Ctx &C, const Work &w, int q, Work &c) {
+  c.face = w.face;
+  c.level = w.level + 1;
+  c.i = (w.i << 1) | (uint32_t)(q >> 1);
+  c.j = (w.j << 1) | (uint32_t)(q & 1);
+  c.box = inflate(cell_bounds(c.face, c.level, c.i, c.j), C.bp.margin_deg);
+  classify(C, c.box, w.interior, w.bnd, w.edges, c);
+}
+
+void dfs(Ctx &C, const Work &w, Sink &s) {
+  if (C.failed.load(std::memory_order_relaxed)) return;
+  if (!settle(C, w, s)) return;
+  Work c;
+  for (int q = 0; q < 4; q++) {
+    make_child(C, w, q, c);
+    dfs(C, c, s);
+  }
+}
+
+// ------------------------------------------------------------------- LUT
+
+}  // namespace
+
+struct LutDedup {
+  std::unordered_map<std::string, uint32_t> map;
+};
+LutDedup *lut_dedup_new() { return new LutDedup; }
+void lut_dedup_free(LutDedup *d) { delete d; }
+
+uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup) {
+  if (n <= 0) return 0;
+  std::vector<uint32_t> r(refs, refs + n);
+  std::sort(r.begin(), r.end(), [](uint32_t a, uint32_t b) { return (a >> 1) < (b >> 1); });
+  if (n == 1) return ((uint64_t)r[0] << 2) | kTagOne;
+  if (n == 2) return ((uint64_t)r[0] << 2) | ((uint64_t)r[1] << 33) | kTagTwo;
+  std::vector<uint32_t> list;
+  list.reserve(n + 2);
+  uint32_t nt = 0;
+  for (uint32_t v : r) nt += v & 1u;
+  list.push_back(nt);
+  for (uint32_t v : r)
+    if (v & 1u) list.push_back(v >> 1);
+  list.push_back((uint32_t)n - nt);
+  for (uint32_t v : r)
+    if (!(v & 1u)) list.push_back(v >> 1);
+  std::string key((const char *)list.data(), list.size() * sizeof(uint32_t));
+  auto it = dedup->map.find(key);
+  uint32_t off;
+  if (it != dedup->map.end()) {
+    off = it->second;
+  } else {
+    off = (uint32_t)lut.size();
+    lut.insert(lut.end(), list.begin(), list.end());
+    dedup->map.emplace(std::move(key), off);
+  }
+  return ((uint64_t)off << 2) | kTagLut;
+}
+
+uint64_t host_lookup(const HostIndex &idx, uint64_t id) {
+  int face = (int)(id >> 61);
+  if (face > 5) return 0;
+  const FaceRoot &f = idx.faces[face];
+  if (f.root < 0) return 0;
+  uint64_t key = (id >> 1) & ((1ull << 60) - 1);
+  int sh = 60 - 2 * f.plevel;
+  if (f.plevel > 0 && (key >> sh) != f.prefix) return 0;
+  uint64_t node = (uint64_t)f.root;
+  for (;;) {
+    sh -= 8;
+    uint64_t e = idx.nodes[node * 256 + ((key >> sh) & 255u)];
+    if ((e & kTagMask) != kTagPtr || e == 0) return e;
+    node = e >> 2;
+  }
+}
+
+int build_host_index(const double *verts, const int64_t *ring_off, const int32_t *poly_ring_off,
+                     int32_t n_polys, const BuildParams &bp, HostIndex &out, std::string &err) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (n_polys < 0 || n_polys > (1 << 30)) {
+    err = "n_polys must be in 0 .. 2^30";
+    return ACT_E_POLY;
+  }
+  // ------------------------------------------------ validate and prepare
+  Prep P;
+  P.n_polys = n_polys;
+  P.e_off.assign(n_polys + 1, 0);
+  P.bbox.resize(n_polys);
+  out = HostIndex();
+  out.mode = bp.mode;
+  out.precision_m = bp.precision_m;
+  out.max_level = bp.max_level;
+  out.n_polys = n_polys;
+  out.poly_edge_off.assign(n_polys + 1, 0);
+  out.poly_origin.resize(2 * (size_t)n_polys);
+  out.poly_m.resize(n_polys);
+  if (poly_ring_off[0] != 0) {
+    err = "poly_ring_off[0] must be 0";
+    return ACT_E_POLY;
+  }
+  for (int p = 0; p < n_polys; p++) {
+    int r0 = poly_ring_off[p], r1 = poly_ring_off[p + 1];
+    if (r1 <= r0) {
+      err = "polygon " + std::to_string(p) + " has no ring";
+      return ACT_E_POLY;
+    }
+    Box bb{INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int r = r0; r < r1; r++) {
+      int64_t k0 = ring_off[r], k1 = ring_off[r + 1];
+      if (k1 < k0) {
+        err = "ring offsets must be non-decreasing";
+        return ACT_E_POLY;
+      }
+      std::vector<double> ring;  // x y pairs after dropping duplicates
+      for (int64_t k = k0; k < k1; k++) {
+        double lat = verts[2 * k], lng = verts[2 * k + 1];
+        if (!std::isfinite(lat) || !std::isfinite(lng) || std::fabs(lat) > 90 ||
+            std::fabs(lng) > 180) {
+          err = "polygon " + std::to_string(p) + ": vertex out of range or not finite";
+          return ACT_E_POLY;
+        }
+        size_t m = ring.size();
+        if (m >= 2 && ring[m - 2] == lng && ring[m - 1] == lat) continue;
+        ring.push_back(lng);
+        ring.push_back(lat);
+      }
+      while (ring.size() >= 4 && ring[0] == ring[ring.size() - 2] && ring[1] == ring.back()) {
+        ring.pop_back();
+        ring.pop_back();
+      }
+      size_t m = ring.size() / 2;
+      if (m < 3) {
+        err = "polygon " + std::to_string(p) + ": ring with fewer than 3 distinct vertices";
+        return ACT_E_POLY;
+      }
+      for (size_t k = 0; k < m; k++) {
+        size_t kn = (k + 1) % m;
+        P.ex.insert(P.ex.end(), {ring[2 * k], ring[2 * k + 1], ring[2 * kn], ring[2 * kn + 1]});
+        bb.lng0 = std::min(bb.lng0, ring[2 * k]);
+        bb.lng1 = std::max(bb.lng1, ring[2 * k]);
+        bb.lat0 = std::min(bb.lat0, ring[2 * k + 1]);
+        bb.lat1 = std::max(bb.lat1, ring[2 * k + 1]);
+      }
+    }
+    P.e_off[p + 1] = (int32_t)(P.ex.size() / 4);
+    P.bbox[p] = bb;
+  }
+  if (P.ex.size() / 4 > (size_t)INT32_MAX) {
+    err = "too many edges";
+    return ACT_E_POLY;
+  }
+  // ------------------------------------------------------- polygon store
+  size_t n_edges = P.ex.size() / 4;
+  out.poly_edge_off = P.e_off;
+  out.edges64 = P.ex;
+  out.edges32.resize(4 * n_edges);
+  for (int p = 0; p < n_polys; p++) {
+    double ox = 0.5 * (P.bbox[p].lng0 + P.bbox[p].lng1);
+    double oy = 0.5 * (P.bbox[p].lat0 + P.bbox[p].lat1);
+    out.poly_origin[2 * p] = ox;
+    out.poly_origin[2 * p + 1] = oy;
+    float m = 0;
+    for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++)
+      for (int c = 0; c < 4; c++) {
+        double o = (c & 1) ? oy : ox;
+        float v = (float)(P.ex[4 * (size_t)e + c] - o);
+        out.edges32[4 * (size_t)e + c] = v;
+        m = std::max(m, std::fabs(v));
+      }
+    out.poly_m[p] = m;
+  }
+  // --------------------------------------------------------- subdivision
+  uint16_t htab[1024];
+  hilbert_table4(htab);
+  Ctx C;
+  C.P = &P;
+  C.bp = bp;
+  C.htab = htab;
+  int nthreads = bp.threads > 0 ? bp.threads : (int)std::max(1u, std::thread::hardware_concurrency());
+
+  std::vector<int32_t> all_polys;
+  std::vector<Bref> all_bnd;
+  std::vector<int32_t> all_edges;
+  for (int p = 0; p < n_polys; p++) {
+    all_bnd.push_back({p, (int32_t)all_edges.size(), P.e_off[p + 1] - P.e_off[p]});
+    for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) all_edges.push_back(e);
+  }
+  std::vector<Work> frontier;
+  Sink top;
+  for (int face = 0; face < 6; face++) {
+    Work w;
+    w.face = face;
+    w.level = 0;
+    w.i = w.j = 0;
+    w.box = inflate(cell_bounds(face, 0, 0, 0), bp.margin_deg);
+    std::vector<int32_t> none;
+    classify(C, w.box, none, all_bnd, all_edges, w);
+    frontier.push_back(std::move(w));
+  }
+  all_bnd.clear();
+  all_edges.clear();
+  // expand breadth-first until there is enough independent work
+  std::vector<Work> tasks;
+  while (!frontier.empty()) {
+    std::vector<Work> next;
+    for (Work &w : frontier) {
+      if (!settle(C, w, top)) continue;
+      for (int q = 0; q < 4; q++) {
+        Work c;
+        make_child(C, w, q, c);
+        next.push_back(std::move(c));
+      }
+    }
+    frontier.swap(next);
+    if (frontier.size() >= (size_t)(64 * nthreads)) break;
+  }
+  tasks.swap(frontier);
+  std::vector<Sink> sinks(nthreads);
+  std::atomic<size_t> cursor{0};
+  auto worker = [&](int t) {
+    for (;;) {
+      size_t k = cursor.fetch_add(1);
+      if (k >= tasks.size()) break;
+      dfs(C, tasks[k], sinks[t]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; t++) pool.emplace_back(worker, t);
+  worker(0);
+  for (auto &th : pool) th.join();
+  tasks.clear();
+  if (C.failed) {
+    err = C.err;
+    return ACT_E_ARG;
+  }
+  // gather cells
+  struct Cell {
+    uint64_t id;
+    int level;
+    const uint32_t *refs;
+    int n;
+  };
+  std::vector<Cell> cells;
+  auto gather = [&](const Sink &s) {
+    for (const CellOut &c : s.cells) cells.push_back({c.id, c.level, &s.refs[c.ref_off], c.ref_cnt});
+  };
+  gather(top);
+  for (const Sink &s : sinks) gather(s);
+  std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) { return a.id < b.id; });
+  out.n_cells = (int64_t)cells.size();
+  // ------------------------------------------------------------- tries
+  out.nodes.assign(256, 0);  // node 0 reserved
+  LutDedup dedup;
+  size_t c0 = 0;
+  for (int face = 0; face < 6; face++) {
+    size_t c1 = c0;
+    while (c1 < cells.size() && (int)(cells[c1].id >> 61) == face) c1++;
+    if (c1 == c0) continue;
+    int lmin = 30, lmax = 0;
+    uint64_t k0 = cell_key(cells[c0].id), diff = 0;
+    for (size_t k = c0; k < c1; k++) {
+      lmin = std::min(lmin, cells[k].level);
+      lmax = std::max(lmax, cells[k].level);
+      diff |= cell_key(cells[k].id) ^ k0;
+    }
+    int common_bits = diff ? 59 - (63 - __builtin_clzll(diff)) : 60;
+    int lc = std::min(lmin, common_bits / 2);
+    int lp = lc - ((4 - (lmax - lc) % 4) % 4);
+    if (lp < 0) {
+      lp = lc;
+      if (lp + 4 * ((lmax - lp + 3) / 4) > kMaxLevel) {
+        err = "cells on one face span too wide a range for the trie's level alignment";
+        return ACT_E_RANGE;
+      }
+    }
+    FaceRoot &F = out.faces[face];
+    F.plevel = lp;
+    F.prefix = lp > 0 ? (k0 >> (60 - 2 * lp)) : 0;
+    F.root = (int32_t)(out.nodes.size() / 256);
+    out.nodes.resize(out.nodes.size() + 256, 0);
+    for (size_t k = c0; k < c1; k++) {
+      const Cell &c = cells[k];
+      uint64_t key = cell_key(c.id);
+      int l = c.level;
+      int kd = l <= lp ? 0 : (l - lp - 1) / 4;
+      uint64_t node = (uint64_t)F.root;
+      for (int d = 0; d < kd; d++) {
+        int sh = 60 - 2 * lp - 8 * (d + 1);
+        uint64_t slot = node * 256 + ((key >> sh) & 255u);
+        uint64_t e = out.nodes[slot];
+        if (e == 0) {
+          uint64_t nn = out.nodes.size() / 256;
+          out.nodes[slot] = nn << 2;
+          out.nodes.resize(out.nodes.size() + 256, 0);
+          node = nn;
+        } else if ((e & kTagMask) == kTagPtr) {
+          node = e >> 2;
+        } else {
+          err = "internal: overlapping cells in the super covering";
+          return ACT_E_POLY;
+        }
+      }
+      int sh = 60 - 2 * lp - 8 * (kd + 1);
+      uint64_t base = (key >> sh) & 255u;
+      uint64_t count = 1ull << (2 * (lp + 4 * (kd + 1) - l));
+      uint64_t entry = encode_refs(c.refs, c.n, out.lut, &dedup);
+      if (out.lut.size() >= (1ull << 31)) {
+        err = "lookup table exceeds 2^31 words";
+        return ACT_E_RANGE;
+      }
+      for (uint64_t b = base; b < base + count; b++) {
+        uint64_t slot = node * 256 + b;
+        if (out.nodes[slot] != 0) {
+          err = "internal: overlapping cells in the super covering";
+          return ACT_E_POLY;
+        }
+        out.nodes[slot] = entry;
+      }
+      F.depth = std::max(F.depth, kd + 1);
+      out.max_depth = std::max(out.max_depth, kd + 1);
+      out.max_refs = std::max(out.max_refs, c.n);
+      out.max_cell_level = std::max(out.max_cell_level, l);
+      bool all_true = true;
+      for (int r = 0; r < c.n; r++) all_true &= (c.refs[r] & 1u) != 0;
+      out.n_cells_interior_only += all_true;
+    }
+    c0 = c1;
+  }
+  out.build_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return ACT_OK;
+}
+
+}  // namespace act

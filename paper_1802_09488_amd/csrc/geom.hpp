@@ -1,0 +1,175 @@
+// geom.hpp -- orientation predicates and the point-in-polygon edge test used
+// by the index builder (host) and the refinement tiers (GPU).
+//
+// Join predicate: ST_Covers (Section II) in the plane x = longitude,
+// y = latitude (degrees), closed polygons, even-odd crossing number of a ray
+// towards +x (the ray tracing PIP test, Section II). Per edge (a, b) and
+// point p:
+//   on boundary  <=> orient(a, b, p) == 0 and p inside the edge's closed box;
+//   crossing     <=> (a.y > p.y) != (b.y > p.y) and p lies left of the
+//                    upward-directed edge (orient > 0 for b.y > a.y,
+//                    orient < 0 otherwise).
+// orient(a, b, p) = (bx-ax)(py-ay) - (by-ay)(px-ax).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#define ACT_HD __host__ __device__ __forceinline__
+
+namespace act {
+
+// ---------------------------------------------------------------------------
+// Exact orientation sign in fp64 (builder, refinement tiers 2 and 3).
+//
+// Tier 2: fp64 evaluation with the static error bound (3 + 16 eps) eps
+// (|l| + |r|), eps = 2^-53 (Shewchuk 1997, orient2d "ccwerrboundA").
+// Tier 3: the determinant expanded into six products
+//   bx*py - bx*ay - ax*py - by*px + by*ax + ay*px,
+// each split exactly into value + rounding error with an FMA, the twelve
+// terms summed without error into a nonoverlapping expansion; its most
+// significant nonzero component carries the sign. Exact unless a product
+// underflows (nonzero coordinates above 2^-450 in magnitude).
+// ---------------------------------------------------------------------------
+
+ACT_HD void exact_mul(double a, double b, double &p, double &e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+ACT_HD void exact_add(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  double z = s - a;
+  e = (a - (s - z)) + (b - z);
+}
+
+ACT_HD int orient_sign_expansion(double ax, double ay, double bx, double by,
+                                 double px, double py) {
+  double t[12];
+  exact_mul(bx, py, t[0], t[1]);
+  exact_mul(-bx, ay, t[2], t[3]);
+  exact_mul(-ax, py, t[4], t[5]);
+  exact_mul(-by, px, t[6], t[7]);
+  exact_mul(by, ax, t[8], t[9]);
+  exact_mul(ay, px, t[10], t[11]);
+  double h[12];
+#pragma unroll
+  for (int k = 0; k < 12; k++) {
+    double q = t[k];
+#pragma unroll
+    for (int i = 0; i < k; i++) {
+      double s, e;
+      exact_add(q, h[i], s, e);
+      h[i] = e;
+      q = s;
+    }
+    h[k] = q;
+  }
+  int sign = 0;
+#pragma unroll
+  for (int i = 0; i < 12; i++) {
+    // components ascend in magnitude: the last nonzero one decides
+    sign = h[i] > 0.0 ? 1 : (h[i] < 0.0 ? -1 : sign);
+  }
+  return sign;
+}
+
+// Returns +1/-1 when the fp64 filter decides, 0 when it does not.
+ACT_HD int orient_sign_fp64_filter(double ax, double ay, double bx, double by,
+                                   double px, double py) {
+#pragma clang fp contract(off)
+  const double eps = 1.1102230246251565e-16;  // 2^-53
+  double l = (bx - ax) * (py - ay);
+  double r = (by - ay) * (px - ax);
+  double det = l - r;
+  double bound = (3.0 + 16.0 * eps) * eps * (fabs(l) + fabs(r));
+  return det > bound ? 1 : (-det > bound ? -1 : 0);
+}
+
+ACT_HD int orient_sign_exact(double ax, double ay, double bx, double by,
+                             double px, double py) {
+  int s = orient_sign_fp64_filter(ax, ay, bx, by, px, py);
+  return s != 0 ? s : orient_sign_expansion(ax, ay, bx, by, px, py);
+}
+
+// ---------------------------------------------------------------------------
+// Tier 1: fp32 orientation on coordinates translated by a per-polygon fp64
+// origin o and rounded to fp32 (the polygon's vertices once on the host, the
+// point on the GPU: fp64 subtraction, then round-to-nearest to fp32).
+//
+// Error bound (derived for this code, contraction off, u = 2^-24):
+//  * input rounding: |x_hat - (x - o)| <= eta with
+//      eta = u (1 + 2^-20) M + 2^-100,
+//    M >= every |x_hat| involved (fp64 then fp32 rounding of x - o; the
+//    2^-100 term absorbs fp32 underflow);
+//  * evaluation: d1 = bx-ax, d2 = py-ay, d3 = by-ay, d4 = px-ax (rounded),
+//    t1 = d1 d2, t2 = d3 d4, det = t1 - t2 (rounded) differs from the exact
+//    determinant D' of the rounded inputs by at most
+//      (u + 3u/(1 - 6u)) (|t1| + |t2|) <= (4u + 32u^2)(|t1| + |t2|);
+//  * input perturbation: each exact difference moves by <= 2 eta, so
+//      |D' - D| <= 2 eta (|d1|+|d2|+|d3|+|d4|)/(1-u) + 8 eta^2,
+//    D being the exact determinant of the original fp64 coordinates
+//    (translation leaves it unchanged);
+//  * the bound itself is evaluated in fp32: the result is inflated by
+//    (1 + 16u) and an absolute 1e-30 covers product underflow.
+// The sign of det is the exact sign whenever |det| > B.
+// ---------------------------------------------------------------------------
+
+ACT_HD float tier1_eta(float m) {
+  return 5.9604644775390625e-08f * (1.0f + 9.5367431640625e-07f) * m +
+         7.888609052210118e-31f;  // 2^-100
+}
+
+ACT_HD int orient_sign_fp32_filter(float ax, float ay, float bx, float by,
+                                   float px, float py, float eta) {
+#pragma clang fp contract(off)
+  const float u = 5.9604644775390625e-08f;  // 2^-24
+  float d1 = bx - ax, d2 = py - ay, d3 = by - ay, d4 = px - ax;
+  float t1 = d1 * d2, t2 = d3 * d4;
+  float det = t1 - t2;
+  float s = fabsf(d1) + fabsf(d2) + fabsf(d3) + fabsf(d4);
+  float B = (4.0f * u + 32.0f * u * u) * (fabsf(t1) + fabsf(t2)) +
+            2.0f * eta * s * (1.0f + 2.0f * u) + 8.0f * eta * eta;
+  B = B * (1.0f + 16.0f * u) + 1e-30f;
+  return det > B ? 1 : (-det > B ? -1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// One edge of the crossing-number test on original fp64 coordinates, with
+// exact orientation (tiers 2 + 3). Returns 2 if p lies on the edge,
+// 1 if the edge toggles the crossing parity, 0 otherwise.
+// ---------------------------------------------------------------------------
+ACT_HD int edge_test_exact(double ax, double ay, double bx, double by,
+                           double px, double py) {
+  bool straddle = (ay > py) != (by > py);
+  bool in_box = px >= fmin(ax, bx) && px <= fmax(ax, bx) && py >= fmin(ay, by) &&
+                py <= fmax(ay, by);
+  if (!straddle && !in_box) return 0;
+  int s = orient_sign_exact(ax, ay, bx, by, px, py);
+  if (in_box && s == 0) return 2;
+  if (straddle && ((by > ay) ? (s > 0) : (s < 0))) return 1;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Closed segment vs closed axis-aligned box, exact (separating axes: the two
+// box axes and the segment's normal).
+// ---------------------------------------------------------------------------
+ACT_HD bool segment_meets_box(double ax, double ay, double bx, double by,
+                              double x0, double x1, double y0, double y1) {
+  if (fmax(ax, bx) < x0 || fmin(ax, bx) > x1 || fmax(ay, by) < y0 ||
+      fmin(ay, by) > y1)
+    return false;
+  int s0 = orient_sign_exact(ax, ay, bx, by, x0, y0);
+  int s1 = orient_sign_exact(ax, ay, bx, by, x1, y0);
+  int s2 = orient_sign_exact(ax, ay, bx, by, x1, y1);
+  int s3 = orient_sign_exact(ax, ay, bx, by, x0, y1);
+  if (s0 > 0 && s1 > 0 && s2 > 0 && s3 > 0) return false;
+  if (s0 < 0 && s1 < 0 && s2 < 0 && s3 < 0) return false;
+  return true;
+}
+
+}  // namespace act

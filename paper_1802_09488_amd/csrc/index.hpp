@@ -1,0 +1,84 @@
+// index.hpp -- host-side representation of a built index and the layout of
+// its device image (shared by the builder and the GPU runtime).
+//
+// Adaptive Cell Trie (Section III-C, Fig. 6): nodes of 256 tagged 8-byte
+// entries (fanout 256 = 4 cell levels per node). Tag = two low bits:
+//   00  child pointer: node index << 2; the value 0 is the sentinel
+//       (false hit) -- node 0 is reserved and never referenced;
+//   01  one inlined reference: bits 2..32 = polygon id << 1 | interior;
+//   10  two inlined references: bits 2..32 and 33..63, ascending ids;
+//   11  lookup-table word offset << 2.
+// Lookup table: one uint32 array; each list is
+//   n_true, true ids..., n_cand, candidate ids... (ids ascending per part).
+// Per face: a root node, the common prefix shared by every indexed cell on
+// the face (prefix level Lp), and the alignment of node levels: the root
+// covers levels Lp+1..Lp+4, its children Lp+5..Lp+8, and so on (the
+// per-face common prefix of Section IV-B2 / Listing 4 with the level
+// granularity g = 4 of Section III-C).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/act.h"
+
+namespace act {
+
+constexpr uint64_t kTagMask = 3;
+constexpr uint64_t kTagPtr = 0, kTagOne = 1, kTagTwo = 2, kTagLut = 3;
+
+struct FaceRoot {
+  int32_t root = -1;      // node index, -1 if the face has no cells
+  int32_t plevel = 0;     // prefix level Lp
+  uint64_t prefix = 0;    // the 2*Lp leading key bits
+  int32_t depth = 0;      // number of node levels below the prefix
+};
+
+struct HostIndex {
+  int32_t mode = ACT_EXACT;
+  double precision_m = 0;
+  int32_t max_level = 20;
+  int32_t n_polys = 0;
+
+  FaceRoot faces[6];
+  std::vector<uint64_t> nodes;   // 256 entries per node, node 0 reserved
+  std::vector<uint32_t> lut;
+
+  // polygon store (x = lng, y = lat)
+  std::vector<int32_t> poly_edge_off;  // n_polys + 1
+  std::vector<double> poly_origin;     // 2 per polygon (x, y)
+  std::vector<float> poly_m;           // largest |translated fp32 coordinate|
+  std::vector<float> edges32;          // 4 per edge: ax ay bx by, translated
+  std::vector<double> edges64;         // 4 per edge: ax ay bx by
+
+  // statistics
+  int64_t n_cells = 0, n_cells_interior_only = 0;
+  int32_t max_depth = 0, max_refs = 0, max_cell_level = 0;
+  double build_seconds = 0;
+};
+
+struct BuildParams {
+  int32_t mode;
+  double precision_m;
+  int32_t max_level;
+  int32_t threads;
+  double margin_deg;
+};
+
+// Builds the host index. Returns ACT_OK or an error code with `err` set.
+int build_host_index(const double *verts_latlng, const int64_t *ring_off,
+                     const int32_t *poly_ring_off, int32_t n_polys,
+                     const BuildParams &bp, HostIndex &out, std::string &err);
+
+// Host trie lookup of a leaf cell id: the tagged entry the descent ends at.
+uint64_t host_lookup(const HostIndex &idx, uint64_t id);
+
+// Encode one reference list (refs[k] = id << 1 | interior) into a tagged
+// entry, deduplicating lists of three or more in `lut` via `dedup`.
+struct LutDedup;
+LutDedup *lut_dedup_new();
+void lut_dedup_free(LutDedup *);
+uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup);
+
+}  // namespace act

@@ -1,0 +1,206 @@
+"""GPU parity: the HIP probe (through the C ABI) vs the brute-force oracle.
+
+Exact mode must match bit for bit: out[i] (lowest covering id or -1) and the
+set of further (point, polygon) pairs. Approximate mode must respect its
+guarantee: no covering polygon missed, and every extra pair's point lies
+within precision_m of that polygon's boundary.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cellid as C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def act():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_09488_amd as act
+    return act
+
+
+_IDX = {}
+
+
+def index(act, w, mode, prec=0.0):
+    key = (w, mode, prec)
+    if key not in _IDX:
+        _IDX[key] = (synth.workload_polygons(w), None)
+        P = _IDX[key][0]
+        _IDX[key] = (P, act.build(P, mode, prec))
+    return _IDX[key]
+
+
+def gpu_join(idx, pts, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    out, pairs, ctr = idx.join_ex(t, capacity=max(4096, len(pts) // 4), **kw)
+    torch.cuda.synchronize()
+    pr = pairs.cpu().numpy() if pairs is not None else np.zeros((0, 2), np.int64)
+    order = np.lexsort((pr[:, 1], pr[:, 0])) if len(pr) else np.zeros(0, np.int64)
+    return out.cpu().numpy(), pr[order], ctr
+
+
+def assert_exact(P, pts, out, pairs, label=""):
+    ref = oracle.join(P, pts)
+    bad = np.nonzero(out != ref.out)[0]
+    assert bad.size == 0, "%s: %d mismatches, first %s: gpu %s oracle %s" % (
+        label, bad.size, bad[:5], out[bad[:5]], ref.out[bad[:5]])
+    assert np.array_equal(pairs, ref.pairs), "%s: pair sets differ (%d vs %d)" % (
+        label, len(pairs), len(ref.pairs))
+    return ref
+
+
+def assert_approx(P, pts, out, pairs, prec, label=""):
+    ref = oracle.join(P, pts)
+    got = set(map(tuple, pairs.tolist()))
+    got |= {(i, int(o)) for i, o in enumerate(out) if o >= 0}
+    want = set(map(tuple, ref.pair_set().tolist()))
+    missing = want - got
+    assert not missing, "%s: %d covering pairs missing, e.g. %s" % (label, len(missing),
+                                                                     sorted(missing)[:3])
+    extra = np.asarray(sorted(got - want), dtype=np.int64).reshape(-1, 2)
+    if len(extra):
+        d = oracle.boundary_dist_pairs(P, pts, extra)
+        assert d.max() <= prec + 1e-6, "%s: extra pair %.3f m from boundary" % (label, d.max())
+    # out[i] is the lowest reported id
+    lowest = {}
+    for i, p in got:
+        lowest[i] = min(lowest.get(i, 1 << 40), p)
+    for i, o in enumerate(out):
+        assert o == lowest.get(i, -1)
+    return len(extra), len(got)
+
+
+def edge_case_points(P, rng):
+    """Vertices (on boundaries, shared by neighbours), hole vertices, exact
+    dyadic points, invalid and out-of-domain points, points outside the box."""
+    v = P.verts
+    mids = 0.5 * (v[:-1] + v[1:])  # near (not exactly on) edges
+    bad = np.array([[np.nan, -74.0], [40.7, np.inf], [-np.inf, 0], [91.0, -74.0],
+                    [40.7, -181.0], [90.0, 180.0], [-90.0, -180.0], [0.0, 0.0],
+                    [40.7, 106.0], [-40.7, -74.0]])
+    outside = np.stack([rng.uniform(39, 42, 500), rng.uniform(-75.5, -72.5, 500)], 1)
+    return np.concatenate([v, mids, bad, outside])
+
+
+def test_c1_exact_all_points(act):
+    P, idx = index(act, "c1", "exact")
+    pts = synth.workload_points("c1")
+    out, pairs, ctr = gpu_join(idx, pts, counters=True)
+    assert_exact(P, pts, out, pairs, "c1")
+    assert ctr["points"] == len(pts)
+
+
+def test_c1_exact_edge_cases(act):
+    P, idx = index(act, "c1", "exact")
+    pts = edge_case_points(P, np.random.default_rng(3))
+    out, pairs, _ = gpu_join(idx, pts)
+    ref = assert_exact(P, pts, out, pairs, "c1-edges")
+    assert len(ref.pairs) > 100  # shared vertices really produce multi-matches
+
+
+def test_c1_fp64_refine_identical(act):
+    P, idx = index(act, "c1", "exact")
+    pts = np.concatenate([synth.workload_points("c1"), edge_case_points(P, np.random.default_rng(4))])
+    a = gpu_join(idx, pts)
+    b = gpu_join(idx, pts, refine=act.ACT_REFINE_FP64)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 257, 4097, 100003])
+def test_ragged_sizes(act, n):
+    P, idx = index(act, "c1", "exact")
+    pts = synth.uniform_points(0, n, seed=91)
+    out, pairs, _ = gpu_join(idx, pts)
+    assert_exact(P, pts, out, pairs, "n=%d" % n)
+
+
+def test_empty_batch(act):
+    P, idx = index(act, "c1", "exact")
+    t = torch.zeros((0, 2), dtype=torch.float64, device="cuda")
+    out = idx.join(t)
+    torch.cuda.synchronize()
+    assert out.shape == (0,)
+
+
+def test_block_sizes_and_repeats_identical(act):
+    P, idx = index(act, "c2", "exact")
+    pts = synth.workload_points("c2", 0, 300000)
+    base = gpu_join(idx, pts)
+    for blk in (64, 128, 256):
+        for _ in range(2):
+            o = gpu_join(idx, pts, block=blk)
+            assert np.array_equal(o[0], base[0]) and np.array_equal(o[1], base[1])
+
+
+def test_c1_approx_guarantee(act):
+    P, idx = index(act, "c1", "approx", 4.0)
+    pts = np.concatenate([synth.workload_points("c1"), edge_case_points(P, np.random.default_rng(5))])
+    out, pairs, _ = gpu_join(idx, pts)
+    assert_approx(P, pts, out, pairs, 4.0, "c1-approx4")
+
+
+def test_c2_exact_sample(act):
+    P, idx = index(act, "c2", "exact")
+    pts = np.concatenate([synth.workload_points("c2", 0, 1_000_000),
+                          edge_case_points(P, np.random.default_rng(6))])
+    out, pairs, ctr = gpu_join(idx, pts, counters=True)
+    assert_exact(P, pts, out, pairs, "c2")
+    assert ctr["candidates"] > 0 and ctr["edge_fp64"] < ctr["edges"]
+
+
+def test_c2_approx_sample(act):
+    P, idx = index(act, "c2", "approx", 4.0)
+    pts = synth.workload_points("c2", 0, 1_000_000)
+    out, pairs, _ = gpu_join(idx, pts)
+    n_extra, n_pairs = assert_approx(P, pts, out, pairs, 4.0, "c2-approx4")
+    assert n_extra < 0.05 * n_pairs
+
+
+def test_c2_full_size_sampled(act):
+    """All 1e8 points of the workload in one launch (the benchmark's
+    configuration); the oracle checks 200k seeded random positions, and the
+    fp32-filter output equals the all-fp64 output everywhere."""
+    P, idx = index(act, "c2", "exact")
+    n = synth.WORKLOADS["c2"]["n_points"]
+    pts = torch.from_numpy(synth.workload_points("c2", 0, n)).cuda()
+    out = idx.join(pts)
+    out64, _, _ = idx.join_ex(pts, refine=act.ACT_REFINE_FP64)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out64)
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(n, 200000, replace=False))
+    sp = pts[torch.from_numpy(sel).cuda()].cpu().numpy()
+    ref = oracle.join(P, sp)
+    assert np.array_equal(out[torch.from_numpy(sel).cuda()].cpu().numpy(), ref.out)
+    del pts
+
+
+def test_cell_ids_match_reference(act):
+    rng = np.random.default_rng(8)
+    pts = np.concatenate([
+        np.stack([rng.uniform(-90, 90, 300000), rng.uniform(-180, 180, 300000)], 1),
+        synth.workload_points("c2", 0, 300000),
+        np.array([[0, 0], [90, 0], [-90, 0], [0, 180], [0, -180], [0, 45], [35.26438968, 45.0]]),
+    ])
+    t = torch.from_numpy(pts).cuda()
+    got = act.cell_ids(t).cpu().numpy().view(np.uint64)
+    want = C.cell_ids(pts[:, 0], pts[:, 1])
+    diff = np.nonzero(got != want)[0]
+    # ids may differ only where the point sits within rounding of a leaf
+    # boundary (different sin/cos implementations); the GPU's leaf must then
+    # be a neighbour of the reference leaf
+    assert diff.size < 1e-4 * len(pts), diff.size
+    if diff.size:
+        f1, i1, j1 = C.decode_leaf(got[diff])
+        f2, i2, j2 = C.decode_leaf(want[diff])
+        same = f1 == f2
+        assert np.all(np.abs(i1 - i2)[same] <= 1) and np.all(np.abs(j1 - j2)[same] <= 1)
+    bad = torch.tensor([[np.nan, 0.0], [0.0, 200.0]], dtype=torch.float64, device="cuda")
+    assert act.cell_ids(bad).cpu().tolist() == [0, 0]

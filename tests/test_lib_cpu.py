@@ -1,0 +1,219 @@
+"""CPU tests of the HIP library's host side (no GPU compute): symbol exports,
+the index builder's structure and conservativeness, the lookup-table
+encoding of Fig. 6b, the fp32 refinement tier's error bound, error paths."""
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cellid as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def act():
+    import paper_1802_09488_amd as act
+    return act
+
+
+def test_exports_every_declared_symbol(act):
+    hdr = open(os.path.join(ROOT, "include", "act.h")).read()
+    names = set(re.findall(r"\b(act_[a-z0-9_]+)\s*\(", hdr))
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(act.lib, n), n
+    assert act.version().startswith("act-mi355x")
+
+
+def _decode(entry, lut):
+    """(polygon id, interior) references of a tagged trie entry."""
+    e = int(entry)
+    tag = e & 3
+    if e == 0:
+        return []
+    if tag == 1:
+        v = [(e >> 2) & 0x7fffffff]
+    elif tag == 2:
+        v = [(e >> 2) & 0x7fffffff, (e >> 33) & 0x7fffffff]
+    elif tag == 3:
+        off = e >> 2
+        nt = int(lut[off])
+        v = [(int(x) << 1) | 1 for x in lut[off + 1:off + 1 + nt]]
+        nc = int(lut[off + 1 + nt])
+        v += [int(x) << 1 for x in lut[off + 2 + nt:off + 2 + nt + nc]]
+    else:
+        raise AssertionError("pointer entry returned by a lookup")
+    return [(x >> 1, x & 1) for x in v]
+
+
+def _truth(res):
+    t = {}
+    for i, o in enumerate(res.out):
+        if o >= 0:
+            t.setdefault(i, set()).add(int(o))
+    for i, p in res.pairs:
+        t.setdefault(int(i), set()).add(int(p))
+    return t
+
+
+def _structural_check(act, P, idx, pts, precision_m=None):
+    ids = C.cell_ids(pts[:, 0], pts[:, 1])
+    ent = idx.lookup_host(ids)
+    lut = idx.lut_host()
+    res = oracle.join(P, pts)
+    truth = _truth(res)
+    extra = []
+    for i in range(len(pts)):
+        refs = _decode(ent[i], lut)
+        ids_i = {p for p, _ in refs}
+        T = truth.get(i, set())
+        # conservative: every covering polygon is referenced by the point's cell
+        assert T <= ids_i, (i, T, refs)
+        # true hits are true
+        for p, interior in refs:
+            if interior:
+                assert p in T, (i, p)
+            elif p not in T:
+                extra.append((i, p))
+    if precision_m is not None and extra:
+        e = np.asarray(extra, dtype=np.int64)
+        d = oracle.boundary_dist_pairs(P, pts, e)
+        assert d.max() <= precision_m + 1e-6, d.max()
+    return ent
+
+
+def test_builder_c1_exact_structure(act):
+    P = synth.workload_polygons("c1")
+    idx = act.build(P, "exact", device=-1)
+    st = idx.stats()
+    assert st["n_polys"] == 16 and st["max_cell_level"] == 20
+    # depth bound: ceil((max level - prefix level) / 4) node levels (Section III-C)
+    lp = st["face_prefix_level"][4]
+    assert lp >= 0 and st["max_depth"] <= -(-(20 - lp) // 4) <= 8
+    pts = np.concatenate([synth.workload_points("c1", 0, 30000), P.verts])
+    _structural_check(act, P, idx, pts)
+
+
+def test_builder_c2_approx_guarantee(act):
+    P = synth.workload_polygons("c2")
+    idx = act.build(P, "approx", 4.0, device=-1)
+    st = idx.stats()
+    assert st["mode"] == 1 and st["max_cell_level"] >= 21
+    pts = synth.workload_points("c2", 0, 20000)
+    _structural_check(act, P, idx, pts, precision_m=4.0)
+
+
+def test_lut_matches_fig6b_golden(act):
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "lut_fig6b.txt"))
+            if l.strip() and not l.startswith("#")]
+    lut = np.zeros(0, np.uint32)
+    for _, off, tru, cand, words in rows:
+        refs = [(int(x) << 1) | 1 for x in tru.split(",")] + [int(x) << 1 for x in cand.split(",")]
+        entry, lut = act.encode_refs_host(refs, lut)
+        assert entry & 3 == 3 and entry >> 2 == int(off)
+        w = [int(x) for x in words.split(",")]
+        assert lut[int(off):int(off) + len(w)].tolist() == w
+    # identical lists are stored once
+    entry, lut2 = act.encode_refs_host([(5 << 1) | 1, 3 << 1, 1 << 1], lut)
+    assert entry >> 2 == 0 and len(lut2) == len(lut)
+
+
+def test_inline_payload_encoding(act):
+    e, lut = act.encode_refs_host([(7 << 1) | 1])
+    assert e & 3 == 1 and (e >> 2) == (7 << 1) | 1 and len(lut) == 0
+    e, lut = act.encode_refs_host([(9 << 1), (3 << 1) | 1])
+    assert e & 3 == 2 and ((e >> 2) & 0x7fffffff) == (3 << 1) | 1 and (e >> 33) == 9 << 1
+    big = (1 << 30) - 1
+    e, _ = act.encode_refs_host([(big << 1) | 1, (big - 1) << 1])
+    assert (e >> 33) == (big << 1) | 1
+
+
+def _frac_sign(a, b, p):
+    ax, ay, bx, by, px, py = (Fraction(float(v)) for v in (*a, *b, *p))
+    d = (bx - ax) * (py - ay) - (by - ay) * (px - ax)
+    return (d > 0) - (d < 0)
+
+
+def test_fp32_tier_never_decides_wrong(act):
+    """Invariant fuzz of the fp32 tier's error bound: whenever it decides,
+    the sign equals the exact one (near-degenerate lat/lng cases)."""
+    rng = np.random.default_rng(21)
+    decided = 0
+    n = 30000
+    for k in range(n):
+        o = np.array([rng.uniform(-74.2, -73.7), rng.uniform(40.5, 40.9)])
+        a = o + rng.uniform(-0.05, 0.05, 2)
+        b = a + rng.uniform(-1e-3, 1e-3, 2) * 10.0 ** rng.integers(-4, 1)
+        t = rng.uniform(-0.2, 1.2)
+        off = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-16, -5)
+        p = a + t * (b - a) + off
+        m = float(np.max(np.abs(np.float32(np.concatenate([a - o, b - o])))))
+        s = act.orient_fp32_host(a, b, p, o, m)
+        if s != 0:
+            decided += 1
+            assert s == _frac_sign(a, b, p), (a, b, p, o)
+    assert decided > n // 10
+
+
+def test_exact_orient_matches_rationals(act):
+    rng = np.random.default_rng(22)
+    for k in range(20000):
+        a = rng.uniform(-75, -73, 2)
+        b = rng.uniform(-75, -73, 2)
+        t = rng.uniform(-1, 2)
+        p = a + t * (b - a) + rng.integers(-2, 3, 2) * np.spacing(a)
+        assert act.orient_exact_host(a, b, p) == _frac_sign(a, b, p)
+
+
+def _raw_build(act, verts, ring_off, poly_ring_off, mode=0, prec=0.0, device=-1):
+    import ctypes
+    from paper_1802_09488_amd import _binding as B
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    ro = np.ascontiguousarray(ring_off, dtype=np.int64)
+    pro = np.ascontiguousarray(poly_ring_off, dtype=np.int32)
+    opts = B.BuildOpts(max_level=0, device=device, threads=1, reserved=0, margin_deg=0.0)
+    h = ctypes.c_void_p()
+    rc = B.lib.act_build(v.ctypes.data, ro.ctypes.data, pro.ctypes.data, len(pro) - 1, mode, prec,
+                         ctypes.byref(opts), ctypes.byref(h))
+    if rc == 0:
+        B.lib.act_free(h)
+    return rc
+
+
+def test_error_paths(act):
+    from paper_1802_09488_amd import _binding as B
+    sq = np.array([[0, 0], [0, 1], [1, 1], [1, 0]], float)
+    assert _raw_build(act, sq, [0, 4], [0, 1]) == 0
+    assert _raw_build(act, sq[:2], [0, 2], [0, 1]) == B.ACT_E_POLY          # < 3 vertices
+    assert _raw_build(act, np.array([[0, 0], [0, 0], [0, 0], [1, 1]], float),
+                      [0, 4], [0, 1]) == B.ACT_E_POLY                        # duplicates only
+    bad = sq.copy()
+    bad[1, 0] = np.nan
+    assert _raw_build(act, bad, [0, 4], [0, 1]) == B.ACT_E_POLY            # NaN vertex
+    bad = sq.copy()
+    bad[1, 1] = 200.0
+    assert _raw_build(act, bad, [0, 4], [0, 1]) == B.ACT_E_POLY            # lng out of range
+    assert _raw_build(act, sq, [0, 4], [0, 1], mode=7) == B.ACT_E_ARG
+    assert _raw_build(act, sq, [0, 4], [0, 1], mode=1, prec=0.001) == B.ACT_E_ARG
+    assert _raw_build(act, sq, [0, 4], [0, 0]) == B.ACT_E_POLY             # polygon w/o ring
+    # joins on a host-only index are refused before anything is launched
+    P = synth.Polygons.from_rings([[sq]])
+    idx = act.build(P, "exact", device=-1)
+    rc = B.lib.act_join(idx.handle, None, 10, None, None)
+    assert rc == B.ACT_E_DEVICE
+    assert b"without a device" in B.lib.act_last_error()
+    assert B.lib.act_join(None, None, 0, None, None) == B.ACT_E_ARG
+
+
+def test_empty_polygon_set(act):
+    P = synth.Polygons(np.zeros((0, 2)), np.zeros(1, np.int64), np.zeros(1, np.int32))
+    idx = act.build(P, "exact", device=-1)
+    st = idx.stats()
+    assert st["n_cells"] == 0 and st["n_faces"] == 0
+    ids = C.cell_ids(np.array([40.7]), np.array([-74.0]))
+    assert idx.lookup_host(ids).tolist() == [0]
