@@ -169,10 +169,11 @@ typedef struct {
   int64_t *d_n_pairs;
   uint64_t *d_counters;    /* optional (NULL): ACT_NCOUNTERS accumulators    */
   int32_t refine;          /* ACT_REFINE_*                                   */
-  int32_t block;           /* threads per block (0 = tuned/default; 64..1024,
-                              a multiple of 64)                              */
-  int32_t lds_levels;      /* trie levels staged in LDS (-1 = tuned/default) */
-  int32_t reserved;
+  int32_t block;           /* threads per block: 0 (default) or 256         */
+  int32_t lds_levels;      /* top trie node levels staged in LDS: 0, 1, 2, or
+                              -1 for the default (deepest that fits 48 KiB)  */
+  int32_t grid;            /* blocks launched (0 = default 2048); each wave
+                              walks tiles of 64 points grid-stride           */
 } act_join_args;
 
 int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);

@@ -94,7 +94,8 @@ class Index:
         return out
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
-                refine=ACT_REFINE_FP32_FILTER, block=0, lds_levels=-1, stream=None):
+                refine=ACT_REFINE_FP32_FILTER, block=0, lds_levels=-1, grid=0,
+                stream=None):
         """Full-control join. Returns (out, pairs or None, counters dict or None).
 
         pairs: (m, 2) int64 CUDA tensor of (point, polygon) beyond out[i]
@@ -113,6 +114,7 @@ class Index:
         a.refine = refine
         a.block = block
         a.lds_levels = lds_levels
+        a.grid = grid
         pp = pq = cnt = ctr = None
         if capacity is not None:
             pp = torch.empty(max(1, capacity), dtype=torch.int64, device=dev)

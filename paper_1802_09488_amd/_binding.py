@@ -43,7 +43,7 @@ class JoinArgs(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("d_n_pairs", ctypes.c_void_p),
                 ("d_counters", ctypes.c_void_p), ("refine", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("grid", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

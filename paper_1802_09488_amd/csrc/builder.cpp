@@ -403,6 +403,45 @@ uint64_t host_lookup(const HostIndex &idx, uint64_t id) {
   }
 }
 
+// Renumber trie nodes breadth-first (roots, then their children, ...) and
+// rewrite child pointers accordingly.
+static void renumber_breadth_first(HostIndex &x) {
+  size_t n_nodes = x.nodes.size() / 256;
+  std::vector<uint64_t> order;
+  std::vector<int> depth;
+  order.reserve(n_nodes);
+  for (int f = 0; f < 6; f++)
+    if (x.faces[f].root >= 0) {
+      order.push_back((uint64_t)x.faces[f].root);
+      depth.push_back(0);
+    }
+  for (size_t q = 0; q < order.size(); q++) {
+    const uint64_t *e = &x.nodes[order[q] * 256];
+    for (int b = 0; b < 256; b++)
+      if ((e[b] & kTagMask) == kTagPtr && e[b] != 0) {
+        order.push_back(e[b] >> 2);
+        depth.push_back(depth[q] + 1);
+      }
+  }
+  std::vector<uint64_t> newidx(n_nodes, 0);
+  for (size_t q = 0; q < order.size(); q++) newidx[order[q]] = q + 1;
+  std::vector<uint64_t> nn((order.size() + 1) * 256, 0);
+  for (size_t q = 0; q < order.size(); q++) {
+    const uint64_t *e = &x.nodes[order[q] * 256];
+    uint64_t *d = &nn[(q + 1) * 256];
+    for (int b = 0; b < 256; b++)
+      d[b] = ((e[b] & kTagMask) == kTagPtr && e[b] != 0) ? (newidx[e[b] >> 2] << 2) : e[b];
+  }
+  for (int f = 0; f < 6; f++)
+    if (x.faces[f].root >= 0) x.faces[f].root = (int32_t)newidx[x.faces[f].root];
+  x.nodes.swap(nn);
+  x.n_d0 = x.n_d1 = 0;
+  for (int d : depth) {
+    x.n_d0 += d == 0;
+    x.n_d1 += d == 1;
+  }
+}
+
 int build_host_index(const double *verts, const int64_t *ring_off, const int32_t *poly_ring_off,
                      int32_t n_polys, const BuildParams &bp, HostIndex &out, std::string &err) {
   auto t0 = std::chrono::steady_clock::now();
@@ -655,6 +694,7 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     }
     c0 = c1;
   }
+  renumber_breadth_first(out);
   out.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return ACT_OK;

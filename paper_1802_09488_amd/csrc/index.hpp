@@ -55,6 +55,10 @@ struct HostIndex {
   // statistics
   int64_t n_cells = 0, n_cells_interior_only = 0;
   int32_t max_depth = 0, max_refs = 0, max_cell_level = 0;
+  // Nodes are numbered breadth-first: roots occupy indices 1 .. n_d0, the
+  // nodes one level below them n_d0+1 .. n_d0+n_d1 (LDS staging of the top
+  // levels copies these contiguous ranges).
+  int32_t n_d0 = 0, n_d1 = 0;
   double build_seconds = 0;
 };
 

@@ -92,107 +92,208 @@ struct ProbeParams {
   int32_t root[6];
   int32_t shift[6];  // 60 - 2 * prefix level
   uint64_t prefix[6];
-  int32_t mode;
+  int32_t n_lds_nodes;  // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
 };
 
-// --------------------------------------------------------------- device
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
 
-struct LdsTable {
-  const uint16_t *t;
-  __device__ uint16_t operator[](uint32_t k) const { return t[k]; }
-};
+// --------------------------------------------------------- device math
+//
+// The projection needs fp64 (level-30 cells are 2^-30 of a face wide) but
+// only to ~1e-13 relative: the builder's conservative cell boxes carry a
+// 1e-9 degree margin. The pieces below are written for the argument ranges
+// that occur and cost far fewer instructions than the general library
+// routines.
 
-// Steps 2-4: leaf cell of a point. Returns false for invalid points.
+// sin and cos of x degrees, |x| <= 180. Quadrant reduction in degrees is
+// exact: r = x - 90 k with k = rint(x / 90) (Sterbenz: x and 90 k are within
+// a factor of two when k != 0). Then t = r pi / 180, |t| <= pi/4 (+ rounding)
+// and the Taylor series up to t^15 (sin) and t^16 (cos); truncation error
+// below t^17/17! = 5e-17.
+__device__ __forceinline__ void sincos_deg(double x, double &s, double &c) {
+  const double k = rint(x * (1.0 / 90.0));
+  const double r = fma(k, -90.0, x);
+  const double t = r * 0.017453292519943295;  // pi / 180
+  const double t2 = t * t;
+  double ps = fma(t2, -1.0 / 1307674368000.0, 1.0 / 6227020800.0);  // -1/15!, 1/13!
+  ps = fma(t2, ps, -1.0 / 39916800.0);                              // -1/11!
+  ps = fma(t2, ps, 1.0 / 362880.0);                                 //  1/9!
+  ps = fma(t2, ps, -1.0 / 5040.0);                                  // -1/7!
+  ps = fma(t2, ps, 1.0 / 120.0);                                    //  1/5!
+  ps = fma(t2, ps, -1.0 / 6.0);                                     // -1/3!
+  const double sn = fma(t * t2, ps, t);
+  double pc = fma(t2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);  // 1/16!, -1/14!
+  pc = fma(t2, pc, 1.0 / 479001600.0);                                 //  1/12!
+  pc = fma(t2, pc, -1.0 / 3628800.0);                                  // -1/10!
+  pc = fma(t2, pc, 1.0 / 40320.0);                                     //  1/8!
+  pc = fma(t2, pc, -1.0 / 720.0);                                      // -1/6!
+  pc = fma(t2, pc, 1.0 / 24.0);                                        //  1/4!
+  pc = fma(t2, pc, -0.5);
+  const double cs = fma(t2, pc, 1.0);
+  // rotate by q quarter turns: (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn)
+  const int q = (int)k & 3;
+  s = (q & 1) ? cs : sn;
+  c = (q & 1) ? sn : cs;
+  if (q & 2) s = -s;
+  if ((q + 1) & 2) c = -c;
+}
+
+// 1 / a for a in [1/sqrt(3), 1]: hardware estimate + two Newton steps.
+__device__ __forceinline__ double rcp_nr(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(a) for a in [1, 4]: reciprocal square root estimate, two Newton
+// steps on it, one multiply.
+__device__ __forceinline__ double sqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  double h = fma(-a * y, y, 1.0);
+  y = fma(0.5 * y, h, y);
+  h = fma(-a * y, y, 1.0);
+  y = fma(0.5 * y, h, y);
+  return a * y;
+}
+
+// st(w) * 2^30 as a 30-bit cell coordinate.
+__device__ __forceinline__ uint32_t leaf_coord(double w) {
+  const double h = 0.5 * sqrt_nr(fma(3.0, fabs(w), 1.0));
+  const double s = w >= 0.0 ? h : 1.0 - h;
+  const uint32_t i = (uint32_t)fmax(s * kTwo30, 0.0);
+  return min(i, (1u << 30) - 1u);
+}
+
+// Steps 2-4: leaf cell (face, 60-bit Hilbert key) of a point; false for
+// points that are not finite or outside |lat| <= 90, |lng| <= 180.
 __device__ __forceinline__ bool dev_leaf(double lat, double lng, const uint16_t *htab,
-                                         uint32_t &face, uint64_t &pos) {
+                                         uint32_t &face, uint64_t &key) {
   if (!(fabs(lat) <= 90.0 && fabs(lng) <= 180.0)) return false;
   double slat, clat, slng, clng;
-  sincospi(lat * (1.0 / 180.0), &slat, &clat);
-  sincospi(lng * (1.0 / 180.0), &slng, &clng);
-  double x = clat * clng, y = clat * slng, z = slat;
-  double ax = fabs(x), ay = fabs(y), az = fabs(z);
-  double m, c1, c2;
-  uint32_t a;
-  if (ax >= ay && ax >= az) {
-    a = 0; m = x; c1 = y; c2 = z;
-  } else if (ay >= az) {
-    a = 1; m = y; c1 = z; c2 = x;
-  } else {
-    a = 2; m = z; c1 = x; c2 = y;
+  sincos_deg(lat, slat, clat);
+  sincos_deg(lng, slng, clng);
+  const double x = clat * clng, y = clat * slng, z = slat;
+  const double ax = fabs(x), ay = fabs(y), az = fabs(z);
+  const bool fx = ax >= ay && ax >= az;
+  const bool fy = !fx && ay >= az;
+  const double m = fx ? x : (fy ? y : z);
+  const double c1 = fx ? y : (fy ? z : x);
+  const double c2 = fx ? z : (fy ? x : y);
+  face = (fx ? 0u : (fy ? 1u : 2u)) + (m < 0.0 ? 3u : 0u);
+  const double r = rcp_nr(fabs(m));
+  const uint32_t i = leaf_coord(c1 * r), j = leaf_coord(c2 * r);
+  // Hilbert position, 4 levels per table step (32 padded levels: the two
+  // leading zero levels leave the state unchanged and add zero digits).
+  uint32_t e = 0, hi = 0, lo = 0;
+#pragma unroll
+  for (int sh = 28; sh >= 0; sh -= 4) {
+    const uint32_t idx = (e & 0x300u) | (((i >> sh) & 15u) << 4) | ((j >> sh) & 15u);
+    e = htab[idx];
+    if (sh >= 16) hi = (hi << 8) | (e & 255u);
+    else lo = (lo << 8) | (e & 255u);
   }
-  face = a + (m < 0.0 ? 3u : 0u);
-  double inv = 1.0 / fabs(m);
-  double s = st_from_uv(c1 * inv), t = st_from_uv(c2 * inv);
-  uint32_t i = (uint32_t)fmin(fmax(floor(s * kTwo30), 0.0), kTwo30 - 1.0);
-  uint32_t j = (uint32_t)fmin(fmax(floor(t * kTwo30), 0.0), kTwo30 - 1.0);
-  pos = hilbert_pos30(i, j, LdsTable{htab});
+  key = ((uint64_t)hi << 32) | lo;
   return true;
 }
 
-// Point-in-polygon for a candidate (point, polygon) pair, ST_Covers rule.
-// refine = ACT_REFINE_FP32_FILTER: fp32 tier first; undecided edges (equal
-// rounded y / undecided orientation) are re-tested exactly in fp64.
-__device__ bool dev_covers(const ProbeParams &P, int poly, double lat, double lng,
-                           unsigned long long &c_edges, unsigned long long &c_fp64,
-                           unsigned long long &c_exact) {
+// --------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint64_t ballot(bool b) { return __ballot(b); }
+
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Orders LDS traffic of one wavefront (its lanes run in lockstep).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One edge of the crossing-number test. fp32 tier on origin-translated
+// coordinates; edges it cannot decide go to the exact fp64 test.
+// Returns 0 (no effect), 1 (toggle parity), 2 (point on the edge).
+template <bool COUNT>
+__device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e, float qx, float qy,
+                                                    float eta, double px, double py,
+                                                    uint32_t &c_fp64, uint32_t &c_exact) {
+  const float4 g = P.e32[e];  // ax ay bx by
+  const bool a_up = g.y > qy, a_dn = g.y < qy;
+  const bool b_up = g.w > qy, b_dn = g.w < qy;
+  if ((a_up && b_up) || (a_dn && b_dn)) return 0;  // strictly above/below
+  if ((a_up || a_dn) && (b_up || b_dn)) {           // strict straddle
+    const int s = orient_sign_fp32_filter(g.x, g.y, g.z, g.w, qx, qy, eta);
+    if (s != 0) return (b_up ? (s > 0) : (s < 0)) ? 1 : 0;
+  }
+  const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
+  if (COUNT) {
+    c_fp64++;
+    if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
+  }
+  return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
+}
+
+template <bool COUNT>
+__device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px, double py,
+                                         uint32_t &c_fp64, uint32_t &c_exact) {
+  const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
+  if ((A.y > py && B.y > py) || (A.y < py && B.y < py)) return 0;
+  if (COUNT) {
+    c_fp64++;
+    if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
+  }
+  return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
+}
+
+// Whole-wave point-in-polygon test of one (point, polygon) pair: lane l
+// takes edges e0 + l, e0 + l + 64, ...; crossing parity = parity of the
+// popcount of the toggle ballots; any lane on an edge decides "covered".
+// Must be called by all 64 lanes with wave-uniform arguments.
+template <bool COUNT>
+__device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double lng, int lane,
+                            uint32_t &c_fp64, uint32_t &c_exact) {
   const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
   const double px = lng, py = lat;
-  int inside = 0;
-  c_edges += (unsigned long long)(e1 - e0);
+  uint32_t par = 0;
   if (P.refine == ACT_REFINE_FP32_FILTER) {
     const double2 o = P.origin[poly];
     const float qx = (float)(px - o.x), qy = (float)(py - o.y);
     const float eta = tier1_eta(fmaxf(P.pm[poly], fmaxf(fabsf(qx), fabsf(qy))));
-    for (int e = e0; e < e1; e++) {
-      const float4 g = P.e32[e];  // ax ay bx by (translated)
-      const bool a_up = g.y > qy, a_dn = g.y < qy;
-      const bool b_up = g.w > qy, b_dn = g.w < qy;
-      if ((a_up && b_up) || (a_dn && b_dn)) continue;  // edge entirely above/below
-      int s = 0;
-      if ((a_up || a_dn) && (b_up || b_dn)) s = orient_sign_fp32_filter(g.x, g.y, g.z, g.w, qx, qy, eta);
-      if (s != 0) {
-        // strict straddle and p off the edge's line: parity only
-        if (b_up ? (s > 0) : (s < 0)) inside ^= 1;
-        continue;
-      }
-      c_fp64++;
-      const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
-      if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
-      int r = edge_test_exact(A.x, A.y, B.x, B.y, px, py);
-      if (r == 2) return true;
-      inside ^= r;
+    for (int base = e0; base < e1; base += 64) {
+      const int e = base + lane;
+      const int r = e < e1 ? edge_fp32_then_exact<COUNT>(P, e, qx, qy, eta, px, py, c_fp64, c_exact) : 0;
+      if (ballot(r == 2)) return true;
+      par ^= (uint32_t)__popcll(ballot(r == 1));
     }
   } else {
-    for (int e = e0; e < e1; e++) {
-      const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
-      if ((A.y > py && B.y > py) || (A.y < py && B.y < py)) continue;
-      c_fp64++;
-      if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
-      int r = edge_test_exact(A.x, A.y, B.x, B.y, px, py);
-      if (r == 2) return true;
-      inside ^= r;
+    for (int base = e0; base < e1; base += 64) {
+      const int e = base + lane;
+      const int r = e < e1 ? edge_fp64<COUNT>(P, e, px, py, c_fp64, c_exact) : 0;
+      if (ballot(r == 2)) return true;
+      par ^= (uint32_t)__popcll(ballot(r == 1));
     }
   }
-  return inside != 0;
+  return (par & 1u) != 0;
 }
 
+// Lowest match goes to out[i]; every other match becomes a pair.
 struct Hits {
   int32_t best = -1;
-  __device__ void add(const ProbeParams &P, int64_t i, int32_t poly) {
-    int32_t other;
+  __device__ __forceinline__ void add(const ProbeParams &P, int64_t i, int32_t poly) {
     if (best < 0) {
       best = poly;
       return;
     }
-    if (poly < best) {
-      other = best;
-      best = poly;
-    } else {
-      other = poly;
-    }
+    const int32_t other = poly < best ? best : poly;
+    best = poly < best ? poly : best;
     if (P.pair_pt) {
-      unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
+      const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
       if ((int64_t)k < P.cap) {
         P.pair_pt[k] = i;
         P.pair_poly[k] = other;
@@ -201,112 +302,158 @@ struct Hits {
   }
 };
 
-__global__ __launch_bounds__(256) void probe_kernel(ProbeParams P) {
+// Steps 5-6: face root, prefix check and descent. The first LDS_DEPTH node
+// levels are read from the LDS copy of nodes 1 .. n_lds_nodes (breadth-first
+// numbering puts the top levels first).
+template <int LDS_DEPTH>
+__device__ __forceinline__ uint64_t descend(const ProbeParams &P, const uint64_t *s_nodes,
+                                            int root, int sh, uint64_t key, uint32_t &reads) {
+  uint64_t node = (uint64_t)root, e = 0;
+#pragma unroll
+  for (int d = 0; d < LDS_DEPTH; d++) {
+    sh -= 8;
+    e = s_nodes[(node - 1) * 256 + ((key >> sh) & 255u)];
+    reads++;
+    if ((e & kTagMask) != kTagPtr || e == 0) return e;
+    node = e >> 2;
+  }
+  for (;;) {
+    sh -= 8;
+    e = P.nodes[node * 256 + ((key >> sh) & 255u)];
+    reads++;
+    if ((e & kTagMask) != kTagPtr || e == 0) return e;
+    node = e >> 2;
+  }
+}
+
+// The probe. Each wavefront walks tiles of 64 consecutive points (one per
+// lane), so every lane of a wave executes the same number of iterations and
+// the cooperative refinement can use whole-wave ballots.
+template <bool EXACT, int LDS_DEPTH, bool COUNT>
+__global__ __launch_bounds__(kBlock) void probe_kernel(ProbeParams P) {
+  extern __shared__ uint64_t s_nodes[];
   __shared__ uint16_t s_htab[1024];
   __shared__ uint64_t s_prefix[6];
   __shared__ int32_t s_root[6], s_shift[6];
-  for (int k = threadIdx.x; k < 1024; k += blockDim.x) s_htab[k] = P.htab[k];
+  __shared__ int32_t q_poly[kWaves][64];
+  __shared__ double q_lat[kWaves][64], q_lng[kWaves][64];
+  for (int k = threadIdx.x; k < 1024; k += kBlock) s_htab[k] = P.htab[k];
+  if (LDS_DEPTH > 0)
+    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kBlock) s_nodes[k] = P.nodes[256 + k];
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int f = 0; f < 6; f++) {  // constant indices: read straight from kernel arguments
+    for (int f = 0; f < 6; f++) {
       s_prefix[f] = P.prefix[f];
       s_root[f] = P.root[f];
       s_shift[f] = P.shift[f];
     }
   }
   __syncthreads();
-  unsigned long long c_inv = 0, c_false = 0, c_true = 0, c_candpts = 0, c_cand = 0, c_edges = 0,
-                     c_fp64 = 0, c_exact = 0, c_nodes = 0, c_lut = 0, c_pts = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P.n; i += stride) {
-    const double2 pt = P.pts[i];
-    const double lat = pt.x, lng = pt.y;
-    c_pts++;
-    uint32_t face;
-    uint64_t key;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t c_pts = 0, c_inv = 0, c_false = 0, c_true = 0, c_candpts = 0, c_cand = 0,
+           c_edges = 0, c_fp64 = 0, c_exact = 0, c_reads = 0, c_lut = 0;
+  const int64_t ntiles = (P.n + 63) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < ntiles; tile += nwaves) {
+    const int64_t i = tile * 64 + lane;
+    const bool live = i < P.n;
+    double lat = 0.0, lng = 0.0;
+    if (live) {
+      const double2 pt = P.pts[i];
+      lat = pt.x;
+      lng = pt.y;
+    }
+    uint32_t face = 0;
+    uint64_t key = 0, e = 0;
+    const bool valid = live && dev_leaf(lat, lng, s_htab, face, key);
+    if (valid) {
+      const int sh = s_shift[face], root = s_root[face];
+      if (root >= 0 && (key >> sh) == s_prefix[face])
+        e = descend<LDS_DEPTH>(P, s_nodes, root, sh, key, c_reads);
+    }
+    if (COUNT) {
+      c_pts += live;
+      c_inv += live && !valid;
+      c_false += valid && e == 0;
+    }
+    // stage 3: decode the entry; true hits (approx: all references) out
     Hits hits;
-    if (!dev_leaf(lat, lng, s_htab, face, key)) {
-      c_inv++;
-      P.out[i] = -1;
-      continue;
-    }
-    // stage 1: root and common prefix
-    int sh = s_shift[face];
-    int root = s_root[face];
-    uint64_t e = 0;
-    if (root >= 0 && (key >> sh) == s_prefix[face]) {
-      // stage 2: descent
-      uint64_t node = (uint64_t)root;
-      for (;;) {
-        sh -= 8;
-        e = P.nodes[node * 256 + ((key >> sh) & 255u)];
-        c_nodes++;
-        if ((e & kTagMask) != kTagPtr || e == 0) break;
-        node = e >> 2;
-      }
-    }
-    if (e == 0) {
-      c_false++;
-      P.out[i] = -1;
-      continue;
-    }
-    // stage 3: decode and emit
     const uint32_t tag = (uint32_t)(e & kTagMask);
-    uint32_t inl[2];
-    int n_inl = 0;
-    bool any_cand = false;
-    if (tag == kTagOne) {
-      inl[0] = (uint32_t)((e >> 2) & 0x7fffffffu);
-      n_inl = 1;
-    } else if (tag == kTagTwo) {
-      inl[0] = (uint32_t)((e >> 2) & 0x7fffffffu);
-      inl[1] = (uint32_t)((e >> 33) & 0x7fffffffu);
-      n_inl = 2;
-    }
-    for (int r = 0; r < n_inl; r++) {
-      int32_t poly = (int32_t)(inl[r] >> 1);
-      if ((inl[r] & 1u) || P.mode == ACT_APPROX) {
-        hits.add(P, i, poly);
-      } else {
-        any_cand = true;
-        c_cand++;
-        if (dev_covers(P, poly, lat, lng, c_edges, c_fp64, c_exact)) hits.add(P, i, poly);
+    uint32_t cand0 = 0, cand1 = 0, lut_cand = 0;
+    int ncand = 0;
+    bool from_lut = false;
+    if (e != 0 && tag != kTagLut) {
+      const uint32_t r0 = (uint32_t)((e >> 2) & 0x7fffffffu);
+      if (!EXACT || (r0 & 1u)) hits.add(P, i, (int32_t)(r0 >> 1));
+      else cand0 = r0 >> 1, ncand = 1;
+      if (tag == kTagTwo) {
+        const uint32_t r1 = (uint32_t)((e >> 33) & 0x7fffffffu);
+        if (!EXACT || (r1 & 1u)) hits.add(P, i, (int32_t)(r1 >> 1));
+        else if (ncand == 0) cand0 = r1 >> 1, ncand = 1;
+        else cand1 = r1 >> 1, ncand = 2;
       }
-    }
-    if (tag == kTagLut) {
-      c_lut++;
-      uint32_t off = (uint32_t)(e >> 2);
-      uint32_t nt = P.lut[off];
+    } else if (tag == kTagLut) {
+      const uint32_t off = (uint32_t)(e >> 2);
+      const uint32_t nt = P.lut[off];
       for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
-      uint32_t nc = P.lut[off + 1 + nt];
-      for (uint32_t r = 0; r < nc; r++) {
-        int32_t poly = (int32_t)P.lut[off + 2 + nt + r];
-        if (P.mode == ACT_APPROX) {
-          hits.add(P, i, poly);
-        } else {
-          any_cand = true;
-          c_cand++;
-          if (dev_covers(P, poly, lat, lng, c_edges, c_fp64, c_exact)) hits.add(P, i, poly);
+      const uint32_t nc = P.lut[off + 1 + nt];
+      if (!EXACT) {
+        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
+      } else {
+        ncand = (int)nc;
+        lut_cand = off + 2 + nt;
+        from_lut = true;
+      }
+      if (COUNT) c_lut++;
+    }
+    if (COUNT) {
+      c_true += e != 0 && ncand == 0;
+      c_candpts += ncand > 0;
+      c_cand += ncand;
+    }
+    if (EXACT) {
+      // candidates, one round per candidate rank: compact the wave's
+      // candidates into its LDS queue, refine each with the whole wave
+      for (int r = 0;; r++) {
+        const bool has = r < ncand;
+        const uint64_t mask = ballot(has);
+        if (mask == 0) break;
+        const int cnt = __popcll(mask);
+        const int slot = lane_rank(mask);
+        int32_t my_poly = 0;
+        if (has) {
+          my_poly = (int32_t)(from_lut ? P.lut[lut_cand + r] : (r == 0 ? cand0 : cand1));
+          q_poly[wid][slot] = my_poly;
+          q_lat[wid][slot] = lat;
+          q_lng[wid][slot] = lng;
         }
+        wave_sync();
+        uint64_t covered = 0;
+        for (int q = 0; q < cnt; q++) {
+          const int poly = __builtin_amdgcn_readfirstlane(q_poly[wid][q]);
+          if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+          if (wave_covers<COUNT>(P, poly, q_lat[wid][q], q_lng[wid][q], lane, c_fp64, c_exact))
+            covered |= 1ull << q;
+        }
+        wave_sync();
+        if (has && ((covered >> slot) & 1ull)) hits.add(P, i, my_poly);
       }
     }
-    if (any_cand) c_candpts++;
-    else c_true++;
-    P.out[i] = hits.best;
+    if (live) P.out[i] = hits.best;
   }
-  if (P.counters) {
+  if (COUNT) {
     unsigned long long *C = P.counters;
-    atomicAdd(C + ACT_CNT_POINTS, c_pts);
-    atomicAdd(C + ACT_CNT_INVALID, c_inv);
-    atomicAdd(C + ACT_CNT_FALSE_HIT, c_false);
-    atomicAdd(C + ACT_CNT_SOLELY_TRUE, c_true);
-    atomicAdd(C + ACT_CNT_CAND_POINTS, c_candpts);
-    atomicAdd(C + ACT_CNT_CANDIDATES, c_cand);
-    atomicAdd(C + ACT_CNT_EDGES, c_edges);
-    atomicAdd(C + ACT_CNT_EDGE_FP64, c_fp64);
-    atomicAdd(C + ACT_CNT_EDGE_EXACT, c_exact);
-    atomicAdd(C + ACT_CNT_NODE_READS, c_nodes);
-    atomicAdd(C + ACT_CNT_LUT_READS, c_lut);
+    atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c_pts);
+    atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c_inv);
+    atomicAdd(C + ACT_CNT_FALSE_HIT, (unsigned long long)c_false);
+    atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c_true);
+    atomicAdd(C + ACT_CNT_CAND_POINTS, (unsigned long long)c_candpts);
+    atomicAdd(C + ACT_CNT_CANDIDATES, (unsigned long long)c_cand);
+    atomicAdd(C + ACT_CNT_EDGES, (unsigned long long)c_edges);
+    atomicAdd(C + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
+    atomicAdd(C + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
+    atomicAdd(C + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+    atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c_lut);
   }
 }
 
@@ -319,9 +466,21 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double2 p = pts[i];
     uint32_t face;
-    uint64_t pos;
-    ids[i] = dev_leaf(p.x, p.y, s_htab, face, pos) ? (((uint64_t)face << 61) | (pos << 1) | 1ull) : 0ull;
+    uint64_t key;
+    ids[i] = dev_leaf(p.x, p.y, s_htab, face, key) ? (((uint64_t)face << 61) | (key << 1) | 1ull) : 0ull;
   }
+}
+
+using ProbeFn = void (*)(ProbeParams);
+static ProbeFn probe_fn(bool exact, int lds_depth, bool count) {
+  static const ProbeFn tab[2][3][2] = {
+      {{probe_kernel<false, 0, false>, probe_kernel<false, 0, true>},
+       {probe_kernel<false, 1, false>, probe_kernel<false, 1, true>},
+       {probe_kernel<false, 2, false>, probe_kernel<false, 2, true>}},
+      {{probe_kernel<true, 0, false>, probe_kernel<true, 0, true>},
+       {probe_kernel<true, 1, false>, probe_kernel<true, 1, true>},
+       {probe_kernel<true, 2, false>, probe_kernel<true, 2, true>}}};
+  return tab[exact][lds_depth][count];
 }
 
 // ------------------------------------------------------------------ host
@@ -402,6 +561,20 @@ static int grid_for(int64_t n, int block) {
   return (int)std::min<int64_t>(std::max<int64_t>(blocks, 1), 8192);
 }
 
+constexpr int kLdsTrieBudget = 48 * 1024;
+
+// Node count staged in LDS for `depth` levels (0 if it does not fit).
+static int lds_nodes_for(const HostIndex &h, int depth) {
+  int n = depth >= 2 ? h.n_d0 + h.n_d1 : (depth == 1 ? h.n_d0 : 0);
+  return n * 2048 <= kLdsTrieBudget ? n : -1;
+}
+
+static int default_lds_depth(const HostIndex &h) {
+  for (int d = 2; d >= 1; d--)
+    if (lds_nodes_for(h, d) > 0) return d;
+  return 0;
+}
+
 static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
   if (!a) return fail(ACT_E_ARG, "args is NULL");
@@ -413,9 +586,14 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     return fail(ACT_E_ARG, "pair output needs point, poly, counter arrays and capacity >= 0");
   if (a->refine != ACT_REFINE_FP32_FILTER && a->refine != ACT_REFINE_FP64)
     return fail(ACT_E_ARG, "unknown refine mode");
-  int block = a->block > 0 ? a->block : 256;
-  if (block != 64 && block != 128 && block != 256)
-    return fail(ACT_E_ARG, "block must be 64, 128 or 256");
+  if (a->block != 0 && a->block != kBlock) return fail(ACT_E_ARG, "block must be 0 or 256");
+  if (a->grid < 0 || a->grid > 65536) return fail(ACT_E_ARG, "grid must be 0 .. 65536");
+  const HostIndex &h = x->host;
+  int depth = a->lds_levels < 0 ? default_lds_depth(h) : a->lds_levels;
+  if (depth > 2) return fail(ACT_E_ARG, "lds_levels must be -1, 0, 1 or 2");
+  int n_lds = depth > 0 ? lds_nodes_for(h, depth) : 0;
+  if (n_lds < 0) return fail(ACT_E_RANGE, "top trie levels do not fit the LDS budget");
+  if (depth > 0 && n_lds == 0) depth = 0;  // empty trie
   int rc = check_stream_device(x, stream);
   if (rc) return rc;
   if (a->n == 0) return ACT_OK;
@@ -437,16 +615,19 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.e64 = x->dev.e64;
   P.htab = x->dev.htab;
   for (int f = 0; f < 6; f++) {
-    const FaceRoot &F = x->host.faces[f];
+    const FaceRoot &F = h.faces[f];
     P.root[f] = F.root;
     P.shift[f] = 60 - 2 * F.plevel;
     P.prefix[f] = F.prefix;
   }
-  P.mode = x->host.mode;
+  P.n_lds_nodes = n_lds;
   P.refine = a->refine;
+  int64_t tiles_blocks = (a->n + kBlock - 1) / kBlock;
+  int grid = a->grid > 0 ? a->grid : 2048;
+  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, tiles_blocks));
   DeviceGuard g(x->device);
-  hipLaunchKernelGGL(probe_kernel, dim3(grid_for(a->n, block)), dim3(block), 0,
-                     (hipStream_t)stream, P);
+  ProbeFn fn = probe_fn(h.mode == ACT_EXACT, depth, a->d_counters != nullptr);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), (size_t)n_lds * 2048, (hipStream_t)stream, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
   return ACT_OK;

@@ -129,14 +129,26 @@ def test_empty_batch(act):
     assert out.shape == (0,)
 
 
-def test_block_sizes_and_repeats_identical(act):
-    P, idx = index(act, "c2", "exact")
+@pytest.mark.parametrize("mode,prec", [("exact", 0.0), ("approx", 4.0)])
+def test_launch_shapes_and_repeats_identical(act, mode, prec):
+    """Output does not depend on the grid size, the LDS-staged trie depth or
+    the run (determinism / race check)."""
+    P, idx = index(act, "c2", mode, prec)
     pts = synth.workload_points("c2", 0, 300000)
     base = gpu_join(idx, pts)
-    for blk in (64, 128, 256):
-        for _ in range(2):
-            o = gpu_join(idx, pts, block=blk)
-            assert np.array_equal(o[0], base[0]) and np.array_equal(o[1], base[1])
+    fits = []
+    for lds in (0, 1, 2):
+        try:
+            gpu_join(idx, pts[:64], lds_levels=lds)
+            fits.append(lds)
+        except act.ActError as e:  # top levels larger than the LDS budget
+            assert e.code == -7
+    assert 0 in fits and 1 in fits
+    for grid in (1, 7, 256, 0):
+        for lds in fits:
+            for _ in range(2):
+                o = gpu_join(idx, pts, grid=grid, lds_levels=lds)
+                assert np.array_equal(o[0], base[0]) and np.array_equal(o[1], base[1]), (grid, lds)
 
 
 def test_c1_approx_guarantee(act):
