@@ -142,6 +142,18 @@ int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int32_t *d_out, int64_t *d_pair_point, int32_t *d_pair_poly,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
 
+/*
+ * act_workspace_reserve -- exact-mode joins queue their candidate
+ * (point, polygon) pairs in a per-stream device workspace owned by the
+ * index (12 bytes per entry, default 4 Mi entries). It is allocated on the
+ * first exact join on a stream; call this beforehand to pay that cost early
+ * (e.g. before capturing joins into a HIP graph, where allocation is not
+ * allowed) or to enlarge it. Joins never fail for lack of queue space: a
+ * lane whose candidate does not fit refines it itself. Workspaces live until
+ * act_free. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_OOM, ACT_E_HIP.
+ */
+int act_workspace_reserve(const act_index *idx, void *stream, int64_t capacity);
+
 /* Join counters (uint64 each), accumulated by act_join_ex when asked. */
 enum {
   ACT_CNT_POINTS = 0,      /* points probed                                  */
@@ -169,11 +181,19 @@ typedef struct {
   int64_t *d_n_pairs;
   uint64_t *d_counters;    /* optional (NULL): ACT_NCOUNTERS accumulators    */
   int32_t refine;          /* ACT_REFINE_*                                   */
-  int32_t block;           /* threads per block: 0 (default) or 256         */
+  int32_t block;           /* probe threads per block: 0 (default) or 1024  */
   int32_t lds_levels;      /* top trie node levels staged in LDS: 0, 1, 2, or
-                              -1 for the default (deepest that fits 48 KiB)  */
-  int32_t grid;            /* blocks launched (0 = default 2048); each wave
-                              walks tiles of 64 points grid-stride           */
+                              -1 for the default (deepest that fits 64 KiB
+                              of 32-bit entries)                             */
+  int32_t grid;            /* probe blocks launched (0 = default 1024); each
+                              wave walks tiles of 64 points grid-stride      */
+  int64_t queue_limit;     /* exact mode: use at most this many entries of
+                              the stream's candidate queue (0 = all of it);
+                              points that do not fit are resolved by a
+                              slower per-point pass -- a knob for tests     */
+  int32_t points_per_lane; /* points each probe lane carries per step: 1, 2
+                              (0 = default 2)                                */
+  int32_t reserved2;
 } act_join_args;
 
 int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
@@ -214,12 +234,12 @@ typedef struct {
 int act_index_stats(const act_index *idx, act_stats *out);
 
 /*
- * act_lookup_host -- host-side trie lookup of n level-30 cell ids (for
- * inspection and tests): writes the tagged trie entry each id ends at
- * (0 = false hit) to entries[i]. Host pointers.
+ * act_lookup_host -- host-side trie lookup of n leaf cells given as
+ * (face, i, j) with 30-bit i, j (inspection and tests): writes the tagged
+ * trie entry each ends at (0 = false hit) to entries[i]. Host pointers.
  */
-int act_lookup_host(const act_index *idx, const uint64_t *ids, int64_t n,
-                    uint64_t *entries);
+int act_lookup_host(const act_index *idx, const int32_t *face, const uint32_t *i,
+                    const uint32_t *j, int64_t n, uint64_t *entries);
 
 /*
  * act_lut_host -- copy of the lookup table (host). If `words` is NULL only

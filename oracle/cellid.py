@@ -14,9 +14,8 @@ this project:
   * axis a = argmax(|x|, |y|, |z|), ties to the lower axis;
     face = a (positive side) or a + 3 (negative side);
   * u = c[(a+1) % 3] / |c[a]|, v = c[(a+2) % 3] / |c[a]|, both in [-1, 1];
-  * s = st(u), t = st(v) with the quadratic transform
-        st(w) = 0.5 * sqrt(1 + 3w)        for w >= 0
-              = 1 - 0.5 * sqrt(1 - 3w)    for w <  0;
+  * s = st(u), t = st(v) with the linear transform st(w) = (1 + w) / 2
+    (one of the projections S2 itself offers; the paper names none);
   * i = clamp(floor(2^30 s), 0, 2^30 - 1), j likewise from t;
   * Hilbert position d of (i, j) on the 2^30 x 2^30 grid, most significant
     level first: quadrant (rx, ry) -> digit (3 rx) xor ry, i.e. the first
@@ -35,15 +34,11 @@ N = 1 << MAX_LEVEL
 
 
 def st_from_uv(w):
-    w = np.asarray(w, dtype=np.float64)
-    return np.where(w >= 0, 0.5 * np.sqrt(1.0 + 3.0 * np.maximum(w, 0)),
-                    1.0 - 0.5 * np.sqrt(1.0 - 3.0 * np.minimum(w, 0)))
+    return 0.5 * (1.0 + np.asarray(w, dtype=np.float64))
 
 
 def uv_from_st(s):
-    s = np.asarray(s, dtype=np.float64)
-    return np.where(s >= 0.5, (4.0 * s * s - 1.0) / 3.0,
-                    (1.0 - 4.0 * (1.0 - s) ** 2) / 3.0)
+    return 2.0 * np.asarray(s, dtype=np.float64) - 1.0
 
 
 def xyz(lat, lng):

@@ -65,10 +65,10 @@ class Index:
         self.precision_m = precision_m
         self.device = device
 
-    def __del__(self):
+    def __del__(self, _free=lib.act_free):
         h, self._h = getattr(self, "_h", None), None
         if h:
-            lib.act_free(h)
+            _free(h)
 
     def close(self):
         self.__del__()
@@ -95,7 +95,7 @@ class Index:
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
                 refine=ACT_REFINE_FP32_FILTER, block=0, lds_levels=-1, grid=0,
-                stream=None):
+                queue_limit=0, points_per_lane=0, stream=None):
         """Full-control join. Returns (out, pairs or None, counters dict or None).
 
         pairs: (m, 2) int64 CUDA tensor of (point, polygon) beyond out[i]
@@ -115,6 +115,8 @@ class Index:
         a.block = block
         a.lds_levels = lds_levels
         a.grid = grid
+        a.queue_limit = queue_limit
+        a.points_per_lane = points_per_lane
         pp = pq = cnt = ctr = None
         if capacity is not None:
             pp = torch.empty(max(1, capacity), dtype=torch.int64, device=dev)
@@ -130,7 +132,9 @@ class Index:
         if capacity is not None:
             m = int(cnt.item())
             if m > capacity:
-                raise ActError(_b.ACT_E_OVERFLOW, "%d pairs exceed capacity %d" % (m, capacity))
+                err = ActError(_b.ACT_E_OVERFLOW, "%d pairs exceed capacity %d" % (m, capacity))
+                err.needed = m
+                raise err
             pairs = torch.stack([pp[:m], pq[:m].to(torch.int64)], 1)
         cdict = None
         if counters:
@@ -148,14 +152,17 @@ class Index:
         except ActError as e:
             if e.code != _b.ACT_E_OVERFLOW or capacity is not None:
                 raise
-            need = int(str(e).split()[3])
-            out, pairs, _ = self.join_ex(points, capacity=need, stream=stream)
+            out, pairs, _ = self.join_ex(points, capacity=e.needed, stream=stream)
         return out, pairs
 
-    def lookup_host(self, ids: np.ndarray) -> np.ndarray:
-        ids = np.ascontiguousarray(ids, dtype=np.uint64)
-        ent = np.empty(ids.shape[0], np.uint64)
-        _b.check(lib.act_lookup_host(self._h, _np_ptr(ids), ids.shape[0], _np_ptr(ent)))
+    def lookup_host(self, face, i, j) -> np.ndarray:
+        """Host trie lookup of leaf cells (face, i, j): tagged entries."""
+        f = np.ascontiguousarray(face, dtype=np.int32)
+        a = np.ascontiguousarray(i, dtype=np.uint32)
+        b = np.ascontiguousarray(j, dtype=np.uint32)
+        ent = np.empty(f.shape[0], np.uint64)
+        _b.check(lib.act_lookup_host(self._h, _np_ptr(f), _np_ptr(a), _np_ptr(b), f.shape[0],
+                                     _np_ptr(ent)))
         return ent
 
     def lut_host(self) -> np.ndarray:

@@ -43,7 +43,8 @@ class JoinArgs(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("d_n_pairs", ctypes.c_void_p),
                 ("d_counters", ctypes.c_void_p), ("refine", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("queue_limit", ctypes.c_int64),
+                ("points_per_lane", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -75,9 +76,10 @@ def _load():
         "act_join": ([p, p, i64, p, p], ctypes.c_int),
         "act_join_pairs": ([p, p, i64, p, p, p, i64, p, p], ctypes.c_int),
         "act_join_ex": ([p, p, p], ctypes.c_int),
+        "act_workspace_reserve": ([p, p, i64], ctypes.c_int),
         "act_cell_ids": ([p, i64, p, p], ctypes.c_int),
         "act_index_stats": ([p, p], ctypes.c_int),
-        "act_lookup_host": ([p, p, i64, p], ctypes.c_int),
+        "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),
         "act_lut_host": ([p, p, p], ctypes.c_int),
         "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),
         "act_orient_fp32_host": ([p, p, p, p, ctypes.c_float], ctypes.c_int),

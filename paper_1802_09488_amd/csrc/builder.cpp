@@ -23,7 +23,8 @@
 // Physical index (Section III-C): cells are denormalised to the node levels
 // of their face (g = 4 levels per node, Fig. 6a), references of fewer than
 // three polygons are inlined into the tagged entry, longer lists are
-// deduplicated into the lookup table (Fig. 6b).
+// deduplicated into the lookup table (Fig. 6b). The trie is keyed by each
+// cell's quadtree path (see index.hpp).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -229,8 +230,8 @@ struct Work {
 };
 
 struct CellOut {
-  uint64_t id;
-  int32_t level;
+  int32_t face, level;
+  uint32_t i, j;  // coordinates at the cell's level
   int32_t ref_off, ref_cnt;
 };
 
@@ -242,7 +243,6 @@ struct Sink {
 struct Ctx {
   const Prep *P;
   BuildParams bp;
-  const uint16_t *htab;
   std::atomic<bool> failed{false};
   std::string err;
 };
@@ -280,8 +280,10 @@ void classify(const Ctx &C, const Box &box, const std::vector<int32_t> &pint,
 
 void emit(const Ctx &C, const Work &w, Sink &s) {
   CellOut c;
-  c.id = cell_id(w.face, w.level, w.i, w.j, C.htab);
+  c.face = w.face;
   c.level = w.level;
+  c.i = w.i;
+  c.j = w.j;
   c.ref_off = (int32_t)s.refs.size();
   size_t a = 0, b = 0;
   // merge interior (flag 1) and boundary (flag 0) ids in ascending order
@@ -357,12 +359,13 @@ struct LutDedup {
 LutDedup *lut_dedup_new() { return new LutDedup; }
 void lut_dedup_free(LutDedup *d) { delete d; }
 
-uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup) {
+static uint64_t encode_refs_impl(const uint32_t *refs, int n, std::vector<uint32_t> &lut,
+                                 LutDedup *dedup, bool inline_ok) {
   if (n <= 0) return 0;
   std::vector<uint32_t> r(refs, refs + n);
   std::sort(r.begin(), r.end(), [](uint32_t a, uint32_t b) { return (a >> 1) < (b >> 1); });
-  if (n == 1) return ((uint64_t)r[0] << 2) | kTagOne;
-  if (n == 2) return ((uint64_t)r[0] << 2) | ((uint64_t)r[1] << 33) | kTagTwo;
+  if (inline_ok && n == 1) return ((uint64_t)r[0] << 2) | kTagOne;
+  if (inline_ok && n == 2) return ((uint64_t)r[0] << 2) | ((uint64_t)r[1] << 33) | kTagTwo;
   std::vector<uint32_t> list;
   list.reserve(n + 2);
   uint32_t nt = 0;
@@ -386,18 +389,42 @@ uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, Lu
   return ((uint64_t)off << 2) | kTagLut;
 }
 
-uint64_t host_lookup(const HostIndex &idx, uint64_t id) {
-  int face = (int)(id >> 61);
-  if (face > 5) return 0;
+uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup) {
+  return encode_refs_impl(refs, n, lut, dedup, true);
+}
+
+uint64_t encode_refs_lut(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup) {
+  return encode_refs_impl(refs, n, lut, dedup, false);
+}
+
+// The top node levels are also kept as 32-bit entries (the GPU stages them
+// in LDS). An entry fits when its high 32 bits are zero: child pointers,
+// lookup-table offsets and single references of polygon ids below 2^29. The
+// others -- two inlined references, or a single reference of a larger id --
+// are rewritten as lookup-table references in those levels.
+static void narrow_top_levels(HostIndex &x, LutDedup *dedup) {
+  const size_t n_top = (size_t)x.n_d0 + (size_t)x.n_d1;
+  for (size_t k = 256; k < (1 + n_top) * 256; k++) {
+    const uint64_t e = x.nodes[k];
+    if ((e >> 32) == 0) continue;
+    uint32_t refs[2];
+    int n = 0;
+    refs[n++] = (uint32_t)((e >> 2) & 0x7fffffffu);
+    if ((e & kTagMask) == kTagTwo) refs[n++] = (uint32_t)((e >> 33) & 0x7fffffffu);
+    x.nodes[k] = encode_refs_lut(refs, n, x.lut, dedup);
+  }
+}
+
+uint64_t host_lookup(const HostIndex &idx, int face, uint32_t i, uint32_t j) {
+  if (face < 0 || face > 5) return 0;
   const FaceRoot &f = idx.faces[face];
   if (f.root < 0) return 0;
-  uint64_t key = (id >> 1) & ((1ull << 60) - 1);
-  int sh = 60 - 2 * f.plevel;
-  if (f.plevel > 0 && (key >> sh) != f.prefix) return 0;
+  int sh = kMaxLevel - f.plevel;
+  if ((i >> sh) != f.pi || (j >> sh) != f.pj) return 0;
   uint64_t node = (uint64_t)f.root;
   for (;;) {
-    sh -= 8;
-    uint64_t e = idx.nodes[node * 256 + ((key >> sh) & 255u)];
+    sh -= 4;
+    uint64_t e = idx.nodes[node * 256 + node_slot(i, j, sh)];
     if ((e & kTagMask) != kTagPtr || e == 0) return e;
     node = e >> 2;
   }
@@ -527,23 +554,26 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     double oy = 0.5 * (P.bbox[p].lat0 + P.bbox[p].lat1);
     out.poly_origin[2 * p] = ox;
     out.poly_origin[2 * p + 1] = oy;
+    // fp32 copy translated by the origin and oriented upward (lower
+    // endpoint first); the fp64 copy keeps the input orientation
     float m = 0;
-    for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++)
+    for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) {
+      const double *q = &P.ex[4 * (size_t)e];
+      const bool flip = q[1] > q[3];
+      const double src[4] = {flip ? q[2] : q[0], flip ? q[3] : q[1], flip ? q[0] : q[2],
+                             flip ? q[1] : q[3]};
       for (int c = 0; c < 4; c++) {
-        double o = (c & 1) ? oy : ox;
-        float v = (float)(P.ex[4 * (size_t)e + c] - o);
+        float v = (float)(src[c] - ((c & 1) ? oy : ox));
         out.edges32[4 * (size_t)e + c] = v;
         m = std::max(m, std::fabs(v));
       }
+    }
     out.poly_m[p] = m;
   }
   // --------------------------------------------------------- subdivision
-  uint16_t htab[1024];
-  hilbert_table4(htab);
   Ctx C;
   C.P = &P;
   C.bp = bp;
-  C.htab = htab;
   int nthreads = bp.threads > 0 ? bp.threads : (int)std::max(1u, std::thread::hardware_concurrency());
 
   std::vector<int32_t> all_polys;
@@ -601,20 +631,25 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     err = C.err;
     return ACT_E_ARG;
   }
-  // gather cells
+  // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
+  // shifted to level 30
   struct Cell {
-    uint64_t id;
-    int level;
+    int face, level;
+    uint32_t I, J;
     const uint32_t *refs;
     int n;
   };
   std::vector<Cell> cells;
   auto gather = [&](const Sink &s) {
-    for (const CellOut &c : s.cells) cells.push_back({c.id, c.level, &s.refs[c.ref_off], c.ref_cnt});
+    for (const CellOut &c : s.cells)
+      cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
+                       &s.refs[c.ref_off], c.ref_cnt});
   };
   gather(top);
   for (const Sink &s : sinks) gather(s);
-  std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) { return a.id < b.id; });
+  std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) {
+    return a.face != b.face ? a.face < b.face : (a.I != b.I ? a.I < b.I : a.J < b.J);
+  });
   out.n_cells = (int64_t)cells.size();
   // ------------------------------------------------------------- tries
   out.nodes.assign(256, 0);  // node 0 reserved
@@ -622,17 +657,20 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   size_t c0 = 0;
   for (int face = 0; face < 6; face++) {
     size_t c1 = c0;
-    while (c1 < cells.size() && (int)(cells[c1].id >> 61) == face) c1++;
+    while (c1 < cells.size() && cells[c1].face == face) c1++;
     if (c1 == c0) continue;
+    // common prefix level: deepest level shared by every cell of the face
     int lmin = 30, lmax = 0;
-    uint64_t k0 = cell_key(cells[c0].id), diff = 0;
+    uint32_t diff = 0;
     for (size_t k = c0; k < c1; k++) {
       lmin = std::min(lmin, cells[k].level);
       lmax = std::max(lmax, cells[k].level);
-      diff |= cell_key(cells[k].id) ^ k0;
+      diff |= (cells[k].I ^ cells[c0].I) | (cells[k].J ^ cells[c0].J);
     }
-    int common_bits = diff ? 59 - (63 - __builtin_clzll(diff)) : 60;
-    int lc = std::min(lmin, common_bits / 2);
+    int common = diff ? 29 - (31 - __builtin_clz(diff)) : 30;
+    int lc = std::min(lmin, common);
+    // node levels Lp+1..Lp+4, Lp+5..Lp+8, ...: align the finest level with
+    // a node's last level so that the most numerous cells are not replicated
     int lp = lc - ((4 - (lmax - lc) % 4) % 4);
     if (lp < 0) {
       lp = lc;
@@ -643,18 +681,17 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     }
     FaceRoot &F = out.faces[face];
     F.plevel = lp;
-    F.prefix = lp > 0 ? (k0 >> (60 - 2 * lp)) : 0;
+    F.pi = cells[c0].I >> (kMaxLevel - lp);
+    F.pj = cells[c0].J >> (kMaxLevel - lp);
     F.root = (int32_t)(out.nodes.size() / 256);
     out.nodes.resize(out.nodes.size() + 256, 0);
     for (size_t k = c0; k < c1; k++) {
       const Cell &c = cells[k];
-      uint64_t key = cell_key(c.id);
       int l = c.level;
-      int kd = l <= lp ? 0 : (l - lp - 1) / 4;
+      int kd = l <= lp ? 0 : (l - lp - 1) / 4;  // node level holding the cell
       uint64_t node = (uint64_t)F.root;
       for (int d = 0; d < kd; d++) {
-        int sh = 60 - 2 * lp - 8 * (d + 1);
-        uint64_t slot = node * 256 + ((key >> sh) & 255u);
+        uint64_t slot = node * 256 + node_slot(c.I, c.J, kMaxLevel - lp - 4 * (d + 1));
         uint64_t e = out.nodes[slot];
         if (e == 0) {
           uint64_t nn = out.nodes.size() / 256;
@@ -668,22 +705,26 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
           return ACT_E_POLY;
         }
       }
-      int sh = 60 - 2 * lp - 8 * (kd + 1);
-      uint64_t base = (key >> sh) & 255u;
-      uint64_t count = 1ull << (2 * (lp + 4 * (kd + 1) - l));
+      // denormalise: the cell covers a 2^k x 2^k block of the node's 16 x 16
+      // (i nibble, j nibble) entries, k = levels between the cell and the
+      // node's last level
+      const int sh = kMaxLevel - lp - 4 * (kd + 1);
+      const uint32_t ni = (c.I >> sh) & 15u, nj = (c.J >> sh) & 15u;
+      const uint32_t span = 1u << (lp + 4 * (kd + 1) - l);
       uint64_t entry = encode_refs(c.refs, c.n, out.lut, &dedup);
       if (out.lut.size() >= (1ull << 31)) {
         err = "lookup table exceeds 2^31 words";
         return ACT_E_RANGE;
       }
-      for (uint64_t b = base; b < base + count; b++) {
-        uint64_t slot = node * 256 + b;
-        if (out.nodes[slot] != 0) {
-          err = "internal: overlapping cells in the super covering";
-          return ACT_E_POLY;
+      for (uint32_t a = 0; a < span; a++)
+        for (uint32_t b = 0; b < span; b++) {
+          uint64_t slot = node * 256 + (((ni + a) << 4) | (nj + b));
+          if (out.nodes[slot] != 0) {
+            err = "internal: overlapping cells in the super covering";
+            return ACT_E_POLY;
+          }
+          out.nodes[slot] = entry;
         }
-        out.nodes[slot] = entry;
-      }
       F.depth = std::max(F.depth, kd + 1);
       out.max_depth = std::max(out.max_depth, kd + 1);
       out.max_refs = std::max(out.max_refs, c.n);
@@ -695,6 +736,11 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     c0 = c1;
   }
   renumber_breadth_first(out);
+  narrow_top_levels(out, &dedup);
+  if (out.lut.size() >= (1ull << 30)) {
+    err = "lookup table exceeds 2^30 words";
+    return ACT_E_RANGE;
+  }
   out.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return ACT_OK;

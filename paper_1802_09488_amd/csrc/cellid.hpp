@@ -6,7 +6,7 @@
 //   x = cos(lat) cos(lng), y = cos(lat) sin(lng), z = sin(lat);
 //   axis a = argmax |c| (ties to the lower axis), face = a or a + 3 (negative);
 //   u = c[(a+1)%3] / |c[a]|, v = c[(a+2)%3] / |c[a]|;
-//   s = st(u), t = st(v), st(w) = sqrt(1+3w)/2 (w >= 0), 1 - sqrt(1-3w)/2;
+//   s = st(u), t = st(v), st(w) = (1 + w) / 2 (linear; S2 offers it too);
 //   i = clamp(floor(2^30 s)), j = clamp(floor(2^30 t));
 //   Hilbert digit per level from the quadrant (rx, ry) as (3 rx) xor ry,
 //   sub-squares with ry = 0 reflected (rx = 1) and transposed.
@@ -26,14 +26,9 @@ namespace act {
 constexpr int kMaxLevel = 30;
 constexpr double kTwo30 = 1073741824.0;
 
-ACT_HD double st_from_uv(double u) {
-  return u >= 0.0 ? 0.5 * sqrt(1.0 + 3.0 * u) : 1.0 - 0.5 * sqrt(1.0 - 3.0 * u);
-}
+ACT_HD double st_from_uv(double u) { return 0.5 * (1.0 + u); }
 
-ACT_HD double uv_from_st(double s) {
-  return s >= 0.5 ? (4.0 * s * s - 1.0) * (1.0 / 3.0)
-                  : (1.0 - 4.0 * (1.0 - s) * (1.0 - s)) * (1.0 / 3.0);
-}
+ACT_HD double uv_from_st(double s) { return 2.0 * s - 1.0; }
 
 // Hilbert state machine. State = (swap s, flip f): the transform taking the
 // original sub-square coordinates to the curve's canonical frame (flip =

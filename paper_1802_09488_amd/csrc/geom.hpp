@@ -46,35 +46,39 @@ ACT_HD void exact_add(double a, double b, double &s, double &e) {
   e = (a - (s - z)) + (b - z);
 }
 
+// Grow a nonoverlapping expansion h[0..n) by b (exactly).
+ACT_HD void expansion_grow(volatile double *h, int &n, double b) {
+  double q = b;
+  for (int i = 0; i < n; i++) {
+    double s, e;
+    exact_add(q, h[i], s, e);
+    h[i] = e;
+    q = s;
+  }
+  h[n++] = q;
+}
+
+// This path runs only when the fp64 filter cannot decide (exactly or nearly
+// collinear inputs). The expansion lives in a small private array so that
+// kernels carrying this code keep their register budget.
 ACT_HD int orient_sign_expansion(double ax, double ay, double bx, double by,
                                  double px, double py) {
-  double t[12];
-  exact_mul(bx, py, t[0], t[1]);
-  exact_mul(-bx, ay, t[2], t[3]);
-  exact_mul(-ax, py, t[4], t[5]);
-  exact_mul(-by, px, t[6], t[7]);
-  exact_mul(by, ax, t[8], t[9]);
-  exact_mul(ay, px, t[10], t[11]);
-  double h[12];
-#pragma unroll
-  for (int k = 0; k < 12; k++) {
-    double q = t[k];
-#pragma unroll
-    for (int i = 0; i < k; i++) {
-      double s, e;
-      exact_add(q, h[i], s, e);
-      h[i] = e;
-      q = s;
-    }
-    h[k] = q;
+  volatile double h[12];
+  int n = 0;
+  const double f1[6] = {bx, -bx, -ax, -by, by, ay};
+  const double f2[6] = {py, ay, py, px, ax, px};
+  for (int k = 0; k < 6; k++) {
+    double p, e;
+    exact_mul(f1[k], f2[k], p, e);
+    expansion_grow(h, n, e);
+    expansion_grow(h, n, p);
   }
-  int sign = 0;
-#pragma unroll
-  for (int i = 0; i < 12; i++) {
-    // components ascend in magnitude: the last nonzero one decides
-    sign = h[i] > 0.0 ? 1 : (h[i] < 0.0 ? -1 : sign);
+  for (int i = n - 1; i >= 0; i--) {
+    const double v = h[i];
+    if (v > 0.0) return 1;  // components ascend in magnitude
+    if (v < 0.0) return -1;
   }
-  return sign;
+  return 0;
 }
 
 // Returns +1/-1 when the fp64 filter decides, 0 when it does not.

@@ -15,11 +15,22 @@
 // covers levels Lp+1..Lp+4, its children Lp+5..Lp+8, and so on (the
 // per-face common prefix of Section IV-B2 / Listing 4 with the level
 // granularity g = 4 of Section III-C).
+//
+// Key: the method needs only that a child's key extends its parent's
+// (Section II); it does not depend on the curve. The trie is keyed by the
+// cell's quadtree path: a node covering levels L+1..L+4 indexes its 256
+// entries by (4 bits of i, 4 bits of j) below level L, i.e. entry
+// 16 * ni + nj. The nodes, their contents and depths are those of a trie
+// over the Hilbert-ordered cell ids; only the order of entries inside a node
+// differs. A probe forms each node's key byte from (i, j) directly, with no
+// sequential curve state.
 #pragma once
 
 #include <cstdint>
 #include <string>
 #include <vector>
+
+#include <hip/hip_runtime.h>
 
 #include "../../include/act.h"
 
@@ -31,9 +42,15 @@ constexpr uint64_t kTagPtr = 0, kTagOne = 1, kTagTwo = 2, kTagLut = 3;
 struct FaceRoot {
   int32_t root = -1;      // node index, -1 if the face has no cells
   int32_t plevel = 0;     // prefix level Lp
-  uint64_t prefix = 0;    // the 2*Lp leading key bits
+  uint32_t pi = 0, pj = 0;  // the common prefix: (i, j) >> (30 - Lp)
   int32_t depth = 0;      // number of node levels below the prefix
 };
+
+// Entry of (leaf coordinates i, j) in the node whose levels end `sh` bits
+// above the leaf level.
+inline __host__ __device__ uint32_t node_slot(uint32_t i, uint32_t j, int sh) {
+  return (((i >> sh) & 15u) << 4) | ((j >> sh) & 15u);
+}
 
 struct HostIndex {
   int32_t mode = ACT_EXACT;
@@ -49,15 +66,16 @@ struct HostIndex {
   std::vector<int32_t> poly_edge_off;  // n_polys + 1
   std::vector<double> poly_origin;     // 2 per polygon (x, y)
   std::vector<float> poly_m;           // largest |translated fp32 coordinate|
-  std::vector<float> edges32;          // 4 per edge: ax ay bx by, translated
+  std::vector<float> edges32;          // 4 per edge, translated, lower endpoint first
   std::vector<double> edges64;         // 4 per edge: ax ay bx by
 
   // statistics
   int64_t n_cells = 0, n_cells_interior_only = 0;
   int32_t max_depth = 0, max_refs = 0, max_cell_level = 0;
   // Nodes are numbered breadth-first: roots occupy indices 1 .. n_d0, the
-  // nodes one level below them n_d0+1 .. n_d0+n_d1 (LDS staging of the top
-  // levels copies these contiguous ranges).
+  // nodes one level below them n_d0+1 .. n_d0+n_d1. Every entry of these two
+  // levels has its high 32 bits zero, so the GPU stages them in LDS as
+  // 32-bit entries.
   int32_t n_d0 = 0, n_d1 = 0;
   double build_seconds = 0;
 };
@@ -75,8 +93,9 @@ int build_host_index(const double *verts_latlng, const int64_t *ring_off,
                      const int32_t *poly_ring_off, int32_t n_polys,
                      const BuildParams &bp, HostIndex &out, std::string &err);
 
-// Host trie lookup of a leaf cell id: the tagged entry the descent ends at.
-uint64_t host_lookup(const HostIndex &idx, uint64_t id);
+// Host trie lookup of a leaf cell (face, i, j): the tagged entry the
+// descent ends at.
+uint64_t host_lookup(const HostIndex &idx, int face, uint32_t i, uint32_t j);
 
 // Encode one reference list (refs[k] = id << 1 | interior) into a tagged
 // entry, deduplicating lists of three or more in `lut` via `dedup`.
@@ -84,5 +103,7 @@ struct LutDedup;
 LutDedup *lut_dedup_new();
 void lut_dedup_free(LutDedup *);
 uint64_t encode_refs(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup);
+// As encode_refs, but always a lookup-table reference.
+uint64_t encode_refs_lut(const uint32_t *refs, int n, std::vector<uint32_t> &lut, LutDedup *dedup);
 
 }  // namespace act

@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -58,8 +59,20 @@ struct DevImage {
   float4 *e32 = nullptr;
   double2 *e64 = nullptr;
   uint16_t *htab = nullptr;
+  struct FaceDev *faces = nullptr;
+  uint32_t *top32 = nullptr;
   size_t bytes = 0;
 };
+
+// Per-stream scratch of exact-mode joins: the candidate queue.
+struct Workspace {
+  int64_t *q_pt = nullptr;
+  int32_t *q_poly = nullptr;
+  uint32_t *q_ctl = nullptr;
+  int64_t cap = 0;
+};
+
+constexpr int64_t kDefaultQueue = 1 << 22;
 
 }  // namespace act
 
@@ -67,9 +80,19 @@ struct act_index {
   act::HostIndex host;
   act::DevImage dev;
   int device = -1;
+  mutable std::mutex ws_mu;
+  mutable std::unordered_map<void *, act::Workspace> ws;
 };
 
 namespace act {
+
+// Per-face lookup data in LDS: root node, prefix level shift and the
+// common prefix (i, j) >> (30 - Lp) shared by all of the face's cells.
+struct FaceDev {
+  int32_t root;  // node index, -1 if the face has no cells
+  int32_t sh0;   // 30 - Lp
+  uint32_t pi, pj;
+};
 
 // Kernel parameters (passed by value).
 struct ProbeParams {
@@ -89,55 +112,54 @@ struct ProbeParams {
   const float4 *e32;
   const double2 *e64;
   const uint16_t *htab;
-  int32_t root[6];
-  int32_t shift[6];  // 60 - 2 * prefix level
-  uint64_t prefix[6];
-  int32_t n_lds_nodes;  // trie nodes 1 .. n_lds_nodes staged in LDS
+  const FaceDev *faces;  // 6 entries (device)
+  const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 as 32-bit entries
+  int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
+  // exact mode: candidate queue (workspace of the launching stream)
+  int64_t *q_pt;
+  int32_t *q_poly;
+  uint32_t *q_ctl;  // [s] entries in segment s; [kSegs] refine blocks done;
+                    // [kSegs+1] pending points exist; [kSegs+2] fixup blocks done
+  int64_t q_seg_cap;  // entries per segment
 };
 
-constexpr int kBlock = 256;
+
+constexpr int kBlock = 256;  // refine / fixup kernels
 constexpr int kWaves = kBlock / 64;
+// The probe runs 1024-thread blocks: one LDS copy of the top trie levels
+// then serves 16 wavefronts, and two blocks fill a CU.
+constexpr int kProbeBlock = 1024;
+constexpr int kProbeWaves = kProbeBlock / 64;
+// The candidate queue is split into segments with their own counters so
+// that appends (one atomic per wave) do not serialise on one address.
+constexpr int kSegs = 256;
+constexpr int kRefineGrid = 2048;  // kRefineGrid * kWaves is a multiple of kSegs
 
 // --------------------------------------------------------- device math
 //
 // The projection needs fp64 (level-30 cells are 2^-30 of a face wide) but
 // only to ~1e-13 relative: the builder's conservative cell boxes carry a
 // 1e-9 degree margin. The pieces below are written for the argument ranges
-// that occur and cost far fewer instructions than the general library
-// routines.
+// that occur and cost far fewer instructions than general library routines.
 
-// sin and cos of x degrees, |x| <= 180. Quadrant reduction in degrees is
-// exact: r = x - 90 k with k = rint(x / 90) (Sterbenz: x and 90 k are within
-// a factor of two when k != 0). Then t = r pi / 180, |t| <= pi/4 (+ rounding)
-// and the Taylor series up to t^15 (sin) and t^16 (cos); truncation error
-// below t^17/17! = 5e-17.
-__device__ __forceinline__ void sincos_deg(double x, double &s, double &c) {
-  const double k = rint(x * (1.0 / 90.0));
-  const double r = fma(k, -90.0, x);
-  const double t = r * 0.017453292519943295;  // pi / 180
+// sin and cos of t, |t| <= pi/4 (+ rounding): Taylor series to t^13 / t^14;
+// the first omitted terms are below 2.1e-14 and 1.1e-15.
+__device__ __forceinline__ void sincos_quarter(double t, double &s, double &c) {
   const double t2 = t * t;
-  double ps = fma(t2, -1.0 / 1307674368000.0, 1.0 / 6227020800.0);  // -1/15!, 1/13!
-  ps = fma(t2, ps, -1.0 / 39916800.0);                              // -1/11!
-  ps = fma(t2, ps, 1.0 / 362880.0);                                 //  1/9!
-  ps = fma(t2, ps, -1.0 / 5040.0);                                  // -1/7!
-  ps = fma(t2, ps, 1.0 / 120.0);                                    //  1/5!
-  ps = fma(t2, ps, -1.0 / 6.0);                                     // -1/3!
-  const double sn = fma(t * t2, ps, t);
-  double pc = fma(t2, 1.0 / 20922789888000.0, -1.0 / 87178291200.0);  // 1/16!, -1/14!
-  pc = fma(t2, pc, 1.0 / 479001600.0);                                 //  1/12!
-  pc = fma(t2, pc, -1.0 / 3628800.0);                                  // -1/10!
-  pc = fma(t2, pc, 1.0 / 40320.0);                                     //  1/8!
-  pc = fma(t2, pc, -1.0 / 720.0);                                      // -1/6!
-  pc = fma(t2, pc, 1.0 / 24.0);                                        //  1/4!
-  pc = fma(t2, pc, -0.5);
-  const double cs = fma(t2, pc, 1.0);
-  // rotate by q quarter turns: (sn, cs), (cs, -sn), (-sn, -cs), (-cs, sn)
-  const int q = (int)k & 3;
-  s = (q & 1) ? cs : sn;
-  c = (q & 1) ? sn : cs;
-  if (q & 2) s = -s;
-  if ((q + 1) & 2) c = -c;
+  double p = fma(t2, 1.0 / 6227020800.0, -1.0 / 39916800.0);  //  1/13!, -1/11!
+  p = fma(t2, p, 1.0 / 362880.0);                              //  1/9!
+  p = fma(t2, p, -1.0 / 5040.0);                               // -1/7!
+  p = fma(t2, p, 1.0 / 120.0);                                 //  1/5!
+  p = fma(t2, p, -1.0 / 6.0);                                  // -1/3!
+  s = fma(t * t2, p, t);
+  double q = fma(t2, -1.0 / 87178291200.0, 1.0 / 479001600.0);  // -1/14!, 1/12!
+  q = fma(t2, q, -1.0 / 3628800.0);                              // -1/10!
+  q = fma(t2, q, 1.0 / 40320.0);                                 //  1/8!
+  q = fma(t2, q, -1.0 / 720.0);                                  // -1/6!
+  q = fma(t2, q, 1.0 / 24.0);                                    //  1/4!
+  q = fma(t2, q, -0.5);
+  c = fma(t2, q, 1.0);
 }
 
 // 1 / a for a in [1/sqrt(3), 1]: hardware estimate + two Newton steps.
@@ -149,55 +171,69 @@ __device__ __forceinline__ double rcp_nr(double a) {
   return fma(r, e, r);
 }
 
-// sqrt(a) for a in [1, 4]: reciprocal square root estimate, two Newton
-// steps on it, one multiply.
-__device__ __forceinline__ double sqrt_nr(double a) {
-  double y = __builtin_amdgcn_rsq(a);
-  double h = fma(-a * y, y, 1.0);
-  y = fma(0.5 * y, h, y);
-  h = fma(-a * y, y, 1.0);
-  y = fma(0.5 * y, h, y);
-  return a * y;
-}
-
-// st(w) * 2^30 as a 30-bit cell coordinate.
+// Linear st transform of a face coordinate w in [-1, 1] as a 30-bit cell
+// coordinate: floor(2^30 (1 + w) / 2), clamped.
 __device__ __forceinline__ uint32_t leaf_coord(double w) {
-  const double h = 0.5 * sqrt_nr(fma(3.0, fabs(w), 1.0));
-  const double s = w >= 0.0 ? h : 1.0 - h;
-  const uint32_t i = (uint32_t)fmax(s * kTwo30, 0.0);
+  const uint32_t i = (uint32_t)fmax(fma(w, 536870912.0, 536870912.0), 0.0);
   return min(i, (1u << 30) - 1u);
 }
 
-// Steps 2-4: leaf cell (face, 60-bit Hilbert key) of a point; false for
+// Steps 2-3: leaf cell coordinates (face, i, j) of a point; false for
 // points that are not finite or outside |lat| <= 90, |lng| <= 180.
-__device__ __forceinline__ bool dev_leaf(double lat, double lng, const uint16_t *htab,
-                                         uint32_t &face, uint64_t &key) {
+//
+// Both angles are reduced exactly in degrees, x = 90 k + r with
+// k = rint(x / 90), |r| <= 45 (Sterbenz: x and 90 k are within a factor of
+// two when k != 0). The longitude's quadrant q = k mod 4 then tells which of
+// |x|, |y| is larger, so the face needs one more comparison (|z| against
+// that maximum; ties go to the lower axis), and the major magnitude is the
+// maximum of the three.
+__device__ __forceinline__ bool project(double lat, double lng, uint32_t &face, uint32_t &i,
+                                        uint32_t &j) {
   if (!(fabs(lat) <= 90.0 && fabs(lng) <= 180.0)) return false;
-  double slat, clat, slng, clng;
-  sincos_deg(lat, slat, clat);
-  sincos_deg(lng, slng, clng);
-  const double x = clat * clng, y = clat * slng, z = slat;
-  const double ax = fabs(x), ay = fabs(y), az = fabs(z);
-  const bool fx = ax >= ay && ax >= az;
-  const bool fy = !fx && ay >= az;
-  const double m = fx ? x : (fy ? y : z);
-  const double c1 = fx ? y : (fy ? z : x);
-  const double c2 = fx ? z : (fy ? x : y);
-  face = (fx ? 0u : (fy ? 1u : 2u)) + (m < 0.0 ? 3u : 0u);
-  const double r = rcp_nr(fabs(m));
-  const uint32_t i = leaf_coord(c1 * r), j = leaf_coord(c2 * r);
-  // Hilbert position, 4 levels per table step (32 padded levels: the two
-  // leading zero levels leave the state unchanged and add zero digits).
-  uint32_t e = 0, hi = 0, lo = 0;
-#pragma unroll
-  for (int sh = 28; sh >= 0; sh -= 4) {
-    const uint32_t idx = (e & 0x300u) | (((i >> sh) & 15u) << 4) | ((j >> sh) & 15u);
-    e = htab[idx];
-    if (sh >= 16) hi = (hi << 8) | (e & 255u);
-    else lo = (lo << 8) | (e & 255u);
-  }
-  key = ((uint64_t)hi << 32) | lo;
+  const double kl = rint(lng * (1.0 / 90.0));
+  const double kp = rint(lat * (1.0 / 90.0));
+  double sl, cl, sp, cp;
+  sincos_quarter(fma(kl, -90.0, lng) * 0.017453292519943295, sl, cl);
+  sincos_quarter(fma(kp, -90.0, lat) * 0.017453292519943295, sp, cp);
+  // latitude: k in {-1, 0, 1}; sin(lat) = k cos r, cos(lat) = |sin r| if k != 0
+  const double slat = kp == 0.0 ? sp : copysign(cp, kp);
+  const double clat = kp == 0.0 ? cp : fabs(sp);
+  // longitude quadrant q: (cos, sin) = (c, s), (-s, c), (-c, -s), (s, -c)
+  const uint32_t q = (uint32_t)(int)kl & 3u;
+  const bool odd = q & 1u;
+  double cosl = odd ? sl : cl, sinl = odd ? cl : sl;
+  if ((q + 1u) & 2u) cosl = -cosl;
+  if (q & 2u) sinl = -sinl;
+  const double x = clat * cosl, y = clat * sinl, z = slat;
+  const double mxy = fmax(fabs(x), fabs(y));
+  const bool polar = fabs(z) > mxy;
+  const double r = rcp_nr(fmax(mxy, fabs(z)));
+  // minor coordinates in axis order: x face (y, z), y face (z, x), z face (x, y)
+  const double c1 = polar ? x : (odd ? z : y);
+  const double c2 = polar ? y : (odd ? x : z);
+  face = polar ? (z < 0.0 ? 5u : 2u) : (odd ? 1u : 0u) + ((q & 2u) ? 3u : 0u);
+  i = leaf_coord(c1 * r);
+  j = leaf_coord(c2 * r);
   return true;
+}
+
+// One Hilbert table step: 4 levels starting below bit `sh` of (i, j).
+// `st` holds the curve state << 8; returns the 4 digits (one key byte).
+__device__ __forceinline__ uint32_t hstep(const uint16_t *htab, uint32_t &st, uint32_t i,
+                                          uint32_t j, int sh) {
+  const uint32_t ent = htab[st | (((i >> sh) & 15u) << 4) | ((j >> sh) & 15u)];
+  st = ent & 0x300u;
+  return ent & 255u;
+}
+
+// Full 60-bit Hilbert position of a leaf (32 padded levels, 8 steps).
+__device__ __forceinline__ uint64_t hilbert60(const uint16_t *htab, uint32_t i, uint32_t j) {
+  uint32_t st = 0, hi = 0, lo = 0;
+#pragma unroll
+  for (int sh = 28; sh >= 16; sh -= 4) hi = (hi << 8) | hstep(htab, st, i, j, sh);
+#pragma unroll
+  for (int sh = 12; sh >= 0; sh -= 4) lo = (lo << 8) | hstep(htab, st, i, j, sh);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // --------------------------------------------------------- wave helpers
@@ -219,17 +255,20 @@ __device__ __forceinline__ void wave_sync() {
 // One edge of the crossing-number test. fp32 tier on origin-translated
 // coordinates; edges it cannot decide go to the exact fp64 test.
 // Returns 0 (no effect), 1 (toggle parity), 2 (point on the edge).
+// fp32 edges are stored oriented upward (g.y <= g.w): the point is level
+// with the edge's half-open y-range [ya, yb) exactly when ya <= py < yb, and
+// the ray crosses it when the point lies left of the edge (orient > 0).
+// Strict comparisons of rounded values imply the same strict order of the
+// exact values; equal rounded values go to the exact test.
 template <bool COUNT>
-__device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e, float qx, float qy,
-                                                    float eta, double px, double py,
-                                                    uint32_t &c_fp64, uint32_t &c_exact) {
-  const float4 g = P.e32[e];  // ax ay bx by
-  const bool a_up = g.y > qy, a_dn = g.y < qy;
-  const bool b_up = g.w > qy, b_dn = g.w < qy;
-  if ((a_up && b_up) || (a_dn && b_dn)) return 0;  // strictly above/below
-  if ((a_up || a_dn) && (b_up || b_dn)) {           // strict straddle
+__device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e, float4 g,
+                                                    float qx, float qy, float eta, double px,
+                                                    double py, uint32_t &c_fp64,
+                                                    uint32_t &c_exact) {
+  if (g.y > qy || g.w < qy) return 0;  // strictly below / above the edge
+  if (g.y < qy && g.w > qy) {           // strictly inside the y-range
     const int s = orient_sign_fp32_filter(g.x, g.y, g.z, g.w, qx, qy, eta);
-    if (s != 0) return (b_up ? (s > 0) : (s < 0)) ? 1 : 0;
+    if (s != 0) return s > 0 ? 1 : 0;
   }
   const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
   if (COUNT) {
@@ -253,33 +292,54 @@ __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px,
 
 // Whole-wave point-in-polygon test of one (point, polygon) pair: lane l
 // takes edges e0 + l, e0 + l + 64, ...; crossing parity = parity of the
-// popcount of the toggle ballots; any lane on an edge decides "covered".
-// Must be called by all 64 lanes with wave-uniform arguments.
+// popcounts of the toggle ballots; any lane on an edge decides "covered".
+// The next chunk of edges is loaded while the current one is tested. Must be
+// called by all 64 lanes with wave-uniform arguments.
 template <bool COUNT>
 __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double lng, int lane,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
   const double px = lng, py = lat;
   uint32_t par = 0;
+  bool on = false;
   if (P.refine == ACT_REFINE_FP32_FILTER) {
     const double2 o = P.origin[poly];
     const float qx = (float)(px - o.x), qy = (float)(py - o.y);
     const float eta = tier1_eta(fmaxf(P.pm[poly], fmaxf(fabsf(qx), fabsf(qy))));
+    float4 nxt = e0 + lane < e1 ? P.e32[e0 + lane] : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int base = e0; base < e1; base += 64) {
       const int e = base + lane;
-      const int r = e < e1 ? edge_fp32_then_exact<COUNT>(P, e, qx, qy, eta, px, py, c_fp64, c_exact) : 0;
-      if (ballot(r == 2)) return true;
+      const float4 g = nxt;
+      if (e + 64 < e1) nxt = P.e32[e + 64];
+      const int r = e < e1 ? edge_fp32_then_exact<COUNT>(P, e, g, qx, qy, eta, px, py, c_fp64,
+                                                         c_exact)
+                           : 0;
+      on |= ballot(r == 2) != 0;
       par ^= (uint32_t)__popcll(ballot(r == 1));
     }
   } else {
     for (int base = e0; base < e1; base += 64) {
       const int e = base + lane;
       const int r = e < e1 ? edge_fp64<COUNT>(P, e, px, py, c_fp64, c_exact) : 0;
-      if (ballot(r == 2)) return true;
+      on |= ballot(r == 2) != 0;
       par ^= (uint32_t)__popcll(ballot(r == 1));
     }
   }
-  return (par & 1u) != 0;
+  return on || (par & 1u) != 0;
+}
+
+// Merge a refined match into out[pt] (written by the probe: best true hit
+// or -1). As unsigned, -1 is the largest value, so atomicMin keeps the
+// lowest id; the id that loses becomes a pair.
+__device__ __forceinline__ void merge_min(const ProbeParams &P, int64_t pt, int32_t poly) {
+  const uint32_t prev = atomicMin((uint32_t *)(P.out + pt), (uint32_t)poly);
+  if (prev == 0xffffffffu || !P.pair_pt) return;
+  const int32_t other = (uint32_t)poly < prev ? (int32_t)prev : poly;
+  const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
+  if ((int64_t)k < P.cap) {
+    P.pair_pt[k] = pt;
+    P.pair_poly[k] = other;
+  }
 }
 
 // Lowest match goes to out[i]; every other match becomes a pair.
@@ -302,144 +362,260 @@ struct Hits {
   }
 };
 
-// Steps 5-6: face root, prefix check and descent. The first LDS_DEPTH node
-// levels are read from the LDS copy of nodes 1 .. n_lds_nodes (breadth-first
+// Steps 5-6: prefix check (Listing 4) and comparison-free descent
+// (Listing 5). Each node consumes 4 levels of the cell's quadtree path, its
+// key byte being (4 bits of i, 4 bits of j). The first LDS_DEPTH node levels
+// are read from the LDS copy of nodes 1 .. n_lds_nodes (breadth-first
 // numbering puts the top levels first).
 template <int LDS_DEPTH>
-__device__ __forceinline__ uint64_t descend(const ProbeParams &P, const uint64_t *s_nodes,
-                                            int root, int sh, uint64_t key, uint32_t &reads) {
-  uint64_t node = (uint64_t)root, e = 0;
+__device__ __forceinline__ uint64_t lookup(const ProbeParams &P, const uint32_t *s_nodes,
+                                           const FaceDev &F, uint32_t i, uint32_t j,
+                                           uint32_t &reads) {
+  const int root = F.root;
+  int sh = F.sh0;
+  if (root < 0 || (i >> sh) != F.pi || (j >> sh) != F.pj) return 0;
+  uint64_t node = (uint64_t)root, e;
 #pragma unroll
   for (int d = 0; d < LDS_DEPTH; d++) {
-    sh -= 8;
-    e = s_nodes[(node - 1) * 256 + ((key >> sh) & 255u)];
+    sh -= 4;
+    e = s_nodes[(node - 1) * 256 + node_slot(i, j, sh)];  // high 32 bits are zero
     reads++;
     if ((e & kTagMask) != kTagPtr || e == 0) return e;
     node = e >> 2;
   }
   for (;;) {
-    sh -= 8;
-    e = P.nodes[node * 256 + ((key >> sh) & 255u)];
+    sh -= 4;
+    e = P.nodes[node * 256 + node_slot(i, j, sh)];
     reads++;
     if ((e & kTagMask) != kTagPtr || e == 0) return e;
     node = e >> 2;
   }
 }
 
-// The probe. Each wavefront walks tiles of 64 consecutive points (one per
-// lane), so every lane of a wave executes the same number of iterations and
-// the cooperative refinement can use whole-wave ballots.
-template <bool EXACT, int LDS_DEPTH, bool COUNT>
-__global__ __launch_bounds__(kBlock) void probe_kernel(ProbeParams P) {
-  extern __shared__ uint64_t s_nodes[];
-  __shared__ uint16_t s_htab[1024];
-  __shared__ uint64_t s_prefix[6];
-  __shared__ int32_t s_root[6], s_shift[6];
-  __shared__ int32_t q_poly[kWaves][64];
-  __shared__ double q_lat[kWaves][64], q_lng[kWaves][64];
-  for (int k = threadIdx.x; k < 1024; k += kBlock) s_htab[k] = P.htab[k];
-  if (LDS_DEPTH > 0)
-    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kBlock) s_nodes[k] = P.nodes[256 + k];
-  if (threadIdx.x == 0) {
+constexpr int32_t kPending = -2;  // out[] marker: point left to fixup_kernel
+
+__device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == kTagPtr && e != 0; }
+
+// Steps 5-6 for NP points of a lane at once: the descents run side by side,
+// so each step issues up to NP independent node loads.
+template <int LDS_DEPTH, int NP>
+__device__ __forceinline__ void lookup_n(const ProbeParams &P, const uint32_t *s_nodes,
+                                         const FaceDev *s_face, const uint32_t (&face)[NP],
+                                         const uint32_t (&ci)[NP], const uint32_t (&cj)[NP],
+                                         const bool (&valid)[NP], uint64_t (&e)[NP],
+                                         uint32_t &reads) {
+  uint64_t node[NP];
+  int sh[NP];
+  bool act[NP];
 #pragma unroll
-    for (int f = 0; f < 6; f++) {
-      s_prefix[f] = P.prefix[f];
-      s_root[f] = P.root[f];
-      s_shift[f] = P.shift[f];
+  for (int p = 0; p < NP; p++) {
+    e[p] = 0;
+    act[p] = false;
+    sh[p] = 0;
+    node[p] = 0;
+    if (valid[p]) {
+      const FaceDev &F = s_face[face[p]];
+      sh[p] = F.sh0;
+      node[p] = (uint64_t)F.root;
+      act[p] = F.root >= 0 && (ci[p] >> sh[p]) == F.pi && (cj[p] >> sh[p]) == F.pj;
     }
   }
+#pragma unroll
+  for (int d = 0; d < LDS_DEPTH; d++) {
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+      if (act[p]) {
+        sh[p] -= 4;
+        e[p] = s_nodes[(node[p] - 1) * 256 + node_slot(ci[p], cj[p], sh[p])];
+        reads++;
+        act[p] = is_child(e[p]);
+        node[p] = e[p] >> 2;
+      }
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < NP; p++) any |= act[p];
+    if (!any) break;
+    uint64_t x[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+      if (act[p]) {
+        sh[p] -= 4;
+        x[p] = P.nodes[node[p] * 256 + node_slot(ci[p], cj[p], sh[p])];
+      }
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+      if (act[p]) {
+        e[p] = x[p];
+        reads++;
+        act[p] = is_child(x[p]);
+        node[p] = x[p] >> 2;
+      }
+  }
+}
+
+// The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
+// per lane, at lane and lane + 64, ...), so all lanes of a wave run the
+// same number of iterations; the next tile's points are loaded while the
+// current tile is processed.
+//
+// Exact mode: a lane's candidate (point, polygon) pairs are appended to the
+// stream's candidate queue all at once (one atomic per wave and segment) and
+// refined by refine_kernel. Points whose candidates do not fit, or with more
+// than three candidates, are marked pending and resolved by fixup_kernel;
+// their true hits are left to that kernel too.
+template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP>
+__global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
+  extern __shared__ uint32_t s_nodes[];
+  __shared__ FaceDev s_face[6];
+  if (LDS_DEPTH > 0)
+    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
+  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
   uint32_t c_pts = 0, c_inv = 0, c_false = 0, c_true = 0, c_candpts = 0, c_cand = 0,
-           c_edges = 0, c_fp64 = 0, c_exact = 0, c_reads = 0, c_lut = 0;
-  const int64_t ntiles = (P.n + 63) >> 6;
-  const int64_t nwaves = (int64_t)gridDim.x * kWaves;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < ntiles; tile += nwaves) {
-    const int64_t i = tile * 64 + lane;
-    const bool live = i < P.n;
-    double lat = 0.0, lng = 0.0;
-    if (live) {
-      const double2 pt = P.pts[i];
-      lat = pt.x;
-      lng = pt.y;
+           c_reads = 0, c_lut = 0;
+  constexpr int TILE = 64 * NP;
+  const int64_t ntiles = (P.n + TILE - 1) / TILE;
+  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
+  int64_t tile = (int64_t)blockIdx.x * kProbeWaves + wid;
+  double2 nxt[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int64_t k = tile * TILE + p * 64 + lane;
+    nxt[p] = (tile < ntiles && k < P.n) ? P.pts[k] : make_double2(0.0, 0.0);
+  }
+  for (; tile < ntiles; tile += nwaves) {
+    int64_t i[NP];
+    bool live[NP], valid[NP];
+    double lat[NP], lng[NP];
+    uint32_t face[NP], ci[NP], cj[NP];
+    uint64_t e[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      i[p] = tile * TILE + p * 64 + lane;
+      live[p] = i[p] < P.n;
+      lat[p] = nxt[p].x;
+      lng[p] = nxt[p].y;
+      const int64_t k = (tile + nwaves) * TILE + p * 64 + lane;
+      if (tile + nwaves < ntiles && k < P.n) nxt[p] = P.pts[k];
     }
-    uint32_t face = 0;
-    uint64_t key = 0, e = 0;
-    const bool valid = live && dev_leaf(lat, lng, s_htab, face, key);
-    if (valid) {
-      const int sh = s_shift[face], root = s_root[face];
-      if (root >= 0 && (key >> sh) == s_prefix[face])
-        e = descend<LDS_DEPTH>(P, s_nodes, root, sh, key, c_reads);
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      face[p] = ci[p] = cj[p] = 0;
+      valid[p] = live[p] && project(lat[p], lng[p], face[p], ci[p], cj[p]);
     }
-    if (COUNT) {
-      c_pts += live;
-      c_inv += live && !valid;
-      c_false += valid && e == 0;
-    }
-    // stage 3: decode the entry; true hits (approx: all references) out
-    Hits hits;
-    const uint32_t tag = (uint32_t)(e & kTagMask);
-    uint32_t cand0 = 0, cand1 = 0, lut_cand = 0;
-    int ncand = 0;
-    bool from_lut = false;
-    if (e != 0 && tag != kTagLut) {
-      const uint32_t r0 = (uint32_t)((e >> 2) & 0x7fffffffu);
-      if (!EXACT || (r0 & 1u)) hits.add(P, i, (int32_t)(r0 >> 1));
-      else cand0 = r0 >> 1, ncand = 1;
-      if (tag == kTagTwo) {
-        const uint32_t r1 = (uint32_t)((e >> 33) & 0x7fffffffu);
-        if (!EXACT || (r1 & 1u)) hits.add(P, i, (int32_t)(r1 >> 1));
-        else if (ncand == 0) cand0 = r1 >> 1, ncand = 1;
-        else cand1 = r1 >> 1, ncand = 2;
+    lookup_n<LDS_DEPTH, NP>(P, s_nodes, s_face, face, ci, cj, valid, e, c_reads);
+    // stage 3: the entries' references (Section III-E: one payload, two
+    // payloads or a lookup-table offset)
+    uint32_t tag[NP], r0[NP], r1[NP], off[NP], nt[NP], nc[NP];
+    int n_inl[NP];
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      if (COUNT) {
+        c_pts += live[p];
+        c_inv += live[p] && !valid[p];
+        c_false += valid[p] && e[p] == 0;
       }
-    } else if (tag == kTagLut) {
-      const uint32_t off = (uint32_t)(e >> 2);
-      const uint32_t nt = P.lut[off];
-      for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
-      const uint32_t nc = P.lut[off + 1 + nt];
-      if (!EXACT) {
-        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
+      tag[p] = (uint32_t)(e[p] & kTagMask);
+      r0[p] = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
+      r1[p] = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
+      n_inl[p] = e[p] == 0 || tag[p] == kTagLut ? 0 : (tag[p] == kTagTwo ? 2 : 1);
+      off[p] = nt[p] = nc[p] = 0;
+      if (tag[p] == kTagLut) {
+        off[p] = (uint32_t)(e[p] >> 2);
+        nt[p] = P.lut[off[p]];
+        nc[p] = P.lut[off[p] + 1 + nt[p]];
+        if (COUNT) c_lut++;
+      }
+    }
+    if (!EXACT) {
+      // approximate mode: every reference is reported
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        Hits hits;
+        if (n_inl[p] > 0) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
+        if (n_inl[p] > 1) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
+        for (uint32_t r = 0; r < nt[p]; r++) hits.add(P, i[p], (int32_t)P.lut[off[p] + 1 + r]);
+        for (uint32_t r = 0; r < nc[p]; r++)
+          hits.add(P, i[p], (int32_t)P.lut[off[p] + 2 + nt[p] + r]);
+        if (COUNT) c_true += e[p] != 0;
+        if (live[p]) P.out[i[p]] = hits.best;
+      }
+      continue;
+    }
+    bool c0[NP], c1[NP], pending[NP];
+    uint32_t ncand[NP], nq = 0;
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      c0[p] = n_inl[p] > 0 && !(r0[p] & 1u);
+      c1[p] = n_inl[p] > 1 && !(r1[p] & 1u);
+      ncand[p] = tag[p] == kTagLut ? nc[p] : (uint32_t)c0[p] + (uint32_t)c1[p];
+      pending[p] = ncand[p] > 3;
+      nq += pending[p] ? 0u : ncand[p];
+    }
+    // reserve the lane's queue slots (nq <= 3 NP < 8: three ballots give the
+    // wave's exclusive prefix sum)
+    const uint64_t m1 = ballot(nq & 1u), m2 = ballot(nq & 2u), m4 = ballot(nq & 4u);
+    if (m1 | m2 | m4) {
+      const int seg = blockIdx.x & (kSegs - 1);
+      uint32_t base = 0;
+      if (lane == 0)
+        base = atomicAdd(P.q_ctl + seg,
+                         (uint32_t)(__popcll(m1) + 2 * __popcll(m2) + 4 * __popcll(m4)));
+      base = __shfl(base, 0);
+      const int64_t at = (int64_t)base + __popcll(m1 & below) + 2 * __popcll(m2 & below) +
+                         4 * __popcll(m4 & below);
+      if (nq > 0) {
+        // slots below the segment's capacity are always written (refine
+        // reads up to the capacity); a lane that does not fit writes -1
+        const bool fits = at + nq <= P.q_seg_cap;
+        int64_t *qp = P.q_pt + seg * P.q_seg_cap;
+        int32_t *qy = P.q_poly + seg * P.q_seg_cap;
+        uint32_t k = 0;
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+          if (pending[p] || ncand[p] == 0) continue;
+          for (uint32_t r = 0; r < (tag[p] == kTagLut ? nc[p] : 2u); r++) {
+            uint32_t poly;
+            if (tag[p] == kTagLut) {
+              poly = P.lut[off[p] + 2 + nt[p] + r];
+            } else {
+              if (!(r == 0 ? c0[p] : c1[p])) continue;
+              poly = (r == 0 ? r0[p] : r1[p]) >> 1;
+            }
+            if (at + k < P.q_seg_cap) {
+              qp[at + k] = fits ? i[p] : -1;
+              qy[at + k] = (int32_t)poly;
+            }
+            k++;
+          }
+          pending[p] = !fits;
+        }
+      }
+    }
+    bool any_pending = false;
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      if (pending[p]) {
+        if (live[p]) P.out[i[p]] = kPending;
+        any_pending |= live[p];
       } else {
-        ncand = (int)nc;
-        lut_cand = off + 2 + nt;
-        from_lut = true;
+        Hits hits;
+        if (n_inl[p] > 0 && (r0[p] & 1u)) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
+        if (n_inl[p] > 1 && (r1[p] & 1u)) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
+        for (uint32_t r = 0; r < nt[p]; r++) hits.add(P, i[p], (int32_t)P.lut[off[p] + 1 + r]);
+        if (live[p]) P.out[i[p]] = hits.best;
       }
-      if (COUNT) c_lut++;
-    }
-    if (COUNT) {
-      c_true += e != 0 && ncand == 0;
-      c_candpts += ncand > 0;
-      c_cand += ncand;
-    }
-    if (EXACT) {
-      // candidates, one round per candidate rank: compact the wave's
-      // candidates into its LDS queue, refine each with the whole wave
-      for (int r = 0;; r++) {
-        const bool has = r < ncand;
-        const uint64_t mask = ballot(has);
-        if (mask == 0) break;
-        const int cnt = __popcll(mask);
-        const int slot = lane_rank(mask);
-        int32_t my_poly = 0;
-        if (has) {
-          my_poly = (int32_t)(from_lut ? P.lut[lut_cand + r] : (r == 0 ? cand0 : cand1));
-          q_poly[wid][slot] = my_poly;
-          q_lat[wid][slot] = lat;
-          q_lng[wid][slot] = lng;
-        }
-        wave_sync();
-        uint64_t covered = 0;
-        for (int q = 0; q < cnt; q++) {
-          const int poly = __builtin_amdgcn_readfirstlane(q_poly[wid][q]);
-          if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
-          if (wave_covers<COUNT>(P, poly, q_lat[wid][q], q_lng[wid][q], lane, c_fp64, c_exact))
-            covered |= 1ull << q;
-        }
-        wave_sync();
-        if (has && ((covered >> slot) & 1ull)) hits.add(P, i, my_poly);
+      if (COUNT) {
+        c_true += e[p] != 0 && ncand[p] == 0;
+        c_candpts += ncand[p] > 0;
+        c_cand += ncand[p];
       }
     }
-    if (live) P.out[i] = hits.best;
+    if (ballot(any_pending) && lane == 0) P.q_ctl[kSegs + 1] = 1u;
   }
   if (COUNT) {
     unsigned long long *C = P.counters;
@@ -449,11 +625,142 @@ __global__ __launch_bounds__(kBlock) void probe_kernel(ProbeParams P) {
     atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c_true);
     atomicAdd(C + ACT_CNT_CAND_POINTS, (unsigned long long)c_candpts);
     atomicAdd(C + ACT_CNT_CANDIDATES, (unsigned long long)c_cand);
-    atomicAdd(C + ACT_CNT_EDGES, (unsigned long long)c_edges);
-    atomicAdd(C + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
-    atomicAdd(C + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
     atomicAdd(C + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
     atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c_lut);
+  }
+}
+
+// Points the probe marked pending (candidate queue full, or more than three
+// candidates): resolved here one point at a time per wavefront, candidates
+// refined by the whole wave. Returns at once when the probe marked none.
+template <int LDS_DEPTH, bool COUNT>
+__global__ __launch_bounds__(kBlock) void fixup_kernel(ProbeParams P) {
+  if (*(volatile uint32_t *)(P.q_ctl + kSegs + 1) == 0u) return;
+  extern __shared__ uint32_t s_nodes[];
+  __shared__ FaceDev s_face[6];
+  __shared__ uint32_t s_last;
+  if (LDS_DEPTH > 0)
+    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kBlock) s_nodes[k] = P.top32[k];
+  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t c_reads = 0, c_fp64 = 0, c_exact = 0, c_edges = 0;
+  const int64_t ntiles = (P.n + 63) >> 6;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < ntiles;
+       tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t i = tile * 64 + lane;
+    const bool pend = i < P.n && P.out[i] == kPending;
+    uint64_t mask = ballot(pend);
+    uint64_t e = 0;
+    double lat = 0.0, lng = 0.0;
+    if (pend) {
+      const double2 pt = P.pts[i];
+      lat = pt.x;
+      lng = pt.y;
+      uint32_t face, ci, cj;
+      if (project(lat, lng, face, ci, cj))
+        e = lookup<LDS_DEPTH>(P, s_nodes, s_face[face], ci, cj, c_reads);
+    }
+    while (mask) {
+      const int src = __ffsll((long long)mask) - 1;
+      mask &= mask - 1;
+      const uint64_t ee = __shfl(e, src);
+      const double plat = __shfl(lat, src), plng = __shfl(lng, src);
+      const int64_t pi = tile * 64 + src;
+      Hits hits;
+      const uint32_t tag = (uint32_t)(ee & kTagMask);
+      if (tag == kTagOne || tag == kTagTwo) {
+        for (int r = 0; r < (tag == kTagTwo ? 2 : 1); r++) {
+          const uint32_t v = (uint32_t)((ee >> (r == 0 ? 2 : 33)) & 0x7fffffffu);
+          if (COUNT && lane == 0 && !(v & 1u)) c_edges += (uint32_t)(P.eoff[(v >> 1) + 1] - P.eoff[v >> 1]);
+          if ((v & 1u) || wave_covers<COUNT>(P, (int)(v >> 1), plat, plng, lane, c_fp64, c_exact))
+            if (lane == 0) hits.add(P, pi, (int32_t)(v >> 1));
+        }
+      } else if (tag == kTagLut) {
+        const uint32_t off = (uint32_t)(ee >> 2);
+        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
+        for (uint32_t r = 0; r < nt; r++)
+          if (lane == 0) hits.add(P, pi, (int32_t)P.lut[off + 1 + r]);
+        for (uint32_t r = 0; r < nc; r++) {
+          const int poly = (int)P.lut[off + 2 + nt + r];
+          if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+          if (wave_covers<COUNT>(P, poly, plat, plng, lane, c_fp64, c_exact) && lane == 0)
+            hits.add(P, pi, poly);
+        }
+      }
+      if (lane == 0) P.out[pi] = hits.best;
+    }
+  }
+  if (COUNT) {
+    atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
+    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
+    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(P.q_ctl + kSegs + 2, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    P.q_ctl[kSegs + 1] = 0u;
+    P.q_ctl[kSegs + 2] = 0u;
+    __threadfence();
+  }
+}
+
+// Refinement of the queued candidates: one wavefront per (point, polygon)
+// pair, lanes over the polygon's edges. The last block to finish resets the
+// queue for the stream's next join (no memset: safe under graph capture).
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void refine_kernel(ProbeParams P) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t wave = (int64_t)blockIdx.x * kWaves + wid;
+  const int seg = (int)(wave % kSegs);
+  const int64_t per_seg = (int64_t)gridDim.x * kWaves / kSegs;  // waves per segment
+  const int64_t count = min((int64_t)(*(volatile uint32_t *)(P.q_ctl + seg)), P.q_seg_cap);
+  const int64_t* q_pt = P.q_pt + seg * P.q_seg_cap;
+  const int32_t* q_poly = P.q_poly + seg * P.q_seg_cap;
+  uint32_t c_edges = 0, c_fp64 = 0, c_exact = 0;
+  // each wave takes 64 consecutive entries of its segment at a time: lane l
+  // loads entry l and its point (coalesced), then the wave refines the 64
+  // pairs one after the other, reading each from lane registers
+  for (int64_t q0 = (wave / kSegs) * 64; q0 < count; q0 += per_seg * 64) {
+    const int64_t q = q0 + lane;
+    int64_t my_pt = 0;
+    int32_t my_poly = 0;
+    double2 my_p = make_double2(0.0, 0.0);
+    if (q < count) {
+      my_pt = q_pt[q];
+      my_poly = q_poly[q];
+      if (my_pt >= 0) my_p = P.pts[my_pt];
+    }
+    const int cnt = (int)min<int64_t>(64, count - q0);
+    for (int k = 0; k < cnt; k++) {
+      if (__shfl(my_pt, k) < 0) continue;  // slot of a point left pending
+      const int32_t poly = __shfl(my_poly, k);
+      const double lat = __shfl(my_p.x, k), lng = __shfl(my_p.y, k);
+      if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+      if (wave_covers<COUNT>(P, poly, lat, lng, lane, c_fp64, c_exact) && lane == k)
+        merge_min(P, my_pt, poly);
+    }
+  }
+  if (COUNT) {
+    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
+    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
+    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
+  }
+  __shared__ uint32_t s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(P.q_ctl + kSegs, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {  // every other block has finished reading the counters
+    for (int k = threadIdx.x; k <= kSegs; k += kBlock) P.q_ctl[k] = 0;
+    __threadfence();
   }
 }
 
@@ -465,22 +772,36 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double2 p = pts[i];
-    uint32_t face;
-    uint64_t key;
-    ids[i] = dev_leaf(p.x, p.y, s_htab, face, key) ? (((uint64_t)face << 61) | (key << 1) | 1ull) : 0ull;
+    uint32_t face, ci, cj;
+    ids[i] = project(p.x, p.y, face, ci, cj)
+                 ? (((uint64_t)face << 61) | (hilbert60(s_htab, ci, cj) << 1) | 1ull)
+                 : 0ull;
   }
 }
 
 using ProbeFn = void (*)(ProbeParams);
-static ProbeFn probe_fn(bool exact, int lds_depth, bool count) {
-  static const ProbeFn tab[2][3][2] = {
-      {{probe_kernel<false, 0, false>, probe_kernel<false, 0, true>},
-       {probe_kernel<false, 1, false>, probe_kernel<false, 1, true>},
-       {probe_kernel<false, 2, false>, probe_kernel<false, 2, true>}},
-      {{probe_kernel<true, 0, false>, probe_kernel<true, 0, true>},
-       {probe_kernel<true, 1, false>, probe_kernel<true, 1, true>},
-       {probe_kernel<true, 2, false>, probe_kernel<true, 2, true>}}};
-  return tab[exact][lds_depth][count];
+constexpr int kFixupGrid = 256;
+static ProbeFn fixup_fn(int lds_depth, bool count) {
+  static const ProbeFn tab[3][2] = {{fixup_kernel<0, false>, fixup_kernel<0, true>},
+                                    {fixup_kernel<1, false>, fixup_kernel<1, true>},
+                                    {fixup_kernel<2, false>, fixup_kernel<2, true>}};
+  return tab[lds_depth][count];
+}
+template <bool EXACT, int LDS, bool COUNT>
+static ProbeFn probe_np(int np) {
+  return np == 1 ? probe_kernel<EXACT, LDS, COUNT, 1> : probe_kernel<EXACT, LDS, COUNT, 2>;
+}
+
+static ProbeFn probe_fn(bool exact, int lds_depth, bool count, int np) {
+  using F = ProbeFn (*)(int);
+  static const F tab[2][3][2] = {
+      {{probe_np<false, 0, false>, probe_np<false, 0, true>},
+       {probe_np<false, 1, false>, probe_np<false, 1, true>},
+       {probe_np<false, 2, false>, probe_np<false, 2, true>}},
+      {{probe_np<true, 0, false>, probe_np<true, 0, true>},
+       {probe_np<true, 1, false>, probe_np<true, 1, true>},
+       {probe_np<true, 2, false>, probe_np<true, 2, true>}}};
+  return tab[exact][lds_depth][count](np);
 }
 
 // ------------------------------------------------------------------ host
@@ -503,7 +824,7 @@ struct DeviceGuard {
 };
 
 static void free_image(DevImage &d) {
-  void *ptrs[] = {d.nodes, d.lut, d.eoff, d.origin, d.pm, d.e32, d.e64, d.htab};
+  void *ptrs[] = {d.nodes, d.lut, d.eoff, d.origin, d.pm, d.e32, d.e64, d.htab, d.faces, d.top32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -525,6 +846,44 @@ static int upload(T *&dst, const void *src, size_t bytes, size_t &total) {
   return ACT_OK;
 }
 
+static void free_workspace(Workspace &w) {
+  if (w.q_pt) (void)hipFree(w.q_pt);
+  if (w.q_poly) (void)hipFree(w.q_poly);
+  if (w.q_ctl) (void)hipFree(w.q_ctl);
+  w = Workspace();
+}
+
+// The stream's workspace with at least `cap` queue entries; allocated (and
+// its control words zeroed) on first use. Call with the index's device
+// current.
+static int get_workspace(const act_index *x, void *stream, int64_t cap, Workspace *&out) {
+  std::lock_guard<std::mutex> lk(x->ws_mu);
+  Workspace &w = x->ws[stream];
+  if (w.cap < cap) {
+    free_workspace(w);
+    if (hipMalloc((void **)&w.q_pt, sizeof(int64_t) * cap) != hipSuccess ||
+        hipMalloc((void **)&w.q_poly, sizeof(int32_t) * cap) != hipSuccess ||
+        hipMalloc((void **)&w.q_ctl, 4 * (kSegs + 4)) != hipSuccess) {
+      free_workspace(w);
+      return fail(ACT_E_OOM, "cannot allocate the candidate queue");
+    }
+    if (hipMemset(w.q_ctl, 0, 4 * (kSegs + 4)) != hipSuccess) {
+      free_workspace(w);
+      return fail(ACT_E_HIP, "cannot clear the candidate queue");
+    }
+    w.cap = cap;
+  }
+  out = &w;
+  return ACT_OK;
+}
+
+static void face_table(const HostIndex &h, FaceDev f[6]) {
+  for (int k = 0; k < 6; k++) {
+    const FaceRoot &F = h.faces[k];
+    f[k] = FaceDev{F.root, kMaxLevel - F.plevel, F.pi, F.pj};
+  }
+}
+
 static int upload_image(act_index *x) {
   const HostIndex &h = x->host;
   DevImage &d = x->dev;
@@ -539,6 +898,14 @@ static int upload_image(act_index *x) {
   if ((rc = upload(d.e32, h.edges32.data(), h.edges32.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.e64, h.edges64.data(), h.edges64.size() * 8, d.bytes))) return rc;
   if ((rc = upload(d.htab, htab, sizeof htab, d.bytes))) return rc;
+  FaceDev f[6];
+  face_table(h, f);
+  if ((rc = upload(d.faces, f, sizeof f, d.bytes))) return rc;
+  // the top two node levels as 32-bit entries (their high halves are zero)
+  const size_t n_top = (size_t)(h.n_d0 + h.n_d1) * 256;
+  std::vector<uint32_t> top(n_top);
+  for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
+  if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -561,12 +928,12 @@ static int grid_for(int64_t n, int block) {
   return (int)std::min<int64_t>(std::max<int64_t>(blocks, 1), 8192);
 }
 
-constexpr int kLdsTrieBudget = 48 * 1024;
+constexpr int kLdsTrieBudget = 64 * 1024;  // bytes of 32-bit top-level entries per block
 
 // Node count staged in LDS for `depth` levels (0 if it does not fit).
 static int lds_nodes_for(const HostIndex &h, int depth) {
   int n = depth >= 2 ? h.n_d0 + h.n_d1 : (depth == 1 ? h.n_d0 : 0);
-  return n * 2048 <= kLdsTrieBudget ? n : -1;
+  return n * 1024 <= kLdsTrieBudget ? n : -1;
 }
 
 static int default_lds_depth(const HostIndex &h) {
@@ -586,8 +953,11 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     return fail(ACT_E_ARG, "pair output needs point, poly, counter arrays and capacity >= 0");
   if (a->refine != ACT_REFINE_FP32_FILTER && a->refine != ACT_REFINE_FP64)
     return fail(ACT_E_ARG, "unknown refine mode");
-  if (a->block != 0 && a->block != kBlock) return fail(ACT_E_ARG, "block must be 0 or 256");
+  if (a->block != 0 && a->block != kProbeBlock) return fail(ACT_E_ARG, "block must be 0 or 1024");
   if (a->grid < 0 || a->grid > 65536) return fail(ACT_E_ARG, "grid must be 0 .. 65536");
+  if (a->queue_limit < 0) return fail(ACT_E_ARG, "queue_limit < 0");
+  if (a->points_per_lane < 0 || a->points_per_lane > 2)
+    return fail(ACT_E_ARG, "points_per_lane must be 0, 1 or 2");
   const HostIndex &h = x->host;
   int depth = a->lds_levels < 0 ? default_lds_depth(h) : a->lds_levels;
   if (depth > 2) return fail(ACT_E_ARG, "lds_levels must be -1, 0, 1 or 2");
@@ -614,22 +984,43 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.e32 = x->dev.e32;
   P.e64 = x->dev.e64;
   P.htab = x->dev.htab;
-  for (int f = 0; f < 6; f++) {
-    const FaceRoot &F = h.faces[f];
-    P.root[f] = F.root;
-    P.shift[f] = 60 - 2 * F.plevel;
-    P.prefix[f] = F.prefix;
-  }
+  P.faces = x->dev.faces;
+  P.top32 = x->dev.top32;
   P.n_lds_nodes = n_lds;
   P.refine = a->refine;
-  int64_t tiles_blocks = (a->n + kBlock - 1) / kBlock;
-  int grid = a->grid > 0 ? a->grid : 2048;
+  const int np = a->points_per_lane > 0 ? a->points_per_lane : 2;
+  int64_t tiles_blocks = (a->n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
+  int grid = a->grid > 0 ? a->grid : 1024;
   grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, tiles_blocks));
   DeviceGuard g(x->device);
-  ProbeFn fn = probe_fn(h.mode == ACT_EXACT, depth, a->d_counters != nullptr);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlock), (size_t)n_lds * 2048, (hipStream_t)stream, P);
+  const bool exact = h.mode == ACT_EXACT;
+  const bool count = a->d_counters != nullptr;
+  if (exact) {
+    Workspace *w = nullptr;
+    rc = get_workspace(x, stream, kDefaultQueue, w);
+    if (rc) return rc;
+    P.q_pt = w->q_pt;
+    P.q_poly = w->q_poly;
+    P.q_ctl = w->q_ctl;
+    const int64_t cap = a->queue_limit > 0 ? std::min(a->queue_limit, w->cap) : w->cap;
+    P.q_seg_cap = cap / kSegs;
+  }
+  hipLaunchKernelGGL(probe_fn(exact, depth, count, np), dim3(grid), dim3(kProbeBlock),
+                     (size_t)n_lds * 1024, (hipStream_t)stream, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
+  if (exact) {
+    hipLaunchKernelGGL(count ? refine_kernel<true> : refine_kernel<false>, dim3(kRefineGrid),
+                       dim3(kBlock), 0, (hipStream_t)stream, P);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ACT_E_HIP, std::string("refine launch: ") + hipGetErrorString(e));
+    hipLaunchKernelGGL(fixup_fn(depth, count), dim3(kFixupGrid), dim3(kBlock),
+                       (size_t)n_lds * 1024, (hipStream_t)stream, P);
+    e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ACT_E_HIP, std::string("fixup launch: ") + hipGetErrorString(e));
+  }
   return ACT_OK;
 }
 
@@ -704,8 +1095,20 @@ void act_free(act_index *x) {
   if (x->device >= 0) {
     DeviceGuard g(x->device);
     free_image(x->dev);
+    for (auto &kv : x->ws) free_workspace(kv.second);
   }
   delete x;
+}
+
+int act_workspace_reserve(const act_index *x, void *stream, int64_t capacity) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (capacity < 0 || capacity > (1ll << 31)) return fail(ACT_E_ARG, "capacity out of range");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  int rc = check_stream_device(x, stream);
+  if (rc) return rc;
+  DeviceGuard g(x->device);
+  Workspace *w = nullptr;
+  return get_workspace(x, stream, std::max<int64_t>(capacity, kDefaultQueue), w);
 }
 
 int act_join_ex(const act_index *x, const act_join_args *args, void *stream) {
@@ -795,9 +1198,10 @@ int act_index_stats(const act_index *x, act_stats *o) {
   return ACT_OK;
 }
 
-int act_lookup_host(const act_index *x, const uint64_t *ids, int64_t n, uint64_t *entries) {
-  if (!x || n < 0 || (n > 0 && (!ids || !entries))) return fail(ACT_E_ARG, "bad argument");
-  for (int64_t k = 0; k < n; k++) entries[k] = host_lookup(x->host, ids[k]);
+int act_lookup_host(const act_index *x, const int32_t *face, const uint32_t *i,
+                    const uint32_t *j, int64_t n, uint64_t *entries) {
+  if (!x || n < 0 || (n > 0 && (!face || !i || !j || !entries))) return fail(ACT_E_ARG, "bad argument");
+  for (int64_t k = 0; k < n; k++) entries[k] = host_lookup(x->host, face[k], i[k], j[k]);
   return ACT_OK;
 }
 

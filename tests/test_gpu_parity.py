@@ -28,6 +28,11 @@ def act():
 _IDX = {}
 
 
+def act_mod():
+    import paper_1802_09488_amd
+    return paper_1802_09488_amd
+
+
 def index(act, w, mode, prec=0.0):
     key = (w, mode, prec)
     if key not in _IDX:
@@ -39,7 +44,12 @@ def index(act, w, mode, prec=0.0):
 
 def gpu_join(idx, pts, **kw):
     t = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
-    out, pairs, ctr = idx.join_ex(t, capacity=max(4096, len(pts) // 4), **kw)
+    try:
+        out, pairs, ctr = idx.join_ex(t, capacity=max(4096, len(pts) // 4), **kw)
+    except act_mod().ActError as e:
+        if e.code != -5:
+            raise
+        out, pairs, ctr = idx.join_ex(t, capacity=e.needed, **kw)
     torch.cuda.synchronize()
     pr = pairs.cpu().numpy() if pairs is not None else np.zeros((0, 2), np.int64)
     order = np.lexsort((pr[:, 1], pr[:, 0])) if len(pr) else np.zeros(0, np.int64)
@@ -146,9 +156,11 @@ def test_launch_shapes_and_repeats_identical(act, mode, prec):
     assert 0 in fits and 1 in fits
     for grid in (1, 7, 256, 0):
         for lds in fits:
-            for _ in range(2):
-                o = gpu_join(idx, pts, grid=grid, lds_levels=lds)
-                assert np.array_equal(o[0], base[0]) and np.array_equal(o[1], base[1]), (grid, lds)
+            for npl in (1, 2):
+                for _ in range(2):
+                    o = gpu_join(idx, pts, grid=grid, lds_levels=lds, points_per_lane=npl)
+                    assert np.array_equal(o[0], base[0]) and np.array_equal(o[1], base[1]), \
+                        (grid, lds, npl)
 
 
 def test_c1_approx_guarantee(act):
@@ -216,3 +228,54 @@ def test_cell_ids_match_reference(act):
         assert np.all(np.abs(i1 - i2)[same] <= 1) and np.all(np.abs(j1 - j2)[same] <= 1)
     bad = torch.tensor([[np.nan, 0.0], [0.0, 200.0]], dtype=torch.float64, device="cuda")
     assert act.cell_ids(bad).cpu().tolist() == [0, 0]
+
+
+def overlapping_polygons(seed=12, n=9):
+    """n star-shaped polygons around nearly the same centre, with holes in
+    some: cells near their crowded boundaries reference many polygons, many
+    of them as candidates (lookup-table lists longer than three)."""
+    rng = np.random.default_rng(seed)
+    polys = []
+    for k in range(n):
+        c = np.array([40.70, -73.95]) + rng.normal(0, 0.002, 2)
+        m = int(rng.integers(8, 40))
+        ang = np.sort(rng.uniform(0, 2 * np.pi, m))
+        rad = 0.01 * rng.uniform(0.7, 1.3, m)
+        outer = np.stack([c[0] + rad * np.sin(ang), c[1] + rad * np.cos(ang) / 0.76], 1)
+        rings = [outer]
+        if k % 3 == 0:
+            hang = np.sort(rng.uniform(0, 2 * np.pi, 12))
+            hrad = 0.002 * rng.uniform(0.8, 1.2, 12)
+            rings.append(np.stack([c[0] + hrad * np.sin(hang), c[1] + hrad * np.cos(hang) / 0.76], 1))
+        polys.append(rings)
+    return synth.Polygons.from_rings(polys)
+
+
+@pytest.mark.parametrize("queue_limit", [0, 256, 4096])
+def test_overlapping_polygons_long_candidate_lists(act, queue_limit):
+    """Exact parity where cells hold up to n references (long LUT lists go to
+    the per-point pass) and with a tiny candidate queue (overflow goes to
+    the per-point pass as well)."""
+    P = overlapping_polygons()
+    idx = act.build(P, "exact", max_level=16)
+    st = idx.stats()
+    assert st["max_refs"] >= 5
+    rng = np.random.default_rng(13)
+    pts = np.concatenate([
+        np.stack([rng.uniform(40.68, 40.72, 200000), rng.uniform(-73.98, -73.92, 200000)], 1),
+        P.verts])
+    out, pairs, ctr = gpu_join(idx, pts, counters=True, queue_limit=queue_limit)
+    ref = assert_exact(P, pts, out, pairs, "overlap q=%d" % queue_limit)
+    assert ref.cnt.max() >= 5
+    # repeated joins on the same stream reuse (and reset) the queue correctly
+    out2, pairs2, _ = gpu_join(idx, pts, queue_limit=queue_limit)
+    assert np.array_equal(out2, out) and np.array_equal(pairs2, pairs)
+
+
+def test_overlapping_polygons_approx(act):
+    P = overlapping_polygons(seed=14)
+    idx = act.build(P, "approx", 2.0)
+    rng = np.random.default_rng(15)
+    pts = np.stack([rng.uniform(40.68, 40.72, 100000), rng.uniform(-73.98, -73.92, 100000)], 1)
+    out, pairs, _ = gpu_join(idx, pts)
+    assert_approx(P, pts, out, pairs, 2.0, "overlap approx")

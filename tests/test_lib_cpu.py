@@ -62,8 +62,9 @@ def _truth(res):
 
 
 def _structural_check(act, P, idx, pts, precision_m=None):
-    ids = C.cell_ids(pts[:, 0], pts[:, 1])
-    ent = idx.lookup_host(ids)
+    face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    ent = idx.lookup_host(face, i, j)
     lut = idx.lut_host()
     res = oracle.join(P, pts)
     truth = _truth(res)
@@ -215,5 +216,4 @@ def test_empty_polygon_set(act):
     idx = act.build(P, "exact", device=-1)
     st = idx.stats()
     assert st["n_cells"] == 0 and st["n_faces"] == 0
-    ids = C.cell_ids(np.array([40.7]), np.array([-74.0]))
-    assert idx.lookup_host(ids).tolist() == [0]
+    assert idx.lookup_host([4], [5], [7]).tolist() == [0]
