@@ -55,12 +55,20 @@ enum {
 
 enum { ACT_EXACT = 0, ACT_APPROX = 1 };
 
-/* Refinement arithmetic for candidate hits in exact mode. */
+/* Refinement of candidate hits in exact mode. All modes give identical,
+ * exact results; they differ in cost. */
 enum {
-  ACT_REFINE_FP32_FILTER = 0, /* fp32 crossing test with a proven error bound,
-                                 fp64 re-test of undecided edges, exact
-                                 expansion arithmetic as the last resort      */
-  ACT_REFINE_FP64 = 1         /* every edge test in fp64 (+ exact fallback)  */
+  ACT_REFINE_AUTO = 0,        /* ACT_REFINE_LOCAL                              */
+  ACT_REFINE_LOCAL = 1,       /* cell-local test: only the polygon edges that
+                                 meet the candidate cell's box are tested
+                                 (exactly); the crossings of the remaining
+                                 edges come from parity breakpoints the
+                                 builder stored for the cell                  */
+  ACT_REFINE_FP32_FILTER = 2, /* the crossing test over all of the polygon's
+                                 edges (Section II ray tracing): fp32 with a
+                                 proven error bound, fp64 re-test of undecided
+                                 edges, exact expansion arithmetic last       */
+  ACT_REFINE_FP64 = 3         /* all edges, every test in fp64 (+ exact)      */
 };
 
 typedef struct act_index act_index;
@@ -229,6 +237,7 @@ typedef struct {
   int32_t reserved;
   double precision_m;
   double build_seconds;
+  int64_t local_words;      /* cell-local refinement records (32-bit words)   */
 } act_stats;
 
 int act_index_stats(const act_index *idx, act_stats *out);
@@ -240,6 +249,16 @@ int act_index_stats(const act_index *idx, act_stats *out);
  */
 int act_lookup_host(const act_index *idx, const int32_t *face, const uint32_t *i,
                     const uint32_t *j, int64_t n, uint64_t *entries);
+
+/*
+ * act_refine_local_host -- evaluate, on the host, the cell-local refinement
+ * record of candidate polygon `poly` in the cell of leaf (face, i, j) for
+ * the point (lat, lng) (tests): *covered = 1 if the polygon covers the
+ * point, 0 otherwise. ACT_E_ARG if `poly` is not a candidate of that cell
+ * or the index has no records (approximate mode).
+ */
+int act_refine_local_host(const act_index *idx, int32_t face, uint32_t i, uint32_t j,
+                          double lat, double lng, int32_t poly, int32_t *covered);
 
 /*
  * act_lut_host -- copy of the lookup table (host). If `words` is NULL only

@@ -22,11 +22,12 @@ import ctypes
 import numpy as np
 
 from . import _binding as _b
-from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64,
-                       COUNTER_NAMES, ActError)
+from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
+                       ACT_REFINE_FP64, ACT_REFINE_LOCAL, COUNTER_NAMES, ActError)
 
 __all__ = ["build", "Index", "cell_ids", "ActError", "ACT_EXACT", "ACT_APPROX",
-           "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64", "version", "lib"]
+           "ACT_REFINE_AUTO", "ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64",
+           "version", "lib"]
 
 lib = _b.lib
 
@@ -94,7 +95,7 @@ class Index:
         return out
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
-                refine=ACT_REFINE_FP32_FILTER, block=0, lds_levels=-1, grid=0,
+                refine=ACT_REFINE_AUTO, block=0, lds_levels=-1, grid=0,
                 queue_limit=0, points_per_lane=0, stream=None):
         """Full-control join. Returns (out, pairs or None, counters dict or None).
 
@@ -164,6 +165,13 @@ class Index:
         _b.check(lib.act_lookup_host(self._h, _np_ptr(f), _np_ptr(a), _np_ptr(b), f.shape[0],
                                      _np_ptr(ent)))
         return ent
+
+    def refine_local_host(self, face, i, j, lat, lng, poly) -> bool:
+        """Evaluate the cell-local refinement record on the host."""
+        c = ctypes.c_int32(0)
+        _b.check(lib.act_refine_local_host(self._h, int(face), int(i), int(j), float(lat),
+                                           float(lng), int(poly), ctypes.byref(c)))
+        return bool(c.value)
 
     def lut_host(self) -> np.ndarray:
         n = ctypes.c_int64(0)

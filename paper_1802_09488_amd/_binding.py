@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libact.so")
 ACT_OK, ACT_E_ARG, ACT_E_POLY, ACT_E_OOM, ACT_E_HIP, ACT_E_OVERFLOW, ACT_E_DEVICE, ACT_E_RANGE = \
     0, -1, -2, -3, -4, -5, -6, -7
 ACT_EXACT, ACT_APPROX = 0, 1
-ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1
+ACT_REFINE_AUTO, ACT_REFINE_LOCAL, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1, 2, 3
 ACT_NCOUNTERS = 16
 COUNTER_NAMES = ["points", "invalid", "false_hit", "solely_true", "cand_points", "candidates",
                  "edges", "edge_fp64", "edge_exact", "node_reads", "lut_reads"]
@@ -56,7 +56,8 @@ class Stats(ctypes.Structure):
                 ("max_refs", ctypes.c_int32), ("max_cell_level", ctypes.c_int32),
                 ("n_faces", ctypes.c_int32), ("face_prefix_level", ctypes.c_int32 * 6),
                 ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double)]
+                ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double),
+                ("local_words", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -81,6 +82,8 @@ def _load():
         "act_index_stats": ([p, p], ctypes.c_int),
         "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),
         "act_lut_host": ([p, p, p], ctypes.c_int),
+        "act_refine_local_host": ([p, i32, ctypes.c_uint32, ctypes.c_uint32, d, d, i32, p],
+                                  ctypes.c_int),
         "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),
         "act_orient_fp32_host": ([p, p, p, p, ctypes.c_float], ctypes.c_int),
         "act_orient_exact_host": ([p, p, p], ctypes.c_int),

@@ -20,6 +20,10 @@
 // great-circle edges), inflated by a margin that dominates the GPU's fp64
 // projection rounding. All predicates on that box are exact (geom.hpp).
 //
+// Exact mode adds, per candidate (cell, polygon), a cell-local refinement
+// record (see local_record) so that a candidate point need not be tested
+// against all of the polygon's edges.
+//
 // Physical index (Section III-C): cells are denormalised to the node levels
 // of their face (g = 4 levels per node, Fig. 6a), references of fewer than
 // three polygons are inlined into the tagged entry, longer lists are
@@ -238,6 +242,8 @@ struct CellOut {
 struct Sink {
   std::vector<CellOut> cells;
   std::vector<uint32_t> refs;  // id << 1 | interior
+  std::vector<uint32_t> locs;  // per ref: local record offset in `local` (candidates)
+  std::vector<uint32_t> local; // cell-local refinement records (exact mode)
 };
 
 struct Ctx {
@@ -278,6 +284,52 @@ void classify(const Ctx &C, const Box &box, const std::vector<int32_t> &pint,
   std::sort(w.interior.begin(), w.interior.end());
 }
 
+// Cell-local refinement record of polygon p for a cell with box b (exact
+// mode). For a point q inside b, the ray from q towards +x crosses
+//   * edges that meet b: tested exactly at probe time (stored);
+//   * edges that do not meet b: within b's latitude band such an edge lies
+//     wholly left or wholly right of b; a right one is crossed exactly when
+//     it straddles q's latitude, [ylo <= q.y] xor [yhi <= q.y] with the
+//     half-open rule. Their parity is stored as a base bit (breakpoints at
+//     or below the band's bottom) plus the sorted breakpoints inside the
+//     band. Edges outside the band and horizontal edges never contribute.
+// Layout (32-bit words, doubles 8-byte aligned): n_local, n_break | base << 31,
+// n_local x (ax, ay, bx, by), n_break breakpoints ascending.
+static uint32_t local_record(const Prep &P, int p, const Box &b, std::vector<uint32_t> &out) {
+  std::vector<double> loc, brk;
+  int base = 0;
+  for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) {
+    const double *q = &P.ex[4 * (size_t)e];
+    if (b.wrap || segment_meets(q, b)) {  // boxes across the antimeridian keep every edge
+      loc.insert(loc.end(), q, q + 4);
+      continue;
+    }
+    const bool up = q[1] <= q[3];
+    const double lx = up ? q[0] : q[2], ly = up ? q[1] : q[3];
+    const double ux = up ? q[2] : q[0], uy = up ? q[3] : q[1];
+    if (ly == uy || uy < b.lat0 || ly > b.lat1) continue;
+    const double ys = std::max(ly, b.lat0);
+    if (orient_sign_exact(lx, ly, ux, uy, b.lng1, ys) <= 0) continue;  // left of the box
+    for (double y : {ly, uy}) {
+      if (y <= b.lat0) base ^= 1;
+      else if (y <= b.lat1) brk.push_back(y);
+    }
+  }
+  std::sort(brk.begin(), brk.end());
+  const uint32_t off = (uint32_t)out.size();
+  out.push_back((uint32_t)(loc.size() / 4));
+  out.push_back((uint32_t)brk.size() | ((uint32_t)base << 31));
+  auto put = [&](double v) {
+    uint32_t w[2];
+    std::memcpy(w, &v, 8);
+    out.push_back(w[0]);
+    out.push_back(w[1]);
+  };
+  for (double v : loc) put(v);
+  for (double v : brk) put(v);
+  return off;
+}
+
 void emit(const Ctx &C, const Work &w, Sink &s) {
   CellOut c;
   c.face = w.face;
@@ -291,11 +343,16 @@ void emit(const Ctx &C, const Work &w, Sink &s) {
   bids.reserve(w.bnd.size());
   for (const Bref &br : w.bnd) bids.push_back(br.poly);
   std::sort(bids.begin(), bids.end());
+  const bool local = C.bp.mode == ACT_EXACT;
   while (a < w.interior.size() || b < bids.size()) {
-    if (b >= bids.size() || (a < w.interior.size() && w.interior[a] < bids[b]))
+    if (b >= bids.size() || (a < w.interior.size() && w.interior[a] < bids[b])) {
       s.refs.push_back(((uint32_t)w.interior[a++] << 1) | 1u);
-    else
-      s.refs.push_back((uint32_t)bids[b++] << 1);
+      s.locs.push_back(UINT32_MAX);
+    } else {
+      s.refs.push_back((uint32_t)bids[b] << 1);
+      s.locs.push_back(local ? local_record(*C.P, bids[b], w.box, s.local) : UINT32_MAX);
+      b++;
+    }
   }
   c.ref_cnt = (int32_t)s.refs.size() - c.ref_off;
   s.cells.push_back(c);
@@ -637,16 +694,24 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     int face, level;
     uint32_t I, J;
     const uint32_t *refs;
+    const uint32_t *locs;
+    uint64_t local_base;  // offset of the cell's sink in out.local
     int n;
   };
   std::vector<Cell> cells;
   auto gather = [&](const Sink &s) {
+    const uint64_t base = out.local.size();
+    out.local.insert(out.local.end(), s.local.begin(), s.local.end());
     for (const CellOut &c : s.cells)
       cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
-                       &s.refs[c.ref_off], c.ref_cnt});
+                       &s.refs[c.ref_off], &s.locs[c.ref_off], base, c.ref_cnt});
   };
   gather(top);
   for (const Sink &s : sinks) gather(s);
+  if (out.local.size() >= (1ull << 32)) {
+    err = "cell-local refinement records exceed 2^32 words";
+    return ACT_E_RANGE;
+  }
   std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) {
     return a.face != b.face ? a.face < b.face : (a.I != b.I ? a.I < b.I : a.J < b.J);
   });
@@ -711,7 +776,30 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
       const int sh = kMaxLevel - lp - 4 * (kd + 1);
       const uint32_t ni = (c.I >> sh) & 15u, nj = (c.J >> sh) & 15u;
       const uint32_t span = 1u << (lp + 4 * (kd + 1) - l);
-      uint64_t entry = encode_refs(c.refs, c.n, out.lut, &dedup);
+      bool has_cand = false;
+      for (int r = 0; r < c.n; r++) has_cand |= !(c.refs[r] & 1u);
+      uint64_t entry;
+      if (has_cand && bp.mode == ACT_EXACT) {
+        // candidate cell: lookup-table list followed by the candidates'
+        // local record offsets
+        std::vector<uint32_t> tru, cand, locs;
+        for (int r = 0; r < c.n; r++) {
+          if (c.refs[r] & 1u) {
+            tru.push_back(c.refs[r] >> 1);
+          } else {
+            cand.push_back(c.refs[r] >> 1);
+            locs.push_back((uint32_t)(c.local_base + c.locs[r]));
+          }
+        }
+        entry = ((uint64_t)out.lut.size() << 2) | kTagLut;
+        out.lut.push_back((uint32_t)tru.size());
+        out.lut.insert(out.lut.end(), tru.begin(), tru.end());
+        out.lut.push_back((uint32_t)cand.size());
+        out.lut.insert(out.lut.end(), cand.begin(), cand.end());
+        out.lut.insert(out.lut.end(), locs.begin(), locs.end());
+      } else {
+        entry = encode_refs(c.refs, c.n, out.lut, &dedup);
+      }
       if (out.lut.size() >= (1ull << 31)) {
         err = "lookup table exceeds 2^31 words";
         return ACT_E_RANGE;

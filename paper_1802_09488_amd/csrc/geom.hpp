@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 
 #define ACT_HD __host__ __device__ __forceinline__
 
@@ -156,6 +157,36 @@ ACT_HD int edge_test_exact(double ax, double ay, double bx, double by,
   if (in_box && s == 0) return 2;
   if (straddle && ((by > ay) ? (s > 0) : (s < 0))) return 1;
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Cell-local refinement record (built by the index builder for a candidate
+// (cell, polygon) pair): covered-ness of a point inside the cell's box from
+// the edges that meet the box (exact tests), a base parity and the parity
+// breakpoints of the edges passing right of the box. Record layout (32-bit
+// words): n_local, n_break | base << 31, n_local x (ax ay bx by) fp64,
+// n_break fp64 breakpoints.
+// ---------------------------------------------------------------------------
+ACT_HD double word_double(const uint32_t *w) {
+  const uint64_t u = ((uint64_t)w[1] << 32) | w[0];
+  double d;
+  memcpy(&d, &u, sizeof d);
+  return d;
+}
+
+ACT_HD bool local_record_covers(const uint32_t *rec, double px, double py) {
+  const uint32_t n_local = rec[0], h1 = rec[1];
+  const uint32_t n_break = h1 & 0x7fffffffu;
+  uint32_t par = h1 >> 31;
+  const uint32_t *d = rec + 2;
+  for (uint32_t k = 0; k < n_local; k++, d += 8) {
+    const int r = edge_test_exact(word_double(d), word_double(d + 2), word_double(d + 4),
+                                  word_double(d + 6), px, py);
+    if (r == 2) return true;
+    par ^= (uint32_t)r;
+  }
+  for (uint32_t k = 0; k < n_break; k++, d += 2) par ^= word_double(d) <= py ? 1u : 0u;
+  return par != 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -61,6 +61,7 @@ struct DevImage {
   uint16_t *htab = nullptr;
   struct FaceDev *faces = nullptr;
   uint32_t *top32 = nullptr;
+  uint32_t *local = nullptr;
   size_t bytes = 0;
 };
 
@@ -68,6 +69,7 @@ struct DevImage {
 struct Workspace {
   int64_t *q_pt = nullptr;
   int32_t *q_poly = nullptr;
+  uint32_t *q_loc = nullptr;
   uint32_t *q_ctl = nullptr;
   int64_t cap = 0;
 };
@@ -117,8 +119,10 @@ struct ProbeParams {
   int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
   // exact mode: candidate queue (workspace of the launching stream)
+  const uint32_t *local;  // cell-local refinement records (exact mode)
   int64_t *q_pt;
   int32_t *q_poly;
+  uint32_t *q_loc;  // local record of each queued candidate (ACT_REFINE_LOCAL)
   uint32_t *q_ctl;  // [s] entries in segment s; [kSegs] refine blocks done;
                     // [kSegs+1] pending points exist; [kSegs+2] fixup blocks done
   int64_t q_seg_cap;  // entries per segment
@@ -302,7 +306,7 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
   const double px = lng, py = lat;
   uint32_t par = 0;
   bool on = false;
-  if (P.refine == ACT_REFINE_FP32_FILTER) {
+  if (P.refine != ACT_REFINE_FP64) {
     const double2 o = P.origin[poly];
     const float qx = (float)(px - o.x), qy = (float)(py - o.y);
     const float eta = tier1_eta(fmaxf(P.pm[poly], fmaxf(fabsf(qx), fabsf(qy))));
@@ -579,9 +583,10 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
         for (int p = 0; p < NP; p++) {
           if (pending[p] || ncand[p] == 0) continue;
           for (uint32_t r = 0; r < (tag[p] == kTagLut ? nc[p] : 2u); r++) {
-            uint32_t poly;
+            uint32_t poly, loc = 0xffffffffu;
             if (tag[p] == kTagLut) {
               poly = P.lut[off[p] + 2 + nt[p] + r];
+              if (P.q_loc) loc = P.lut[off[p] + 2 + nt[p] + nc[p] + r];
             } else {
               if (!(r == 0 ? c0[p] : c1[p])) continue;
               poly = (r == 0 ? r0[p] : r1[p]) >> 1;
@@ -589,6 +594,7 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
             if (at + k < P.q_seg_cap) {
               qp[at + k] = fits ? i[p] : -1;
               qy[at + k] = (int32_t)poly;
+              if (P.q_loc) P.q_loc[seg * P.q_seg_cap + at + k] = loc;
             }
             k++;
           }
@@ -764,6 +770,59 @@ __global__ __launch_bounds__(kBlock) void refine_kernel(ProbeParams P) {
   }
 }
 
+// Cell-local refinement of the queued candidates: one lane per candidate,
+// the test reads only the candidate cell's record (edges meeting the cell
+// plus parity breakpoints). A candidate without a record (not produced by
+// current builds) is tested against all edges by its lane.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void refine_local_kernel(ProbeParams P) {
+  uint32_t c_edges = 0, c_fp64 = 0, c_exact = 0;
+  const int64_t total = (int64_t)kSegs * P.q_seg_cap;
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * kBlock) {
+    const int seg = (int)(g / P.q_seg_cap);
+    if (g - seg * P.q_seg_cap >= (int64_t)P.q_ctl[seg]) continue;
+    const int64_t pt = P.q_pt[g];
+    if (pt < 0) continue;
+    const int32_t poly = P.q_poly[g];
+    const uint32_t loc = P.q_loc[g];
+    const double2 p = P.pts[pt];
+    bool cov;
+    if (loc != 0xffffffffu) {
+      cov = local_record_covers(P.local + loc, p.y, p.x);
+      if (COUNT) c_edges += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+    } else {
+      const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
+      uint32_t par = 0;
+      cov = false;
+      for (int e = e0; e < e1 && !cov; e++) {
+        const int r = edge_fp64<COUNT>(P, e, p.y, p.x, c_fp64, c_exact);
+        cov = r == 2;
+        par ^= (uint32_t)(r & 1);
+      }
+      cov = cov || par;
+      if (COUNT) c_edges += (uint32_t)(e1 - e0);
+    }
+    if (cov) merge_min(P, pt, poly);
+  }
+  if (COUNT) {
+    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
+    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
+    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
+  }
+  __shared__ uint32_t s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(P.q_ctl + kSegs, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_last) {  // every other block has finished: reset the queue
+    for (int k = threadIdx.x; k <= kSegs; k += kBlock) P.q_ctl[k] = 0;
+    __threadfence();
+  }
+}
+
 __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_t n,
                                                       const uint16_t *htab, uint64_t *ids) {
   __shared__ uint16_t s_htab[1024];
@@ -824,7 +883,8 @@ struct DeviceGuard {
 };
 
 static void free_image(DevImage &d) {
-  void *ptrs[] = {d.nodes, d.lut, d.eoff, d.origin, d.pm, d.e32, d.e64, d.htab, d.faces, d.top32};
+  void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
+                  d.e64,   d.htab,  d.faces, d.top32,  d.local};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -847,27 +907,28 @@ static int upload(T *&dst, const void *src, size_t bytes, size_t &total) {
 }
 
 static void free_workspace(Workspace &w) {
-  if (w.q_pt) (void)hipFree(w.q_pt);
-  if (w.q_poly) (void)hipFree(w.q_poly);
-  if (w.q_ctl) (void)hipFree(w.q_ctl);
+  void *ptrs[] = {w.q_pt, w.q_poly, w.q_loc, w.q_ctl};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
   w = Workspace();
 }
 
 // The stream's workspace with at least `cap` queue entries; allocated (and
-// its control words zeroed) on first use. Call with the index's device
-// current.
+// its counters zeroed) on first use. Call with the index's device current.
 static int get_workspace(const act_index *x, void *stream, int64_t cap, Workspace *&out) {
   std::lock_guard<std::mutex> lk(x->ws_mu);
   Workspace &w = x->ws[stream];
   if (w.cap < cap) {
     free_workspace(w);
-    if (hipMalloc((void **)&w.q_pt, sizeof(int64_t) * cap) != hipSuccess ||
-        hipMalloc((void **)&w.q_poly, sizeof(int32_t) * cap) != hipSuccess ||
-        hipMalloc((void **)&w.q_ctl, 4 * (kSegs + 4)) != hipSuccess) {
+    bool ok = hipMalloc((void **)&w.q_pt, sizeof(int64_t) * cap) == hipSuccess &&
+              hipMalloc((void **)&w.q_poly, sizeof(int32_t) * cap) == hipSuccess &&
+              hipMalloc((void **)&w.q_loc, sizeof(uint32_t) * cap) == hipSuccess &&
+              hipMalloc((void **)&w.q_ctl, 4 * (kSegs + 8)) == hipSuccess;
+    if (!ok) {
       free_workspace(w);
       return fail(ACT_E_OOM, "cannot allocate the candidate queue");
     }
-    if (hipMemset(w.q_ctl, 0, 4 * (kSegs + 4)) != hipSuccess) {
+    if (hipMemset(w.q_ctl, 0, 4 * (kSegs + 8)) != hipSuccess) {
       free_workspace(w);
       return fail(ACT_E_HIP, "cannot clear the candidate queue");
     }
@@ -906,6 +967,7 @@ static int upload_image(act_index *x) {
   std::vector<uint32_t> top(n_top);
   for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
   if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
+  if ((rc = upload(d.local, h.local.data(), h.local.size() * 4, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -951,7 +1013,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   bool pairs = a->d_pair_point || a->d_pair_poly || a->d_n_pairs;
   if (pairs && (!a->d_pair_point || !a->d_pair_poly || !a->d_n_pairs || a->pair_capacity < 0))
     return fail(ACT_E_ARG, "pair output needs point, poly, counter arrays and capacity >= 0");
-  if (a->refine != ACT_REFINE_FP32_FILTER && a->refine != ACT_REFINE_FP64)
+  if (a->refine < ACT_REFINE_AUTO || a->refine > ACT_REFINE_FP64)
     return fail(ACT_E_ARG, "unknown refine mode");
   if (a->block != 0 && a->block != kProbeBlock) return fail(ACT_E_ARG, "block must be 0 or 1024");
   if (a->grid < 0 || a->grid > 65536) return fail(ACT_E_ARG, "grid must be 0 .. 65536");
@@ -987,7 +1049,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.faces = x->dev.faces;
   P.top32 = x->dev.top32;
   P.n_lds_nodes = n_lds;
-  P.refine = a->refine;
+  P.refine = a->refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : a->refine;
+  P.local = x->dev.local;
   const int np = a->points_per_lane > 0 ? a->points_per_lane : 2;
   int64_t tiles_blocks = (a->n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
   int grid = a->grid > 0 ? a->grid : 1024;
@@ -1001,17 +1064,23 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     if (rc) return rc;
     P.q_pt = w->q_pt;
     P.q_poly = w->q_poly;
+    P.q_loc = P.refine == ACT_REFINE_LOCAL ? w->q_loc : nullptr;
     P.q_ctl = w->q_ctl;
     const int64_t cap = a->queue_limit > 0 ? std::min(a->queue_limit, w->cap) : w->cap;
     P.q_seg_cap = cap / kSegs;
+
   }
   hipLaunchKernelGGL(probe_fn(exact, depth, count, np), dim3(grid), dim3(kProbeBlock),
                      (size_t)n_lds * 1024, (hipStream_t)stream, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
   if (exact) {
-    hipLaunchKernelGGL(count ? refine_kernel<true> : refine_kernel<false>, dim3(kRefineGrid),
-                       dim3(kBlock), 0, (hipStream_t)stream, P);
+    if (P.refine == ACT_REFINE_LOCAL)
+      hipLaunchKernelGGL(count ? refine_local_kernel<true> : refine_local_kernel<false>,
+                         dim3(kRefineGrid), dim3(kBlock), 0, (hipStream_t)stream, P);
+    else
+      hipLaunchKernelGGL(count ? refine_kernel<true> : refine_kernel<false>, dim3(kRefineGrid),
+                         dim3(kBlock), 0, (hipStream_t)stream, P);
     e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("refine launch: ") + hipGetErrorString(e));
@@ -1195,6 +1264,7 @@ int act_index_stats(const act_index *x, act_stats *o) {
   o->mode = h.mode;
   o->precision_m = h.precision_m;
   o->build_seconds = h.build_seconds;
+  o->local_words = (int64_t)h.local.size();
   return ACT_OK;
 }
 
@@ -1203,6 +1273,23 @@ int act_lookup_host(const act_index *x, const int32_t *face, const uint32_t *i,
   if (!x || n < 0 || (n > 0 && (!face || !i || !j || !entries))) return fail(ACT_E_ARG, "bad argument");
   for (int64_t k = 0; k < n; k++) entries[k] = host_lookup(x->host, face[k], i[k], j[k]);
   return ACT_OK;
+}
+
+int act_refine_local_host(const act_index *x, int32_t face, uint32_t i, uint32_t j, double lat,
+                          double lng, int32_t poly, int32_t *covered) {
+  if (!x || !covered) return fail(ACT_E_ARG, "bad argument");
+  const HostIndex &h = x->host;
+  const uint64_t e = host_lookup(h, face, i, j);
+  if ((e & kTagMask) != kTagLut || h.local.empty())
+    return fail(ACT_E_ARG, "no cell-local record for this cell");
+  const uint32_t off = (uint32_t)(e >> 2);
+  const uint32_t nt = h.lut[off], nc = h.lut[off + 1 + nt];
+  for (uint32_t r = 0; r < nc; r++)
+    if ((int32_t)h.lut[off + 2 + nt + r] == poly) {
+      *covered = local_record_covers(&h.local[h.lut[off + 2 + nt + nc + r]], lng, lat) ? 1 : 0;
+      return ACT_OK;
+    }
+  return fail(ACT_E_ARG, "polygon is not a candidate of this cell");
 }
 
 int act_lut_host(const act_index *x, uint32_t *words, int64_t *n_words) {

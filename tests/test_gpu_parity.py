@@ -115,12 +115,25 @@ def test_c1_exact_edge_cases(act):
     assert len(ref.pairs) > 100  # shared vertices really produce multi-matches
 
 
-def test_c1_fp64_refine_identical(act):
+REFINE_MODES = ["ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64"]
+
+
+@pytest.mark.parametrize("mode", REFINE_MODES)
+def test_c1_refine_modes_exact(act, mode):
+    """Every refinement mode gives the oracle's result, edge cases included."""
     P, idx = index(act, "c1", "exact")
     pts = np.concatenate([synth.workload_points("c1"), edge_case_points(P, np.random.default_rng(4))])
-    a = gpu_join(idx, pts)
-    b = gpu_join(idx, pts, refine=act.ACT_REFINE_FP64)
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+    assert_exact(P, pts, out, pairs, "c1-" + mode)
+
+
+@pytest.mark.parametrize("mode", REFINE_MODES)
+def test_c2_refine_modes_exact(act, mode):
+    P, idx = index(act, "c2", "exact")
+    pts = np.concatenate([synth.workload_points("c2", 0, 200000),
+                          edge_case_points(P, np.random.default_rng(5))])
+    out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+    assert_exact(P, pts, out, pairs, "c2-" + mode)
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 257, 4097, 100003])
@@ -190,14 +203,16 @@ def test_c2_approx_sample(act):
 def test_c2_full_size_sampled(act):
     """All 1e8 points of the workload in one launch (the benchmark's
     configuration); the oracle checks 200k seeded random positions, and the
-    fp32-filter output equals the all-fp64 output everywhere."""
+    cell-local, fp32-filter and all-fp64 refinements agree everywhere."""
     P, idx = index(act, "c2", "exact")
     n = synth.WORKLOADS["c2"]["n_points"]
     pts = torch.from_numpy(synth.workload_points("c2", 0, n)).cuda()
     out = idx.join(pts)
-    out64, _, _ = idx.join_ex(pts, refine=act.ACT_REFINE_FP64)
-    torch.cuda.synchronize()
-    assert torch.equal(out, out64)
+    for mode in (act.ACT_REFINE_FP32_FILTER, act.ACT_REFINE_FP64):
+        other, _, _ = idx.join_ex(pts, refine=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(out, other), mode
+        del other
     rng = np.random.default_rng(7)
     sel = np.sort(rng.choice(n, 200000, replace=False))
     sp = pts[torch.from_numpy(sel).cuda()].cpu().numpy()

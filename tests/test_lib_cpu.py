@@ -134,6 +134,34 @@ def test_inline_payload_encoding(act):
     assert (e >> 33) == (big << 1) | 1
 
 
+@pytest.mark.parametrize("wl", ["c1", "c2"])
+def test_cell_local_records_match_oracle(act, wl):
+    """The cell-local refinement record of every candidate (cell, polygon)
+    pair met by the points decides ST_Covers exactly as the oracle does
+    (points from the workload, polygon vertices, edge midpoints and points
+    nudged one ulp around them)."""
+    P = synth.workload_polygons(wl)
+    idx = act.build(P, "exact", device=-1)
+    assert idx.stats()["local_words"] > 0
+    rng = np.random.default_rng(23)
+    v = P.verts[rng.choice(len(P.verts), min(len(P.verts), 3000), replace=False)]
+    nudged = v + rng.integers(-1, 2, v.shape) * np.spacing(v)
+    pts = np.concatenate([synth.workload_points(wl, 0, 3000), v, nudged])
+    face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    ent = idx.lookup_host(face, i, j)
+    lut = idx.lut_host()
+    checked = 0
+    for k in range(len(pts)):
+        for p, interior in _decode(ent[k], lut):
+            if interior:
+                continue
+            got = idx.refine_local_host(face[k], i[k], j[k], pts[k, 0], pts[k, 1], p)
+            assert got == oracle.covers(P, p, pts[k, 0], pts[k, 1]), (k, p, pts[k])
+            checked += 1
+    assert checked > 1000
+
+
 def _frac_sign(a, b, p):
     ax, ay, bx, by, px, py = (Fraction(float(v)) for v in (*a, *b, *p))
     d = (bx - ax) * (py - ay) - (by - ay) * (px - ax)
