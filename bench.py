@@ -4,17 +4,30 @@ Workload (the paper's neighbourhood-scale join, synthetic stand-in): 290
 Voronoi polygons over the NYC box (20..800 vertices, 5% with a hole) and
 1e8 fp64 (lat, lng) points from a 64-component Gaussian mixture + 10%
 uniform, resident in HBM before timing. One step = one act_join of all 1e8
-points in exact mode (projection, trie descent, refinement, output); the
-approximate mode at 4 m is timed the same way and reported beside it.
+points in exact mode (projection, trie descent, candidate resolution with
+exact refinement, output). Reported beside it: the approximate mode at 4 m,
+the refinement variants (cell-local, fp32 filter + fp64/exact re-test over
+all edges, all-fp64 over all edges), per-step latency percentiles, the
+probe kernel's HBM roofline, and the CPU oracle on the host's cores.
 
-Prints one JSON line. `--gpus N` with N > 1 exits: this build targets one
-GPU.
+Prints one JSON line. `--gpus N` with N > 1 exits: the run measures one GPU.
+
+Profile helpers (turn rocprofv3 output of a run of this script into the
+text summaries kept under profiles/):
+  python bench.py --summarize-trace DIR      (rocprofv3 --kernel-trace --stats
+                                              --output-format csv -d DIR)
+  python bench.py --summarize-pmc FDIR WDIR  (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+                                              --output-format csv -d FDIR / WDIR)
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -23,43 +36,113 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_POINT = 20  # 16 B fp64 (lat, lng) in + 4 B int32 id out
+COPY_BYTES = 1 << 30  # calibration copy (device to device)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_probe_c2.md")
+KERNEL_SOURCES = ["probe.hip", "geom.hpp", "cellid.hpp", "index.hpp"]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def time_joins(idx, pts, out, steps, warmup, refine=0):
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1802_09488_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Probe HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel sources sha256/16: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    out = {}
+    for mode in ("exact", "approx"):
+        r = re.search(r"\| probe_kernel %s \| ([0-9.e+]+) \|" % mode, txt)
+        if r:
+            out[mode] = float(r.group(1))
+    return out or None
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def time_joins(idx, pts, out, steps, warmup, **kw):
+    """Times `steps` joins (after `warmup`): wall clock around all of them,
+    HIP events around each join and after its probe kernel."""
     import torch
     for _ in range(warmup):
-        idx.join_ex(pts, out, refine=refine)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+        idx.join_ex(pts, out, **kw)
+    ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
+    for _, m, _ in ev:
+        m.record()  # creates the event the library records after the probe
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for a, b in ev:
+    for a, m, b in ev:
         a.record()
-        idx.join_ex(pts, out, refine=refine)
+        idx.join_ex(pts, out, probe_event=m, **kw)
         b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kms = [a.elapsed_time(b) for a, b in ev]
-    return wall, kms
+    total = [a.elapsed_time(b) for a, _, b in ev]
+    probe = [a.elapsed_time(m) for a, m, _ in ev]
+    return wall, total, probe
 
 
-def cpu_baseline(P, workload, n_sample):
+def copy_calibration():
+    """A plain device-to-device copy of COPY_BYTES (the hipMemcpy blit
+    kernel): its rocprofv3 FETCH_SIZE / WRITE_SIZE readings calibrate the
+    counters, and its rate is the achievable copy bandwidth."""
+    import torch
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    del src, dst
+    return {"bytes_each_way": COPY_BYTES, "ms": ms, "GBps_read_plus_write": 2 * COPY_BYTES / ms / 1e6}
+
+
+def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
+    """The oracle (brute force: bbox prefilter + exact point-in-polygon
+    against every polygon, OpenMP over points) on the host's cores over the
+    first n_sample points of the stream; its output is compared with the
+    GPU's exact-mode output for those points."""
+    import numpy as np
+
     import oracle
     import synth
-    pts = synth.workload_points(workload, 0, n_sample)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    oracle.join(P, pts[:1000], nthreads=cores)
-    t0 = time.perf_counter()
-    oracle.join(P, pts, nthreads=cores)
-    dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d points of the %s stream, exact join (brute force, bbox "
-                      "prefilter + exact PIP), %d threads, %.1f s" % (n_sample, workload, cores, dt)}
+    oracle.join(P, synth.workload_points(workload, 0, 1000), nthreads=cores)  # warm
+    step = 1 << 24
+    dt = 0.0
+    mism = 0
+    for s in range(0, n_sample, step):
+        e = min(n_sample, s + step)
+        pts = synth.workload_points(workload, s, e)
+        t0 = time.perf_counter()
+        ref = oracle.join(P, pts, nthreads=cores)
+        dt += time.perf_counter() - t0
+        mism += int(np.count_nonzero(ref.out != gpu_out[s:e]))
+    base = {"value": n_sample / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": "points 0..%d of the %s stream (%s), exact join, %d threads, %.1f s"
+                      % (n_sample, workload, "the whole workload" if n_sample == len(gpu_out)
+                         else "a prefix", cores, dt)}
+    parity = {"points_checked": n_sample, "out_mismatches": mism}
+    return base, parity
 
 
 def main():
@@ -69,13 +152,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--points", type=int, default=0, help="override the point count")
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="oracle points (default: the whole workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-approx", action="store_true")
+    ap.add_argument("--summarize-trace", metavar="DIR")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
+    if args.summarize_pmc:
+        return summarize_pmc(*args.summarize_pmc)
     if args.gpus != 1:
         print("bench.py measures one GPU: the probe replicates the immutable index per GPU and "
-              "splits points, and this build runs and reports the single-GPU case only "
+              "splits the points, and this benchmark runs and reports the single-GPU case only "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -92,11 +181,9 @@ def main():
     t0 = time.perf_counter()
     idx = act.build(P, "exact")
     t_build_exact = time.perf_counter() - t0
-    idx_a = None
-    if not args.no_approx:
-        t0 = time.perf_counter()
-        idx_a = act.build(P, "approx", 4.0)
-        t_build_approx = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    idx_a = act.build(P, "approx", 4.0)
+    t_build_approx = time.perf_counter() - t0
     log("generating %d points" % n)
     pts = torch.empty((n, 2), dtype=torch.float64, device="cuda")
     step = 1 << 24
@@ -104,16 +191,36 @@ def main():
         e = min(n, s + step)
         pts[s:e].copy_(torch.from_numpy(synth.workload_points(args.workload, s, e)))
     out = torch.empty(n, dtype=torch.int32, device="cuda")
+    idx.reserve(n)  # one pass over all points
     torch.cuda.synchronize()
+    calib = copy_calibration()
 
     log("timing exact")
-    wall, kms = time_joins(idx, pts, out, args.steps, args.warmup)
-    kernel_ms = float(np.mean(kms))
-    ms_per_step = 1000.0 * wall / args.steps
+    wall, tot, prb = time_joins(idx, pts, out, args.steps, args.warmup)
     value = n * args.steps / wall
+    exact_out = out.cpu().numpy()
     _, _, ctr = idx.join_ex(pts, out, counters=True)
-    wall64, kms64 = time_joins(idx, pts, out, max(3, args.steps // 2), 1,
-                               refine=act.ACT_REFINE_FP64)
+    log("timing approx@4m")
+    wall_a, tot_a, prb_a = time_joins(idx_a, pts, out, args.steps, args.warmup)
+    _, _, ctr_a = idx_a.join_ex(pts, out, counters=True)
+    log("timing refinement variants")
+    k = max(3, args.steps // 2)
+    var = {}
+    for name, mode in (("local", act.ACT_REFINE_LOCAL), ("fp32_filter", act.ACT_REFINE_FP32_FILTER),
+                       ("fp64", act.ACT_REFINE_FP64)):
+        wv, tv, pv = time_joins(idx, pts, out, k, 1, refine=mode)
+        var[name] = {"points_per_s": n * k / wv, "join_ms_mean": float(np.mean(tv)),
+                     "resolve_ms_mean": float(np.mean(tv) - np.mean(pv))}
+        if mode != act.ACT_REFINE_LOCAL:
+            torch.cuda.synchronize()
+            var[name]["identical_to_local"] = bool(np.array_equal(out.cpu().numpy(), exact_out))
+    var["fp32_filter_over_fp64_speedup"] = (var["fp64"]["join_ms_mean"]
+                                            / var["fp32_filter"]["join_ms_mean"])
+
+    probe_ms = float(np.mean(prb))
+    achieved = BYTES_PER_POINT * n / (probe_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    st, sa = idx.stats(), idx_a.stats()
     res = {
         "metric": "joined points/sec (exact & approx@4m) + HBM roofline %; p50/p99 batch latency",
         "value": value,
@@ -121,47 +228,116 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1000.0 * wall / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %d Voronoi polygons (NYC box), %d fp64 mixture points, "
-                               "exact join (covering level 20); approx@4m beside it"
-                               % (args.workload, P.n_polys, n),
-                   "n_points": n, "n_polys": P.n_polys, "n_edges": int(idx.stats()["n_edges"]),
-                   "mode": "exact", "parallelism": "single GPU"},
+        "config": {"workload": "%s: %d Voronoi polygons over the NYC box (%d edges), %d fp64 "
+                               "mixture points resident in HBM, exact join (covering level 20, "
+                               "cell-local refinement); approx@4m beside it"
+                               % (args.workload, P.n_polys, st["n_edges"], n),
+                   "n_points": n, "n_polys": P.n_polys, "mode": "exact",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic["exact"] if traffic and "exact" in traffic else None,
+                     "kernel": "probe_kernel (exact mode)", "kernel_ms": probe_ms,
+                     "bytes_per_point": BYTES_PER_POINT, "points_per_launch": n},
+        "latency_ms": {"p50": percentile(tot, 50), "p99": percentile(tot, 99),
+                       "what": "one join of all points (one step), HIP events"},
+        "exact": {"join_ms_mean": float(np.mean(tot)), "probe_ms_mean": probe_ms,
+                  "resolve_ms_mean": float(np.mean(tot) - probe_ms)},
+        "approx4m": {"points_per_s": n * args.steps / wall_a,
+                     "join_ms_mean": float(np.mean(tot_a)),
+                     "latency_ms": {"p50": percentile(tot_a, 50), "p99": percentile(tot_a, 99)},
+                     "roofline_frac": BYTES_PER_POINT * n / (np.mean(prb_a) * 1e-3) / 1e9
+                     / PEAK_HBM_GBS,
+                     "traffic": traffic["approx"] if traffic and "approx" in traffic else None},
+        "refine_variants": var,
+        "counters_exact": ctr,
+        "counters_approx4m": ctr_a,
+        "index": {"exact": {k2: st[k2] for k2 in ("n_cells", "n_nodes", "node_bytes", "lut_words",
+                                                  "local_words", "device_bytes", "max_depth")},
+                  "approx4m": {k2: sa[k2] for k2 in ("n_cells", "n_nodes", "node_bytes",
+                                                     "lut_words", "device_bytes", "max_depth")},
+                  "build_s_exact": t_build_exact, "build_s_approx4m": t_build_approx},
+        "copy_calibration": calib,
+        "kernel_sources_sha256_16": kernel_source_hash(),
     }
-    achieved = BYTES_PER_POINT * n / (kernel_ms * 1e-3) / 1e9
-    res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                       "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                       "kernel": "probe_kernel", "kernel_ms": kernel_ms,
-                       "bytes_per_point": BYTES_PER_POINT}
-    res["fp32_filter_vs_fp64"] = {"fp32_filter_points_per_s": value,
-                                  "fp64_points_per_s": n * len(kms64) / wall64,
-                                  "fp64_kernel_ms": float(np.mean(kms64))}
-    res["counters"] = ctr
-    st = idx.stats()
-    res["index"] = {"exact": {k: st[k] for k in ("n_cells", "n_nodes", "node_bytes", "lut_words",
-                                                 "device_bytes", "max_depth")},
-                    "build_s_exact": t_build_exact}
-    if idx_a is not None:
-        log("timing approx@4m")
-        wa, kma = time_joins(idx_a, pts, out, args.steps, args.warmup)
-        sa = idx_a.stats()
-        res["approx4m"] = {"points_per_s": n * args.steps / wa, "kernel_ms": float(np.mean(kma)),
-                           "hbm_frac": BYTES_PER_POINT * n / (np.mean(kma) * 1e-3) / 1e9
-                           / PEAK_HBM_GBS}
-        res["index"]["approx4m"] = {k: sa[k] for k in ("n_cells", "n_nodes", "node_bytes",
-                                                       "device_bytes", "max_depth")}
-        res["index"]["build_s_approx4m"] = t_build_approx
     del pts, out
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("cpu baseline")
-        res["cpu_baseline"] = cpu_baseline(P, args.workload, min(args.cpu_sample, n))
+        log("cpu baseline (oracle)")
+        ns = min(args.cpu_sample or n, n)
+        res["cpu_baseline"], res["parity_vs_oracle"] = cpu_baseline_and_parity(
+            P, args.workload, ns, exact_out)
     print(json.dumps(res), flush=True)
+
+
+# ------------------------------------------------------------ profile summaries
+
+def _csv_rows(d, suffix):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _short(name):
+    name = re.sub(r"\(.*", "", name)
+    return name.replace("void ", "").replace("act::", "")
+
+
+def summarize_trace(d):
+    rows = _csv_rows(d, "kernel_stats.csv")
+    print("| kernel | calls | avg (us) | min (us) | max (us) | total (ms) |")
+    print("|---|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        print("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
+            _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+            float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6))
+
+
+def summarize_pmc(fdir, wdir):
+    """HBM bytes per launch of the probe kernels: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by the factor that makes the same
+    counter read COPY_BYTES for the calibration copy."""
+    import numpy as np
+    per = {}
+    for d, ctr in ((fdir, "FETCH_SIZE"), (wdir, "WRITE_SIZE")):
+        vals = {}
+        for r in _csv_rows(d, "counter_collection.csv"):
+            if r["Counter_Name"] != ctr:
+                continue
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        copies = max((v for k, v in vals.items() if "copyBuffer" in k), key=max)
+        cal = COPY_BYTES / max(copies)
+        per[ctr] = (cal, vals)
+    fcal, fv = per["FETCH_SIZE"]
+    wcal, wv = per["WRITE_SIZE"]
+    print("kernel sources sha256/16: `%s`" % kernel_source_hash())
+    print()
+    print("calibration (1 GiB device-to-device copy): FETCH_SIZE x %.4f, WRITE_SIZE x %.4f"
+          % (fcal, wcal))
+    print()
+    print("| kernel | HBM bytes per launch | fetch (scaled) | write (scaled) | launches |")
+    print("|---|---|---|---|---|")
+    for k in sorted(fv):
+        pm = re.search(r"probe_kernel<(true|false), \d+, false, \d+>", k)
+        rm = re.search(r"resolve_kernel<(true|false), false>", k)
+        if not pm and not rm:
+            continue  # other kernels, and the counting variants
+        label = ("probe_kernel %s" % ("exact" if pm.group(1) == "true" else "approx")) if pm \
+            else ("resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges"))
+        f = float(np.median(fv[k])) * fcal
+        wr = float(np.median(wv.get(k, [0.0]))) * wcal
+        print("| %s | %.4g | %.4g | %.4g | %d |" % (label, f + wr, f, wr, len(fv[k])))
 
 
 if __name__ == "__main__":

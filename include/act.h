@@ -151,16 +151,17 @@ int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
 
 /*
- * act_workspace_reserve -- exact-mode joins queue their candidate
- * (point, polygon) pairs in a per-stream device workspace owned by the
- * index (12 bytes per entry, default 4 Mi entries). It is allocated on the
- * first exact join on a stream; call this beforehand to pay that cost early
- * (e.g. before capturing joins into a HIP graph, where allocation is not
- * allowed) or to enlarge it. Joins never fail for lack of queue space: a
- * lane whose candidate does not fit refines it itself. Workspaces live until
- * act_free. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_OOM, ACT_E_HIP.
+ * act_workspace_reserve -- exact-mode joins mark the points that need
+ * refinement in a per-stream pending mask owned by the index (one bit per
+ * point of a pass). The first exact join on a stream allocates it for
+ * max(n, 16 Mi) points; a later, longer join runs in passes of that many
+ * points (no allocation). Call this beforehand to size it for `points`
+ * points per pass, e.g. before capturing joins into a HIP graph, where
+ * allocation is not allowed; enlarging an existing workspace synchronises
+ * the stream first. No-op for approximate-mode indexes. Workspaces live
+ * until act_free. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_OOM, ACT_E_HIP.
  */
-int act_workspace_reserve(const act_index *idx, void *stream, int64_t capacity);
+int act_workspace_reserve(const act_index *idx, void *stream, int64_t points);
 
 /* Join counters (uint64 each), accumulated by act_join_ex when asked. */
 enum {
@@ -173,7 +174,7 @@ enum {
   ACT_CNT_EDGES,           /* edges visited by refinement                    */
   ACT_CNT_EDGE_FP64,       /* edges the fp32 tier left undecided             */
   ACT_CNT_EDGE_EXACT,      /* edges the fp64 filter left undecided           */
-  ACT_CNT_NODE_READS,      /* trie entries read (all levels)                 */
+  ACT_CNT_NODE_READS,      /* trie entries read (all levels, LDS included)   */
   ACT_CNT_LUT_READS,       /* cells whose references live in the LUT         */
   ACT_NCOUNTERS = 16
 };
@@ -195,13 +196,15 @@ typedef struct {
                               of 32-bit entries)                             */
   int32_t grid;            /* probe blocks launched (0 = default 1024); each
                               wave walks tiles of 64 points grid-stride      */
-  int64_t queue_limit;     /* exact mode: use at most this many entries of
-                              the stream's candidate queue (0 = all of it);
-                              points that do not fit are resolved by a
-                              slower per-point pass -- a knob for tests     */
+  int64_t pass_points;     /* exact mode: points per probe + resolve pass, at
+                              most the workspace's (0 = the workspace's)    */
   int32_t points_per_lane; /* points each probe lane carries per step: 1, 2
                               (0 = default 2)                                */
   int32_t reserved2;
+  void *probe_event;       /* optional hipEvent_t, recorded on the stream
+                              after each probe launch (so, in a one-pass
+                              join, between the probe and the resolve
+                              kernel): lets a caller time the probe alone   */
 } act_join_args;
 
 int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
@@ -209,8 +212,9 @@ int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
 /*
  * act_cell_ids -- level-30 cell ids of n points (Section II, S2 paragraph:
  * 3 face bits, a Hilbert-ordered bit pair per level, a marker bit). The
- * projection is lat/lng -> unit sphere -> cube face (u, v) -> quadratic
- * (s, t) -> 30-bit (i, j) -> Hilbert position, in fp64. Invalid points get
+ * projection is lat/lng -> unit sphere -> cube face (u, v) -> linear
+ * (s, t) = ((1 + u) / 2, (1 + v) / 2) -> 30-bit (i, j) -> Hilbert
+ * position, in fp64. Invalid points get
  * id 0. d_points: device 2*n doubles; d_ids: device n uint64. The points'
  * device must be the current HIP device.
  */
@@ -295,6 +299,12 @@ int act_orient_fp32_host(const double *a, const double *b, const double *p,
 int act_orient_exact_host(const double *a, const double *b, const double *p);
 
 /* Message of the last failure on the calling thread ("" if none). */
+/*
+ * act_abi_sizes -- sizeof(act_build_opts), sizeof(act_join_args) and
+ * sizeof(act_stats) in sizes[0..2], for bindings that mirror the structs.
+ */
+int act_abi_sizes(int64_t *sizes);
+
 const char *act_last_error(void);
 
 /* Library version string. */

@@ -96,7 +96,7 @@ class Index:
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
                 refine=ACT_REFINE_AUTO, block=0, lds_levels=-1, grid=0,
-                queue_limit=0, points_per_lane=0, stream=None):
+                pass_points=0, points_per_lane=0, probe_event=None, stream=None):
         """Full-control join. Returns (out, pairs or None, counters dict or None).
 
         pairs: (m, 2) int64 CUDA tensor of (point, polygon) beyond out[i]
@@ -116,8 +116,10 @@ class Index:
         a.block = block
         a.lds_levels = lds_levels
         a.grid = grid
-        a.queue_limit = queue_limit
+        a.pass_points = pass_points
         a.points_per_lane = points_per_lane
+        if probe_event is not None:  # a recorded torch.cuda.Event (its HIP event handle)
+            a.probe_event = probe_event.cuda_event
         pp = pq = cnt = ctr = None
         if capacity is not None:
             pp = torch.empty(max(1, capacity), dtype=torch.int64, device=dev)
@@ -142,6 +144,10 @@ class Index:
             c = ctr.cpu().numpy()
             cdict = {k: int(c[i]) for i, k in enumerate(COUNTER_NAMES)}
         return out, pairs, cdict
+
+    def reserve(self, points, stream=None):
+        """Size the stream's exact-mode workspace for `points` points per pass."""
+        _b.check(lib.act_workspace_reserve(self._h, _stream_ptr(stream), int(points)))
 
     def join_pairs(self, points, capacity=None, stream=None):
         """(out, pairs): pairs is (m, 2) int64 of (point, polygon) beyond out[i].

@@ -43,8 +43,9 @@ class JoinArgs(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("d_n_pairs", ctypes.c_void_p),
                 ("d_counters", ctypes.c_void_p), ("refine", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("queue_limit", ctypes.c_int64),
-                ("points_per_lane", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("pass_points", ctypes.c_int64),
+                ("points_per_lane", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("probe_event", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -82,6 +83,7 @@ def _load():
         "act_index_stats": ([p, p], ctypes.c_int),
         "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),
         "act_lut_host": ([p, p, p], ctypes.c_int),
+        "act_abi_sizes": ([p], ctypes.c_int),
         "act_refine_local_host": ([p, i32, ctypes.c_uint32, ctypes.c_uint32, d, d, i32, p],
                                   ctypes.c_int),
         "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),

@@ -829,6 +829,10 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     err = "lookup table exceeds 2^30 words";
     return ACT_E_RANGE;
   }
+  if (out.nodes.size() / 256 >= (1ull << 30)) {  // pointer entries carry 30-bit node indices
+    err = "trie exceeds 2^30 nodes";
+    return ACT_E_RANGE;
+  }
   out.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return ACT_OK;

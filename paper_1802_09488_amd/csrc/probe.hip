@@ -5,17 +5,20 @@
 //   1. coalesced 16-byte load of (lat, lng) fp64;
 //   2. domain check (non-finite / |lat| > 90 / |lng| > 180 -> no match);
 //   3. fp64 projection lat/lng -> unit sphere -> cube face -> (u, v) ->
-//      quadratic (s, t) -> 30-bit (i, j) (Section II, S2 paragraph);
+//      linear (s, t) -> 30-bit (i, j) (Section II, S2 paragraph);
 //   4. Hilbert position via a 4-levels-per-step state table held in LDS;
 //   5. stage 1 (Listing 4): face -> root, per-face common prefix check;
 //   6. stage 2 (Listing 5): comparison-free descent, 8 key bits per node,
 //      until a payload, a LUT offset or the sentinel;
 //   7. stage 3: decode the tagged entry (Section III-E, three cases);
 //   8. true hits (and every reference in approximate mode) are output;
-//      candidate hits are refined by the crossing-number test of
-//      Section II with the ST_Covers boundary rule: fp32 on
-//      origin-translated coordinates with a proven error bound, fp64 +
-//      exact arithmetic for the edges the bound leaves undecided;
+//      in exact mode a point whose cell has candidate references is marked
+//      in a per-64-point pending mask and left to the resolve kernel, which
+//      refines its candidates by the crossing-number test of Section II
+//      with the ST_Covers boundary rule (cell-local records by default;
+//      optionally over all edges: fp32 on origin-translated coordinates
+//      with a proven error bound, fp64 + exact arithmetic for the edges the
+//      bound leaves undecided);
 //   9. out[i] = lowest matching id (or -1), further matches -> pair list.
 #include <hip/hip_runtime.h>
 
@@ -65,16 +68,14 @@ struct DevImage {
   size_t bytes = 0;
 };
 
-// Per-stream scratch of exact-mode joins: the candidate queue.
+// Per-stream scratch of exact-mode joins: the pending mask, one bit per
+// point of a pass (a join longer than `cap` points runs in passes).
 struct Workspace {
-  int64_t *q_pt = nullptr;
-  int32_t *q_poly = nullptr;
-  uint32_t *q_loc = nullptr;
-  uint32_t *q_ctl = nullptr;
-  int64_t cap = 0;
+  uint64_t *mask = nullptr;
+  int64_t cap = 0;  // points
 };
 
-constexpr int64_t kDefaultQueue = 1 << 22;
+constexpr int64_t kDefaultPass = 1 << 24;
 
 }  // namespace act
 
@@ -118,27 +119,17 @@ struct ProbeParams {
   const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 as 32-bit entries
   int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
-  // exact mode: candidate queue (workspace of the launching stream)
   const uint32_t *local;  // cell-local refinement records (exact mode)
-  int64_t *q_pt;
-  int32_t *q_poly;
-  uint32_t *q_loc;  // local record of each queued candidate (ACT_REFINE_LOCAL)
-  uint32_t *q_ctl;  // [s] entries in segment s; [kSegs] refine blocks done;
-                    // [kSegs+1] pending points exist; [kSegs+2] fixup blocks done
-  int64_t q_seg_cap;  // entries per segment
+  uint64_t *mask;         // exact mode: pending points of this pass, bit per point
+  int64_t base;           // index of pts[0] in the caller's array (pair output)
 };
 
 
-constexpr int kBlock = 256;  // refine / fixup kernels
-constexpr int kWaves = kBlock / 64;
+constexpr int kBlock = 256;  // resolve kernels
 // The probe runs 1024-thread blocks: one LDS copy of the top trie levels
 // then serves 16 wavefronts, and two blocks fill a CU.
 constexpr int kProbeBlock = 1024;
 constexpr int kProbeWaves = kProbeBlock / 64;
-// The candidate queue is split into segments with their own counters so
-// that appends (one atomic per wave) do not serialise on one address.
-constexpr int kSegs = 256;
-constexpr int kRefineGrid = 2048;  // kRefineGrid * kWaves is a multiple of kSegs
 
 // --------------------------------------------------------- device math
 //
@@ -332,20 +323,6 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
   return on || (par & 1u) != 0;
 }
 
-// Merge a refined match into out[pt] (written by the probe: best true hit
-// or -1). As unsigned, -1 is the largest value, so atomicMin keeps the
-// lowest id; the id that loses becomes a pair.
-__device__ __forceinline__ void merge_min(const ProbeParams &P, int64_t pt, int32_t poly) {
-  const uint32_t prev = atomicMin((uint32_t *)(P.out + pt), (uint32_t)poly);
-  if (prev == 0xffffffffu || !P.pair_pt) return;
-  const int32_t other = (uint32_t)poly < prev ? (int32_t)prev : poly;
-  const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
-  if ((int64_t)k < P.cap) {
-    P.pair_pt[k] = pt;
-    P.pair_poly[k] = other;
-  }
-}
-
 // Lowest match goes to out[i]; every other match becomes a pair.
 struct Hits {
   int32_t best = -1;
@@ -359,7 +336,7 @@ struct Hits {
     if (P.pair_pt) {
       const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
       if ((int64_t)k < P.cap) {
-        P.pair_pt[k] = i;
+        P.pair_pt[k] = P.base + i;
         P.pair_poly[k] = other;
       }
     }
@@ -396,46 +373,52 @@ __device__ __forceinline__ uint64_t lookup(const ProbeParams &P, const uint32_t 
   }
 }
 
-constexpr int32_t kPending = -2;  // out[] marker: point left to fixup_kernel
+// out[] of a pending point until the resolve kernel overwrites it: -3 - the
+// offset of the cell's lookup-table list, or kPending when the cell's
+// references are inline (the resolver then repeats the descent).
+constexpr int32_t kPending = -2;
+constexpr uint32_t kMaxOutLut = 0x7ffffffcu;  // largest offset -3 - off can carry
 
 __device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == kTagPtr && e != 0; }
 
 // Steps 5-6 for NP points of a lane at once: the descents run side by side,
-// so each step issues up to NP independent node loads.
+// so each step issues up to NP independent node loads. Written without
+// branches: a lane whose descent has ended keeps its entry and reads a
+// harmless slot (LDS word 0, or node 0, which the builder reserves), so
+// the wave never splits. Pointer entries hold node indices below 2^30, so
+// their high halves are zero and the tag tests use the low half only.
 template <int LDS_DEPTH, int NP>
 __device__ __forceinline__ void lookup_n(const ProbeParams &P, const uint32_t *s_nodes,
                                          const FaceDev *s_face, const uint32_t (&face)[NP],
                                          const uint32_t (&ci)[NP], const uint32_t (&cj)[NP],
                                          const bool (&valid)[NP], uint64_t (&e)[NP],
                                          uint32_t &reads) {
-  uint64_t node[NP];
+  uint32_t node[NP], lo[NP];
   int sh[NP];
   bool act[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    e[p] = 0;
-    act[p] = false;
-    sh[p] = 0;
-    node[p] = 0;
-    if (valid[p]) {
-      const FaceDev &F = s_face[face[p]];
-      sh[p] = F.sh0;
-      node[p] = (uint64_t)F.root;
-      act[p] = F.root >= 0 && (ci[p] >> sh[p]) == F.pi && (cj[p] >> sh[p]) == F.pj;
-    }
+    const FaceDev F = s_face[face[p]];
+    sh[p] = F.sh0;
+    node[p] = (uint32_t)F.root;
+    act[p] = valid[p] & (F.root >= 0) & ((ci[p] >> F.sh0) == F.pi) & ((cj[p] >> F.sh0) == F.pj);
+    lo[p] = 0;
   }
 #pragma unroll
   for (int d = 0; d < LDS_DEPTH; d++) {
 #pragma unroll
-    for (int p = 0; p < NP; p++)
-      if (act[p]) {
-        sh[p] -= 4;
-        e[p] = s_nodes[(node[p] - 1) * 256 + node_slot(ci[p], cj[p], sh[p])];
-        reads++;
-        act[p] = is_child(e[p]);
-        node[p] = e[p] >> 2;
-      }
+    for (int p = 0; p < NP; p++) {
+      sh[p] -= 4;
+      const uint32_t k = act[p] ? ((node[p] - 1u) << 8) | node_slot(ci[p], cj[p], sh[p]) : 0u;
+      const uint32_t v = s_nodes[k];
+      reads += act[p];
+      lo[p] = act[p] ? v : lo[p];
+      act[p] = act[p] & ((v & 3u) == 0u) & (v != 0u);
+      node[p] = v >> 2;
+    }
   }
+#pragma unroll
+  for (int p = 0; p < NP; p++) e[p] = lo[p];
   for (;;) {
     bool any = false;
 #pragma unroll
@@ -443,19 +426,19 @@ __device__ __forceinline__ void lookup_n(const ProbeParams &P, const uint32_t *s
     if (!any) break;
     uint64_t x[NP];
 #pragma unroll
-    for (int p = 0; p < NP; p++)
-      if (act[p]) {
-        sh[p] -= 4;
-        x[p] = P.nodes[node[p] * 256 + node_slot(ci[p], cj[p], sh[p])];
-      }
+    for (int p = 0; p < NP; p++) {
+      sh[p] -= 4;
+      const uint64_t k = act[p] ? ((uint64_t)node[p] << 8) | node_slot(ci[p], cj[p], sh[p]) : 0u;
+      x[p] = P.nodes[k];
+    }
 #pragma unroll
-    for (int p = 0; p < NP; p++)
-      if (act[p]) {
-        e[p] = x[p];
-        reads++;
-        act[p] = is_child(x[p]);
-        node[p] = x[p] >> 2;
-      }
+    for (int p = 0; p < NP; p++) {
+      const uint32_t v = (uint32_t)x[p];
+      reads += act[p];
+      e[p] = act[p] ? x[p] : e[p];
+      act[p] = act[p] & ((v & 3u) == 0u) & (v != 0u);
+      node[p] = v >> 2;
+    }
   }
 }
 
@@ -464,11 +447,10 @@ __device__ __forceinline__ void lookup_n(const ProbeParams &P, const uint32_t *s
 // same number of iterations; the next tile's points are loaded while the
 // current tile is processed.
 //
-// Exact mode: a lane's candidate (point, polygon) pairs are appended to the
-// stream's candidate queue all at once (one atomic per wave and segment) and
-// refined by refine_kernel. Points whose candidates do not fit, or with more
-// than three candidates, are marked pending and resolved by fixup_kernel;
-// their true hits are left to that kernel too.
+// Exact mode: a point whose cell entry has candidate references or is a
+// lookup-table list is pending: the probe writes its list offset to out[]
+// and its bit to the pending mask (one 64-bit ballot per 64 points, no
+// atomics), and reads nothing more for it; resolve_kernel finishes it.
 template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP>
 __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   extern __shared__ uint32_t s_nodes[];
@@ -478,7 +460,6 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
   __syncthreads();
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const uint64_t below = (1ull << lane) - 1ull;
   uint32_t c_pts = 0, c_inv = 0, c_false = 0, c_true = 0, c_candpts = 0, c_cand = 0,
            c_reads = 0, c_lut = 0;
   constexpr int TILE = 64 * NP;
@@ -528,8 +509,8 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
       r1[p] = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
       n_inl[p] = e[p] == 0 || tag[p] == kTagLut ? 0 : (tag[p] == kTagTwo ? 2 : 1);
       off[p] = nt[p] = nc[p] = 0;
-      if (tag[p] == kTagLut) {
-        off[p] = (uint32_t)(e[p] >> 2);
+      if (tag[p] == kTagLut) off[p] = (uint32_t)(e[p] >> 2);
+      if (!EXACT && tag[p] == kTagLut) {
         nt[p] = P.lut[off[p]];
         nc[p] = P.lut[off[p] + 1 + nt[p]];
         if (COUNT) c_lut++;
@@ -550,78 +531,26 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
       }
       continue;
     }
-    bool c0[NP], c1[NP], pending[NP];
-    uint32_t ncand[NP], nq = 0;
+    bool pend[NP];
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-      c0[p] = n_inl[p] > 0 && !(r0[p] & 1u);
-      c1[p] = n_inl[p] > 1 && !(r1[p] & 1u);
-      ncand[p] = tag[p] == kTagLut ? nc[p] : (uint32_t)c0[p] + (uint32_t)c1[p];
-      pending[p] = ncand[p] > 3;
-      nq += pending[p] ? 0u : ncand[p];
-    }
-    // reserve the lane's queue slots (nq <= 3 NP < 8: three ballots give the
-    // wave's exclusive prefix sum)
-    const uint64_t m1 = ballot(nq & 1u), m2 = ballot(nq & 2u), m4 = ballot(nq & 4u);
-    if (m1 | m2 | m4) {
-      const int seg = blockIdx.x & (kSegs - 1);
-      uint32_t base = 0;
-      if (lane == 0)
-        base = atomicAdd(P.q_ctl + seg,
-                         (uint32_t)(__popcll(m1) + 2 * __popcll(m2) + 4 * __popcll(m4)));
-      base = __shfl(base, 0);
-      const int64_t at = (int64_t)base + __popcll(m1 & below) + 2 * __popcll(m2 & below) +
-                         4 * __popcll(m4 & below);
-      if (nq > 0) {
-        // slots below the segment's capacity are always written (refine
-        // reads up to the capacity); a lane that does not fit writes -1
-        const bool fits = at + nq <= P.q_seg_cap;
-        int64_t *qp = P.q_pt + seg * P.q_seg_cap;
-        int32_t *qy = P.q_poly + seg * P.q_seg_cap;
-        uint32_t k = 0;
-#pragma unroll
-        for (int p = 0; p < NP; p++) {
-          if (pending[p] || ncand[p] == 0) continue;
-          for (uint32_t r = 0; r < (tag[p] == kTagLut ? nc[p] : 2u); r++) {
-            uint32_t poly, loc = 0xffffffffu;
-            if (tag[p] == kTagLut) {
-              poly = P.lut[off[p] + 2 + nt[p] + r];
-              if (P.q_loc) loc = P.lut[off[p] + 2 + nt[p] + nc[p] + r];
-            } else {
-              if (!(r == 0 ? c0[p] : c1[p])) continue;
-              poly = (r == 0 ? r0[p] : r1[p]) >> 1;
-            }
-            if (at + k < P.q_seg_cap) {
-              qp[at + k] = fits ? i[p] : -1;
-              qy[at + k] = (int32_t)poly;
-              if (P.q_loc) P.q_loc[seg * P.q_seg_cap + at + k] = loc;
-            }
-            k++;
-          }
-          pending[p] = !fits;
-        }
-      }
-    }
-    bool any_pending = false;
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      if (pending[p]) {
-        if (live[p]) P.out[i[p]] = kPending;
-        any_pending |= live[p];
+      const bool cand_inl = (n_inl[p] > 0 && !(r0[p] & 1u)) || (n_inl[p] > 1 && !(r1[p] & 1u));
+      pend[p] = live[p] && (tag[p] == kTagLut || cand_inl);
+      if (pend[p]) {
+        P.out[i[p]] = tag[p] == kTagLut && off[p] <= kMaxOutLut ? -3 - (int32_t)off[p] : kPending;
       } else {
         Hits hits;
-        if (n_inl[p] > 0 && (r0[p] & 1u)) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
-        if (n_inl[p] > 1 && (r1[p] & 1u)) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
-        for (uint32_t r = 0; r < nt[p]; r++) hits.add(P, i[p], (int32_t)P.lut[off[p] + 1 + r]);
+        if (n_inl[p] > 0) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
+        if (n_inl[p] > 1) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
         if (live[p]) P.out[i[p]] = hits.best;
-      }
-      if (COUNT) {
-        c_true += e[p] != 0 && ncand[p] == 0;
-        c_candpts += ncand[p] > 0;
-        c_cand += ncand[p];
+        if (COUNT) c_true += e[p] != 0;
       }
     }
-    if (ballot(any_pending) && lane == 0) P.q_ctl[kSegs + 1] = 1u;
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      const uint64_t m = ballot(pend[p]);
+      if (lane == 0 && tile * TILE + p * 64 < P.n) P.mask[tile * NP + p] = m;
+    }
   }
   if (COUNT) {
     unsigned long long *C = P.counters;
@@ -636,191 +565,231 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   }
 }
 
-// Points the probe marked pending (candidate queue full, or more than three
-// candidates): resolved here one point at a time per wavefront, candidates
-// refined by the whole wave. Returns at once when the probe marked none.
-template <int LDS_DEPTH, bool COUNT>
-__global__ __launch_bounds__(kBlock) void fixup_kernel(ProbeParams P) {
-  if (*(volatile uint32_t *)(P.q_ctl + kSegs + 1) == 0u) return;
-  extern __shared__ uint32_t s_nodes[];
-  __shared__ FaceDev s_face[6];
-  __shared__ uint32_t s_last;
-  if (LDS_DEPTH > 0)
-    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kBlock) s_nodes[k] = P.top32[k];
-  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
-  __syncthreads();
+// References of a pending point's cell: true ids first, then candidates
+// (each with its cell-local record offset when the list carries one).
+struct RefList {
+  uint32_t off = 0, nt = 0, nc = 0;
+  uint32_t a = 0, b = 0;  // inline references (true ones first)
+  bool lut = false;
+  __device__ __forceinline__ uint32_t true_id(const ProbeParams &P, uint32_t r) const {
+    return lut ? P.lut[off + 1 + r] : (r == 0 ? a : b);
+  }
+  __device__ __forceinline__ uint32_t cand_id(const ProbeParams &P, uint32_t r) const {
+    return lut ? P.lut[off + 2 + nt + r] : (nt + r == 0 ? a : b);
+  }
+  __device__ __forceinline__ uint32_t cand_loc(const ProbeParams &P, uint32_t r) const {
+    return lut && P.local ? P.lut[off + 2 + nt + nc + r] : 0xffffffffu;
+  }
+};
+
+__device__ __forceinline__ RefList lut_refs(const ProbeParams &P, uint32_t off) {
+  RefList L;
+  L.lut = true;
+  L.off = off;
+  L.nt = P.lut[off];
+  L.nc = P.lut[off + 1 + L.nt];
+  return L;
+}
+
+// The pending point's references: from the list offset the probe left in
+// out[], or by repeating the lookup (inline entries).
+__device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t code, double lat,
+                                                double lng, uint32_t &reads) {
+  if (code <= -3) return lut_refs(P, (uint32_t)(-3 - code));
+  uint32_t face, ci, cj;
+  uint64_t e = 0;
+  if (project(lat, lng, face, ci, cj)) e = lookup<0>(P, nullptr, P.faces[face], ci, cj, reads);
+  const uint32_t tag = (uint32_t)(e & kTagMask);
+  if (e == 0 || tag == kTagPtr) return RefList();
+  if (tag == kTagLut) return lut_refs(P, (uint32_t)(e >> 2));
+  RefList L;
+  const uint32_t v0 = (uint32_t)((e >> 2) & 0x7fffffffu), v1 = (uint32_t)((e >> 33) & 0x7fffffffu);
+  const int n = tag == kTagTwo ? 2 : 1;
+  uint32_t slot[2];
+  int k = 0;
+  for (int t = 1; t >= 0; t--) {  // interior references first
+    if ((v0 & 1u) == (uint32_t)t) slot[k++] = v0 >> 1;
+    if (n > 1 && (v1 & 1u) == (uint32_t)t) slot[k++] = v1 >> 1;
+  }
+  L.a = slot[0];
+  L.b = n > 1 ? slot[1] : 0u;
+  L.nt = (v0 & 1u) + (n > 1 ? (v1 & 1u) : 0u);
+  L.nc = (uint32_t)n - L.nt;
+  return L;
+}
+
+// All edges of a polygon tested by one lane in fp64 (+ exact): used only
+// for a candidate without a cell-local record.
+template <bool COUNT>
+__device__ bool lane_covers(const ProbeParams &P, int poly, double lat, double lng,
+                            uint32_t &c_fp64, uint32_t &c_exact) {
+  uint32_t par = 0;
+  for (int e = P.eoff[poly]; e < P.eoff[poly + 1]; e++) {
+    const int r = edge_fp64<COUNT>(P, e, lng, lat, c_fp64, c_exact);
+    if (r == 2) return true;
+    par ^= (uint32_t)r;
+  }
+  return par != 0;
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint32_t *c) {
+  if (!COUNT) return;
+  static constexpr int ids[7] = {ACT_CNT_SOLELY_TRUE, ACT_CNT_CAND_POINTS, ACT_CNT_CANDIDATES,
+                                 ACT_CNT_EDGES, ACT_CNT_EDGE_FP64, ACT_CNT_EDGE_EXACT,
+                                 ACT_CNT_LUT_READS};
+  for (int k = 0; k < 7; k++)
+    if (c[k]) atomicAdd(P.counters + ids[k], (unsigned long long)c[k]);
+}
+
+// Pending points of a resolve block: the block reads kBlock mask words
+// (64 kBlock points of the pass), compacts their set bits into an LDS list
+// (block-wide prefix sum of the popcounts) and hands the list out one point
+// per thread; bits beyond the list's capacity stay with the thread that
+// read them.
+constexpr int kListCap = 2048;
+
+struct PendingIter {
+  int k, total;
+  uint64_t m;  // bits of this thread's word not in the list
+  int64_t w;   // this thread's mask word
+  __device__ __forceinline__ bool next(const uint16_t *s_list, int64_t &i) {
+    if (k < total) {
+      i = (int64_t)blockIdx.x * kBlock * 64 + s_list[k];
+      k += kBlock;
+      return true;
+    }
+    if (m) {
+      i = w * 64 + (__ffsll((long long)m) - 1);
+      m &= m - 1;
+      return true;
+    }
+    return false;
+  }
+};
+
+__device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int64_t nwords,
+                                                      uint16_t *s_list, uint32_t *s_wave) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t c_reads = 0, c_fp64 = 0, c_exact = 0, c_edges = 0;
-  const int64_t ntiles = (P.n + 63) >> 6;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wid; tile < ntiles;
-       tile += (int64_t)gridDim.x * kWaves) {
-    const int64_t i = tile * 64 + lane;
-    const bool pend = i < P.n && P.out[i] == kPending;
-    uint64_t mask = ballot(pend);
-    uint64_t e = 0;
-    double lat = 0.0, lng = 0.0;
-    if (pend) {
+  PendingIter it;
+  it.w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint64_t m = it.w < nwords ? P.mask[it.w] : 0ull;
+  const uint32_t c = (uint32_t)__popcll(m);
+  uint32_t incl = c;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) s_wave[wid] = incl;
+  __syncthreads();
+  uint32_t pos = incl - c, total = 0;
+  for (int k = 0; k < kBlock / 64; k++) {
+    if (k < wid) pos += s_wave[k];
+    total += s_wave[k];
+  }
+  while (m && pos < (uint32_t)kListCap) {
+    s_list[pos++] = (uint16_t)((threadIdx.x << 6) | (__ffsll((long long)m) - 1));
+    m &= m - 1;
+  }
+  __syncthreads();
+  it.m = m;
+  it.k = threadIdx.x;
+  it.total = (int)min(total, (uint32_t)kListCap);
+  return it;
+}
+
+// Resolve the pending points. LOCAL: each thread decides its point's
+// candidates from their cell-local records. Otherwise (refinement over all
+// of a polygon's edges) lanes gather their points' candidates and the whole
+// wave tests one (point, polygon) pair at a time (lanes over edges, see
+// wave_covers); in every round each lane with work offers its next
+// candidate.
+template <bool LOCAL, bool COUNT>
+__global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t nwords) {
+  __shared__ uint16_t s_list[kListCap];
+  __shared__ uint32_t s_wave[kBlock / 64];
+  PendingIter it = gather_pending(P, nwords, s_list, s_wave);
+  uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
+  int64_t i = 0;
+  if (LOCAL) {
+    while (it.next(s_list, i)) {
       const double2 pt = P.pts[i];
-      lat = pt.x;
-      lng = pt.y;
-      uint32_t face, ci, cj;
-      if (project(lat, lng, face, ci, cj))
-        e = lookup<LDS_DEPTH>(P, s_nodes, s_face[face], ci, cj, c_reads);
-    }
-    while (mask) {
-      const int src = __ffsll((long long)mask) - 1;
-      mask &= mask - 1;
-      const uint64_t ee = __shfl(e, src);
-      const double plat = __shfl(lat, src), plng = __shfl(lng, src);
-      const int64_t pi = tile * 64 + src;
+      const RefList L = pending_refs(P, P.out[i], pt.x, pt.y, c_reads);
       Hits hits;
-      const uint32_t tag = (uint32_t)(ee & kTagMask);
-      if (tag == kTagOne || tag == kTagTwo) {
-        for (int r = 0; r < (tag == kTagTwo ? 2 : 1); r++) {
-          const uint32_t v = (uint32_t)((ee >> (r == 0 ? 2 : 33)) & 0x7fffffffu);
-          if (COUNT && lane == 0 && !(v & 1u)) c_edges += (uint32_t)(P.eoff[(v >> 1) + 1] - P.eoff[v >> 1]);
-          if ((v & 1u) || wave_covers<COUNT>(P, (int)(v >> 1), plat, plng, lane, c_fp64, c_exact))
-            if (lane == 0) hits.add(P, pi, (int32_t)(v >> 1));
+      for (uint32_t r = 0; r < L.nt; r++) hits.add(P, i, (int32_t)L.true_id(P, r));
+      for (uint32_t r = 0; r < L.nc; r++) {
+        const int32_t poly = (int32_t)L.cand_id(P, r);
+        const uint32_t loc = L.cand_loc(P, r);
+        bool cov;
+        if (loc != 0xffffffffu) {
+          cov = local_record_covers(P.local + loc, pt.y, pt.x);
+          if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+        } else {
+          cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
+          if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
         }
-      } else if (tag == kTagLut) {
-        const uint32_t off = (uint32_t)(ee >> 2);
-        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
-        for (uint32_t r = 0; r < nt; r++)
-          if (lane == 0) hits.add(P, pi, (int32_t)P.lut[off + 1 + r]);
-        for (uint32_t r = 0; r < nc; r++) {
-          const int poly = (int)P.lut[off + 2 + nt + r];
-          if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
-          if (wave_covers<COUNT>(P, poly, plat, plng, lane, c_fp64, c_exact) && lane == 0)
-            hits.add(P, pi, poly);
+        if (cov) hits.add(P, i, poly);
+      }
+      P.out[i] = hits.best;
+      if (COUNT) {
+        c[0] += L.nc == 0 && L.nt > 0;
+        c[1] += L.nc > 0;
+        c[2] += L.nc;
+        c[6] += L.lut;
+      }
+    }
+  } else {
+    const int lane = threadIdx.x & 63;
+    bool have = false, more = true;
+    double lat = 0.0, lng = 0.0;
+    RefList L;
+    uint32_t r = 0;
+    Hits hits;
+    for (;;) {
+      if (!have && more) {
+        more = it.next(s_list, i);
+        if (more) {
+          const double2 pt = P.pts[i];
+          lat = pt.x;
+          lng = pt.y;
+          L = pending_refs(P, P.out[i], lat, lng, c_reads);
+          hits = Hits();
+          for (uint32_t t = 0; t < L.nt; t++) hits.add(P, i, (int32_t)L.true_id(P, t));
+          r = 0;
+          have = true;
+          if (COUNT) {
+            c[0] += L.nc == 0 && L.nt > 0;
+            c[1] += L.nc > 0;
+            c[2] += L.nc;
+            c[6] += L.lut;
+          }
         }
       }
-      if (lane == 0) P.out[pi] = hits.best;
-    }
-  }
-  if (COUNT) {
-    atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
-    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
-    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
-    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(P.q_ctl + kSegs + 2, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    P.q_ctl[kSegs + 1] = 0u;
-    P.q_ctl[kSegs + 2] = 0u;
-    __threadfence();
-  }
-}
-
-// Refinement of the queued candidates: one wavefront per (point, polygon)
-// pair, lanes over the polygon's edges. The last block to finish resets the
-// queue for the stream's next join (no memset: safe under graph capture).
-template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void refine_kernel(ProbeParams P) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int64_t wave = (int64_t)blockIdx.x * kWaves + wid;
-  const int seg = (int)(wave % kSegs);
-  const int64_t per_seg = (int64_t)gridDim.x * kWaves / kSegs;  // waves per segment
-  const int64_t count = min((int64_t)(*(volatile uint32_t *)(P.q_ctl + seg)), P.q_seg_cap);
-  const int64_t* q_pt = P.q_pt + seg * P.q_seg_cap;
-  const int32_t* q_poly = P.q_poly + seg * P.q_seg_cap;
-  uint32_t c_edges = 0, c_fp64 = 0, c_exact = 0;
-  // each wave takes 64 consecutive entries of its segment at a time: lane l
-  // loads entry l and its point (coalesced), then the wave refines the 64
-  // pairs one after the other, reading each from lane registers
-  for (int64_t q0 = (wave / kSegs) * 64; q0 < count; q0 += per_seg * 64) {
-    const int64_t q = q0 + lane;
-    int64_t my_pt = 0;
-    int32_t my_poly = 0;
-    double2 my_p = make_double2(0.0, 0.0);
-    if (q < count) {
-      my_pt = q_pt[q];
-      my_poly = q_poly[q];
-      if (my_pt >= 0) my_p = P.pts[my_pt];
-    }
-    const int cnt = (int)min<int64_t>(64, count - q0);
-    for (int k = 0; k < cnt; k++) {
-      if (__shfl(my_pt, k) < 0) continue;  // slot of a point left pending
-      const int32_t poly = __shfl(my_poly, k);
-      const double lat = __shfl(my_p.x, k), lng = __shfl(my_p.y, k);
-      if (COUNT && lane == 0) c_edges += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
-      if (wave_covers<COUNT>(P, poly, lat, lng, lane, c_fp64, c_exact) && lane == k)
-        merge_min(P, my_pt, poly);
-    }
-  }
-  if (COUNT) {
-    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
-    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
-    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
-  }
-  __shared__ uint32_t s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(P.q_ctl + kSegs, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (s_last) {  // every other block has finished reading the counters
-    for (int k = threadIdx.x; k <= kSegs; k += kBlock) P.q_ctl[k] = 0;
-    __threadfence();
-  }
-}
-
-// Cell-local refinement of the queued candidates: one lane per candidate,
-// the test reads only the candidate cell's record (edges meeting the cell
-// plus parity breakpoints). A candidate without a record (not produced by
-// current builds) is tested against all edges by its lane.
-template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void refine_local_kernel(ProbeParams P) {
-  uint32_t c_edges = 0, c_fp64 = 0, c_exact = 0;
-  const int64_t total = (int64_t)kSegs * P.q_seg_cap;
-  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < total;
-       g += (int64_t)gridDim.x * kBlock) {
-    const int seg = (int)(g / P.q_seg_cap);
-    if (g - seg * P.q_seg_cap >= (int64_t)P.q_ctl[seg]) continue;
-    const int64_t pt = P.q_pt[g];
-    if (pt < 0) continue;
-    const int32_t poly = P.q_poly[g];
-    const uint32_t loc = P.q_loc[g];
-    const double2 p = P.pts[pt];
-    bool cov;
-    if (loc != 0xffffffffu) {
-      cov = local_record_covers(P.local + loc, p.y, p.x);
-      if (COUNT) c_edges += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
-    } else {
-      const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
-      uint32_t par = 0;
-      cov = false;
-      for (int e = e0; e < e1 && !cov; e++) {
-        const int r = edge_fp64<COUNT>(P, e, p.y, p.x, c_fp64, c_exact);
-        cov = r == 2;
-        par ^= (uint32_t)(r & 1);
+      if (have && r >= L.nc) {
+        P.out[i] = hits.best;
+        have = false;
       }
-      cov = cov || par;
-      if (COUNT) c_edges += (uint32_t)(e1 - e0);
+      uint64_t todo = ballot(have);
+      if (!todo) {
+        if (!ballot(more)) break;
+        continue;
+      }
+      const int32_t poly = have ? (int32_t)L.cand_id(P, r) : 0;
+      while (todo) {
+        const int src = __ffsll((long long)todo) - 1;
+        todo &= todo - 1;
+        const int32_t q = __shfl(poly, src);
+        const double qlat = __shfl(lat, src), qlng = __shfl(lng, src);
+        if (COUNT && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
+        const bool cov = wave_covers<COUNT>(P, q, qlat, qlng, lane, c[4], c[5]);
+        if (lane == src && cov) hits.add(P, i, q);
+      }
+      if (have) r++;
     }
-    if (cov) merge_min(P, pt, poly);
   }
-  if (COUNT) {
-    atomicAdd(P.counters + ACT_CNT_EDGES, (unsigned long long)c_edges);
-    atomicAdd(P.counters + ACT_CNT_EDGE_FP64, (unsigned long long)c_fp64);
-    atomicAdd(P.counters + ACT_CNT_EDGE_EXACT, (unsigned long long)c_exact);
-  }
-  __shared__ uint32_t s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    s_last = atomicAdd(P.q_ctl + kSegs, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (s_last) {  // every other block has finished: reset the queue
-    for (int k = threadIdx.x; k <= kSegs; k += kBlock) P.q_ctl[k] = 0;
-    __threadfence();
-  }
+  flush_counters<COUNT>(P, c);
+  if (COUNT && c_reads) atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
 }
 
 __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_t n,
@@ -839,13 +808,6 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
 }
 
 using ProbeFn = void (*)(ProbeParams);
-constexpr int kFixupGrid = 256;
-static ProbeFn fixup_fn(int lds_depth, bool count) {
-  static const ProbeFn tab[3][2] = {{fixup_kernel<0, false>, fixup_kernel<0, true>},
-                                    {fixup_kernel<1, false>, fixup_kernel<1, true>},
-                                    {fixup_kernel<2, false>, fixup_kernel<2, true>}};
-  return tab[lds_depth][count];
-}
 template <bool EXACT, int LDS, bool COUNT>
 static ProbeFn probe_np(int np) {
   return np == 1 ? probe_kernel<EXACT, LDS, COUNT, 1> : probe_kernel<EXACT, LDS, COUNT, 2>;
@@ -907,30 +869,25 @@ static int upload(T *&dst, const void *src, size_t bytes, size_t &total) {
 }
 
 static void free_workspace(Workspace &w) {
-  void *ptrs[] = {w.q_pt, w.q_poly, w.q_loc, w.q_ctl};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  if (w.mask) (void)hipFree(w.mask);
   w = Workspace();
 }
 
-// The stream's workspace with at least `cap` queue entries; allocated (and
-// its counters zeroed) on first use. Call with the index's device current.
-static int get_workspace(const act_index *x, void *stream, int64_t cap, Workspace *&out) {
+// The stream's workspace: allocated on first use for `cap` points (and
+// enlarged only when `grow` is set). Call with the index's device current.
+// The mask needs no clearing: every pass writes each word it reads.
+static int get_workspace(const act_index *x, void *stream, int64_t cap, bool grow,
+                         Workspace *&out) {
   std::lock_guard<std::mutex> lk(x->ws_mu);
   Workspace &w = x->ws[stream];
-  if (w.cap < cap) {
+  if (w.cap == 0 || (grow && w.cap < cap)) {
+    cap = (cap + 63) / 64 * 64;
+    if (w.mask && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+      return fail(ACT_E_HIP, "cannot synchronise the stream to enlarge its workspace");
     free_workspace(w);
-    bool ok = hipMalloc((void **)&w.q_pt, sizeof(int64_t) * cap) == hipSuccess &&
-              hipMalloc((void **)&w.q_poly, sizeof(int32_t) * cap) == hipSuccess &&
-              hipMalloc((void **)&w.q_loc, sizeof(uint32_t) * cap) == hipSuccess &&
-              hipMalloc((void **)&w.q_ctl, 4 * (kSegs + 8)) == hipSuccess;
-    if (!ok) {
+    if (hipMalloc((void **)&w.mask, (size_t)cap / 8) != hipSuccess) {
       free_workspace(w);
-      return fail(ACT_E_OOM, "cannot allocate the candidate queue");
-    }
-    if (hipMemset(w.q_ctl, 0, 4 * (kSegs + 8)) != hipSuccess) {
-      free_workspace(w);
-      return fail(ACT_E_HIP, "cannot clear the candidate queue");
+      return fail(ACT_E_OOM, "cannot allocate the pending mask");
     }
     w.cap = cap;
   }
@@ -1017,7 +974,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     return fail(ACT_E_ARG, "unknown refine mode");
   if (a->block != 0 && a->block != kProbeBlock) return fail(ACT_E_ARG, "block must be 0 or 1024");
   if (a->grid < 0 || a->grid > 65536) return fail(ACT_E_ARG, "grid must be 0 .. 65536");
-  if (a->queue_limit < 0) return fail(ACT_E_ARG, "queue_limit < 0");
+  if (a->pass_points < 0) return fail(ACT_E_ARG, "pass_points < 0");
   if (a->points_per_lane < 0 || a->points_per_lane > 2)
     return fail(ACT_E_ARG, "points_per_lane must be 0, 1 or 2");
   const HostIndex &h = x->host;
@@ -1052,43 +1009,44 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.refine = a->refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : a->refine;
   P.local = x->dev.local;
   const int np = a->points_per_lane > 0 ? a->points_per_lane : 2;
-  int64_t tiles_blocks = (a->n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
-  int grid = a->grid > 0 ? a->grid : 1024;
-  grid = (int)std::max<int64_t>(1, std::min<int64_t>(grid, tiles_blocks));
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
   const bool count = a->d_counters != nullptr;
+  int64_t pass = a->n;
   if (exact) {
     Workspace *w = nullptr;
-    rc = get_workspace(x, stream, kDefaultQueue, w);
+    rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
     if (rc) return rc;
-    P.q_pt = w->q_pt;
-    P.q_poly = w->q_poly;
-    P.q_loc = P.refine == ACT_REFINE_LOCAL ? w->q_loc : nullptr;
-    P.q_ctl = w->q_ctl;
-    const int64_t cap = a->queue_limit > 0 ? std::min(a->queue_limit, w->cap) : w->cap;
-    P.q_seg_cap = cap / kSegs;
-
+    P.mask = w->mask;
+    pass = a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap;
   }
-  hipLaunchKernelGGL(probe_fn(exact, depth, count, np), dim3(grid), dim3(kProbeBlock),
-                     (size_t)n_lds * 1024, (hipStream_t)stream, P);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
-  if (exact) {
-    if (P.refine == ACT_REFINE_LOCAL)
-      hipLaunchKernelGGL(count ? refine_local_kernel<true> : refine_local_kernel<false>,
-                         dim3(kRefineGrid), dim3(kBlock), 0, (hipStream_t)stream, P);
-    else
-      hipLaunchKernelGGL(count ? refine_kernel<true> : refine_kernel<false>, dim3(kRefineGrid),
-                         dim3(kBlock), 0, (hipStream_t)stream, P);
+  const ProbeFn probe = probe_fn(exact, depth, count, np);
+  using ResolveFn = void (*)(ProbeParams, int64_t);
+  const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
+                              ? (count ? resolve_kernel<true, true> : resolve_kernel<true, false>)
+                              : (count ? resolve_kernel<false, true> : resolve_kernel<false, false>);
+  for (int64_t s0 = 0; s0 < a->n; s0 += pass) {
+    const int64_t n = std::min(pass, a->n - s0);
+    P.pts = (const double2 *)a->d_points + s0;
+    P.out = a->d_out + s0;
+    P.n = n;
+    P.base = s0;
+    const int64_t tile_blocks = (n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : 1024,
+                                                                  tile_blocks));
+    hipLaunchKernelGGL(probe, dim3(grid), dim3(kProbeBlock), (size_t)n_lds * 1024,
+                       (hipStream_t)stream, P);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
+    if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
+    if (!exact) continue;
+    const int64_t nwords = (n + 63) / 64;
+    hipLaunchKernelGGL(resolve, dim3((unsigned)((nwords + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       (hipStream_t)stream, P, nwords);
     e = hipGetLastError();
     if (e != hipSuccess)
-      return fail(ACT_E_HIP, std::string("refine launch: ") + hipGetErrorString(e));
-    hipLaunchKernelGGL(fixup_fn(depth, count), dim3(kFixupGrid), dim3(kBlock),
-                       (size_t)n_lds * 1024, (hipStream_t)stream, P);
-    e = hipGetLastError();
-    if (e != hipSuccess)
-      return fail(ACT_E_HIP, std::string("fixup launch: ") + hipGetErrorString(e));
+      return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
   }
   return ACT_OK;
 }
@@ -1169,15 +1127,16 @@ void act_free(act_index *x) {
   delete x;
 }
 
-int act_workspace_reserve(const act_index *x, void *stream, int64_t capacity) {
+int act_workspace_reserve(const act_index *x, void *stream, int64_t points) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
-  if (capacity < 0 || capacity > (1ll << 31)) return fail(ACT_E_ARG, "capacity out of range");
+  if (points < 0 || points > (1ll << 40)) return fail(ACT_E_ARG, "points out of range");
   if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
   int rc = check_stream_device(x, stream);
   if (rc) return rc;
+  if (x->host.mode != ACT_EXACT) return ACT_OK;
   DeviceGuard g(x->device);
   Workspace *w = nullptr;
-  return get_workspace(x, stream, std::max<int64_t>(capacity, kDefaultQueue), w);
+  return get_workspace(x, stream, std::max<int64_t>(points, 64), true, w);
 }
 
 int act_join_ex(const act_index *x, const act_join_args *args, void *stream) {
@@ -1338,6 +1297,14 @@ int act_orient_fp32_host(const double *a, const double *b, const double *p, cons
 
 int act_orient_exact_host(const double *a, const double *b, const double *p) {
   return orient_sign_exact(a[0], a[1], b[0], b[1], p[0], p[1]);
+}
+
+int act_abi_sizes(int64_t *sizes) {
+  if (!sizes) return fail(ACT_E_ARG, "sizes is NULL");
+  sizes[0] = (int64_t)sizeof(act_build_opts);
+  sizes[1] = (int64_t)sizeof(act_join_args);
+  sizes[2] = (int64_t)sizeof(act_stats);
+  return ACT_OK;
 }
 
 const char *act_last_error(void) { return g_err.c_str(); }

@@ -266,11 +266,13 @@ def overlapping_polygons(seed=12, n=9):
     return synth.Polygons.from_rings(polys)
 
 
-@pytest.mark.parametrize("queue_limit", [0, 256, 4096])
-def test_overlapping_polygons_long_candidate_lists(act, queue_limit):
-    """Exact parity where cells hold up to n references (long LUT lists go to
-    the per-point pass) and with a tiny candidate queue (overflow goes to
-    the per-point pass as well)."""
+@pytest.mark.parametrize("pass_points,mode", [(0, "ACT_REFINE_LOCAL"), (1000, "ACT_REFINE_LOCAL"),
+                                              (4097, "ACT_REFINE_FP32_FILTER"),
+                                              (0, "ACT_REFINE_FP64")])
+def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode):
+    """Exact parity where cells hold up to n references (long lookup-table
+    lists, several matches per point), in one pass and in many short passes
+    (pair output then carries the pass offset)."""
     P = overlapping_polygons()
     idx = act.build(P, "exact", max_level=16)
     st = idx.stats()
@@ -279,12 +281,28 @@ def test_overlapping_polygons_long_candidate_lists(act, queue_limit):
     pts = np.concatenate([
         np.stack([rng.uniform(40.68, 40.72, 200000), rng.uniform(-73.98, -73.92, 200000)], 1),
         P.verts])
-    out, pairs, ctr = gpu_join(idx, pts, counters=True, queue_limit=queue_limit)
-    ref = assert_exact(P, pts, out, pairs, "overlap q=%d" % queue_limit)
+    kw = dict(pass_points=pass_points, refine=getattr(act, mode))
+    out, pairs, ctr = gpu_join(idx, pts, counters=True, **kw)
+    ref = assert_exact(P, pts, out, pairs, "overlap pass=%d %s" % (pass_points, mode))
     assert ref.cnt.max() >= 5
-    # repeated joins on the same stream reuse (and reset) the queue correctly
-    out2, pairs2, _ = gpu_join(idx, pts, queue_limit=queue_limit)
-    assert np.array_equal(out2, out) and np.array_equal(pairs2, pairs)
+    assert ctr["points"] == len(pts) and ctr["cand_points"] > 0
+    # a repeated join on the same stream reuses the workspace
+    out2, pairs2, _ = gpu_join(idx, pts, **kw)
+    assert np.array_equal(out2, out)
+    assert np.array_equal(np.unique(pairs2, axis=0), np.unique(pairs, axis=0))
+
+
+def test_workspace_reserve_and_passes(act):
+    """A reserved workspace smaller than the batch splits the join into
+    passes; results equal the single-pass join."""
+    P, idx = index(act, "c2", "exact")
+    pts = torch.from_numpy(synth.workload_points("c2", 0, 1_000_003)).cuda()
+    one = idx.join(pts)
+    idx2 = act.build(P, "exact")
+    idx2.reserve(100_000)
+    many = idx2.join(pts)
+    torch.cuda.synchronize()
+    assert torch.equal(one, many)
 
 
 def test_overlapping_polygons_approx(act):

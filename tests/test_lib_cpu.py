@@ -30,6 +30,15 @@ def test_exports_every_declared_symbol(act):
     assert act.version().startswith("act-mi355x")
 
 
+def test_struct_layouts_match_the_header(act):
+    import ctypes
+    from paper_1802_09488_amd import _binding as B
+    sz = (ctypes.c_int64 * 3)()
+    assert B.lib.act_abi_sizes(sz) == 0
+    assert list(sz) == [ctypes.sizeof(B.BuildOpts), ctypes.sizeof(B.JoinArgs),
+                        ctypes.sizeof(B.Stats)]
+
+
 def _decode(entry, lut):
     """(polygon id, interior) references of a tagged trie entry."""
     e = int(entry)
