@@ -82,11 +82,20 @@ typedef struct {
                           host-only index (inspection and tests; joins on it
                           return ACT_E_DEVICE)                               */
   int32_t threads;     /* host build threads (default 0 = hardware count)   */
-  int32_t reserved;
+  int32_t prefix_level; /* trie prefix level Lp of every face (Section III-D:
+                          the face's cells share their first Lp levels,
+                          nodes then cover levels Lp+1..Lp+4, Lp+5..Lp+8,
+                          ...); -1 (default) = the common-ancestor level of
+                          the face's cells, lowered (by at most 3) so that
+                          the finest cells end a node level; an explicit
+                          value is capped at the common-ancestor level      */
   double margin_deg;   /* conservative inflation of every cell's lat/lng box
                           before classification (default 1e-9 deg, which
                           covers fp64 projection rounding by >1e3x)          */
 } act_build_opts;
+
+/* Fills *opts with the defaults (the values act_build uses for NULL). */
+void act_build_opts_init(act_build_opts *opts);
 
 /*
  * act_build -- build an index over n_polys polygons (Sections III-B, III-C).

@@ -188,15 +188,17 @@ class Index:
 
 
 def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
-          device: int = 0, threads: int = 0, margin_deg: float = 0.0) -> Index:
-    """Build an index (host) and upload it to `device` (-1: host only)."""
+          device: int = 0, threads: int = 0, margin_deg: float = 0.0,
+          prefix_level: int = -1) -> Index:
+    """Build an index (host) and upload it to `device` (-1: host only).
+    prefix_level -1 lets the builder choose the trie's prefix level."""
     m = {"exact": ACT_EXACT, "approx": ACT_APPROX}.get(mode, mode)
     v = np.ascontiguousarray(polys.verts, dtype=np.float64)
     ro = np.ascontiguousarray(polys.ring_off, dtype=np.int64)
     pro = np.ascontiguousarray(polys.poly_ring_off, dtype=np.int32)
     n_polys = pro.shape[0] - 1
-    opts = _b.BuildOpts(max_level=max_level, device=device, threads=threads, reserved=0,
-                        margin_deg=margin_deg)
+    opts = _b.BuildOpts(max_level=max_level, device=device, threads=threads,
+                        prefix_level=prefix_level, margin_deg=margin_deg)
     h = ctypes.c_void_p()
     _b.check(lib.act_build(_np_ptr(v), _np_ptr(ro), _np_ptr(pro), n_polys, m, float(precision_m),
                            ctypes.byref(opts), ctypes.byref(h)))

@@ -33,7 +33,7 @@ class ActError(RuntimeError):
 
 class BuildOpts(ctypes.Structure):
     _fields_ = [("max_level", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("prefix_level", ctypes.c_int32),
                 ("margin_deg", ctypes.c_double)]
 
 
@@ -84,6 +84,7 @@ def _load():
         "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),
         "act_lut_host": ([p, p, p], ctypes.c_int),
         "act_abi_sizes": ([p], ctypes.c_int),
+        "act_build_opts_init": ([p], None),
         "act_refine_local_host": ([p, i32, ctypes.c_uint32, ctypes.c_uint32, d, d, i32, p],
                                   ctypes.c_int),
         "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),

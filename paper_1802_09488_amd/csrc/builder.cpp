@@ -509,21 +509,264 @@ static void renumber_breadth_first(HostIndex &x) {
   }
   std::vector<uint64_t> newidx(n_nodes, 0);
   for (size_t q = 0; q < order.size(); q++) newidx[order[q]] = q + 1;
-  std::vector<uint64_t> nn((order.size() + 1) * 256, 0);
-  for (size_t q = 0; q < order.size(); q++) {
-    const uint64_t *e = &x.nodes[order[q] * 256];
-    uint64_t *d = &nn[(q + 1) * 256];
+  for (size_t o = 1, q = order.size(); o < n_nodes; o++)  // unreachable nodes (none expected) last
+    if (newidx[o] == 0) newidx[o] = ++q;
+  order.clear();
+  order.shrink_to_fit();
+  // rewrite the child pointers, then move every node to its new index in
+  // place (cycle by cycle, one node of scratch)
+  for (size_t o = 1; o < n_nodes; o++) {
+    uint64_t *e = &x.nodes[o * 256];
     for (int b = 0; b < 256; b++)
-      d[b] = ((e[b] & kTagMask) == kTagPtr && e[b] != 0) ? (newidx[e[b] >> 2] << 2) : e[b];
+      if ((e[b] & kTagMask) == kTagPtr && e[b] != 0) e[b] = newidx[e[b] >> 2] << 2;
+  }
+  std::vector<bool> done(n_nodes, false);
+  uint64_t buf[256];
+  for (size_t s = 1; s < n_nodes; s++) {
+    if (done[s] || newidx[s] == s) continue;
+    std::memcpy(buf, &x.nodes[s * 256], sizeof buf);
+    size_t cur = s;
+    do {
+      const size_t d = newidx[cur];
+      done[cur] = true;
+      std::swap_ranges(buf, buf + 256, &x.nodes[d * 256]);
+      cur = d;
+    } while (cur != s);
   }
   for (int f = 0; f < 6; f++)
     if (x.faces[f].root >= 0) x.faces[f].root = (int32_t)newidx[x.faces[f].root];
-  x.nodes.swap(nn);
   x.n_d0 = x.n_d1 = 0;
   for (int d : depth) {
     x.n_d0 += d == 0;
     x.n_d1 += d == 1;
   }
+}
+
+// 30 bits of i and j interleaved (i above j at each level), so that sorting
+// by the key lists the cells in quadtree (depth-first) order.
+static uint64_t spread30(uint32_t v) {
+  uint64_t x = v & 0x3fffffffu;
+  x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+  x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+  x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+
+static uint64_t quad_key(uint32_t i, uint32_t j) { return (spread30(i) << 1) | spread30(j); }
+
+// Cells of the super covering, sorted by (face, quadtree key) for the trie
+// build.
+struct Cell {
+  int face, level;
+  uint32_t I, J;            // leaf coordinates of the cell's first leaf
+  uint64_t key;             // quadtree path of that leaf: bits of I and J interleaved
+  const uint32_t *refs;
+  const uint32_t *locs;
+  uint64_t local_base;      // offset of the cell's sink in the local records
+  int n;
+};
+
+constexpr int64_t kPrefixGrowth = 8;
+constexpr int64_t kPrefixMaxNodes = (4ll << 30) / 2048;  // 4 GiB of nodes
+
+// The cells of each face: range [c0, c1) of the sorted cells, the deepest
+// level all of them share (common ancestor, capped by the coarsest cell)
+// and the finest cell level.
+struct FaceCells {
+  size_t c0 = 0, c1 = 0;
+  int lc = 0, lmax = 0;
+};
+
+static void face_ranges(const std::vector<Cell> &cells, FaceCells fc[6]) {
+  size_t c0 = 0;
+  for (int face = 0; face < 6; face++) {
+    size_t c1 = c0;
+    while (c1 < cells.size() && cells[c1].face == face) c1++;
+    FaceCells &F = fc[face];
+    F.c0 = c0;
+    F.c1 = c1;
+    int lmin = 30, lmax = 0;
+    uint32_t diff = 0;
+    for (size_t k = c0; k < c1; k++) {
+      lmin = std::min(lmin, cells[k].level);
+      lmax = std::max(lmax, cells[k].level);
+      diff |= (cells[k].I ^ cells[c0].I) | (cells[k].J ^ cells[c0].J);
+    }
+    const int common = diff ? 29 - (31 - __builtin_clz(diff)) : 30;
+    F.lc = std::min(lmin, common);
+    F.lmax = lmax;
+    c0 = c1;
+  }
+}
+
+// Nodes a face's trie needs with prefix level lp: the root, plus per node
+// depth d >= 1 the distinct ancestors at level lp + 4d of the cells finer
+// than that level. The cells are in quadtree order, so equal ancestors are
+// adjacent. `depth1` receives the count at depth 1.
+static int64_t count_nodes(const std::vector<Cell> &cells, const FaceCells &F, int lp,
+                           int64_t &depth1) {
+  int64_t total = 1;
+  depth1 = 0;
+  for (int d = 1; lp + 4 * d < F.lmax; d++) {
+    const int L = lp + 4 * d, s = 2 * (kMaxLevel - L);
+    int64_t u = 0;
+    uint64_t last = ~0ull;
+    for (size_t k = F.c0; k < F.c1; k++)
+      if (cells[k].level > L && (cells[k].key >> s) != last) {
+        last = cells[k].key >> s;
+        u++;
+      }
+    total += u;
+    if (d == 1) depth1 = u;
+  }
+  return total;
+}
+
+// Prefix levels of the faces. Default: the common-ancestor level lowered (by
+// at most 3) so that the finest cells end a node level, which keeps the
+// most numerous cells from being replicated. The common-ancestor level
+// itself moves the two LDS-staged node levels further down the tree, so
+// more points end their descent in LDS; it is taken when those levels still
+// fit the probe's LDS budget, the trie grows by at most kPrefixGrowth and
+// stays within kPrefixMaxNodes.
+// Returns the number of trie nodes (node 0 included) the choice needs.
+static int64_t choose_prefix(const std::vector<Cell> &cells, const FaceCells fc[6],
+                             const BuildParams &bp, int lp[6]) {
+  int aligned[6];
+  int64_t n_al = 1, n_co = 1, top_co = 0, d1;
+  for (int f = 0; f < 6; f++) {
+    const FaceCells &F = fc[f];
+    aligned[f] = F.lc - ((4 - (F.lmax - F.lc) % 4) % 4);
+    if (aligned[f] < 0) aligned[f] = F.lc;
+    lp[f] = bp.prefix_level >= 0 ? std::min(bp.prefix_level, F.lc) : aligned[f];
+    if (F.c1 == F.c0) continue;
+    n_al += count_nodes(cells, F, lp[f], d1);
+    if (bp.prefix_level < 0) {
+      n_co += count_nodes(cells, F, F.lc, d1);
+      top_co += 1 + d1;
+    }
+  }
+  if (bp.prefix_level < 0 && top_co <= kLdsTrieNodes && n_co <= kPrefixGrowth * n_al &&
+      n_co <= kPrefixMaxNodes) {
+    for (int f = 0; f < 6; f++) lp[f] = fc[f].lc;
+    return n_co;
+  }
+  return n_al;
+}
+
+// Builds the faces' tries and lookup table from the sorted cells into
+// out.nodes / out.lut / out.faces (and the trie statistics), with prefix
+// level lp[face].
+static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], const int lp_face[6],
+                       int64_t n_nodes, HostIndex &out, const BuildParams &bp, std::string &err) {
+  out.nodes.clear();
+  out.lut.clear();
+  for (int f = 0; f < 6; f++) out.faces[f] = FaceRoot();
+  out.max_depth = out.max_refs = out.max_cell_level = 0;
+  out.n_cells_interior_only = 0;
+  out.nodes.reserve(256 * (size_t)n_nodes);
+  out.nodes.assign(256, 0);  // node 0 reserved
+  LutDedup dedup;
+  for (int face = 0; face < 6; face++) {
+    const size_t c0 = fc[face].c0, c1 = fc[face].c1;
+    if (c1 == c0) continue;
+    // node levels Lp+1..Lp+4, Lp+5..Lp+8, ...
+    const int lp = lp_face[face];
+    if (lp + 4 * ((fc[face].lmax - lp + 3) / 4) > kMaxLevel) {
+      err = "cells on one face span too wide a range for the trie's level alignment";
+      return ACT_E_RANGE;
+    }
+    FaceRoot &F = out.faces[face];
+    F.plevel = lp;
+    F.pi = cells[c0].I >> (kMaxLevel - lp);
+    F.pj = cells[c0].J >> (kMaxLevel - lp);
+    F.root = (int32_t)(out.nodes.size() / 256);
+    out.nodes.resize(out.nodes.size() + 256, 0);
+    for (size_t k = c0; k < c1; k++) {
+      const Cell &c = cells[k];
+      int l = c.level;
+      int kd = l <= lp ? 0 : (l - lp - 1) / 4;  // node level holding the cell
+      uint64_t node = (uint64_t)F.root;
+      for (int d = 0; d < kd; d++) {
+        uint64_t slot = node * 256 + node_slot(c.I, c.J, kMaxLevel - lp - 4 * (d + 1));
+        uint64_t e = out.nodes[slot];
+        if (e == 0) {
+          uint64_t nn = out.nodes.size() / 256;
+          out.nodes[slot] = nn << 2;
+          out.nodes.resize(out.nodes.size() + 256, 0);
+          node = nn;
+        } else if ((e & kTagMask) == kTagPtr) {
+          node = e >> 2;
+        } else {
+          err = "internal: overlapping cells in the super covering";
+          return ACT_E_POLY;
+        }
+      }
+      // denormalise: the cell covers a 2^k x 2^k block of the node's 16 x 16
+      // (i nibble, j nibble) entries, k = levels between the cell and the
+      // node's last level
+      const int sh = kMaxLevel - lp - 4 * (kd + 1);
+      const uint32_t ni = (c.I >> sh) & 15u, nj = (c.J >> sh) & 15u;
+      const uint32_t span = 1u << (lp + 4 * (kd + 1) - l);
+      bool has_cand = false;
+      for (int r = 0; r < c.n; r++) has_cand |= !(c.refs[r] & 1u);
+      uint64_t entry;
+      if (has_cand && bp.mode == ACT_EXACT) {
+        // candidate cell: lookup-table list followed by the candidates'
+        // local record offsets
+        std::vector<uint32_t> tru, cand, locs;
+        for (int r = 0; r < c.n; r++) {
+          if (c.refs[r] & 1u) {
+            tru.push_back(c.refs[r] >> 1);
+          } else {
+            cand.push_back(c.refs[r] >> 1);
+            locs.push_back((uint32_t)(c.local_base + c.locs[r]));
+          }
+        }
+        entry = ((uint64_t)out.lut.size() << 2) | kTagLut;
+        out.lut.push_back((uint32_t)tru.size());
+        out.lut.insert(out.lut.end(), tru.begin(), tru.end());
+        out.lut.push_back((uint32_t)cand.size());
+        out.lut.insert(out.lut.end(), cand.begin(), cand.end());
+        out.lut.insert(out.lut.end(), locs.begin(), locs.end());
+      } else {
+        entry = encode_refs(c.refs, c.n, out.lut, &dedup);
+      }
+      if (out.lut.size() >= (1ull << 31)) {
+        err = "lookup table exceeds 2^31 words";
+        return ACT_E_RANGE;
+      }
+      for (uint32_t a = 0; a < span; a++)
+        for (uint32_t b = 0; b < span; b++) {
+          uint64_t slot = node * 256 + (((ni + a) << 4) | (nj + b));
+          if (out.nodes[slot] != 0) {
+            err = "internal: overlapping cells in the super covering";
+            return ACT_E_POLY;
+          }
+          out.nodes[slot] = entry;
+        }
+      F.depth = std::max(F.depth, kd + 1);
+      out.max_depth = std::max(out.max_depth, kd + 1);
+      out.max_refs = std::max(out.max_refs, c.n);
+      out.max_cell_level = std::max(out.max_cell_level, l);
+      bool all_true = true;
+      for (int r = 0; r < c.n; r++) all_true &= (c.refs[r] & 1u) != 0;
+      out.n_cells_interior_only += all_true;
+    }
+  }
+  renumber_breadth_first(out);
+  narrow_top_levels(out, &dedup);
+  if (out.lut.size() >= (1ull << 30)) {
+    err = "lookup table exceeds 2^30 words";
+    return ACT_E_RANGE;
+  }
+  if (out.nodes.size() / 256 >= (1ull << 30)) {  // pointer entries carry 30-bit node indices
+    err = "trie exceeds 2^30 nodes";
+    return ACT_E_RANGE;
+  }
+  return ACT_OK;
 }
 
 int build_host_index(const double *verts, const int64_t *ring_off, const int32_t *poly_ring_off,
@@ -690,20 +933,13 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   }
   // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
   // shifted to level 30
-  struct Cell {
-    int face, level;
-    uint32_t I, J;
-    const uint32_t *refs;
-    const uint32_t *locs;
-    uint64_t local_base;  // offset of the cell's sink in out.local
-    int n;
-  };
   std::vector<Cell> cells;
   auto gather = [&](const Sink &s) {
     const uint64_t base = out.local.size();
     out.local.insert(out.local.end(), s.local.begin(), s.local.end());
     for (const CellOut &c : s.cells)
       cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
+                       quad_key(c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level)),
                        &s.refs[c.ref_off], &s.locs[c.ref_off], base, c.ref_cnt});
   };
   gather(top);
@@ -713,126 +949,16 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     return ACT_E_RANGE;
   }
   std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) {
-    return a.face != b.face ? a.face < b.face : (a.I != b.I ? a.I < b.I : a.J < b.J);
+    return a.face != b.face ? a.face < b.face : a.key < b.key;
   });
   out.n_cells = (int64_t)cells.size();
   // ------------------------------------------------------------- tries
-  out.nodes.assign(256, 0);  // node 0 reserved
-  LutDedup dedup;
-  size_t c0 = 0;
-  for (int face = 0; face < 6; face++) {
-    size_t c1 = c0;
-    while (c1 < cells.size() && cells[c1].face == face) c1++;
-    if (c1 == c0) continue;
-    // common prefix level: deepest level shared by every cell of the face
-    int lmin = 30, lmax = 0;
-    uint32_t diff = 0;
-    for (size_t k = c0; k < c1; k++) {
-      lmin = std::min(lmin, cells[k].level);
-      lmax = std::max(lmax, cells[k].level);
-      diff |= (cells[k].I ^ cells[c0].I) | (cells[k].J ^ cells[c0].J);
-    }
-    int common = diff ? 29 - (31 - __builtin_clz(diff)) : 30;
-    int lc = std::min(lmin, common);
-    // node levels Lp+1..Lp+4, Lp+5..Lp+8, ...: align the finest level with
-    // a node's last level so that the most numerous cells are not replicated
-    int lp = lc - ((4 - (lmax - lc) % 4) % 4);
-    if (lp < 0) {
-      lp = lc;
-      if (lp + 4 * ((lmax - lp + 3) / 4) > kMaxLevel) {
-        err = "cells on one face span too wide a range for the trie's level alignment";
-        return ACT_E_RANGE;
-      }
-    }
-    FaceRoot &F = out.faces[face];
-    F.plevel = lp;
-    F.pi = cells[c0].I >> (kMaxLevel - lp);
-    F.pj = cells[c0].J >> (kMaxLevel - lp);
-    F.root = (int32_t)(out.nodes.size() / 256);
-    out.nodes.resize(out.nodes.size() + 256, 0);
-    for (size_t k = c0; k < c1; k++) {
-      const Cell &c = cells[k];
-      int l = c.level;
-      int kd = l <= lp ? 0 : (l - lp - 1) / 4;  // node level holding the cell
-      uint64_t node = (uint64_t)F.root;
-      for (int d = 0; d < kd; d++) {
-        uint64_t slot = node * 256 + node_slot(c.I, c.J, kMaxLevel - lp - 4 * (d + 1));
-        uint64_t e = out.nodes[slot];
-        if (e == 0) {
-          uint64_t nn = out.nodes.size() / 256;
-          out.nodes[slot] = nn << 2;
-          out.nodes.resize(out.nodes.size() + 256, 0);
-          node = nn;
-        } else if ((e & kTagMask) == kTagPtr) {
-          node = e >> 2;
-        } else {
-          err = "internal: overlapping cells in the super covering";
-          return ACT_E_POLY;
-        }
-      }
-      // denormalise: the cell covers a 2^k x 2^k block of the node's 16 x 16
-      // (i nibble, j nibble) entries, k = levels between the cell and the
-      // node's last level
-      const int sh = kMaxLevel - lp - 4 * (kd + 1);
-      const uint32_t ni = (c.I >> sh) & 15u, nj = (c.J >> sh) & 15u;
-      const uint32_t span = 1u << (lp + 4 * (kd + 1) - l);
-      bool has_cand = false;
-      for (int r = 0; r < c.n; r++) has_cand |= !(c.refs[r] & 1u);
-      uint64_t entry;
-      if (has_cand && bp.mode == ACT_EXACT) {
-        // candidate cell: lookup-table list followed by the candidates'
-        // local record offsets
-        std::vector<uint32_t> tru, cand, locs;
-        for (int r = 0; r < c.n; r++) {
-          if (c.refs[r] & 1u) {
-            tru.push_back(c.refs[r] >> 1);
-          } else {
-            cand.push_back(c.refs[r] >> 1);
-            locs.push_back((uint32_t)(c.local_base + c.locs[r]));
-          }
-        }
-        entry = ((uint64_t)out.lut.size() << 2) | kTagLut;
-        out.lut.push_back((uint32_t)tru.size());
-        out.lut.insert(out.lut.end(), tru.begin(), tru.end());
-        out.lut.push_back((uint32_t)cand.size());
-        out.lut.insert(out.lut.end(), cand.begin(), cand.end());
-        out.lut.insert(out.lut.end(), locs.begin(), locs.end());
-      } else {
-        entry = encode_refs(c.refs, c.n, out.lut, &dedup);
-      }
-      if (out.lut.size() >= (1ull << 31)) {
-        err = "lookup table exceeds 2^31 words";
-        return ACT_E_RANGE;
-      }
-      for (uint32_t a = 0; a < span; a++)
-        for (uint32_t b = 0; b < span; b++) {
-          uint64_t slot = node * 256 + (((ni + a) << 4) | (nj + b));
-          if (out.nodes[slot] != 0) {
-            err = "internal: overlapping cells in the super covering";
-            return ACT_E_POLY;
-          }
-          out.nodes[slot] = entry;
-        }
-      F.depth = std::max(F.depth, kd + 1);
-      out.max_depth = std::max(out.max_depth, kd + 1);
-      out.max_refs = std::max(out.max_refs, c.n);
-      out.max_cell_level = std::max(out.max_cell_level, l);
-      bool all_true = true;
-      for (int r = 0; r < c.n; r++) all_true &= (c.refs[r] & 1u) != 0;
-      out.n_cells_interior_only += all_true;
-    }
-    c0 = c1;
-  }
-  renumber_breadth_first(out);
-  narrow_top_levels(out, &dedup);
-  if (out.lut.size() >= (1ull << 30)) {
-    err = "lookup table exceeds 2^30 words";
-    return ACT_E_RANGE;
-  }
-  if (out.nodes.size() / 256 >= (1ull << 30)) {  // pointer entries carry 30-bit node indices
-    err = "trie exceeds 2^30 nodes";
-    return ACT_E_RANGE;
-  }
+  FaceCells fc[6];
+  face_ranges(cells, fc);
+  int lp[6];
+  const int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
+  const int rc = build_tries(cells, fc, lp, n_nodes, out, bp, err);
+  if (rc) return rc;
   out.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return ACT_OK;

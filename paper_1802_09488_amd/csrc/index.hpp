@@ -86,11 +86,16 @@ struct HostIndex {
   double build_seconds = 0;
 };
 
+// Trie nodes the probe stages in LDS (the top two node levels, as 32-bit
+// entries: 1 KiB per node, 64 KiB per block).
+constexpr int kLdsTrieNodes = 64;
+
 struct BuildParams {
   int32_t mode;
   double precision_m;
   int32_t max_level;
   int32_t threads;
+  int32_t prefix_level;  // -1: automatic
   double margin_deg;
 };
 

@@ -61,7 +61,7 @@ struct DevImage {
   float *pm = nullptr;
   float4 *e32 = nullptr;
   double2 *e64 = nullptr;
-  uint16_t *htab = nullptr;
+  double2 *trig = nullptr;
   struct FaceDev *faces = nullptr;
   uint32_t *top32 = nullptr;
   uint32_t *local = nullptr;
@@ -114,7 +114,7 @@ struct ProbeParams {
   const float *pm;
   const float4 *e32;
   const double2 *e64;
-  const uint16_t *htab;
+  const double2 *trig;   // kTrigEntries (cos, sin) of whole degrees (device)
   const FaceDev *faces;  // 6 entries (device)
   const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 as 32-bit entries
   int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
@@ -138,23 +138,23 @@ constexpr int kProbeWaves = kProbeBlock / 64;
 // 1e-9 degree margin. The pieces below are written for the argument ranges
 // that occur and cost far fewer instructions than general library routines.
 
-// sin and cos of t, |t| <= pi/4 (+ rounding): Taylor series to t^13 / t^14;
-// the first omitted terms are below 2.1e-14 and 1.1e-15.
-__device__ __forceinline__ void sincos_quarter(double t, double &s, double &c) {
-  const double t2 = t * t;
-  double p = fma(t2, 1.0 / 6227020800.0, -1.0 / 39916800.0);  //  1/13!, -1/11!
-  p = fma(t2, p, 1.0 / 362880.0);                              //  1/9!
-  p = fma(t2, p, -1.0 / 5040.0);                               // -1/7!
-  p = fma(t2, p, 1.0 / 120.0);                                 //  1/5!
-  p = fma(t2, p, -1.0 / 6.0);                                  // -1/3!
-  s = fma(t * t2, p, t);
-  double q = fma(t2, -1.0 / 87178291200.0, 1.0 / 479001600.0);  // -1/14!, 1/12!
-  q = fma(t2, q, -1.0 / 3628800.0);                              // -1/10!
-  q = fma(t2, q, 1.0 / 40320.0);                                 //  1/8!
-  q = fma(t2, q, -1.0 / 720.0);                                  // -1/6!
-  q = fma(t2, q, 1.0 / 24.0);                                    //  1/4!
-  q = fma(t2, q, -0.5);
-  c = fma(t2, q, 1.0);
+// Angles are split at the nearest whole degree b: x = b + d, |d| <= 1/2
+// degree. (cos b, sin b) come from a 361-entry table (b = -180 .. 180,
+// computed on the host with the C library), and sin d, cos d from short
+// Taylor series: the first omitted terms are below 4e-19 and 7e-16. The sum
+// formulas then give sin x and cos x to a few units of 1e-16, with no
+// quadrant logic. x - b is exact (Sterbenz's lemma, or b = 0).
+constexpr int kTrigEntries = 361;
+
+__device__ __forceinline__ void sincos_deg(const double2 *trig, double x, double &s, double &c) {
+  const double b = rint(x);
+  const double2 t = trig[(int)b + 180];  // (cos b, sin b)
+  const double d = (x - b) * 0.017453292519943295;
+  const double d2 = d * d;
+  const double sd = fma(d * d2, fma(d2, 1.0 / 120.0, -1.0 / 6.0), d);
+  const double cd = fma(d2, fma(d2, 1.0 / 24.0, -0.5), 1.0);
+  s = fma(t.y, cd, t.x * sd);
+  c = fma(t.x, cd, -(t.y * sd));
 }
 
 // 1 / a for a in [1/sqrt(3), 1]: hardware estimate + two Newton steps.
@@ -175,38 +175,25 @@ __device__ __forceinline__ uint32_t leaf_coord(double w) {
 
 // Steps 2-3: leaf cell coordinates (face, i, j) of a point; false for
 // points that are not finite or outside |lat| <= 90, |lng| <= 180.
-//
-// Both angles are reduced exactly in degrees, x = 90 k + r with
-// k = rint(x / 90), |r| <= 45 (Sterbenz: x and 90 k are within a factor of
-// two when k != 0). The longitude's quadrant q = k mod 4 then tells which of
-// |x|, |y| is larger, so the face needs one more comparison (|z| against
-// that maximum; ties go to the lower axis), and the major magnitude is the
-// maximum of the three.
-__device__ __forceinline__ bool project(double lat, double lng, uint32_t &face, uint32_t &i,
-                                        uint32_t &j) {
+// The face is the axis of the largest |coordinate| (ties go to the lower
+// axis: x before y before z) and its sign; (u, v) are the two other
+// coordinates in cyclic axis order divided by that magnitude.
+__device__ __forceinline__ bool project(const double2 *trig, double lat, double lng,
+                                        uint32_t &face, uint32_t &i, uint32_t &j) {
   if (!(fabs(lat) <= 90.0 && fabs(lng) <= 180.0)) return false;
-  const double kl = rint(lng * (1.0 / 90.0));
-  const double kp = rint(lat * (1.0 / 90.0));
-  double sl, cl, sp, cp;
-  sincos_quarter(fma(kl, -90.0, lng) * 0.017453292519943295, sl, cl);
-  sincos_quarter(fma(kp, -90.0, lat) * 0.017453292519943295, sp, cp);
-  // latitude: k in {-1, 0, 1}; sin(lat) = k cos r, cos(lat) = |sin r| if k != 0
-  const double slat = kp == 0.0 ? sp : copysign(cp, kp);
-  const double clat = kp == 0.0 ? cp : fabs(sp);
-  // longitude quadrant q: (cos, sin) = (c, s), (-s, c), (-c, -s), (s, -c)
-  const uint32_t q = (uint32_t)(int)kl & 3u;
-  const bool odd = q & 1u;
-  double cosl = odd ? sl : cl, sinl = odd ? cl : sl;
-  if ((q + 1u) & 2u) cosl = -cosl;
-  if (q & 2u) sinl = -sinl;
-  const double x = clat * cosl, y = clat * sinl, z = slat;
+  double sp, cp, sl, cl;
+  sincos_deg(trig, lat, sp, cp);
+  sincos_deg(trig, lng, sl, cl);
+  const double x = cp * cl, y = cp * sl, z = sp;
+  const bool xmaj = fabs(x) >= fabs(y);
   const double mxy = fmax(fabs(x), fabs(y));
   const bool polar = fabs(z) > mxy;
   const double r = rcp_nr(fmax(mxy, fabs(z)));
   // minor coordinates in axis order: x face (y, z), y face (z, x), z face (x, y)
-  const double c1 = polar ? x : (odd ? z : y);
-  const double c2 = polar ? y : (odd ? x : z);
-  face = polar ? (z < 0.0 ? 5u : 2u) : (odd ? 1u : 0u) + ((q & 2u) ? 3u : 0u);
+  const double c1 = polar ? x : (xmaj ? y : z);
+  const double c2 = polar ? y : (xmaj ? z : x);
+  const bool neg = polar ? z < 0.0 : (xmaj ? x < 0.0 : y < 0.0);
+  face = (polar ? 2u : (xmaj ? 0u : 1u)) + (neg ? 3u : 0u);
   i = leaf_coord(c1 * r);
   j = leaf_coord(c2 * r);
   return true;
@@ -381,187 +368,249 @@ constexpr uint32_t kMaxOutLut = 0x7ffffffcu;  // largest offset -3 - off can car
 
 __device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == kTagPtr && e != 0; }
 
-// Steps 5-6 for NP points of a lane at once: the descents run side by side,
-// so each step issues up to NP independent node loads. Written without
-// branches: a lane whose descent has ended keeps its entry and reads a
-// harmless slot (LDS word 0, or node 0, which the builder reserves), so
-// the wave never splits. Pointer entries hold node indices below 2^30, so
-// their high halves are zero and the tag tests use the low half only.
-template <int LDS_DEPTH, int NP>
-__device__ __forceinline__ void lookup_n(const ProbeParams &P, const uint32_t *s_nodes,
-                                         const FaceDev *s_face, const uint32_t (&face)[NP],
-                                         const uint32_t (&ci)[NP], const uint32_t (&cj)[NP],
-                                         const bool (&valid)[NP], uint64_t (&e)[NP],
-                                         uint32_t &reads) {
-  uint32_t node[NP], lo[NP];
+// Steps 5-6 for NP points of a lane at once, split into the parts of the
+// probe's pipeline: the prefix check and the LDS-staged levels
+// (descend_lds), one global node level (issue_level / take_level) and the
+// remaining global levels (descend_rest). The descents run side by side,
+// so each step issues up to NP independent loads. Written without branches:
+// a lane whose descent has ended keeps its entry and reads a harmless slot
+// (LDS word 0, or node 0, which the builder reserves), so the wave never
+// splits. Pointer entries hold node indices below 2^30, so their high
+// halves are zero and the tag tests use the low half only.
+template <int NP>
+struct Descent {
+  uint32_t ci[NP], cj[NP], node[NP];
   int sh[NP];
   bool act[NP];
+  uint64_t e[NP];
+};
+
+template <int LDS_DEPTH, int NP>
+__device__ __forceinline__ void descend_lds(const uint32_t *s_nodes, const FaceDev *s_face,
+                                            const uint32_t (&face)[NP], const bool (&valid)[NP],
+                                            Descent<NP> &D, uint32_t &reads) {
+  uint32_t lo[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     const FaceDev F = s_face[face[p]];
-    sh[p] = F.sh0;
-    node[p] = (uint32_t)F.root;
-    act[p] = valid[p] & (F.root >= 0) & ((ci[p] >> F.sh0) == F.pi) & ((cj[p] >> F.sh0) == F.pj);
+    D.sh[p] = F.sh0;
+    D.node[p] = (uint32_t)F.root;
+    D.act[p] = valid[p] & (F.root >= 0) & ((D.ci[p] >> F.sh0) == F.pi) &
+               ((D.cj[p] >> F.sh0) == F.pj);
     lo[p] = 0;
   }
 #pragma unroll
   for (int d = 0; d < LDS_DEPTH; d++) {
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-      sh[p] -= 4;
-      const uint32_t k = act[p] ? ((node[p] - 1u) << 8) | node_slot(ci[p], cj[p], sh[p]) : 0u;
+      D.sh[p] -= 4;
+      const uint32_t k =
+          D.act[p] ? ((D.node[p] - 1u) << 8) | node_slot(D.ci[p], D.cj[p], D.sh[p]) : 0u;
       const uint32_t v = s_nodes[k];
-      reads += act[p];
-      lo[p] = act[p] ? v : lo[p];
-      act[p] = act[p] & ((v & 3u) == 0u) & (v != 0u);
-      node[p] = v >> 2;
+      reads += D.act[p];
+      lo[p] = D.act[p] ? v : lo[p];
+      D.act[p] = D.act[p] & ((v & 3u) == 0u) & (v != 0u);
+      D.node[p] = v >> 2;
     }
   }
 #pragma unroll
-  for (int p = 0; p < NP; p++) e[p] = lo[p];
-  for (;;) {
-    bool any = false;
+  for (int p = 0; p < NP; p++) D.e[p] = lo[p];
+}
+
+template <int NP>
+__device__ __forceinline__ void issue_level(const ProbeParams &P, Descent<NP> &D,
+                                            uint64_t (&x)[NP]) {
 #pragma unroll
-    for (int p = 0; p < NP; p++) any |= act[p];
-    if (!any) break;
-    uint64_t x[NP];
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      sh[p] -= 4;
-      const uint64_t k = act[p] ? ((uint64_t)node[p] << 8) | node_slot(ci[p], cj[p], sh[p]) : 0u;
-      x[p] = P.nodes[k];
-    }
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      const uint32_t v = (uint32_t)x[p];
-      reads += act[p];
-      e[p] = act[p] ? x[p] : e[p];
-      act[p] = act[p] & ((v & 3u) == 0u) & (v != 0u);
-      node[p] = v >> 2;
-    }
+  for (int p = 0; p < NP; p++) {
+    D.sh[p] -= 4;
+    const uint64_t k =
+        D.act[p] ? ((uint64_t)D.node[p] << 8) | node_slot(D.ci[p], D.cj[p], D.sh[p]) : 0u;
+    x[p] = P.nodes[k];
   }
 }
 
-// The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
-// per lane, at lane and lane + 64, ...), so all lanes of a wave run the
-// same number of iterations; the next tile's points are loaded while the
-// current tile is processed.
-//
-// Exact mode: a point whose cell entry has candidate references or is a
-// lookup-table list is pending: the probe writes its list offset to out[]
-// and its bit to the pending mask (one 64-bit ballot per 64 points, no
-// atomics), and reads nothing more for it; resolve_kernel finishes it.
-template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP>
-__global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
-  extern __shared__ uint32_t s_nodes[];
-  __shared__ FaceDev s_face[6];
-  if (LDS_DEPTH > 0)
-    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
-  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t c_pts = 0, c_inv = 0, c_false = 0, c_true = 0, c_candpts = 0, c_cand = 0,
-           c_reads = 0, c_lut = 0;
-  constexpr int TILE = 64 * NP;
-  const int64_t ntiles = (P.n + TILE - 1) / TILE;
-  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
-  int64_t tile = (int64_t)blockIdx.x * kProbeWaves + wid;
-  double2 nxt[NP];
+template <int NP>
+__device__ __forceinline__ void take_level(Descent<NP> &D, const uint64_t (&x)[NP],
+                                           uint32_t &reads) {
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    const int64_t k = tile * TILE + p * 64 + lane;
-    nxt[p] = (tile < ntiles && k < P.n) ? P.pts[k] : make_double2(0.0, 0.0);
+    const uint32_t v = (uint32_t)x[p];
+    reads += D.act[p];
+    D.e[p] = D.act[p] ? x[p] : D.e[p];
+    D.act[p] = D.act[p] & ((v & 3u) == 0u) & (v != 0u);
+    D.node[p] = v >> 2;
   }
-  for (; tile < ntiles; tile += nwaves) {
-    int64_t i[NP];
-    bool live[NP], valid[NP];
-    double lat[NP], lng[NP];
-    uint32_t face[NP], ci[NP], cj[NP];
-    uint64_t e[NP];
+}
+
+template <int NP>
+__device__ __forceinline__ void descend_rest(const ProbeParams &P, Descent<NP> &D,
+                                             uint32_t &reads) {
+  for (;;) {
+    bool any = false;
 #pragma unroll
-    for (int p = 0; p < NP; p++) {
-      i[p] = tile * TILE + p * 64 + lane;
-      live[p] = i[p] < P.n;
-      lat[p] = nxt[p].x;
-      lng[p] = nxt[p].y;
-      const int64_t k = (tile + nwaves) * TILE + p * 64 + lane;
-      if (tile + nwaves < ntiles && k < P.n) nxt[p] = P.pts[k];
-    }
+    for (int p = 0; p < NP; p++) any |= D.act[p];
+    if (!any) break;
+    uint64_t x[NP];
+    issue_level<NP>(P, D, x);
+    take_level<NP>(D, x, reads);
+  }
+}
+
+// Streaming accesses: each point is read once and each output written once,
+// so they bypass the caches' retention (nontemporal), leaving L2 to the
+// trie nodes that every point's descent revisits.
+typedef double act_double2_v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double2 load_point(const double2 *p) {
+  const act_double2_v v = __builtin_nontemporal_load((const act_double2_v *)p);
+  return make_double2(v.x, v.y);
+}
+
+__device__ __forceinline__ void store_out(int32_t *p, int32_t v) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// Step 7-9 for the NP points of a lane in tile `tile`.
+template <bool EXACT, bool COUNT, int NP>
+__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, int lane,
+                                            const uint64_t (&e)[NP], const bool (&live)[NP],
+                                            const bool (&valid)[NP], uint32_t (&c)[8]) {
+  constexpr int TILE = 64 * NP;
+  bool pend[NP];
 #pragma unroll
-    for (int p = 0; p < NP; p++) {
-      face[p] = ci[p] = cj[p] = 0;
-      valid[p] = live[p] && project(lat[p], lng[p], face[p], ci[p], cj[p]);
+  for (int p = 0; p < NP; p++) {
+    const int64_t i = tile * TILE + p * 64 + lane;
+    if (COUNT) {
+      c[0] += live[p];
+      c[1] += live[p] && !valid[p];
+      c[2] += valid[p] && e[p] == 0;
     }
-    lookup_n<LDS_DEPTH, NP>(P, s_nodes, s_face, face, ci, cj, valid, e, c_reads);
-    // stage 3: the entries' references (Section III-E: one payload, two
+    // stage 3: the entry's references (Section III-E: one payload, two
     // payloads or a lookup-table offset)
-    uint32_t tag[NP], r0[NP], r1[NP], off[NP], nt[NP], nc[NP];
-    int n_inl[NP];
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      if (COUNT) {
-        c_pts += live[p];
-        c_inv += live[p] && !valid[p];
-        c_false += valid[p] && e[p] == 0;
-      }
-      tag[p] = (uint32_t)(e[p] & kTagMask);
-      r0[p] = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
-      r1[p] = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
-      n_inl[p] = e[p] == 0 || tag[p] == kTagLut ? 0 : (tag[p] == kTagTwo ? 2 : 1);
-      off[p] = nt[p] = nc[p] = 0;
-      if (tag[p] == kTagLut) off[p] = (uint32_t)(e[p] >> 2);
-      if (!EXACT && tag[p] == kTagLut) {
-        nt[p] = P.lut[off[p]];
-        nc[p] = P.lut[off[p] + 1 + nt[p]];
-        if (COUNT) c_lut++;
-      }
-    }
+    const uint32_t tag = (uint32_t)(e[p] & kTagMask);
+    const uint32_t r0 = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
+    const uint32_t r1 = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
+    const int n_inl = e[p] == 0 || tag == kTagLut ? 0 : (tag == kTagTwo ? 2 : 1);
+    const uint32_t off = (uint32_t)(e[p] >> 2);
     if (!EXACT) {
       // approximate mode: every reference is reported
-#pragma unroll
-      for (int p = 0; p < NP; p++) {
-        Hits hits;
-        if (n_inl[p] > 0) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
-        if (n_inl[p] > 1) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
-        for (uint32_t r = 0; r < nt[p]; r++) hits.add(P, i[p], (int32_t)P.lut[off[p] + 1 + r]);
-        for (uint32_t r = 0; r < nc[p]; r++)
-          hits.add(P, i[p], (int32_t)P.lut[off[p] + 2 + nt[p] + r]);
-        if (COUNT) c_true += e[p] != 0;
-        if (live[p]) P.out[i[p]] = hits.best;
+      Hits hits;
+      if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
+      if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
+      if (tag == kTagLut) {
+        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
+        for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
+        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
+        if (COUNT) c[4]++;
       }
-      continue;
-    }
-    bool pend[NP];
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      const bool cand_inl = (n_inl[p] > 0 && !(r0[p] & 1u)) || (n_inl[p] > 1 && !(r1[p] & 1u));
-      pend[p] = live[p] && (tag[p] == kTagLut || cand_inl);
+      if (COUNT) c[3] += e[p] != 0;
+      if (live[p]) store_out(P.out + i, hits.best);
+      pend[p] = false;
+    } else {
+      // exact mode: a point whose cell entry has candidate references or is
+      // a lookup-table list is pending: its list offset goes to out[] and
+      // its bit to the pending mask; resolve_kernel finishes it
+      const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
+      pend[p] = live[p] && (tag == kTagLut || cand_inl);
       if (pend[p]) {
-        P.out[i[p]] = tag[p] == kTagLut && off[p] <= kMaxOutLut ? -3 - (int32_t)off[p] : kPending;
+        store_out(P.out + i, tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending);
       } else {
         Hits hits;
-        if (n_inl[p] > 0) hits.add(P, i[p], (int32_t)(r0[p] >> 1));
-        if (n_inl[p] > 1) hits.add(P, i[p], (int32_t)(r1[p] >> 1));
-        if (live[p]) P.out[i[p]] = hits.best;
-        if (COUNT) c_true += e[p] != 0;
+        if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
+        if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
+        if (live[p]) store_out(P.out + i, hits.best);
+        if (COUNT) c[3] += e[p] != 0;
       }
     }
+  }
+  if (EXACT) {
 #pragma unroll
     for (int p = 0; p < NP; p++) {
       const uint64_t m = ballot(pend[p]);
       if (lane == 0 && tile * TILE + p * 64 < P.n) P.mask[tile * NP + p] = m;
     }
   }
+}
+
+// The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
+// per lane, at lane and lane + 64, ...), grid-stride, so all lanes of a
+// wave run the same number of iterations. The loop is a two-stage software
+// pipeline: while tile t is projected and descends the LDS-staged levels,
+// the first global node level of tile t - 1 (issued at the end of the
+// previous iteration) is in flight; then tile t - 1 finishes. The point
+// loads run one tile further ahead.
+template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP>
+__global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
+  extern __shared__ uint32_t s_nodes[];
+  __shared__ FaceDev s_face[6];
+  __shared__ double2 s_trig[kTrigEntries];
+  if (LDS_DEPTH > 0)
+    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
+  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
+  if (threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
+  constexpr int TILE = 64 * NP;
+  const int64_t ntiles = (P.n + TILE - 1) / TILE;
+  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
+  const int64_t first = (int64_t)blockIdx.x * kProbeWaves + wid;
+  double2 nxt[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int64_t k = first * TILE + p * 64 + lane;
+    nxt[p] = (first < ntiles && k < P.n) ? load_point(P.pts + k) : make_double2(0.0, 0.0);
+  }
+  // stage B: the tile whose first global level is in flight
+  Descent<NP> B;
+  uint64_t xB[NP];
+  bool liveB[NP], validB[NP];
+  bool hasB = false;
+  int64_t tileB = 0;
+  for (int64_t tile = first;; tile += nwaves) {
+    const bool hasA = tile < ntiles;  // wave-uniform
+    if (!hasA && !hasB) break;
+    Descent<NP> A;
+    bool liveA[NP], validA[NP];
+    if (hasA) {
+      uint32_t face[NP];
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        const int64_t i = tile * TILE + p * 64 + lane;
+        liveA[p] = i < P.n;
+        const double lat = nxt[p].x, lng = nxt[p].y;
+        const int64_t k = (tile + nwaves) * TILE + p * 64 + lane;
+        if (tile + nwaves < ntiles && k < P.n) nxt[p] = load_point(P.pts + k);
+        face[p] = A.ci[p] = A.cj[p] = 0;
+        validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
+      }
+      descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, validA, A, c_reads);
+    }
+    if (hasB) {
+      take_level<NP>(B, xB, c_reads);
+      descend_rest<NP>(P, B, c_reads);
+      finish_tile<EXACT, COUNT, NP>(P, tileB, lane, B.e, liveB, validB, c);
+    }
+    if (hasA) {
+      B = A;
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        liveB[p] = liveA[p];
+        validB[p] = validA[p];
+      }
+      issue_level<NP>(P, B, xB);
+    }
+    hasB = hasA;
+    tileB = tile;
+  }
   if (COUNT) {
     unsigned long long *C = P.counters;
-    atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c_pts);
-    atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c_inv);
-    atomicAdd(C + ACT_CNT_FALSE_HIT, (unsigned long long)c_false);
-    atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c_true);
-    atomicAdd(C + ACT_CNT_CAND_POINTS, (unsigned long long)c_candpts);
-    atomicAdd(C + ACT_CNT_CANDIDATES, (unsigned long long)c_cand);
+    atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c[0]);
+    atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c[1]);
+    atomicAdd(C + ACT_CNT_FALSE_HIT, (unsigned long long)c[2]);
+    atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c[3]);
     atomicAdd(C + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
-    atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c_lut);
+    atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c[4]);
   }
 }
 
@@ -598,7 +647,8 @@ __device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t co
   if (code <= -3) return lut_refs(P, (uint32_t)(-3 - code));
   uint32_t face, ci, cj;
   uint64_t e = 0;
-  if (project(lat, lng, face, ci, cj)) e = lookup<0>(P, nullptr, P.faces[face], ci, cj, reads);
+  if (project(P.trig, lat, lng, face, ci, cj))
+    e = lookup<0>(P, nullptr, P.faces[face], ci, cj, reads);
   const uint32_t tag = (uint32_t)(e & kTagMask);
   if (e == 0 || tag == kTagPtr) return RefList();
   if (tag == kTagLut) return lut_refs(P, (uint32_t)(e >> 2));
@@ -793,15 +843,18 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t 
 }
 
 __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_t n,
-                                                      const uint16_t *htab, uint64_t *ids) {
+                                                      const uint16_t *htab, const double2 *trig,
+                                                      uint64_t *ids) {
   __shared__ uint16_t s_htab[1024];
+  __shared__ double2 s_trig[kTrigEntries];
   for (int k = threadIdx.x; k < 1024; k += blockDim.x) s_htab[k] = htab[k];
+  for (int k = threadIdx.x; k < kTrigEntries; k += blockDim.x) s_trig[k] = trig[k];
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double2 p = pts[i];
     uint32_t face, ci, cj;
-    ids[i] = project(p.x, p.y, face, ci, cj)
+    ids[i] = project(s_trig, p.x, p.y, face, ci, cj)
                  ? (((uint64_t)face << 61) | (hilbert60(s_htab, ci, cj) << 1) | 1ull)
                  : 0ull;
   }
@@ -846,7 +899,7 @@ struct DeviceGuard {
 
 static void free_image(DevImage &d) {
   void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
-                  d.e64,   d.htab,  d.faces, d.top32,  d.local};
+                  d.e64,   d.trig,  d.faces, d.top32,  d.local};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -902,11 +955,20 @@ static void face_table(const HostIndex &h, FaceDev f[6]) {
   }
 }
 
+// (cos b, sin b) for whole degrees b = -180 .. 180, by the C library.
+static void trig_table(std::vector<double2> &t) {
+  t.resize(kTrigEntries);
+  for (int b = -180; b <= 180; b++) {
+    const double a = b * (M_PI / 180.0);
+    t[b + 180] = make_double2(std::cos(a), std::sin(a));
+  }
+}
+
 static int upload_image(act_index *x) {
   const HostIndex &h = x->host;
   DevImage &d = x->dev;
-  uint16_t htab[1024];
-  hilbert_table4(htab);
+  std::vector<double2> trig;
+  trig_table(trig);
   int rc;
   if ((rc = upload(d.nodes, h.nodes.data(), h.nodes.size() * 8, d.bytes))) return rc;
   if ((rc = upload(d.lut, h.lut.data(), h.lut.size() * 4, d.bytes))) return rc;
@@ -915,7 +977,7 @@ static int upload_image(act_index *x) {
   if ((rc = upload(d.pm, h.poly_m.data(), h.poly_m.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.e32, h.edges32.data(), h.edges32.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.e64, h.edges64.data(), h.edges64.size() * 8, d.bytes))) return rc;
-  if ((rc = upload(d.htab, htab, sizeof htab, d.bytes))) return rc;
+  if ((rc = upload(d.trig, trig.data(), trig.size() * sizeof(double2), d.bytes))) return rc;
   FaceDev f[6];
   face_table(h, f);
   if ((rc = upload(d.faces, f, sizeof f, d.bytes))) return rc;
@@ -947,12 +1009,11 @@ static int grid_for(int64_t n, int block) {
   return (int)std::min<int64_t>(std::max<int64_t>(blocks, 1), 8192);
 }
 
-constexpr int kLdsTrieBudget = 64 * 1024;  // bytes of 32-bit top-level entries per block
 
 // Node count staged in LDS for `depth` levels (0 if it does not fit).
 static int lds_nodes_for(const HostIndex &h, int depth) {
   int n = depth >= 2 ? h.n_d0 + h.n_d1 : (depth == 1 ? h.n_d0 : 0);
-  return n * 1024 <= kLdsTrieBudget ? n : -1;
+  return n <= kLdsTrieNodes ? n : -1;
 }
 
 static int default_lds_depth(const HostIndex &h) {
@@ -1002,7 +1063,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.pm = x->dev.pm;
   P.e32 = x->dev.e32;
   P.e64 = x->dev.e64;
-  P.htab = x->dev.htab;
+  P.trig = x->dev.trig;
   P.faces = x->dev.faces;
   P.top32 = x->dev.top32;
   P.n_lds_nodes = n_lds;
@@ -1059,6 +1120,15 @@ using namespace act;
 
 extern "C" {
 
+void act_build_opts_init(act_build_opts *o) {
+  if (!o) return;
+  o->max_level = 20;
+  o->device = 0;
+  o->threads = 0;
+  o->prefix_level = -1;
+  o->margin_deg = 1e-9;
+}
+
 int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t *poly_ring_off,
               int32_t n_polys, int32_t mode, double precision_m, const act_build_opts *opts,
               act_index **out) {
@@ -1070,20 +1140,20 @@ int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t
   if (mode != ACT_EXACT && mode != ACT_APPROX) return fail(ACT_E_ARG, "mode must be ACT_EXACT or ACT_APPROX");
   if (mode == ACT_APPROX && !(precision_m >= 0.05))
     return fail(ACT_E_ARG, "approximate mode needs precision_m >= 0.05");
+  act_build_opts o;
+  act_build_opts_init(&o);
+  if (opts) o = *opts;
   BuildParams bp;
   bp.mode = mode;
   bp.precision_m = mode == ACT_APPROX ? precision_m : 0.0;
-  bp.max_level = 20;
-  bp.threads = 0;
-  bp.margin_deg = 1e-9;
-  int device = 0;
-  if (opts) {
-    if (opts->max_level) bp.max_level = opts->max_level;
-    bp.threads = opts->threads;
-    if (opts->margin_deg > 0) bp.margin_deg = opts->margin_deg;
-    device = opts->device;
-  }
+  bp.max_level = o.max_level ? o.max_level : 20;
+  bp.threads = o.threads;
+  bp.prefix_level = o.prefix_level;
+  bp.margin_deg = o.margin_deg > 0 ? o.margin_deg : 1e-9;
+  const int device = o.device;
   if (bp.max_level < 1 || bp.max_level > kMaxLevel) return fail(ACT_E_ARG, "max_level must be 1..30");
+  if (bp.prefix_level < -1 || bp.prefix_level > kMaxLevel)
+    return fail(ACT_E_ARG, "prefix_level must be -1..30");
   if (!(bp.margin_deg > 0 && bp.margin_deg < 1e-3)) return fail(ACT_E_ARG, "margin_deg out of range");
   if (device >= 0 && device >= device_count())
     return fail(ACT_E_DEVICE, "HIP device " + std::to_string(device) + " not available");
@@ -1174,7 +1244,8 @@ int act_cell_ids(const double *d_points, int64_t n, uint64_t *d_ids, void *strea
   if (n == 0) return ACT_OK;
   if (device_count() <= 0) return fail(ACT_E_DEVICE, "no HIP device");
   static std::mutex mu;
-  static uint16_t *tabs[64] = {nullptr};
+  static uint16_t *tabs[64] = {nullptr};  // per device: Hilbert table, then the trig table
+  static double2 *trigs[64] = {nullptr};
   int dev = 0;
   if (stream) {
     if (hipStreamGetDevice((hipStream_t)stream, &dev) != hipSuccess) return fail(ACT_E_ARG, "invalid stream");
@@ -1188,14 +1259,20 @@ int act_cell_ids(const double *d_points, int64_t n, uint64_t *d_ids, void *strea
     if (!tabs[dev]) {
       uint16_t h[1024];
       hilbert_table4(h);
+      std::vector<double2> t;
+      trig_table(t);
       uint16_t *d = nullptr;
+      double2 *dt = nullptr;
       HIP_TRY(hipMalloc((void **)&d, sizeof h));
       HIP_TRY(hipMemcpy(d, h, sizeof h, hipMemcpyHostToDevice));
+      HIP_TRY(hipMalloc((void **)&dt, t.size() * sizeof(double2)));
+      HIP_TRY(hipMemcpy(dt, t.data(), t.size() * sizeof(double2), hipMemcpyHostToDevice));
+      trigs[dev] = dt;
       tabs[dev] = d;
     }
   }
   hipLaunchKernelGGL(cell_id_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream,
-                     (const double2 *)d_points, n, tabs[dev], d_ids);
+                     (const double2 *)d_points, n, tabs[dev], trigs[dev], d_ids);
   HIP_TRY(hipGetLastError());
   return ACT_OK;
 }

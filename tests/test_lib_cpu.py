@@ -214,7 +214,7 @@ def _raw_build(act, verts, ring_off, poly_ring_off, mode=0, prec=0.0, device=-1)
     v = np.ascontiguousarray(verts, dtype=np.float64)
     ro = np.ascontiguousarray(ring_off, dtype=np.int64)
     pro = np.ascontiguousarray(poly_ring_off, dtype=np.int32)
-    opts = B.BuildOpts(max_level=0, device=device, threads=1, reserved=0, margin_deg=0.0)
+    opts = B.BuildOpts(max_level=0, device=device, threads=1, prefix_level=-1, margin_deg=0.0)
     h = ctypes.c_void_p()
     rc = B.lib.act_build(v.ctypes.data, ro.ctypes.data, pro.ctypes.data, len(pro) - 1, mode, prec,
                          ctypes.byref(opts), ctypes.byref(h))
