@@ -230,7 +230,7 @@ int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
 int act_cell_ids(const double *d_points, int64_t n, uint64_t *d_ids,
                  void *stream);
 
-/* Index metrics (the paper's Table III analogues plus sizes). */
+/* Index metrics (the paper's index-metrics table (Table I) analogues plus sizes). */
 typedef struct {
   int64_t n_polys;
   int64_t n_edges;

@@ -25,9 +25,9 @@
 // against all of the polygon's edges.
 //
 // Physical index (Section III-C): cells are denormalised to the node levels
-// of their face (g = 4 levels per node, Fig. 6a), references of fewer than
+// of their face (g = 4 levels per node, Fig. 7a), references of fewer than
 // three polygons are inlined into the tagged entry, longer lists are
-// deduplicated into the lookup table (Fig. 6b). The trie is keyed by each
+// deduplicated into the lookup table (Fig. 7b). The trie is keyed by each
 // cell's quadtree path (see index.hpp).
 #include <algorithm>
 #include <atomic>

@@ -1,7 +1,7 @@
 // index.hpp -- host-side representation of a built index and the layout of
 // its device image (shared by the builder and the GPU runtime).
 //
-// Adaptive Cell Trie (Section III-C, Fig. 6): nodes of 256 tagged 8-byte
+// Adaptive Cell Trie (Section III-C, Fig. 7): nodes of 256 tagged 8-byte
 // entries (fanout 256 = 4 cell levels per node). Tag = two low bits:
 //   00  child pointer: node index << 2; the value 0 is the sentinel
 //       (false hit) -- node 0 is reserved and never referenced;

@@ -88,15 +88,19 @@ def assert_approx(P, pts, out, pairs, prec, label=""):
 
 
 def edge_case_points(P, rng):
-    """Vertices (on boundaries, shared by neighbours), hole vertices, exact
-    dyadic points, invalid and out-of-domain points, points outside the box."""
+    """Vertices (on boundaries, shared by neighbours; hole vertices where the
+    workload has holes), vertices moved by one ulp in either coordinate,
+    edge midpoints (within rounding of an edge), invalid and out-of-domain
+    points, points outside the box."""
     v = P.verts
     mids = 0.5 * (v[:-1] + v[1:])  # near (not exactly on) edges
+    k = rng.choice(len(v), min(len(v), 4000), replace=False)
+    nudged = v[k] + rng.integers(-1, 2, (len(k), 2)) * np.spacing(v[k])
     bad = np.array([[np.nan, -74.0], [40.7, np.inf], [-np.inf, 0], [91.0, -74.0],
                     [40.7, -181.0], [90.0, 180.0], [-90.0, -180.0], [0.0, 0.0],
                     [40.7, 106.0], [-40.7, -74.0]])
     outside = np.stack([rng.uniform(39, 42, 500), rng.uniform(-75.5, -72.5, 500)], 1)
-    return np.concatenate([v, mids, bad, outside])
+    return np.concatenate([v, nudged, mids, bad, outside])
 
 
 def test_c1_exact_all_points(act):

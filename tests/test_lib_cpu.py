@@ -1,6 +1,6 @@
 """CPU tests of the HIP library's host side (no GPU compute): symbol exports,
 the index builder's structure and conservativeness, the lookup-table
-encoding of Fig. 6b, the fp32 refinement tier's error bound, error paths."""
+encoding of Fig. 7b, the fp32 refinement tier's error bound, error paths."""
 import os
 import re
 from fractions import Fraction
@@ -118,8 +118,8 @@ def test_builder_c2_approx_guarantee(act):
     _structural_check(act, P, idx, pts, precision_m=4.0)
 
 
-def test_lut_matches_fig6b_golden(act):
-    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "lut_fig6b.txt"))
+def test_lut_matches_fig7b_golden(act):
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "lut_fig7b.txt"))
             if l.strip() and not l.startswith("#")]
     lut = np.zeros(0, np.uint32)
     for _, off, tru, cand, words in rows:
