@@ -219,6 +219,53 @@ typedef struct {
 int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
 
 /*
+ * Batched joins (many point batches of uneven size in one pass over the
+ * GPU, the streaming setting of Section V: the paper probes a large point
+ * stream in parallel; here the stream arrives as batches).
+ *
+ * act_batch -- one batch: d_points (device, 2*n doubles, (lat, lng)
+ * interleaved), n (>= 0), d_out (device, n int32: lowest covering polygon
+ * id or -1, as act_join). Batches may not overlap in d_out.
+ */
+typedef struct {
+  const double *d_points;
+  int64_t n;
+  int32_t *d_out;
+} act_batch;
+
+/*
+ * act_join_batched -- join every batch of d_batches (a DEVICE array of nb
+ * act_batch descriptors, caller-owned, read by the GPU during the call).
+ * total_points must be at least the sum of the batches' n (it sizes the
+ * workspace). One fixed set of launches on `stream` serves all batches
+ * (setup, probe, resolve in exact mode, optional finish); the host reads
+ * nothing back, so the call can be captured into a HIP graph once the
+ * stream's workspace is large enough (act_batched_reserve) and replayed.
+ * d_ticks (optional, device, nb + 1 uint64): [0] the wall-clock tick at
+ * which the join started on the GPU, [1 + b] the tick at which batch b was
+ * complete (act_wall_clock_hz gives the tick rate). Extra matches of
+ * overlapping polygons are not reported (out only). A call whose batch
+ * sizes are negative or exceed the workspace writes nothing and leaves a
+ * flag that act_batched_status reports. Errors: ACT_E_ARG, ACT_E_DEVICE,
+ * ACT_E_OOM, ACT_E_RANGE (workspace too small while the stream is being
+ * captured), ACT_E_HIP.
+ */
+int act_join_batched(const act_index *idx, const act_batch *d_batches, int32_t nb,
+                     int64_t total_points, uint64_t *d_ticks, void *stream);
+
+/* Size the stream's batched-join workspace for up to max_batches batches of
+ * max_points points in total (synchronises the stream if it grows). */
+int act_batched_reserve(const act_index *idx, void *stream, int32_t max_batches,
+                        int64_t max_points);
+
+/* Whether the stream's last batched join was well-formed (*ok = 1) or was
+ * refused on the GPU (*ok = 0). Synchronises the stream. */
+int act_batched_status(const act_index *idx, void *stream, int32_t *ok);
+
+/* Rate of the GPU wall clock used by batch completion ticks. */
+int act_wall_clock_hz(int32_t device, double *hz);
+
+/*
  * act_cell_ids -- level-30 cell ids of n points (Section II, S2 paragraph:
  * 3 face bits, a Hilbert-ordered bit pair per level, a marker bit). The
  * projection is lat/lng -> unit sphere -> cube face (u, v) -> linear

@@ -25,7 +25,8 @@ from . import _binding as _b
 from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
                        ACT_REFINE_FP64, ACT_REFINE_LOCAL, COUNTER_NAMES, ActError)
 
-__all__ = ["build", "Index", "cell_ids", "ActError", "ACT_EXACT", "ACT_APPROX",
+__all__ = ["build", "Index", "cell_ids", "batch_descriptors", "wall_clock_hz", "ActError",
+           "ACT_EXACT", "ACT_APPROX",
            "ACT_REFINE_AUTO", "ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64",
            "version", "lib"]
 
@@ -149,6 +150,26 @@ class Index:
         """Size the stream's exact-mode workspace for `points` points per pass."""
         _b.check(lib.act_workspace_reserve(self._h, _stream_ptr(stream), int(points)))
 
+    def join_batched(self, descriptors, total_points, ticks=None, stream=None):
+        """Join many batches at once. `descriptors`: CUDA int64 tensor (nb, 3)
+        from batch_descriptors(); `ticks`: optional CUDA int64 tensor of
+        nb + 1 (GPU wall-clock ticks: start, then each batch's completion).
+        Enqueues only (graph-capturable once the workspace is reserved)."""
+        nb = int(descriptors.shape[0])
+        _b.check(lib.act_join_batched(self._h, ctypes.c_void_p(descriptors.data_ptr()), nb,
+                                      int(total_points),
+                                      ctypes.c_void_p(ticks.data_ptr() if ticks is not None else 0),
+                                      _stream_ptr(stream)))
+
+    def batched_reserve(self, max_batches, max_points, stream=None):
+        _b.check(lib.act_batched_reserve(self._h, _stream_ptr(stream), int(max_batches),
+                                         int(max_points)))
+
+    def batched_ok(self, stream=None) -> bool:
+        ok = ctypes.c_int32(0)
+        _b.check(lib.act_batched_status(self._h, _stream_ptr(stream), ctypes.byref(ok)))
+        return bool(ok.value)
+
     def join_pairs(self, points, capacity=None, stream=None):
         """(out, pairs): pairs is (m, 2) int64 of (point, polygon) beyond out[i].
         Retries once with the exact size if the first capacity was too small."""
@@ -203,6 +224,32 @@ def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
     _b.check(lib.act_build(_np_ptr(v), _np_ptr(ro), _np_ptr(pro), n_polys, m, float(precision_m),
                            ctypes.byref(opts), ctypes.byref(h)))
     return Index(h, m, precision_m, device)
+
+
+def batch_descriptors(batches):
+    """Device array of act_batch descriptors for [(points, out), ...] (CUDA
+    tensors: points (n, 2) float64, out (n,) int32). Returns (descriptors,
+    total points). The tensors must stay alive while joins use them."""
+    import torch
+    rows = []
+    total = 0
+    for pts, out in batches:
+        _check_points(pts)
+        n = int(pts.shape[0])
+        if out.dtype != torch.int32 or out.shape[0] < n or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int32 tensor of at least n elements")
+        rows.append((pts.data_ptr(), n, out.data_ptr()))
+        total += n
+    dev = batches[0][0].device if batches else "cuda"
+    d = torch.tensor(rows, dtype=torch.int64).reshape(-1, 3).to(dev)
+    return d, total
+
+
+def wall_clock_hz(device: int = 0) -> float:
+    """Tick rate of the GPU wall clock behind batched-join ticks."""
+    hz = ctypes.c_double(0.0)
+    _b.check(lib.act_wall_clock_hz(int(device), ctypes.byref(hz)))
+    return hz.value
 
 
 def cell_ids(points, out=None, stream=None):

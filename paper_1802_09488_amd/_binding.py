@@ -84,6 +84,10 @@ def _load():
         "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),
         "act_lut_host": ([p, p, p], ctypes.c_int),
         "act_abi_sizes": ([p], ctypes.c_int),
+        "act_join_batched": ([p, p, i32, i64, p, p], ctypes.c_int),
+        "act_batched_reserve": ([p, p, i32, i64], ctypes.c_int),
+        "act_batched_status": ([p, p, p], ctypes.c_int),
+        "act_wall_clock_hz": ([i32, p], ctypes.c_int),
         "act_build_opts_init": ([p], None),
         "act_refine_local_host": ([p, i32, ctypes.c_uint32, ctypes.c_uint32, d, d, i32, p],
                                   ctypes.c_int),

@@ -73,6 +73,12 @@ struct DevImage {
 struct Workspace {
   uint64_t *mask = nullptr;
   int64_t cap = 0;  // points
+  // batched joins: virtual point space of up to cap_groups 64-point groups
+  uint64_t *bmask = nullptr, *gticks = nullptr;
+  int32_t *group_batch = nullptr;
+  int64_t *vstart = nullptr, *vhdr = nullptr;
+  int64_t cap_groups = 0;
+  int32_t cap_batches = 0;
 };
 
 constexpr int64_t kDefaultPass = 1 << 24;
@@ -122,6 +128,13 @@ struct ProbeParams {
   const uint32_t *local;  // cell-local refinement records (exact mode)
   uint64_t *mask;         // exact mode: pending points of this pass, bit per point
   int64_t base;           // index of pts[0] in the caller's array (pair output)
+  // batched joins: the batches laid end to end in a virtual point space,
+  // each starting at a multiple of 128 points
+  const act_batch *batches;
+  const int32_t *group_batch;  // batch of each 64-point group of that space
+  const int64_t *vstart;       // first virtual point of each batch, [nb] = end
+  const int64_t *vhdr;         // [0] virtual groups in use (0 on a bad call)
+  uint64_t *gticks;            // optional: completion tick of each group
 };
 
 
@@ -323,7 +336,7 @@ struct Hits {
     if (P.pair_pt) {
       const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
       if ((int64_t)k < P.cap) {
-        P.pair_pt[k] = P.base + i;
+        P.pair_pt[k] = i;
         P.pair_poly[k] = other;
       }
     }
@@ -470,16 +483,51 @@ __device__ __forceinline__ void store_out(int32_t *p, int32_t v) {
   __builtin_nontemporal_store(v, p);
 }
 
-// Step 7-9 for the NP points of a lane in tile `tile`.
-template <bool EXACT, bool COUNT, int NP>
-__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, int lane,
-                                            const uint64_t (&e)[NP], const bool (&live)[NP],
-                                            const bool (&valid)[NP], uint32_t (&c)[8]) {
+// Where a tile's points live: its first point, its output, how many points
+// of the tile's 64 NP exist (may exceed 64 NP), and the caller's index of
+// its first point (pair output; single joins only). A single join's tiles
+// are consecutive; a batched join's tile lies inside one batch (batches
+// start at multiples of 128 virtual points).
+struct TileRef {
+  const double2 *pts;
+  int32_t *out;
+  int64_t n;
+  int64_t gi;
+};
+
+template <bool BATCHED, int NP>
+__device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, int64_t tile) {
   constexpr int TILE = 64 * NP;
+  TileRef r;
+  if (!BATCHED) {
+    const int64_t s = tile * TILE;
+    r.pts = P.pts + s;
+    r.out = P.out + s;
+    r.n = P.n - s;
+    r.gi = P.base + s;
+  } else {
+    const int32_t b = P.group_batch[tile * NP];
+    const int64_t off = tile * TILE - P.vstart[b];
+    const act_batch d = P.batches[b];
+    r.pts = (const double2 *)d.d_points + off;
+    r.out = d.d_out + off;
+    r.n = d.n - off;
+    r.gi = -1;
+  }
+  return r;
+}
+
+// Step 7-9 for the NP points of a lane in tile `tile` (points at T).
+template <bool EXACT, bool COUNT, int NP, bool BATCHED>
+__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, const TileRef &T,
+                                            int lane, const uint64_t (&e)[NP],
+                                            const bool (&live)[NP], const bool (&valid)[NP],
+                                            uint32_t (&c)[8]) {
   bool pend[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    const int64_t i = tile * TILE + p * 64 + lane;
+    const int64_t k = p * 64 + lane;  // within the tile
+    const int64_t i = T.gi + k;       // caller's index (pair output)
     if (COUNT) {
       c[0] += live[p];
       c[1] += live[p] && !valid[p];
@@ -504,7 +552,7 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
         if (COUNT) c[4]++;
       }
       if (COUNT) c[3] += e[p] != 0;
-      if (live[p]) store_out(P.out + i, hits.best);
+      if (live[p]) store_out(T.out + k, hits.best);
       pend[p] = false;
     } else {
       // exact mode: a point whose cell entry has candidate references or is
@@ -513,12 +561,12 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
       const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
       pend[p] = live[p] && (tag == kTagLut || cand_inl);
       if (pend[p]) {
-        store_out(P.out + i, tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending);
+        store_out(T.out + k, tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending);
       } else {
         Hits hits;
         if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
         if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
-        if (live[p]) store_out(P.out + i, hits.best);
+        if (live[p]) store_out(T.out + k, hits.best);
         if (COUNT) c[3] += e[p] != 0;
       }
     }
@@ -527,9 +575,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
 #pragma unroll
     for (int p = 0; p < NP; p++) {
       const uint64_t m = ballot(pend[p]);
-      if (lane == 0 && tile * TILE + p * 64 < P.n) P.mask[tile * NP + p] = m;
+      // every group of the virtual space of a batched join has a word
+      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[tile * NP + p] = m;
     }
   }
+  if (P.gticks && lane < NP) P.gticks[tile * NP + lane] = wall_clock64();
 }
 
 // The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
@@ -539,7 +589,7 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
 // the first global node level of tile t - 1 (issued at the end of the
 // previous iteration) is in flight; then tile t - 1 finishes. The point
 // loads run one tile further ahead.
-template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP>
+template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP, bool BATCHED>
 __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   extern __shared__ uint32_t s_nodes[];
   __shared__ FaceDev s_face[6];
@@ -552,14 +602,16 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
   constexpr int TILE = 64 * NP;
-  const int64_t ntiles = (P.n + TILE - 1) / TILE;
+  const int64_t ntiles = BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE;
   const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
   const int64_t first = (int64_t)blockIdx.x * kProbeWaves + wid;
   double2 nxt[NP];
+  TileRef tnext;
+  if (first < ntiles) tnext = tile_ref<BATCHED, NP>(P, first);
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    const int64_t k = first * TILE + p * 64 + lane;
-    nxt[p] = (first < ntiles && k < P.n) ? load_point(P.pts + k) : make_double2(0.0, 0.0);
+    const int64_t k = p * 64 + lane;
+    nxt[p] = (first < ntiles && k < tnext.n) ? load_point(tnext.pts + k) : make_double2(0.0, 0.0);
   }
   // stage B: the tile whose first global level is in flight
   Descent<NP> B;
@@ -567,20 +619,23 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   bool liveB[NP], validB[NP];
   bool hasB = false;
   int64_t tileB = 0;
+  TileRef TB, TA;
   for (int64_t tile = first;; tile += nwaves) {
     const bool hasA = tile < ntiles;  // wave-uniform
     if (!hasA && !hasB) break;
     Descent<NP> A;
     bool liveA[NP], validA[NP];
     if (hasA) {
+      TA = tnext;
+      const bool more = tile + nwaves < ntiles;
+      if (more) tnext = tile_ref<BATCHED, NP>(P, tile + nwaves);
       uint32_t face[NP];
 #pragma unroll
       for (int p = 0; p < NP; p++) {
-        const int64_t i = tile * TILE + p * 64 + lane;
-        liveA[p] = i < P.n;
+        const int64_t k = p * 64 + lane;
+        liveA[p] = k < TA.n;
         const double lat = nxt[p].x, lng = nxt[p].y;
-        const int64_t k = (tile + nwaves) * TILE + p * 64 + lane;
-        if (tile + nwaves < ntiles && k < P.n) nxt[p] = load_point(P.pts + k);
+        if (more && k < tnext.n) nxt[p] = load_point(tnext.pts + k);
         face[p] = A.ci[p] = A.cj[p] = 0;
         validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
       }
@@ -589,10 +644,11 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
     if (hasB) {
       take_level<NP>(B, xB, c_reads);
       descend_rest<NP>(P, B, c_reads);
-      finish_tile<EXACT, COUNT, NP>(P, tileB, lane, B.e, liveB, validB, c);
+      finish_tile<EXACT, COUNT, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c);
     }
     if (hasA) {
       B = A;
+      TB = TA;
 #pragma unroll
       for (int p = 0; p < NP; p++) {
         liveB[p] = liveA[p];
@@ -692,25 +748,27 @@ __device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint3
     if (c[k]) atomicAdd(P.counters + ids[k], (unsigned long long)c[k]);
 }
 
-// Pending points of a resolve block: the block reads kBlock mask words
-// (64 kBlock points of the pass), compacts their set bits into an LDS list
-// (block-wide prefix sum of the popcounts) and hands the list out one point
-// per thread; bits beyond the list's capacity stay with the thread that
-// read them.
+// Pending points of a resolve block range: the block reads kBlock mask
+// words (64 kBlock points of the pass), compacts their set bits into an LDS
+// list (block-wide prefix sum of the popcounts) and hands the list out one
+// point per thread; bits beyond the list's capacity stay with the thread
+// that read them. Points are numbered in the pass (or, for batched joins,
+// the virtual point space).
 constexpr int kListCap = 2048;
 
 struct PendingIter {
   int k, total;
-  uint64_t m;  // bits of this thread's word not in the list
-  int64_t w;   // this thread's mask word
-  __device__ __forceinline__ bool next(const uint16_t *s_list, int64_t &i) {
+  uint64_t m;    // bits of this thread's word not in the list
+  int64_t w;     // this thread's mask word
+  int64_t base;  // first point of the block's range
+  __device__ __forceinline__ bool next(const uint16_t *s_list, int64_t &v) {
     if (k < total) {
-      i = (int64_t)blockIdx.x * kBlock * 64 + s_list[k];
+      v = base + s_list[k];
       k += kBlock;
       return true;
     }
     if (m) {
-      i = w * 64 + (__ffsll((long long)m) - 1);
+      v = w * 64 + (__ffsll((long long)m) - 1);
       m &= m - 1;
       return true;
     }
@@ -718,11 +776,13 @@ struct PendingIter {
   }
 };
 
-__device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int64_t nwords,
-                                                      uint16_t *s_list, uint32_t *s_wave) {
+__device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int64_t blk,
+                                                      int64_t nwords, uint16_t *s_list,
+                                                      uint32_t *s_wave) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   PendingIter it;
-  it.w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  it.base = blk * kBlock * 64;
+  it.w = blk * kBlock + threadIdx.x;
   uint64_t m = it.w < nwords ? P.mask[it.w] : 0ull;
   const uint32_t c = (uint32_t)__popcll(m);
   uint32_t incl = c;
@@ -749,97 +809,226 @@ __device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int6
   return it;
 }
 
-// Resolve the pending points. LOCAL: each thread decides its point's
-// candidates from their cell-local records. Otherwise (refinement over all
-// of a polygon's edges) lanes gather their points' candidates and the whole
-// wave tests one (point, polygon) pair at a time (lanes over edges, see
-// wave_covers); in every round each lane with work offers its next
-// candidate.
-template <bool LOCAL, bool COUNT>
-__global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t nwords) {
+// A pending point: where it is, where its result goes, and the caller's
+// index of it (pair output; single joins only).
+struct PointRef {
+  const double2 *pt;
+  int32_t *out;
+  int64_t gi;
+};
+
+template <bool BATCHED>
+__device__ __forceinline__ PointRef point_ref(const ProbeParams &P, int64_t v) {
+  PointRef r;
+  if (!BATCHED) {
+    r.pt = P.pts + v;
+    r.out = P.out + v;
+    r.gi = P.base + v;
+  } else {
+    const int32_t b = P.group_batch[v >> 6];
+    const int64_t k = v - P.vstart[b];
+    const act_batch d = P.batches[b];
+    r.pt = (const double2 *)d.d_points + k;
+    r.out = d.d_out + k;
+    r.gi = -1;
+  }
+  return r;
+}
+
+// Resolve the pending points, block range by block range. LOCAL: each
+// thread decides its point's candidates from their cell-local records.
+// Otherwise (refinement over all of a polygon's edges) lanes gather their
+// points' candidates and the whole wave tests one (point, polygon) pair at a
+// time (lanes over edges, see wave_covers); in every round each lane with
+// work offers its next candidate.
+template <bool LOCAL, bool COUNT, bool BATCHED>
+__global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t nwords_arg) {
   __shared__ uint16_t s_list[kListCap];
   __shared__ uint32_t s_wave[kBlock / 64];
-  PendingIter it = gather_pending(P, nwords, s_list, s_wave);
+  const int64_t nwords = BATCHED ? P.vhdr[0] : nwords_arg;
   uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
-  int64_t i = 0;
-  if (LOCAL) {
-    while (it.next(s_list, i)) {
-      const double2 pt = P.pts[i];
-      const RefList L = pending_refs(P, P.out[i], pt.x, pt.y, c_reads);
-      Hits hits;
-      for (uint32_t r = 0; r < L.nt; r++) hits.add(P, i, (int32_t)L.true_id(P, r));
-      for (uint32_t r = 0; r < L.nc; r++) {
-        const int32_t poly = (int32_t)L.cand_id(P, r);
-        const uint32_t loc = L.cand_loc(P, r);
-        bool cov;
-        if (loc != 0xffffffffu) {
-          cov = local_record_covers(P.local + loc, pt.y, pt.x);
-          if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
-        } else {
-          cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
-          if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+  for (int64_t blk = blockIdx.x; blk * kBlock < nwords; blk += gridDim.x) {
+    PendingIter it = gather_pending(P, blk, nwords, s_list, s_wave);
+    int64_t v = 0;
+    if (LOCAL) {
+      while (it.next(s_list, v)) {
+        const PointRef R = point_ref<BATCHED>(P, v);
+        const double2 pt = *R.pt;
+        const RefList L = pending_refs(P, *R.out, pt.x, pt.y, c_reads);
+        Hits hits;
+        for (uint32_t r = 0; r < L.nt; r++) hits.add(P, R.gi, (int32_t)L.true_id(P, r));
+        for (uint32_t r = 0; r < L.nc; r++) {
+          const int32_t poly = (int32_t)L.cand_id(P, r);
+          const uint32_t loc = L.cand_loc(P, r);
+          bool cov;
+          if (loc != 0xffffffffu) {
+            cov = local_record_covers(P.local + loc, pt.y, pt.x);
+            if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+          } else {
+            cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
+            if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+          }
+          if (cov) hits.add(P, R.gi, poly);
         }
-        if (cov) hits.add(P, i, poly);
+        *R.out = hits.best;
+        if (COUNT) {
+          c[0] += L.nc == 0 && L.nt > 0;
+          c[1] += L.nc > 0;
+          c[2] += L.nc;
+          c[6] += L.lut;
+        }
       }
-      P.out[i] = hits.best;
-      if (COUNT) {
-        c[0] += L.nc == 0 && L.nt > 0;
-        c[1] += L.nc > 0;
-        c[2] += L.nc;
-        c[6] += L.lut;
-      }
-    }
-  } else {
-    const int lane = threadIdx.x & 63;
-    bool have = false, more = true;
-    double lat = 0.0, lng = 0.0;
-    RefList L;
-    uint32_t r = 0;
-    Hits hits;
-    for (;;) {
-      if (!have && more) {
-        more = it.next(s_list, i);
-        if (more) {
-          const double2 pt = P.pts[i];
-          lat = pt.x;
-          lng = pt.y;
-          L = pending_refs(P, P.out[i], lat, lng, c_reads);
-          hits = Hits();
-          for (uint32_t t = 0; t < L.nt; t++) hits.add(P, i, (int32_t)L.true_id(P, t));
-          r = 0;
-          have = true;
-          if (COUNT) {
-            c[0] += L.nc == 0 && L.nt > 0;
-            c[1] += L.nc > 0;
-            c[2] += L.nc;
-            c[6] += L.lut;
+    } else {
+      const int lane = threadIdx.x & 63;
+      bool have = false, more = true;
+      double lat = 0.0, lng = 0.0;
+      RefList L;
+      PointRef R{nullptr, nullptr, 0};
+      uint32_t r = 0;
+      Hits hits;
+      for (;;) {
+        if (!have && more) {
+          more = it.next(s_list, v);
+          if (more) {
+            R = point_ref<BATCHED>(P, v);
+            const double2 pt = *R.pt;
+            lat = pt.x;
+            lng = pt.y;
+            L = pending_refs(P, *R.out, lat, lng, c_reads);
+            hits = Hits();
+            for (uint32_t t = 0; t < L.nt; t++) hits.add(P, R.gi, (int32_t)L.true_id(P, t));
+            r = 0;
+            have = true;
+            if (COUNT) {
+              c[0] += L.nc == 0 && L.nt > 0;
+              c[1] += L.nc > 0;
+              c[2] += L.nc;
+              c[6] += L.lut;
+            }
           }
         }
+        if (have && r >= L.nc) {
+          *R.out = hits.best;
+          have = false;
+        }
+        uint64_t todo = ballot(have);
+        if (!todo) {
+          if (!ballot(more)) break;
+          continue;
+        }
+        const int32_t poly = have ? (int32_t)L.cand_id(P, r) : 0;
+        while (todo) {
+          const int src = __ffsll((long long)todo) - 1;
+          todo &= todo - 1;
+          const int32_t q = __shfl(poly, src);
+          const double qlat = __shfl(lat, src), qlng = __shfl(lng, src);
+          if (COUNT && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
+          const bool cov = wave_covers<COUNT>(P, q, qlat, qlng, lane, c[4], c[5]);
+          if (lane == src && cov) hits.add(P, R.gi, q);
+        }
+        if (have) r++;
       }
-      if (have && r >= L.nc) {
-        P.out[i] = hits.best;
-        have = false;
-      }
-      uint64_t todo = ballot(have);
-      if (!todo) {
-        if (!ballot(more)) break;
-        continue;
-      }
-      const int32_t poly = have ? (int32_t)L.cand_id(P, r) : 0;
-      while (todo) {
-        const int src = __ffsll((long long)todo) - 1;
-        todo &= todo - 1;
-        const int32_t q = __shfl(poly, src);
-        const double qlat = __shfl(lat, src), qlng = __shfl(lng, src);
-        if (COUNT && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
-        const bool cov = wave_covers<COUNT>(P, q, qlat, qlng, lane, c[4], c[5]);
-        if (lane == src && cov) hits.add(P, i, q);
-      }
-      if (have) r++;
     }
+    __syncthreads();  // the LDS list is rebuilt for the next range
+    if (P.gticks && it.w < nwords) P.gticks[it.w] = wall_clock64();
   }
   flush_counters<COUNT>(P, c);
   if (COUNT && c_reads) atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+}
+
+// ---------------------------------------------------------------- batches
+//
+// A batched join lays its batches end to end in a virtual point space,
+// each starting at a multiple of 128 points (so no probe tile spans two
+// batches), and runs the probe and resolve kernels over that space once.
+// The setup kernel (one block) scans the batch sizes; the fill kernel
+// records the batch of every 64-point group; the finish kernel turns the
+// groups' completion ticks into per-batch completion ticks. None of them
+// needs the host to know the sizes, so the whole call can be captured.
+constexpr int kSetupBlock = 1024;
+
+__global__ __launch_bounds__(kSetupBlock) void batch_setup_kernel(const act_batch *batches,
+                                                                  int32_t nb, int64_t cap_groups,
+                                                                  int64_t *vstart, int64_t *vhdr,
+                                                                  uint64_t *ticks) {
+  __shared__ int64_t s_part[kSetupBlock / 64];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) {
+    s_carry = 0;
+    if (ticks) ticks[0] = wall_clock64();
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  bool bad = false;
+  for (int32_t b0 = 0; b0 < nb; b0 += kSetupBlock) {
+    const int32_t b = b0 + (int32_t)threadIdx.x;
+    int64_t sz = 0;
+    if (b < nb) {
+      const int64_t n = batches[b].n;
+      bad |= n < 0;
+      sz = n > 0 ? (n + 127) / 128 * 128 : 0;
+    }
+    int64_t incl = sz;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) s_part[wid] = incl;
+    __syncthreads();
+    int64_t before = s_carry, total = 0;
+    for (int k = 0; k < kSetupBlock / 64; k++) {
+      if (k < wid) before += s_part[k];
+      total += s_part[k];
+    }
+    if (b < nb) vstart[b] = before + incl - sz;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += total;
+    __syncthreads();
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) {
+    vstart[nb] = s_carry;
+    const int64_t groups = s_carry / 64;
+    vhdr[0] = (bad || groups > cap_groups) ? 0 : groups;  // 0: the join does nothing
+    vhdr[1] = (bad || groups > cap_groups) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_fill_kernel(const int64_t *vstart, int32_t nb,
+                                                         const int64_t *vhdr,
+                                                         int32_t *group_batch) {
+  const int64_t ng = vhdr[0];
+  for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < ng;
+       g += (int64_t)gridDim.x * 256) {
+    // last batch whose first point is at or before the group's
+    int32_t lo = 0, hi = nb - 1;
+    const int64_t v = g * 64;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (vstart[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    group_batch[g] = lo;
+  }
+}
+
+// Completion tick of each batch: the latest tick of its groups (the resolve
+// kernel's, in exact mode, which runs after the probe).
+__global__ __launch_bounds__(256) void batch_finish_kernel(const int64_t *vstart, int32_t nb,
+                                                           const int64_t *vhdr,
+                                                           const uint64_t *gticks,
+                                                           uint64_t *ticks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  const bool ok = vhdr[0] > 0 || vstart[nb] == 0;
+  for (int64_t b = wave; b < nb; b += nwaves) {
+    uint64_t t = 0;
+    if (ok)
+      for (int64_t g = vstart[b] / 64 + lane; g < vstart[b + 1] / 64; g += 64) t = max(t, gticks[g]);
+    for (int d = 32; d > 0; d >>= 1) t = max(t, (uint64_t)__shfl_xor(t, d));
+    if (lane == 0) ticks[1 + b] = ok ? (t ? t : ticks[0]) : 0;
+  }
 }
 
 __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_t n,
@@ -863,7 +1052,7 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
 using ProbeFn = void (*)(ProbeParams);
 template <bool EXACT, int LDS, bool COUNT>
 static ProbeFn probe_np(int np) {
-  return np == 1 ? probe_kernel<EXACT, LDS, COUNT, 1> : probe_kernel<EXACT, LDS, COUNT, 2>;
+  return np == 1 ? probe_kernel<EXACT, LDS, COUNT, 1, false> : probe_kernel<EXACT, LDS, COUNT, 2, false>;
 }
 
 static ProbeFn probe_fn(bool exact, int lds_depth, bool count, int np) {
@@ -876,6 +1065,20 @@ static ProbeFn probe_fn(bool exact, int lds_depth, bool count, int np) {
        {probe_np<true, 1, false>, probe_np<true, 1, true>},
        {probe_np<true, 2, false>, probe_np<true, 2, true>}}};
   return tab[exact][lds_depth][count](np);
+}
+
+// Batched joins: no counters.
+template <bool EXACT, int LDS>
+static ProbeFn probe_batched_np(int np) {
+  return np == 1 ? probe_kernel<EXACT, LDS, false, 1, true> : probe_kernel<EXACT, LDS, false, 2, true>;
+}
+
+static ProbeFn probe_batched_fn(bool exact, int lds_depth, int np) {
+  using F = ProbeFn (*)(int);
+  static const F tab[2][3] = {
+      {probe_batched_np<false, 0>, probe_batched_np<false, 1>, probe_batched_np<false, 2>},
+      {probe_batched_np<true, 0>, probe_batched_np<true, 1>, probe_batched_np<true, 2>}};
+  return tab[exact][lds_depth](np);
 }
 
 // ------------------------------------------------------------------ host
@@ -921,9 +1124,56 @@ static int upload(T *&dst, const void *src, size_t bytes, size_t &total) {
   return ACT_OK;
 }
 
+static void free_batch_workspace(Workspace &w) {
+  void *ptrs[] = {w.bmask, w.gticks, w.group_batch, w.vstart, w.vhdr};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  w.bmask = w.gticks = nullptr;
+  w.group_batch = nullptr;
+  w.vstart = w.vhdr = nullptr;
+  w.cap_groups = 0;
+  w.cap_batches = 0;
+}
+
 static void free_workspace(Workspace &w) {
   if (w.mask) (void)hipFree(w.mask);
+  free_batch_workspace(w);
   w = Workspace();
+}
+
+// The stream's batched-join buffers for nb batches of `points` points in
+// total; allocated or enlarged when too small (not allowed while the stream
+// is being captured). Call with the index's device current.
+static int get_batch_workspace(const act_index *x, void *stream, int32_t nb, int64_t points,
+                               Workspace *&out) {
+  std::lock_guard<std::mutex> lk(x->ws_mu);
+  Workspace &w = x->ws[stream];
+  const int64_t groups = (points + 128 * (int64_t)nb) / 64 + 2;
+  if (w.cap_groups < groups || w.cap_batches < nb) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
+        cs != hipStreamCaptureStatusNone)
+      return fail(ACT_E_RANGE, "batched workspace too small during stream capture; call "
+                               "act_batched_reserve first");
+    if (w.cap_groups && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+      return fail(ACT_E_HIP, "cannot synchronise the stream to enlarge its workspace");
+    const int64_t g = std::max(groups, w.cap_groups);
+    const int32_t b = std::max(nb, w.cap_batches);
+    free_batch_workspace(w);
+    bool ok = hipMalloc((void **)&w.bmask, 8 * (size_t)g) == hipSuccess &&
+              hipMalloc((void **)&w.gticks, 8 * (size_t)g) == hipSuccess &&
+              hipMalloc((void **)&w.group_batch, 4 * (size_t)g) == hipSuccess &&
+              hipMalloc((void **)&w.vstart, 8 * ((size_t)b + 1)) == hipSuccess &&
+              hipMalloc((void **)&w.vhdr, 64) == hipSuccess;
+    if (!ok) {
+      free_batch_workspace(w);
+      return fail(ACT_E_OOM, "cannot allocate the batched-join workspace");
+    }
+    w.cap_groups = g;
+    w.cap_batches = b;
+  }
+  out = &w;
+  return ACT_OK;
 }
 
 // The stream's workspace: allocated on first use for `cap` points (and
@@ -1022,6 +1272,23 @@ static int default_lds_depth(const HostIndex &h) {
   return 0;
 }
 
+// The index's device image in the kernel parameters.
+static void index_params(const act_index *x, int refine, int n_lds, ProbeParams &P) {
+  P.nodes = x->dev.nodes;
+  P.lut = x->dev.lut;
+  P.eoff = x->dev.eoff;
+  P.origin = x->dev.origin;
+  P.pm = x->dev.pm;
+  P.e32 = x->dev.e32;
+  P.e64 = x->dev.e64;
+  P.trig = x->dev.trig;
+  P.faces = x->dev.faces;
+  P.top32 = x->dev.top32;
+  P.n_lds_nodes = n_lds;
+  P.refine = refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : refine;
+  P.local = x->dev.local;
+}
+
 static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
   if (!a) return fail(ACT_E_ARG, "args is NULL");
@@ -1056,19 +1323,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.cap = a->pair_capacity;
   P.n_pairs = a->d_n_pairs;
   P.counters = (unsigned long long *)a->d_counters;
-  P.nodes = x->dev.nodes;
-  P.lut = x->dev.lut;
-  P.eoff = x->dev.eoff;
-  P.origin = x->dev.origin;
-  P.pm = x->dev.pm;
-  P.e32 = x->dev.e32;
-  P.e64 = x->dev.e64;
-  P.trig = x->dev.trig;
-  P.faces = x->dev.faces;
-  P.top32 = x->dev.top32;
-  P.n_lds_nodes = n_lds;
-  P.refine = a->refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : a->refine;
-  P.local = x->dev.local;
+  index_params(x, a->refine, n_lds, P);
   const int np = a->points_per_lane > 0 ? a->points_per_lane : 2;
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
@@ -1084,8 +1339,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   const ProbeFn probe = probe_fn(exact, depth, count, np);
   using ResolveFn = void (*)(ProbeParams, int64_t);
   const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
-                              ? (count ? resolve_kernel<true, true> : resolve_kernel<true, false>)
-                              : (count ? resolve_kernel<false, true> : resolve_kernel<false, false>);
+                              ? (count ? resolve_kernel<true, true, false> : resolve_kernel<true, false, false>)
+                              : (count ? resolve_kernel<false, true, false> : resolve_kernel<false, false, false>);
   for (int64_t s0 = 0; s0 < a->n; s0 += pass) {
     const int64_t n = std::min(pass, a->n - s0);
     P.pts = (const double2 *)a->d_points + s0;
@@ -1109,6 +1364,54 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
   }
+  return ACT_OK;
+}
+
+constexpr int kBatchGrid = 4096;  // fill / resolve blocks of a batched join
+
+static int join_batched_impl(const act_index *x, const act_batch *d_batches, int32_t nb,
+                             int64_t total_points, uint64_t *d_ticks, void *stream) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (nb < 0 || total_points < 0) return fail(ACT_E_ARG, "nb < 0 or total_points < 0");
+  if (nb > 0 && !d_batches) return fail(ACT_E_ARG, "batches is NULL");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  int rc = check_stream_device(x, stream);
+  if (rc) return rc;
+  if (nb == 0) return ACT_OK;
+  const HostIndex &h = x->host;
+  int depth = default_lds_depth(h);
+  int n_lds = depth > 0 ? lds_nodes_for(h, depth) : 0;
+  if (depth > 0 && n_lds <= 0) depth = n_lds = 0;
+  DeviceGuard g(x->device);
+  Workspace *w = nullptr;
+  rc = get_batch_workspace(x, stream, nb, total_points, w);
+  if (rc) return rc;
+  const bool exact = h.mode == ACT_EXACT;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(kSetupBlock), 0, st, d_batches, nb,
+                     w->cap_groups, w->vstart, w->vhdr, d_ticks);
+  hipLaunchKernelGGL(batch_fill_kernel, dim3(kBatchGrid), dim3(256), 0, st, w->vstart, nb,
+                     w->vhdr, w->group_batch);
+  ProbeParams P{};
+  index_params(x, ACT_REFINE_LOCAL, n_lds, P);
+  P.mask = w->bmask;
+  P.batches = d_batches;
+  P.group_batch = w->group_batch;
+  P.vstart = w->vstart;
+  P.vhdr = w->vhdr;
+  P.gticks = d_ticks ? w->gticks : nullptr;
+  hipLaunchKernelGGL(probe_batched_fn(exact, depth, 2), dim3(1024), dim3(kProbeBlock),
+                     (size_t)n_lds * 1024, st, P);
+  if (exact) {
+    void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
+    hipLaunchKernelGGL(resolve, dim3(kBatchGrid), dim3(kBlock), 0, st, P, (int64_t)0);
+  }
+  if (d_ticks)
+    hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)nb + 3) / 4, 4096)),
+                       dim3(256), 0, st, w->vstart, nb, w->vhdr, w->gticks, d_ticks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(ACT_E_HIP, std::string("batched join launch: ") + hipGetErrorString(e));
   return ACT_OK;
 }
 
@@ -1211,6 +1514,45 @@ int act_workspace_reserve(const act_index *x, void *stream, int64_t points) {
 
 int act_join_ex(const act_index *x, const act_join_args *args, void *stream) {
   return join_impl(x, args, stream);
+}
+
+int act_join_batched(const act_index *x, const act_batch *d_batches, int32_t nb,
+                     int64_t total_points, uint64_t *d_ticks, void *stream) {
+  return join_batched_impl(x, d_batches, nb, total_points, d_ticks, stream);
+}
+
+int act_batched_reserve(const act_index *x, void *stream, int32_t max_batches,
+                        int64_t max_points) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (max_batches < 0 || max_points < 0) return fail(ACT_E_ARG, "negative size");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  int rc = check_stream_device(x, stream);
+  if (rc) return rc;
+  DeviceGuard g(x->device);
+  Workspace *w = nullptr;
+  return get_batch_workspace(x, stream, std::max(max_batches, 1), max_points, w);
+}
+
+int act_batched_status(const act_index *x, void *stream, int32_t *ok) {
+  if (!x || !ok) return fail(ACT_E_ARG, "bad argument");
+  std::lock_guard<std::mutex> lk(x->ws_mu);
+  auto it = x->ws.find(stream);
+  if (it == x->ws.end() || !it->second.vhdr) return fail(ACT_E_ARG, "no batched join on this stream");
+  DeviceGuard g(x->device);
+  int64_t hdr[2];
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(hdr, it->second.vhdr, sizeof hdr, hipMemcpyDeviceToHost));
+  *ok = hdr[1] == 0;
+  return ACT_OK;
+}
+
+int act_wall_clock_hz(int32_t device, double *hz) {
+  if (!hz) return fail(ACT_E_ARG, "hz is NULL");
+  if (device < 0 || device >= device_count()) return fail(ACT_E_DEVICE, "no such HIP device");
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device));
+  *hz = 1e3 * khz;
+  return ACT_OK;
 }
 
 int act_join(const act_index *x, const double *d_points, int64_t n, int32_t *d_out, void *stream) {

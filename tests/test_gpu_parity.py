@@ -316,3 +316,101 @@ def test_overlapping_polygons_approx(act):
     pts = np.stack([rng.uniform(40.68, 40.72, 100000), rng.uniform(-73.98, -73.92, 100000)], 1)
     out, pairs, _ = gpu_join(idx, pts)
     assert_approx(P, pts, out, pairs, 2.0, "overlap approx")
+
+
+def _uneven_batches(pts_all, rng, n_batches, hi):
+    """Consecutive slices of pts_all with sizes floor(exp(U(0, ln hi))), plus
+    empty and one-point batches."""
+    sizes = np.maximum(1, np.floor(np.exp(rng.uniform(0, np.log(hi), n_batches)))).astype(np.int64)
+    sizes[::17] = 0
+    sizes[5::23] = 1
+    sizes = sizes[np.cumsum(sizes) <= len(pts_all)]
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    return [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:])]
+
+
+@pytest.mark.parametrize("mode,prec", [("exact", 0.0), ("approx", 4.0)])
+def test_batched_matches_oracle_and_single(act, mode, prec):
+    """Uneven batches (0 .. 2e4 points) in one batched join: every batch's
+    output equals the single join's and the oracle's (exact) or meets the
+    approximate guarantee; completion ticks are set and ordered after the
+    start tick."""
+    P, idx = index(act, "c2", mode, prec)
+    rng = np.random.default_rng(31)
+    pts_all = synth.workload_points("c2", 0, 1_500_000)
+    spans = _uneven_batches(pts_all, rng, 400, 2e4)
+    dev = torch.from_numpy(pts_all).cuda()
+    batches = [(dev[a:b], torch.full((b - a,), -7, dtype=torch.int32, device="cuda"))
+               for a, b in spans]
+    desc, total = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    idx.join_batched(desc, total, ticks=ticks)
+    torch.cuda.synchronize()
+    assert idx.batched_ok()
+    got = np.concatenate([o.cpu().numpy() for _, o in batches])
+    n = spans[-1][1]
+    single = idx.join(dev[:n]).cpu().numpy()
+    assert np.array_equal(got, single)
+    if mode == "exact":
+        ref = oracle.join(P, pts_all[:n])
+        assert np.array_equal(got, ref.out)
+    t = ticks.cpu().numpy().view(np.uint64)
+    assert t[0] > 0 and np.all(t[1:] >= t[0])
+    assert act.wall_clock_hz(0) > 1e6
+
+
+def test_batched_graph_replays(act):
+    """The batched join captured once into a HIP graph (through torch) and
+    replayed three times, with eager joins and output clearing between the
+    replays: every replay reproduces the eager result."""
+    P, idx = index(act, "c2", "exact")
+    rng = np.random.default_rng(32)
+    pts_all = synth.workload_points("c2", 0, 800_000)
+    spans = _uneven_batches(pts_all, rng, 200, 2e4)
+    dev = torch.from_numpy(pts_all).cuda()
+    outs = [torch.empty(b - a, dtype=torch.int32, device="cuda") for a, b in spans]
+    batches = [(dev[a:b], o) for (a, b), o in zip(spans, outs)]
+    desc, total = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    idx.join_batched(desc, total, ticks=ticks)
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    s = torch.cuda.Stream()
+    idx.batched_reserve(len(batches), total, stream=s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        idx.join_batched(desc, total, ticks=ticks)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-9)
+        other = idx.join(dev[: 50_000 * (rep + 1)])  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), rep
+        assert other.shape[0] == 50_000 * (rep + 1)
+
+
+def test_batched_refuses_bad_sizes(act):
+    """A batch list whose sizes exceed the stated total (so the workspace)
+    or are negative is refused on the GPU: nothing is written, the status
+    says so."""
+    P, idx = index(act, "c1", "exact")
+    pts = torch.from_numpy(synth.workload_points("c1", 0, 1000)).cuda()
+    out = torch.full((1000,), -9, dtype=torch.int32, device="cuda")
+    desc, total = act.batch_descriptors([(pts, out)])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        idx.join_batched(desc, 10)  # claims 10 points, the batch has 1000
+        torch.cuda.synchronize()
+        assert not idx.batched_ok()
+        assert int((out == -9).sum()) == 1000
+        bad = desc.clone()
+        bad[0, 1] = -5
+        idx.join_batched(bad, 1000)
+        assert not idx.batched_ok()
+        idx.join_batched(desc, total)
+        assert idx.batched_ok()
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), idx.join(pts).cpu().numpy())
