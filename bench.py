@@ -116,6 +116,59 @@ def copy_calibration():
     return {"bytes_each_way": COPY_BYTES, "ms": ms, "GBps_read_plus_write": 2 * COPY_BYTES / ms / 1e6}
 
 
+def batched_leg(act, idx, pts, exact_out, seed=3004, hi=1e6, replays=5):
+    """The resident points cut into uneven batches (sizes floor(exp(U(0,
+    ln 1e6)))), joined by one batched join captured in a HIP graph and
+    replayed: throughput, the replay's duration, and per-batch completion
+    latency (GPU wall-clock ticks from the join's start)."""
+    import numpy as np
+    import torch
+    n = pts.shape[0]
+    g = np.random.default_rng(seed)
+    sizes = []
+    tot = 0
+    while tot < n:
+        k = int(min(n - tot, max(1, np.floor(np.exp(g.uniform(0.0, np.log(hi)))))))
+        sizes.append(k)
+        tot += k
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    batches = [(pts[a:b], out[a:b]) for a, b in zip(bounds[:-1], bounds[1:])]
+    desc, total = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    idx.batched_reserve(len(batches), total, stream=s)
+    with torch.cuda.stream(s):
+        idx.join_batched(desc, total, ticks=ticks)  # eager once (warm)
+    s.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        idx.join_batched(desc, total, ticks=ticks)
+    hz = act.wall_clock_hz(0)
+    ms, lat50, lat99 = [], [], []
+    for _ in range(replays):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        graph.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+        t = ticks.cpu().numpy().view(np.uint64).astype(np.float64)
+        lat = (t[1:] - t[0]) / hz * 1e3
+        lat50.append(float(np.percentile(lat, 50)))
+        lat99.append(float(np.percentile(lat, 99)))
+    ok = bool(np.array_equal(out.cpu().numpy(), exact_out)) if exact_out is not None else None
+    return {"batches": len(batches), "points": int(total),
+            "batch_sizes": "floor(exp(U(0, ln 1e6))), seed %d" % seed,
+            "graph_replay_ms": float(np.median(ms)),
+            "points_per_s": total / (float(np.median(ms)) * 1e-3),
+            "batch_latency_ms": {"p50": float(np.median(lat50)), "p99": float(np.median(lat99)),
+                                 "what": "per-batch completion tick minus the join's start "
+                                         "tick (GPU wall clock), one graph replay"},
+            "identical_to_single_join": ok}
+
+
 def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
     """The oracle (brute force: bbox prefilter + exact point-in-polygon
     against every polygon, OpenMP over points) on the host's cores over the
@@ -216,6 +269,8 @@ def main():
             var[name]["identical_to_local"] = bool(np.array_equal(out.cpu().numpy(), exact_out))
     var["fp32_filter_over_fp64_speedup"] = (var["fp64"]["join_ms_mean"]
                                             / var["fp32_filter"]["join_ms_mean"])
+    log("batched join (graph replay)")
+    batched = batched_leg(act, idx, pts, exact_out)
 
     probe_ms = float(np.mean(prb))
     achieved = BYTES_PER_POINT * n / (probe_ms * 1e-3) / 1e9
@@ -247,6 +302,7 @@ def main():
                      "bytes_per_point": BYTES_PER_POINT, "points_per_launch": n},
         "latency_ms": {"p50": percentile(tot, 50), "p99": percentile(tot, 99),
                        "what": "one join of all points (one step), HIP events"},
+        "batched_exact": batched,
         "exact": {"join_ms_mean": float(np.mean(tot)), "probe_ms_mean": probe_ms,
                   "resolve_ms_mean": float(np.mean(tot) - probe_ms)},
         "approx4m": {"points_per_s": n * args.steps / wall_a,

@@ -262,6 +262,89 @@ int act_batched_reserve(const act_index *idx, void *stream, int32_t max_batches,
  * refused on the GPU (*ok = 0). Synchronises the stream. */
 int act_batched_status(const act_index *idx, void *stream, int32_t *ok);
 
+/*
+ * act_tune -- autotuner. Times joins of the sample (device, 2*n doubles;
+ * d_out: device scratch of n int32) over probe grid sizes (256 .. 4096
+ * blocks), LDS-staged trie depth (0 .. 2, where the levels fit), points
+ * per lane (1, 2) and, in exact mode, the refinement mapping (cell-local or
+ * all edges with the fp32 filter), picks the fastest (median of 3) and
+ * makes it the index's launch configuration: joins that leave grid = 0,
+ * lds_levels = -1, points_per_lane = 0 or refine = ACT_REFINE_AUTO, and
+ * batched joins, use it from then on. The hand-tuning the paper reports for
+ * its CPUs (Section V) is done by measurement here. With cache_path (a
+ * text file, one line per (index digest, gfx950) -> configuration) a
+ * cached configuration is applied without timing, and new results are
+ * appended. Synchronises the stream. Do not tune an index while joins on
+ * it are in flight. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_HIP.
+ */
+/* 64-bit digest of the index image (trie, lookup table, cell-local records,
+ * edges, mode, precision): equal for equal inputs and build options, on any
+ * thread count. */
+int act_index_digest(const act_index *idx, uint64_t *digest);
+
+typedef struct {
+  int32_t grid, lds_levels, points_per_lane, refine;  /* chosen configuration */
+  float best_ms;          /* its median join time on the sample              */
+  float default_ms;       /* the built-in defaults' median join time         */
+  int32_t n_configs;      /* configurations timed (0 when from the cache)    */
+  int32_t from_cache;     /* 1 if read from cache_path                       */
+  uint64_t index_digest;  /* cache key (0 without cache_path)                */
+} act_tune_result;
+
+int act_tune(act_index *idx, const double *d_sample, int64_t n, int32_t *d_out, void *stream,
+             const char *cache_path, act_tune_result *result);
+
+/*
+ * Serving loop (server.cpp): point-join requests of uneven size against
+ * several resident indexes, admitted continuously and overlapping on the
+ * GPU. A scheduler thread admits requests in arrival order when one of
+ * `slots` streams is free and the request's buffers (20 bytes per point)
+ * fit a device arena and a pinned host arena of `arena_bytes` each
+ * (allocated once; 0 = 90% of free HBM, at most 4 GiB). An admitted request
+ * is staged into pinned memory, copied to the GPU, joined (act_join) and
+ * copied back on its stream; its result lands in the caller's h_out.
+ * Exact-mode workspaces for every (index, stream) are reserved at creation
+ * for max_request_points (longer requests run in passes), so serving
+ * allocates nothing. The indexes must outlive the server.
+ */
+typedef struct act_server act_server;
+
+typedef struct {
+  int32_t slots;               /* concurrent requests on the GPU (default 4)  */
+  int32_t device;              /* HIP device (default 0)                      */
+  int64_t arena_bytes;         /* per-arena bytes (default 0, see above)      */
+  int64_t max_request_points;  /* workspace sizing (default 2^20)             */
+} act_server_opts;
+
+typedef struct {
+  double arrival_s, admitted_s, done_s;  /* act_server_clock() seconds       */
+  int64_t n;
+} act_request_times;
+
+typedef struct {
+  int64_t submitted, admitted, completed, failed, queued, points, arena_bytes;
+  int32_t slots, reserved;
+} act_server_stats;
+
+void act_server_opts_init(act_server_opts *opts);
+int act_server_create(const act_index *const *indexes, int32_t n_indexes,
+                      const act_server_opts *opts, act_server **out);
+/* Queue a request: n points at h_points (host, 2*n doubles) joined with
+ * indexes[index]; results to h_out (host, n int32). Both buffers must stay
+ * valid until act_server_wait returns for the ticket. arrival_s (seconds on
+ * act_server_clock(), 0 = now) is the request's arrival time for latency.
+ * ACT_E_RANGE if the request can never fit the arena. */
+int act_server_submit(act_server *s, int32_t index, const double *h_points, int64_t n,
+                      int32_t *h_out, double arrival_s, uint64_t *ticket);
+/* Block until the request is complete; its times go to *t (may be NULL).
+ * Each ticket is waited for exactly once. */
+int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t);
+int act_server_stats_get(act_server *s, act_server_stats *stats);
+double act_server_clock(void);
+/* Finish every queued request, then release streams and arenas. */
+void act_server_destroy(act_server *s);
+const char *act_server_last_error(void);
+
 /* Rate of the GPU wall clock used by batch completion ticks. */
 int act_wall_clock_hz(int32_t device, double *hz);
 

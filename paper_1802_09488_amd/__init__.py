@@ -25,7 +25,8 @@ from . import _binding as _b
 from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
                        ACT_REFINE_FP64, ACT_REFINE_LOCAL, COUNTER_NAMES, ActError)
 
-__all__ = ["build", "Index", "cell_ids", "batch_descriptors", "wall_clock_hz", "ActError",
+__all__ = ["build", "Index", "Server", "cell_ids", "batch_descriptors", "wall_clock_hz",
+           "ActError",
            "ACT_EXACT", "ACT_APPROX",
            "ACT_REFINE_AUTO", "ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64",
            "version", "lib"]
@@ -161,6 +162,24 @@ class Index:
                                       ctypes.c_void_p(ticks.data_ptr() if ticks is not None else 0),
                                       _stream_ptr(stream)))
 
+    def digest(self) -> int:
+        d = ctypes.c_uint64()
+        _b.check(lib.act_index_digest(self._h, ctypes.byref(d)))
+        return d.value
+
+    def tune(self, sample, cache_path=None, stream=None) -> dict:
+        """Autotune the launch configuration on a sample of points (CUDA
+        (n, 2) float64); see act_tune. Returns the choice and timings."""
+        import torch
+        _check_points(sample)
+        scratch = torch.empty(sample.shape[0], dtype=torch.int32, device=sample.device)
+        r = _b.TuneResult()
+        cp = cache_path.encode() if cache_path else None
+        _b.check(lib.act_tune(self._h, ctypes.c_void_p(sample.data_ptr()), int(sample.shape[0]),
+                              ctypes.c_void_p(scratch.data_ptr()), _stream_ptr(stream), cp,
+                              ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in r._fields_}
+
     def batched_reserve(self, max_batches, max_points, stream=None):
         _b.check(lib.act_batched_reserve(self._h, _stream_ptr(stream), int(max_batches),
                                          int(max_points)))
@@ -243,6 +262,70 @@ def batch_descriptors(batches):
     dev = batches[0][0].device if batches else "cuda"
     d = torch.tensor(rows, dtype=torch.int64).reshape(-1, 3).to(dev)
     return d, total
+
+
+class Server:
+    """Serving loop over resident indexes (act_server_*): requests of host
+    (n, 2) float64 points are admitted by free slots and arena memory and
+    overlap on the GPU; results land in host int32 arrays."""
+
+    def __init__(self, indexes, slots=4, arena_bytes=0, max_request_points=1 << 20, device=0):
+        self._indexes = list(indexes)  # keeps them alive
+        o = _b.ServerOpts()
+        lib.act_server_opts_init(ctypes.byref(o))
+        o.slots, o.arena_bytes, o.max_request_points, o.device = (
+            slots, arena_bytes, max_request_points, device)
+        arr = (ctypes.c_void_p * len(self._indexes))(*[x._h.value for x in self._indexes])
+        h = ctypes.c_void_p()
+        rc = lib.act_server_create(arr, len(self._indexes), ctypes.byref(o), ctypes.byref(h))
+        if rc:
+            raise ActError(rc, lib.act_server_last_error().decode())
+        self._h = h
+        self._live = {}
+
+    @staticmethod
+    def clock() -> float:
+        return lib.act_server_clock()
+
+    def submit(self, index, points, out=None, arrival=0.0):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        if pts.ndim != 2 or pts.shape[1] != 2:
+            raise TypeError("points must be (n, 2) float64")
+        if out is None:
+            out = np.empty(pts.shape[0], dtype=np.int32)
+        t = ctypes.c_uint64()
+        rc = lib.act_server_submit(self._h, int(index), _np_ptr(pts), pts.shape[0], _np_ptr(out),
+                                   float(arrival), ctypes.byref(t))
+        if rc:
+            raise ActError(rc, lib.act_server_last_error().decode())
+        self._live[t.value] = (pts, out)
+        return t.value
+
+    def wait(self, ticket):
+        """(out, times dict) of a submitted request."""
+        tm = _b.RequestTimes()
+        rc = lib.act_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(tm))
+        pts, out = self._live.pop(ticket)
+        if rc:
+            raise ActError(rc, lib.act_server_last_error().decode())
+        return out, {k: getattr(tm, k) for k, _ in tm._fields_}
+
+    def stats(self) -> dict:
+        st = _b.ServerStats()
+        _b.check(lib.act_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.act_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def wall_clock_hz(device: int = 0) -> float:

@@ -48,6 +48,32 @@ class JoinArgs(ctypes.Structure):
                 ("probe_event", ctypes.c_void_p)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
+                ("points_per_lane", ctypes.c_int32), ("refine", ctypes.c_int32),
+                ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("n_configs", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("index_digest", ctypes.c_uint64)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("arena_bytes", ctypes.c_int64), ("max_request_points", ctypes.c_int64)]
+
+
+class RequestTimes(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("admitted_s", ctypes.c_double),
+                ("done_s", ctypes.c_double), ("n", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("points", ctypes.c_int64),
+                ("arena_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_polys", ctypes.c_int64), ("n_edges", ctypes.c_int64),
                 ("n_cells", ctypes.c_int64), ("n_cells_interior_only", ctypes.c_int64),
@@ -88,6 +114,16 @@ def _load():
         "act_batched_reserve": ([p, p, i32, i64], ctypes.c_int),
         "act_batched_status": ([p, p, p], ctypes.c_int),
         "act_wall_clock_hz": ([i32, p], ctypes.c_int),
+        "act_tune": ([p, p, i64, p, p, ctypes.c_char_p, p], ctypes.c_int),
+        "act_index_digest": ([p, p], ctypes.c_int),
+        "act_server_opts_init": ([p], None),
+        "act_server_create": ([p, i32, p, p], ctypes.c_int),
+        "act_server_submit": ([p, i32, p, i64, p, d, p], ctypes.c_int),
+        "act_server_wait": ([p, ctypes.c_uint64, p], ctypes.c_int),
+        "act_server_stats_get": ([p, p], ctypes.c_int),
+        "act_server_clock": ([], d),
+        "act_server_destroy": ([p], None),
+        "act_server_last_error": ([], ctypes.c_char_p),
         "act_build_opts_init": ([p], None),
         "act_refine_local_host": ([p, i32, ctypes.c_uint32, ctypes.c_uint32, d, d, i32, p],
                                   ctypes.c_int),

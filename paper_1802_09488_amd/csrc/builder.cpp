@@ -913,13 +913,15 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     if (frontier.size() >= (size_t)(64 * nthreads)) break;
   }
   tasks.swap(frontier);
-  std::vector<Sink> sinks(nthreads);
+  // one sink per task, gathered in task order: the index image does not
+  // depend on the thread count or on scheduling
+  std::vector<Sink> sinks(tasks.size());
   std::atomic<size_t> cursor{0};
-  auto worker = [&](int t) {
+  auto worker = [&](int) {
     for (;;) {
       size_t k = cursor.fetch_add(1);
       if (k >= tasks.size()) break;
-      dfs(C, tasks[k], sinks[t]);
+      dfs(C, tasks[k], sinks[k]);
     }
   };
   std::vector<std::thread> pool;

@@ -85,10 +85,20 @@ constexpr int64_t kDefaultPass = 1 << 24;
 
 }  // namespace act
 
+// Launch configuration used when a join leaves a knob at its default
+// (set by act_tune; the built-in defaults otherwise).
+struct act_launch {
+  int32_t grid = 1024;
+  int32_t lds_levels = -1;  // -1: deepest that fits
+  int32_t points_per_lane = 2;
+  int32_t refine = ACT_REFINE_LOCAL;
+};
+
 struct act_index {
   act::HostIndex host;
   act::DevImage dev;
   int device = -1;
+  act_launch launch;  // written only by act_tune
   mutable std::mutex ws_mu;
   mutable std::unordered_map<void *, act::Workspace> ws;
 };
@@ -1306,7 +1316,9 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (a->points_per_lane < 0 || a->points_per_lane > 2)
     return fail(ACT_E_ARG, "points_per_lane must be 0, 1 or 2");
   const HostIndex &h = x->host;
-  int depth = a->lds_levels < 0 ? default_lds_depth(h) : a->lds_levels;
+  const act_launch &L = x->launch;
+  const int lds_req = a->lds_levels >= 0 ? a->lds_levels : L.lds_levels;
+  int depth = lds_req < 0 ? default_lds_depth(h) : lds_req;
   if (depth > 2) return fail(ACT_E_ARG, "lds_levels must be -1, 0, 1 or 2");
   int n_lds = depth > 0 ? lds_nodes_for(h, depth) : 0;
   if (n_lds < 0) return fail(ACT_E_RANGE, "top trie levels do not fit the LDS budget");
@@ -1323,8 +1335,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.cap = a->pair_capacity;
   P.n_pairs = a->d_n_pairs;
   P.counters = (unsigned long long *)a->d_counters;
-  index_params(x, a->refine, n_lds, P);
-  const int np = a->points_per_lane > 0 ? a->points_per_lane : 2;
+  index_params(x, a->refine == ACT_REFINE_AUTO ? L.refine : a->refine, n_lds, P);
+  const int np = a->points_per_lane > 0 ? a->points_per_lane : L.points_per_lane;
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
   const bool count = a->d_counters != nullptr;
@@ -1348,7 +1360,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     P.n = n;
     P.base = s0;
     const int64_t tile_blocks = (n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : 1024,
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : L.grid,
                                                                   tile_blocks));
     hipLaunchKernelGGL(probe, dim3(grid), dim3(kProbeBlock), (size_t)n_lds * 1024,
                        (hipStream_t)stream, P);
@@ -1379,7 +1391,8 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   if (rc) return rc;
   if (nb == 0) return ACT_OK;
   const HostIndex &h = x->host;
-  int depth = default_lds_depth(h);
+  const act_launch &L = x->launch;
+  int depth = L.lds_levels < 0 ? default_lds_depth(h) : L.lds_levels;
   int n_lds = depth > 0 ? lds_nodes_for(h, depth) : 0;
   if (depth > 0 && n_lds <= 0) depth = n_lds = 0;
   DeviceGuard g(x->device);
@@ -1393,14 +1406,14 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   hipLaunchKernelGGL(batch_fill_kernel, dim3(kBatchGrid), dim3(256), 0, st, w->vstart, nb,
                      w->vhdr, w->group_batch);
   ProbeParams P{};
-  index_params(x, ACT_REFINE_LOCAL, n_lds, P);
+  index_params(x, ACT_REFINE_LOCAL, n_lds, P);  // batched: cell-local refinement
   P.mask = w->bmask;
   P.batches = d_batches;
   P.group_batch = w->group_batch;
   P.vstart = w->vstart;
   P.vhdr = w->vhdr;
   P.gticks = d_ticks ? w->gticks : nullptr;
-  hipLaunchKernelGGL(probe_batched_fn(exact, depth, 2), dim3(1024), dim3(kProbeBlock),
+  hipLaunchKernelGGL(probe_batched_fn(exact, depth, L.points_per_lane), dim3(L.grid), dim3(kProbeBlock),
                      (size_t)n_lds * 1024, st, P);
   if (exact) {
     void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
@@ -1412,6 +1425,149 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return fail(ACT_E_HIP, std::string("batched join launch: ") + hipGetErrorString(e));
+  return ACT_OK;
+}
+
+// ------------------------------------------------------------- autotuner
+
+// 64-bit digest of the index image (trie, lookup table, records, edges,
+// mode): the key of the tuning cache.
+static uint64_t index_digest(const HostIndex &h) {
+  uint64_t d = 0x9e3779b97f4a7c15ull ^ (uint64_t)h.mode;
+  auto mix = [&d](const void *p, size_t bytes) {
+    const uint8_t *b = (const uint8_t *)p;
+    size_t k = 0;
+    for (; k + 8 <= bytes; k += 8) {
+      uint64_t v;
+      std::memcpy(&v, b + k, 8);
+      d = (d ^ v) * 0x100000001b3ull;
+      d ^= d >> 29;
+    }
+    for (; k < bytes; k++) d = (d ^ b[k]) * 0x100000001b3ull;
+    d ^= (uint64_t)bytes * 0xff51afd7ed558ccdull;
+  };
+  mix(h.nodes.data(), h.nodes.size() * 8);
+  mix(h.lut.data(), h.lut.size() * 4);
+  mix(h.local.data(), h.local.size() * 4);
+  mix(h.edges64.data(), h.edges64.size() * 8);
+  mix(&h.precision_m, sizeof h.precision_m);
+  return d;
+}
+
+static bool cache_lookup(const char *path, uint64_t key, act_launch &L) {
+  if (!path) return false;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return false;
+  char arch[64];
+  unsigned long long k;
+  int g, lds, np, rf;
+  bool hit = false;
+  while (std::fscanf(f, "%llx %63s %d %d %d %d", &k, arch, &g, &lds, &np, &rf) == 6)
+    if (k == key && std::strcmp(arch, "gfx950") == 0) {
+      L.grid = g;
+      L.lds_levels = lds;
+      L.points_per_lane = np;
+      L.refine = rf;
+      hit = true;
+    }
+  std::fclose(f);
+  return hit;
+}
+
+static void cache_store(const char *path, uint64_t key, const act_launch &L) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%016llx gfx950 %d %d %d %d\n", (unsigned long long)key, L.grid, L.lds_levels,
+               L.points_per_lane, L.refine);
+  std::fclose(f);
+}
+
+static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d_out,
+                     void *stream, const char *cache_path, act_tune_result *res) {
+  if (!x || !res) return fail(ACT_E_ARG, "bad argument");
+  if (n <= 0 || !d_sample || !d_out) return fail(ACT_E_ARG, "tuning needs a non-empty sample");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  int rc = check_stream_device(x, stream);
+  if (rc) return rc;
+  std::memset(res, 0, sizeof *res);
+  const uint64_t key = cache_path ? index_digest(x->host) : 0;
+  act_launch best;
+  if (cache_lookup(cache_path, key, best)) {
+    x->launch = best;
+    res->from_cache = 1;
+  } else {
+    DeviceGuard g(x->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_cfg = [&](const act_launch &L, float &ms) -> int {
+      act_join_args a{};
+      a.d_points = d_sample;
+      a.n = n;
+      a.d_out = d_out;
+      a.refine = L.refine;
+      a.grid = L.grid;
+      a.lds_levels = L.lds_levels;
+      a.points_per_lane = L.points_per_lane;
+      int r = join_impl(x, &a, stream);  // warm
+      if (r) return r;
+      float t[3];
+      for (int k = 0; k < 3; k++) {
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(ACT_E_HIP, "event record");
+        r = join_impl(x, &a, stream);
+        if (r) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t[k], e0, e1) != hipSuccess)
+          return fail(ACT_E_HIP, "event timing");
+      }
+      std::sort(t, t + 3);
+      ms = t[1];
+      return ACT_OK;
+    };
+    const act_launch defaults;
+    const act_launch saved = x->launch;
+    x->launch = defaults;
+    float ms;
+    rc = time_cfg(defaults, ms);
+    res->default_ms = ms;
+    res->best_ms = ms;
+    best = defaults;
+    const int grids[] = {256, 512, 1024, 2048, 4096};
+    const bool exact = x->host.mode == ACT_EXACT;
+    for (int gi = 0; gi < 5 && !rc; gi++)
+      for (int lds = 0; lds <= 2 && !rc; lds++) {
+        if (lds > 0 && lds_nodes_for(x->host, lds) < 0) continue;
+        for (int np = 1; np <= 2 && !rc; np++)
+          for (int rf = ACT_REFINE_LOCAL; rf <= (exact ? ACT_REFINE_FP32_FILTER : ACT_REFINE_LOCAL) && !rc; rf++) {
+            act_launch L;
+            L.grid = grids[gi];
+            L.lds_levels = lds;
+            L.points_per_lane = np;
+            L.refine = rf;
+            rc = time_cfg(L, ms);
+            res->n_configs++;
+            if (!rc && ms < res->best_ms) {
+              res->best_ms = ms;
+              best = L;
+            }
+          }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+      x->launch = saved;
+      return rc;
+    }
+    x->launch = best;
+    cache_store(cache_path, key, best);
+  }
+  res->grid = best.grid;
+  res->lds_levels = best.lds_levels;
+  res->points_per_lane = best.points_per_lane;
+  res->refine = best.refine;
+  res->index_digest = key;
   return ACT_OK;
 }
 
@@ -1519,6 +1675,11 @@ int act_join_ex(const act_index *x, const act_join_args *args, void *stream) {
 int act_join_batched(const act_index *x, const act_batch *d_batches, int32_t nb,
                      int64_t total_points, uint64_t *d_ticks, void *stream) {
   return join_batched_impl(x, d_batches, nb, total_points, d_ticks, stream);
+}
+
+int act_tune(act_index *x, const double *d_sample, int64_t n, int32_t *d_out, void *stream,
+             const char *cache_path, act_tune_result *result) {
+  return tune_impl(x, d_sample, n, d_out, stream, cache_path, result);
 }
 
 int act_batched_reserve(const act_index *x, void *stream, int32_t max_batches,
@@ -1668,6 +1829,12 @@ int act_refine_local_host(const act_index *x, int32_t face, uint32_t i, uint32_t
       return ACT_OK;
     }
   return fail(ACT_E_ARG, "polygon is not a candidate of this cell");
+}
+
+int act_index_digest(const act_index *x, uint64_t *digest) {
+  if (!x || !digest) return fail(ACT_E_ARG, "bad argument");
+  *digest = index_digest(x->host);
+  return ACT_OK;
 }
 
 int act_lut_host(const act_index *x, uint32_t *words, int64_t *n_words) {

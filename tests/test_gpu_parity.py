@@ -414,3 +414,75 @@ def test_batched_refuses_bad_sizes(act):
         assert idx.batched_ok()
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), idx.join(pts).cpu().numpy())
+
+
+def test_autotuner_keeps_results_and_caches(act, tmp_path):
+    """act_tune sweeps launch shapes on a sample, makes the fastest the
+    default (outputs unchanged), and a second tune of an identical index
+    takes the configuration from the cache file."""
+    P = synth.workload_polygons("c2")
+    idx = act.build(P, "exact")
+    pts = torch.from_numpy(synth.workload_points("c2", 0, 1_000_000)).cuda()
+    before = idx.join(pts).cpu().numpy()
+    cache = str(tmp_path / "act_tune.txt")
+    r = idx.tune(pts, cache_path=cache)
+    assert r["n_configs"] >= 20 and not r["from_cache"]
+    assert r["grid"] in (256, 512, 1024, 2048, 4096) and r["points_per_lane"] in (1, 2)
+    assert 0 < r["best_ms"] <= r["default_ms"] * 1.0001
+    after = idx.join(pts).cpu().numpy()
+    assert np.array_equal(before, after)
+    idx2 = act.build(P, "exact")
+    r2 = idx2.tune(pts, cache_path=cache)
+    assert r2["from_cache"] and r2["index_digest"] == r["index_digest"]
+    assert (r2["grid"], r2["lds_levels"], r2["points_per_lane"], r2["refine"]) == \
+        (r["grid"], r["lds_levels"], r["points_per_lane"], r["refine"])
+    assert np.array_equal(idx2.join(pts).cpu().numpy(), before)
+    assert np.array_equal(oracle.join(P, pts[:200000].cpu().numpy()).out, before[:200000])
+
+
+def test_server_results_same_alone_and_in_mix(act):
+    """300 requests (0 .. 2e4 points) against two resident indexes (C1 exact,
+    C2 approx@4m), submitted as a burst to a 4-slot server whose arena holds
+    only a few requests at once: each result equals the same request joined
+    alone (and the oracle, for the exact index)."""
+    P1, i1 = index(act, "c1", "exact")
+    P2, i2 = index(act, "c2", "approx", 4.0)
+    rng = np.random.default_rng(41)
+    pool = synth.workload_points("c2", 0, 2_000_000)
+    srv = act.Server([i1, i2], slots=4, arena_bytes=2_000_000, max_request_points=1 << 16)
+    reqs = []
+    for k in range(300):
+        n = 0 if k % 29 == 0 else int(np.floor(np.exp(rng.uniform(0, np.log(2e4)))))
+        a = int(rng.integers(0, len(pool) - n))
+        which = int(rng.integers(0, 2))
+        reqs.append((which, pool[a:a + n]))
+    tickets = [srv.submit(w, p, arrival=act.Server.clock()) for w, p in reqs]
+    for (w, p), t in zip(reqs, tickets):
+        out, tm = srv.wait(t)
+        assert tm["arrival_s"] <= tm["admitted_s"] <= tm["done_s"] and tm["n"] == len(p)
+        if len(p) == 0:
+            continue
+        alone = (i1 if w == 0 else i2).join(torch.from_numpy(p).cuda()).cpu().numpy()
+        assert np.array_equal(out, alone)
+        if w == 0:
+            assert np.array_equal(out, oracle.join(P1, p).out)
+    st = srv.stats()
+    assert st["completed"] == 300 and st["failed"] == 0 and st["queued"] == 0
+    srv.close()
+
+
+def test_server_admission_by_memory(act):
+    """Requests that each need most of the arena are admitted one at a time
+    (memory, not slots, is the limit) and all complete; a request that can
+    never fit is refused at submission."""
+    P, idx = index(act, "c1", "exact")
+    pts = synth.workload_points("c1", 0, 60_000)
+    srv = act.Server([idx], slots=4, arena_bytes=20 * 50_000, max_request_points=1 << 16)
+    ts = [srv.submit(0, pts[k * 10_000:k * 10_000 + 40_000]) for k in range(3)]
+    for k, t in enumerate(ts):
+        out, tm = srv.wait(t)
+        assert np.array_equal(out, oracle.join(P, pts[k * 10_000:k * 10_000 + 40_000]).out)
+    with pytest.raises(act.ActError):
+        srv.submit(0, pts)  # 60k points need 1.2 MB > 1 MB arena
+    assert srv.stats()["completed"] == 3
+    srv.close()

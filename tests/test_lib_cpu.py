@@ -223,6 +223,16 @@ def _raw_build(act, verts, ring_off, poly_ring_off, mode=0, prec=0.0, device=-1)
     return rc
 
 
+def test_build_is_deterministic(act):
+    """The index image does not depend on the build's thread count."""
+    P = synth.workload_polygons("c1")
+    for mode, prec in (("exact", 0.0), ("approx", 4.0)):
+        d1 = act.build(P, mode, prec, device=-1, threads=1).digest()
+        d8 = act.build(P, mode, prec, device=-1, threads=8).digest()
+        d8b = act.build(P, mode, prec, device=-1, threads=8).digest()
+        assert d1 == d8 == d8b
+
+
 def test_error_paths(act):
     from paper_1802_09488_amd import _binding as B
     sq = np.array([[0, 0], [0, 1], [1, 1], [1, 0]], float)
