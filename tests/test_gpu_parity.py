@@ -486,3 +486,40 @@ def test_server_admission_by_memory(act):
         srv.submit(0, pts)  # 60k points need 1.2 MB > 1 MB arena
     assert srv.stats()["completed"] == 3
     srv.close()
+
+
+def c3_sample(n_first, windows, win, seed):
+    """The first n_first points of the C3 stream (batch 0) plus `windows`
+    seeded windows of `win` points anywhere in its 1e9 points (60 batches)."""
+    parts = [synth.workload_points("c3", 0, n_first)]
+    rng = np.random.default_rng(seed)
+    N = synth.WORKLOADS["c3"]["n_points"]
+    for s in rng.integers(0, N - win, windows):
+        parts.append(synth.workload_points("c3", int(s), int(s) + win))
+    return np.concatenate(parts)
+
+
+@pytest.mark.timeout(600)
+def test_c3_exact_sample_all_refine_modes(act):
+    """40,000 polygons, exact mode: batch-0 points and windows across the
+    whole stream, every refinement mode bit-exact against the oracle."""
+    P, idx = index(act, "c3", "exact")
+    pts = np.concatenate([c3_sample(60_000, 16, 4096, 51),
+                          edge_case_points(P, np.random.default_rng(52))[:20_000]])
+    for mode in REFINE_MODES:
+        out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+        assert_exact(P, pts, out, pairs, "c3-" + mode)
+
+
+@pytest.mark.timeout(900)
+def test_c3_approx_1m_guarantee(act):
+    """40,000 polygons at 1 m precision (a ~7 GB trie): no covering pair
+    missing, every extra pair within 1 m of the polygon's boundary."""
+    P = synth.workload_polygons("c3")
+    idx = act.build(P, "approx", 1.0)
+    assert idx.stats()["max_cell_level"] >= 23
+    pts = c3_sample(40_000, 8, 4096, 53)
+    out, pairs, _ = gpu_join(idx, pts)
+    n_extra, n_pairs = assert_approx(P, pts, out, pairs, 1.0, "c3-approx1m")
+    assert n_extra < 0.05 * n_pairs
+    del idx
