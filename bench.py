@@ -169,6 +169,62 @@ def batched_leg(act, idx, pts, exact_out, seed=3004, hi=1e6, replays=5):
             "identical_to_single_join": ok}
 
 
+def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
+                arena_bytes=2 << 30, max_points=65536):
+    """Serving: requests of floor(exp(U(0, ln 65536))) points, each aimed at
+    one of the resident indexes (Bernoulli 1/2), arriving as a Poisson
+    process at each rate in qps_list for `seconds`; points are windows of
+    the indexes' point pools (host). Latency = completion (results in host
+    memory) minus scheduled arrival."""
+    import threading
+
+    import numpy as np
+    srv = act.Server(indexes, slots=slots, arena_bytes=arena_bytes, max_request_points=max_points)
+    g = np.random.default_rng(seed)
+    res = []
+    for qps in qps_list:
+        nreq = int(qps * seconds)
+        sizes = np.floor(np.exp(g.uniform(0.0, np.log(max_points), nreq))).astype(np.int64)
+        target = g.integers(0, len(indexes), nreq)
+        gaps = g.exponential(1.0 / qps, nreq)
+        starts = [g.integers(0, len(pools[t]) - sz) for t, sz in zip(target, sizes)]
+        tickets = [None] * nreq
+        lat = np.zeros(nreq)
+        done_t = np.zeros(nreq)
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for k in range(nreq):
+                ready.acquire()
+                _, tm = srv.wait(tickets[k])
+                lat[k] = tm["done_s"] - tm["arrival_s"]
+                done_t[k] = tm["done_s"]
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = act.Server.clock() + 0.05
+        arrival = t0 + np.cumsum(gaps)
+        for k in range(nreq):
+            while act.Server.clock() < arrival[k]:
+                pass
+            p = pools[target[k]]
+            tickets[k] = srv.submit(int(target[k]), p[starts[k]:starts[k] + sizes[k]],
+                                    arrival=float(arrival[k]))
+            ready.release()
+        th.join()
+        span = float(done_t.max() - arrival[0])
+        res.append({"qps_offered": qps, "requests": nreq, "seconds": seconds,
+                    "points": int(sizes.sum()), "points_per_s": float(sizes.sum()) / span,
+                    "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                                   "p99": 1e3 * float(np.percentile(lat, 99))},
+                    "qps_achieved": nreq / span})
+    st = srv.stats()
+    srv.close()
+    return {"slots": slots, "arena_bytes": int(arena_bytes),
+            "request_points": "floor(exp(U(0, ln %d))), seed %d" % (max_points, seed),
+            "runs": res, "failed": st["failed"]}
+
+
 def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
     """The oracle (brute force: bbox prefilter + exact point-in-polygon
     against every polygon, OpenMP over points) on the host's cores over the
@@ -203,11 +259,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
+                    help="c2 (default): 290 polygons, 1e8 points; c3: 40k polygons, 1e9 "
+                         "points in 2^24 batches; c4: 10,000 uneven batches, one graph "
+                         "replay; c5: serving sweep")
     ap.add_argument("--points", type=int, default=0, help="override the point count")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="oracle points (default: the whole workload)")
+                    help="oracle points (default: the whole c2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="seconds per serving rate (default 2 in c2, 10 in c5)")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
@@ -220,7 +281,10 @@ def main():
               "splits the points, and this benchmark runs and reports the single-GPU case only "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)
 
+
+def run_c2(args):
     import numpy as np
     import torch
 
@@ -271,6 +335,11 @@ def main():
                                             / var["fp32_filter"]["join_ms_mean"])
     log("batched join (graph replay)")
     batched = batched_leg(act, idx, pts, exact_out)
+    log("serving")
+    pools = [synth.workload_points(args.workload, 0, 1 << 22)] * 2
+    serving = serving_leg(act, [idx, idx_a], pools, [1e3, 1e4], args.serve_seconds or 2.0)
+    serving["indexes"] = "c2 exact, c2 approx@4m"
+    
 
     probe_ms = float(np.mean(prb))
     achieved = BYTES_PER_POINT * n / (probe_ms * 1e-3) / 1e9
@@ -303,6 +372,7 @@ def main():
         "latency_ms": {"p50": percentile(tot, 50), "p99": percentile(tot, 99),
                        "what": "one join of all points (one step), HIP events"},
         "batched_exact": batched,
+        "serving": serving,
         "exact": {"join_ms_mean": float(np.mean(tot)), "probe_ms_mean": probe_ms,
                   "resolve_ms_mean": float(np.mean(tot) - probe_ms)},
         "approx4m": {"points_per_s": n * args.steps / wall_a,
@@ -330,6 +400,186 @@ def main():
         res["cpu_baseline"], res["parity_vs_oracle"] = cpu_baseline_and_parity(
             P, args.workload, ns, exact_out)
     print(json.dumps(res), flush=True)
+
+
+def _stage_points(workload, n, step=1 << 24):
+    """Points [0, n) of a workload's stream, generated on the host and
+    staged in HBM."""
+    import torch
+
+    import synth
+    pts = torch.empty((n, 2), dtype=torch.float64, device="cuda")
+    for s in range(0, n, step):
+        e = min(n, s + step)
+        pts[s:e].copy_(torch.from_numpy(synth.workload_points(workload, s, e)))
+    torch.cuda.synchronize()
+    return pts
+
+
+def _line(metric_value, steps, warmup, ms_per_step, config, **extra):
+    res = {"metric": "joined points/sec (exact & approx@4m) + HBM roofline %; "
+                     "p50/p99 batch latency",
+           "value": metric_value, "unit": "points/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": config}
+    res.update(extra)
+    print(json.dumps(res), flush=True)
+
+
+def run_c3(args):
+    """40,000 polygons; 1e9 points staged in HBM (16 GB) and joined as 60
+    batches of 2^24 (one step = the whole stream): exact (cell-local, and
+    the fp32-filter and all-fp64 refinements over all edges) and approx@1m."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    import paper_1802_09488_amd as act
+    w = synth.WORKLOADS["c3"]
+    n = args.points or w["n_points"]
+    bsz = w["batch"]
+    P = synth.workload_polygons("c3")
+    t0 = time.perf_counter()
+    idx = act.build(P, "exact")
+    tb_e = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    idx_a = act.build(P, "approx", 1.0)
+    tb_a = time.perf_counter() - t0
+    log("staging %d points" % n)
+    pts = _stage_points("c3", n)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    idx.reserve(bsz)
+
+    def stream(ix, **kw):
+        for s in range(0, n, bsz):
+            ix.join_ex(pts[s:s + bsz], out[s:s + bsz], **kw)
+
+    def timed(ix, steps, **kw):
+        stream(ix, **kw)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            stream(ix, **kw)
+            b.record()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, [a.elapsed_time(b) for a, b in ev]
+
+    steps = max(1, min(args.steps, 3))
+    wall, ms = timed(idx, steps)
+    sample = synth.workload_points("c3", 0, 200_000)
+    ref = oracle.join(P, sample)
+    torch.cuda.synchronize()
+    ok = bool(np.array_equal(out[:200_000].cpu().numpy(), ref.out))
+    var = {}
+    for name, mode in (("fp32_filter", act.ACT_REFINE_FP32_FILTER), ("fp64", act.ACT_REFINE_FP64)):
+        wv, mv = timed(idx, 1, refine=mode)
+        var[name] = {"points_per_s": n / wv, "stream_ms": float(np.mean(mv))}
+    var["fp32_filter_over_fp64_speedup"] = var["fp64"]["stream_ms"] / var["fp32_filter"]["stream_ms"]
+    wa, ma = timed(idx_a, steps)
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    oracle.join(P, sample, nthreads=cores)
+    dt = time.perf_counter() - t0
+    st, sa = idx.stats(), idx_a.stats()
+    _line(n * steps / wall, steps, 1, 1000 * wall / steps,
+          {"workload": "c3: 40,000 Voronoi polygons over the NYC box, %d fp64 mixture points "
+                       "staged in HBM, joined in batches of 2^24, exact (cell-local refinement)"
+                       % n, "n_points": n, "batch": bsz, "n_polys": P.n_polys,
+           "parallelism": "single GPU"},
+          approx1m={"points_per_s": n * steps / wa, "stream_ms": float(np.mean(ma))},
+          refine_variants=var, parity_vs_oracle={"points_checked": 200_000, "ok": ok},
+          index={"exact": {k: st[k] for k in ("n_cells", "n_nodes", "node_bytes",
+                                                "device_bytes")},
+                 "approx1m": {k: sa[k] for k in ("n_cells", "n_nodes", "node_bytes",
+                                                   "device_bytes")},
+                 "build_s_exact": tb_e, "build_s_approx1m": tb_a},
+          cpu_baseline={"value": len(sample) / dt, "unit": "points/s", "cores": cores,
+                        "kind": "oracle",
+                        "sample": "first 200,000 points of the c3 stream, exact, %.1f s" % dt})
+
+
+def run_c4(args):
+    """10,000 batches of floor(exp(U(0, ln 1e6))) points (seed 3004) of the
+    c3 stream against the 40,000-polygon exact index: the autotuner picks the
+    launch shape on a sample, then one batched join is captured in a HIP
+    graph and replayed (one step = one replay)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1802_09488_amd as act
+    P = synth.workload_polygons("c3")
+    idx = act.build(P, "exact")
+    sizes = synth.batch_sizes(10_000, 3004)
+    total = int(sizes.sum())
+    log("staging %d points in %d batches" % (total, len(sizes)))
+    pts = _stage_points("c3", total)
+    tune = idx.tune(pts[:4_000_000])
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    batches = [(pts[a:b], out[a:b]) for a, b in zip(bounds[:-1], bounds[1:])]
+    desc, tot = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    idx.batched_reserve(len(batches), tot, stream=s)
+    with torch.cuda.stream(s):
+        idx.join_batched(desc, tot, ticks=ticks)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        idx.join_batched(desc, tot, ticks=ticks)
+    hz = act.wall_clock_hz(0)
+    steps = max(1, args.steps)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ms, p50, p99 = [], [], []
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+        t = ticks.cpu().numpy().view(np.uint64).astype(np.float64)
+        lat = (t[1:] - t[0]) / hz * 1e3
+        p50.append(float(np.percentile(lat, 50)))
+        p99.append(float(np.percentile(lat, 99)))
+    wall = time.perf_counter() - t_all
+    single = idx.join(pts[:2_000_000])
+    same = bool(torch.equal(single, out[:2_000_000]))
+    _line(total / (float(np.median(ms)) * 1e-3), steps, args.warmup, float(np.median(ms)),
+          {"workload": "c4: 10,000 uneven batches (%d points) of the c3 stream, 40,000-polygon "
+                       "exact index, one batched join per step (HIP graph replay)" % total,
+           "batches": len(sizes), "n_points": total, "parallelism": "single GPU"},
+          batch_latency_ms={"p50": float(np.median(p50)), "p99": float(np.median(p99)),
+                            "what": "per-batch completion tick minus the join's start tick"},
+          wall_s=wall, tuner=tune, identical_to_single_join=same)
+
+
+def run_c5(args):
+    """Serving: Poisson arrivals at 1e3, 1e4 and 5e4 requests/s of
+    floor(exp(U(0, ln 65536))) points, each aimed at the 290-polygon
+    approx@4m index or the 40,000-polygon exact index."""
+    import synth
+    import paper_1802_09488_amd as act
+    ia = act.build(synth.workload_polygons("c2"), "approx", 4.0)
+    ie = act.build(synth.workload_polygons("c3"), "exact")
+    pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
+    sec = args.serve_seconds or 10.0
+    srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4], sec)
+    srv["indexes"] = "c2 approx@4m, c3 exact"
+    best = max(r["points_per_s"] for r in srv["runs"])
+    _line(best, len(srv["runs"]), 0, 1000.0 * sec,
+          {"workload": "c5: serving, Poisson requests of 1..65,536 points over two resident "
+                       "indexes (c2 approx@4m, c3 exact)", "parallelism": "single GPU"},
+          serving=srv)
 
 
 # ------------------------------------------------------------ profile summaries

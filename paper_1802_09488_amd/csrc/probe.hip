@@ -697,13 +697,43 @@ struct RefList {
   }
 };
 
+// The list's first words are read together (the device copy of the table
+// is padded, so this stays in bounds): lists with up to two true hits need
+// no second, dependent read for their candidate count.
 __device__ __forceinline__ RefList lut_refs(const ProbeParams &P, uint32_t off) {
   RefList L;
   L.lut = true;
   L.off = off;
-  L.nt = P.lut[off];
-  L.nc = P.lut[off + 1 + L.nt];
+  const uint32_t w0 = P.lut[off], w1 = P.lut[off + 1], w2 = P.lut[off + 2], w3 = P.lut[off + 3];
+  L.nt = w0;
+  L.nc = w0 == 0 ? w1 : (w0 == 1 ? w2 : (w0 == 2 ? w3 : P.lut[off + 1 + w0]));
   return L;
+}
+
+// The cell-local record test (local_record_covers) with the header and the
+// first local edge read together (the device copy of the records is padded).
+__device__ __forceinline__ bool local_covers_dev(const uint32_t *rec, double px, double py) {
+  uint32_t w[10];
+#pragma unroll
+  for (int k = 0; k < 10; k++) w[k] = rec[k];
+  const uint32_t n_local = w[0], n_break = w[1] & 0x7fffffffu;
+  uint32_t par = w[1] >> 31;
+  if (n_local > 0) {
+    const int r = edge_test_exact(word_double(w + 2), word_double(w + 4), word_double(w + 6),
+                                  word_double(w + 8), px, py);
+    if (r == 2) return true;
+    par ^= (uint32_t)r;
+  }
+  const uint32_t *d = rec + 10;
+  for (uint32_t k = 1; k < n_local; k++, d += 8) {
+    const int r = edge_test_exact(word_double(d), word_double(d + 2), word_double(d + 4),
+                                  word_double(d + 6), px, py);
+    if (r == 2) return true;
+    par ^= (uint32_t)r;
+  }
+  if (n_local == 0) d = rec + 2;
+  for (uint32_t k = 0; k < n_break; k++, d += 2) par ^= word_double(d) <= py ? 1u : 0u;
+  return par != 0;
 }
 
 // The pending point's references: from the list offset the probe left in
@@ -758,64 +788,51 @@ __device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint3
     if (c[k]) atomicAdd(P.counters + ids[k], (unsigned long long)c[k]);
 }
 
-// Pending points of a resolve block range: the block reads kBlock mask
-// words (64 kBlock points of the pass), compacts their set bits into an LDS
-// list (block-wide prefix sum of the popcounts) and hands the list out one
-// point per thread; bits beyond the list's capacity stay with the thread
-// that read them. Points are numbered in the pass (or, for batched joins,
-// the virtual point space).
-constexpr int kListCap = 2048;
+// Pending points of a resolve block range: 64 mask words (4096 points of
+// the pass, or of a batched join's virtual space). The first wave reads the
+// words and compacts their set bits into an LDS list (prefix sum of the
+// popcounts over its lanes); the list holds every pending point of the
+// range, and the block's threads take its entries one by one.
+constexpr int kRangeWords = 64;
+constexpr int kListCap = kRangeWords * 64;
 
 struct PendingIter {
   int k, total;
-  uint64_t m;    // bits of this thread's word not in the list
-  int64_t w;     // this thread's mask word
   int64_t base;  // first point of the block's range
   __device__ __forceinline__ bool next(const uint16_t *s_list, int64_t &v) {
-    if (k < total) {
-      v = base + s_list[k];
-      k += kBlock;
-      return true;
-    }
-    if (m) {
-      v = w * 64 + (__ffsll((long long)m) - 1);
-      m &= m - 1;
-      return true;
-    }
-    return false;
+    if (k >= total) return false;
+    v = base + s_list[k];
+    k += kBlock;
+    return true;
   }
 };
 
 __device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int64_t blk,
                                                       int64_t nwords, uint16_t *s_list,
-                                                      uint32_t *s_wave) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+                                                      uint32_t *s_total) {
   PendingIter it;
-  it.base = blk * kBlock * 64;
-  it.w = blk * kBlock + threadIdx.x;
-  uint64_t m = it.w < nwords ? P.mask[it.w] : 0ull;
-  const uint32_t c = (uint32_t)__popcll(m);
-  uint32_t incl = c;
+  it.base = blk * kRangeWords * 64;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int64_t w = blk * kRangeWords + lane;
+    uint64_t m = w < nwords ? P.mask[w] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(m);
+    uint32_t incl = c;
 #pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t v = __shfl_up(incl, d);
-    if (lane >= d) incl += v;
-  }
-  if (lane == 63) s_wave[wid] = incl;
-  __syncthreads();
-  uint32_t pos = incl - c, total = 0;
-  for (int k = 0; k < kBlock / 64; k++) {
-    if (k < wid) pos += s_wave[k];
-    total += s_wave[k];
-  }
-  while (m && pos < (uint32_t)kListCap) {
-    s_list[pos++] = (uint16_t)((threadIdx.x << 6) | (__ffsll((long long)m) - 1));
-    m &= m - 1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    uint32_t pos = incl - c;
+    while (m) {
+      s_list[pos++] = (uint16_t)((lane << 6) | (__ffsll((long long)m) - 1));
+      m &= m - 1;
+    }
+    if (lane == 63) *s_total = incl;
   }
   __syncthreads();
-  it.m = m;
   it.k = threadIdx.x;
-  it.total = (int)min(total, (uint32_t)kListCap);
+  it.total = (int)*s_total;
   return it;
 }
 
@@ -854,11 +871,11 @@ __device__ __forceinline__ PointRef point_ref(const ProbeParams &P, int64_t v) {
 template <bool LOCAL, bool COUNT, bool BATCHED>
 __global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t nwords_arg) {
   __shared__ uint16_t s_list[kListCap];
-  __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_total;
   const int64_t nwords = BATCHED ? P.vhdr[0] : nwords_arg;
   uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
-  for (int64_t blk = blockIdx.x; blk * kBlock < nwords; blk += gridDim.x) {
-    PendingIter it = gather_pending(P, blk, nwords, s_list, s_wave);
+  for (int64_t blk = blockIdx.x; blk * kRangeWords < nwords; blk += gridDim.x) {
+    PendingIter it = gather_pending(P, blk, nwords, s_list, &s_total);
     int64_t v = 0;
     if (LOCAL) {
       while (it.next(s_list, v)) {
@@ -872,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t 
           const uint32_t loc = L.cand_loc(P, r);
           bool cov;
           if (loc != 0xffffffffu) {
-            cov = local_record_covers(P.local + loc, pt.y, pt.x);
+            cov = local_covers_dev(P.local + loc, pt.y, pt.x);
             if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
           } else {
             cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
@@ -940,7 +957,8 @@ __global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t 
       }
     }
     __syncthreads();  // the LDS list is rebuilt for the next range
-    if (P.gticks && it.w < nwords) P.gticks[it.w] = wall_clock64();
+    if (P.gticks && threadIdx.x < kRangeWords && blk * kRangeWords + threadIdx.x < nwords)
+      P.gticks[blk * kRangeWords + threadIdx.x] = wall_clock64();
   }
   flush_counters<COUNT>(P, c);
   if (COUNT && c_reads) atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
@@ -1231,7 +1249,11 @@ static int upload_image(act_index *x) {
   trig_table(trig);
   int rc;
   if ((rc = upload(d.nodes, h.nodes.data(), h.nodes.size() * 8, d.bytes))) return rc;
-  if ((rc = upload(d.lut, h.lut.data(), h.lut.size() * 4, d.bytes))) return rc;
+  // device copies of the lookup table and the records carry zero padding
+  // for the resolve kernel's read-ahead (4 and 10 words)
+  std::vector<uint32_t> lut(h.lut);
+  lut.resize(lut.size() + 4, 0u);
+  if ((rc = upload(d.lut, lut.data(), lut.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.eoff, h.poly_edge_off.data(), h.poly_edge_off.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.origin, h.poly_origin.data(), h.poly_origin.size() * 8, d.bytes))) return rc;
   if ((rc = upload(d.pm, h.poly_m.data(), h.poly_m.size() * 4, d.bytes))) return rc;
@@ -1246,7 +1268,9 @@ static int upload_image(act_index *x) {
   std::vector<uint32_t> top(n_top);
   for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
   if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
-  if ((rc = upload(d.local, h.local.data(), h.local.size() * 4, d.bytes))) return rc;
+  std::vector<uint32_t> local(h.local);
+  local.resize(local.size() + 10, 0u);
+  if ((rc = upload(d.local, local.data(), local.size() * 4, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -1370,8 +1394,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
     if (!exact) continue;
     const int64_t nwords = (n + 63) / 64;
-    hipLaunchKernelGGL(resolve, dim3((unsigned)((nwords + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       (hipStream_t)stream, P, nwords);
+    hipLaunchKernelGGL(resolve, dim3((unsigned)((nwords + kRangeWords - 1) / kRangeWords)),
+                       dim3(kBlock), 0, (hipStream_t)stream, P, nwords);
     e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
@@ -1417,7 +1441,7 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
                      (size_t)n_lds * 1024, st, P);
   if (exact) {
     void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
-    hipLaunchKernelGGL(resolve, dim3(kBatchGrid), dim3(kBlock), 0, st, P, (int64_t)0);
+    hipLaunchKernelGGL(resolve, dim3(2 * kBatchGrid), dim3(kBlock), 0, st, P, (int64_t)0);
   }
   if (d_ticks)
     hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)nb + 3) / 4, 4096)),
