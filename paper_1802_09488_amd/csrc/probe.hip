@@ -189,11 +189,12 @@ __device__ __forceinline__ double rcp_nr(double a) {
   return fma(r, e, r);
 }
 
-// Linear st transform of a face coordinate w in [-1, 1] as a 30-bit cell
-// coordinate: floor(2^30 (1 + w) / 2), clamped.
-__device__ __forceinline__ uint32_t leaf_coord(double w) {
-  const uint32_t i = (uint32_t)fmax(fma(w, 536870912.0, 536870912.0), 0.0);
-  return min(i, (1u << 30) - 1u);
+// Linear st transform of a face coordinate w = c / major, w in [-1, 1], as
+// a 30-bit cell coordinate floor(2^30 (1 + w) / 2), clamped; `r29` is
+// 2^29 / major.
+__device__ __forceinline__ uint32_t leaf_coord(double c, double r29) {
+  const int32_t i = (int32_t)fma(c, r29, 536870912.0);
+  return min((uint32_t)max(i, 0), (1u << 30) - 1u);
 }
 
 // Steps 2-3: leaf cell coordinates (face, i, j) of a point; false for
@@ -211,14 +212,32 @@ __device__ __forceinline__ bool project(const double2 *trig, double lat, double 
   const bool xmaj = fabs(x) >= fabs(y);
   const double mxy = fmax(fabs(x), fabs(y));
   const bool polar = fabs(z) > mxy;
-  const double r = rcp_nr(fmax(mxy, fabs(z)));
+  const double r29 = rcp_nr(fmax(mxy, fabs(z))) * 536870912.0;
+  const bool neg = polar ? z < 0.0 : (xmaj ? x < 0.0 : y < 0.0);
+  // the face is usually the same for the whole wavefront (regional data):
+  // then a wave-uniform branch picks the coordinates without selects
+  const uint32_t f = (polar ? 2u : (xmaj ? 0u : 1u)) + (neg ? 3u : 0u);
+  const uint32_t f0 = __builtin_amdgcn_readfirstlane(f);
+  if (__ballot(f != f0) == 0) {
+    face = f0;
+    if (f0 == 0u || f0 == 3u) {
+      i = leaf_coord(y, r29);
+      j = leaf_coord(z, r29);
+    } else if (f0 == 1u || f0 == 4u) {
+      i = leaf_coord(z, r29);
+      j = leaf_coord(x, r29);
+    } else {
+      i = leaf_coord(x, r29);
+      j = leaf_coord(y, r29);
+    }
+    return true;
+  }
   // minor coordinates in axis order: x face (y, z), y face (z, x), z face (x, y)
   const double c1 = polar ? x : (xmaj ? y : z);
   const double c2 = polar ? y : (xmaj ? z : x);
-  const bool neg = polar ? z < 0.0 : (xmaj ? x < 0.0 : y < 0.0);
-  face = (polar ? 2u : (xmaj ? 0u : 1u)) + (neg ? 3u : 0u);
-  i = leaf_coord(c1 * r);
-  j = leaf_coord(c2 * r);
+  face = f;
+  i = leaf_coord(c1, r29);
+  j = leaf_coord(c2, r29);
   return true;
 }
 
@@ -609,7 +628,8 @@ __global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
   if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
   if (threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
   constexpr int TILE = 64 * NP;
   const int64_t ntiles = BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE;
@@ -788,51 +808,66 @@ __device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint3
     if (c[k]) atomicAdd(P.counters + ids[k], (unsigned long long)c[k]);
 }
 
-// Pending points of a resolve block range: 64 mask words (4096 points of
-// the pass, or of a batched join's virtual space). The first wave reads the
-// words and compacts their set bits into an LDS list (prefix sum of the
-// popcounts over its lanes); the list holds every pending point of the
-// range, and the block's threads take its entries one by one.
-constexpr int kRangeWords = 64;
-constexpr int kListCap = kRangeWords * 64;
+// Pending points of a resolve block range: kRangeWords mask words (64
+// points each, of the pass or of a batched join's virtual space), one per
+// thread. The block compacts their set bits into an LDS list (block-wide
+// prefix sum of the popcounts) and hands the list out one point per
+// thread; bits beyond the list's capacity (more than a quarter of the
+// range's points pending) stay with the thread that read them.
+constexpr int kRangeWords = 256;
+constexpr int kResolveBlock = 256;
+constexpr int kListCap = 4096;
 
 struct PendingIter {
   int k, total;
+  uint64_t m;    // bits of this thread's word not in the list
+  int64_t w;     // this thread's mask word
   int64_t base;  // first point of the block's range
   __device__ __forceinline__ bool next(const uint16_t *s_list, int64_t &v) {
-    if (k >= total) return false;
-    v = base + s_list[k];
-    k += kBlock;
-    return true;
+    if (k < total) {
+      v = base + s_list[k];
+      k += kResolveBlock;
+      return true;
+    }
+    if (m) {
+      v = w * 64 + (__ffsll((long long)m) - 1);
+      m &= m - 1;
+      return true;
+    }
+    return false;
   }
 };
 
 __device__ __forceinline__ PendingIter gather_pending(const ProbeParams &P, int64_t blk,
                                                       int64_t nwords, uint16_t *s_list,
-                                                      uint32_t *s_total) {
+                                                      uint32_t *s_wave) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   PendingIter it;
   it.base = blk * kRangeWords * 64;
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    const int64_t w = blk * kRangeWords + lane;
-    uint64_t m = w < nwords ? P.mask[w] : 0ull;
-    const uint32_t c = (uint32_t)__popcll(m);
-    uint32_t incl = c;
+  it.w = blk * kRangeWords + threadIdx.x;
+  uint64_t m = it.w < nwords ? P.mask[it.w] : 0ull;
+  const uint32_t c = (uint32_t)__popcll(m);
+  uint32_t incl = c;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
-    uint32_t pos = incl - c;
-    while (m) {
-      s_list[pos++] = (uint16_t)((lane << 6) | (__ffsll((long long)m) - 1));
-      m &= m - 1;
-    }
-    if (lane == 63) *s_total = incl;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  if (lane == 63) s_wave[wid] = incl;
+  __syncthreads();
+  uint32_t pos = incl - c, total = 0;
+  for (int k = 0; k < kRangeWords / 64; k++) {
+    if (k < wid) pos += s_wave[k];
+    total += s_wave[k];
+  }
+  while (m && pos < (uint32_t)kListCap) {
+    s_list[pos++] = (uint16_t)((threadIdx.x << 6) | (__ffsll((long long)m) - 1));
+    m &= m - 1;
   }
   __syncthreads();
+  it.m = m;
   it.k = threadIdx.x;
-  it.total = (int)*s_total;
+  it.total = (int)min(total, (uint32_t)kListCap);
   return it;
 }
 
@@ -869,13 +904,14 @@ __device__ __forceinline__ PointRef point_ref(const ProbeParams &P, int64_t v) {
 // time (lanes over edges, see wave_covers); in every round each lane with
 // work offers its next candidate.
 template <bool LOCAL, bool COUNT, bool BATCHED>
-__global__ __launch_bounds__(kBlock) void resolve_kernel(ProbeParams P, int64_t nwords_arg) {
+__global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
+                                                                 int64_t nwords_arg) {
   __shared__ uint16_t s_list[kListCap];
-  __shared__ uint32_t s_total;
+  __shared__ uint32_t s_wave[kRangeWords / 64];
   const int64_t nwords = BATCHED ? P.vhdr[0] : nwords_arg;
   uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
   for (int64_t blk = blockIdx.x; blk * kRangeWords < nwords; blk += gridDim.x) {
-    PendingIter it = gather_pending(P, blk, nwords, s_list, &s_total);
+    PendingIter it = gather_pending(P, blk, nwords, s_list, s_wave);
     int64_t v = 0;
     if (LOCAL) {
       while (it.next(s_list, v)) {
@@ -1394,8 +1430,9 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
     if (!exact) continue;
     const int64_t nwords = (n + 63) / 64;
-    hipLaunchKernelGGL(resolve, dim3((unsigned)((nwords + kRangeWords - 1) / kRangeWords)),
-                       dim3(kBlock), 0, (hipStream_t)stream, P, nwords);
+    const int64_t ranges = (nwords + kRangeWords - 1) / kRangeWords;
+    hipLaunchKernelGGL(resolve, dim3((unsigned)std::min<int64_t>(ranges, 65535)),
+                       dim3(kResolveBlock), 0, (hipStream_t)stream, P, nwords);
     e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
@@ -1441,7 +1478,7 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
                      (size_t)n_lds * 1024, st, P);
   if (exact) {
     void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
-    hipLaunchKernelGGL(resolve, dim3(2 * kBatchGrid), dim3(kBlock), 0, st, P, (int64_t)0);
+    hipLaunchKernelGGL(resolve, dim3(2048), dim3(kResolveBlock), 0, st, P, (int64_t)0);
   }
   if (d_ticks)
     hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)nb + 3) / 4, 4096)),
