@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle points (default: the whole c2 workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="c2: only the headline exact and approx@4m joins (for rocprofv3 runs)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
                     help="seconds per serving rate (default 2 in c2, 10 in c5)")
     ap.add_argument("--summarize-trace", metavar="DIR")
@@ -320,6 +322,12 @@ def run_c2(args):
     log("timing approx@4m")
     wall_a, tot_a, prb_a = time_joins(idx_a, pts, out, args.steps, args.warmup)
     _, _, ctr_a = idx_a.join_ex(pts, out, counters=True)
+    if args.profile:
+        res = {"profile_run": True, "exact_probe_ms": float(np.mean(prb)),
+               "approx_probe_ms": float(np.mean(prb_a)),
+               "kernel_sources_sha256_16": kernel_source_hash()}
+        print(json.dumps(res), flush=True)
+        return
     log("timing refinement variants")
     k = max(3, args.steps // 2)
     var = {}
@@ -601,13 +609,19 @@ def _short(name):
 
 
 def summarize_trace(d):
-    rows = _csv_rows(d, "kernel_stats.csv")
-    print("| kernel | calls | avg (us) | min (us) | max (us) | total (ms) |")
-    print("|---|---|---|---|---|---|")
-    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        print("| %s | %s | %.1f | %.1f | %.1f | %.2f |" % (
-            _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
-            float(r["MaxNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6))
+    """Per (kernel, launch grid): calls and durations, from the kernel trace."""
+    import numpy as np
+    rows = _csv_rows(d, "kernel_trace.csv")
+    groups = {}
+    for r in rows:
+        key = (_short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print("| kernel | grid (threads) | block | calls | avg (us) | min (us) | max (us) | total (ms) |")
+    print("|---|---|---|---|---|---|---|---|")
+    for (name, grid, blk), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:14]:
+        v = np.asarray(v)
+        print("| %s | %d | %d | %d | %.1f | %.1f | %.1f | %.2f |" % (
+            name, grid, blk, len(v), v.mean(), v.min(), v.max(), v.sum() / 1e3))
 
 
 def summarize_pmc(fdir, wdir):
@@ -617,11 +631,15 @@ def summarize_pmc(fdir, wdir):
     import numpy as np
     per = {}
     for d, ctr in ((fdir, "FETCH_SIZE"), (wdir, "WRITE_SIZE")):
-        vals = {}
+        vals, grids = {}, {}
         for r in _csv_rows(d, "counter_collection.csv"):
             if r["Counter_Name"] != ctr:
                 continue
-            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+            k, g = r["Kernel_Name"], int(r["Grid_Size"])
+            if g > grids.get(k, -1):  # keep the full-size launches of each kernel
+                grids[k], vals[k] = g, []
+            if g == grids[k]:
+                vals[k].append(float(r["Counter_Value"]) * 1024.0)
         copies = max((v for k, v in vals.items() if "copyBuffer" in k), key=max)
         cal = COPY_BYTES / max(copies)
         per[ctr] = (cal, vals)
@@ -635,8 +653,8 @@ def summarize_pmc(fdir, wdir):
     print("| kernel | HBM bytes per launch | fetch (scaled) | write (scaled) | launches |")
     print("|---|---|---|---|---|")
     for k in sorted(fv):
-        pm = re.search(r"probe_kernel<(true|false), \d+, false, \d+>", k)
-        rm = re.search(r"resolve_kernel<(true|false), false>", k)
+        pm = re.search(r"probe_kernel<(true|false), \d+, false, \d+, false>", k)
+        rm = re.search(r"resolve_kernel<(true|false), false, false>", k)
         if not pm and not rm:
             continue  # other kernels, and the counting variants
         label = ("probe_kernel %s" % ("exact" if pm.group(1) == "true" else "approx")) if pm \
