@@ -88,7 +88,7 @@ constexpr int64_t kDefaultPass = 1 << 24;
 // Launch configuration used when a join leaves a knob at its default
 // (set by act_tune; the built-in defaults otherwise).
 struct act_launch {
-  int32_t grid = 1024;
+  int32_t grid = 2048;
   int32_t lds_levels = -1;  // -1: deepest that fits
   int32_t points_per_lane = 2;
   int32_t refine = ACT_REFINE_LOCAL;
