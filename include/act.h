@@ -377,7 +377,7 @@ typedef struct {
   int32_t n_faces;          /* faces with a trie                              */
   int32_t face_prefix_level[6]; /* per-face common-prefix level, -1 if none  */
   int32_t mode;
-  int32_t reserved;
+  int32_t lds_nodes;        /* trie nodes staged in LDS (default depth)     */
   double precision_m;
   double build_seconds;
   int64_t local_words;      /* cell-local refinement records (32-bit words)   */

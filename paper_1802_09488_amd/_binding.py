@@ -82,12 +82,12 @@ class Stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("max_depth", ctypes.c_int32),
                 ("max_refs", ctypes.c_int32), ("max_cell_level", ctypes.c_int32),
                 ("n_faces", ctypes.c_int32), ("face_prefix_level", ctypes.c_int32 * 6),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("lds_nodes", ctypes.c_int32),
                 ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("local_words", ctypes.c_int64)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["face_prefix_level"] = list(self.face_prefix_level)
         return d
 

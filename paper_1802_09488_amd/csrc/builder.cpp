@@ -660,12 +660,14 @@ static int64_t choose_prefix(const std::vector<Cell> &cells, const FaceCells fc[
 // out.nodes / out.lut / out.faces (and the trie statistics), with prefix
 // level lp[face].
 static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], const int lp_face[6],
-                       int64_t n_nodes, HostIndex &out, const BuildParams &bp, std::string &err) {
+                       int64_t n_nodes, const std::vector<uint32_t> &local, HostIndex &out,
+                       const BuildParams &bp, std::string &err) {
   out.nodes.clear();
   out.lut.clear();
   for (int f = 0; f < 6; f++) out.faces[f] = FaceRoot();
   out.max_depth = out.max_refs = out.max_cell_level = 0;
   out.n_cells_interior_only = 0;
+  out.local_words = 0;
   out.nodes.reserve(256 * (size_t)n_nodes);
   out.nodes.assign(256, 0);  // node 0 reserved
   LutDedup dedup;
@@ -714,8 +716,9 @@ static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], co
       for (int r = 0; r < c.n; r++) has_cand |= !(c.refs[r] & 1u);
       uint64_t entry;
       if (has_cand && bp.mode == ACT_EXACT) {
-        // candidate cell: lookup-table list followed by the candidates'
-        // local record offsets
+        // candidate cell: lookup-table list, the candidates' record offsets,
+        // then the records themselves, so that one contiguous read serves a
+        // pending point
         std::vector<uint32_t> tru, cand, locs;
         for (int r = 0; r < c.n; r++) {
           if (c.refs[r] & 1u) {
@@ -730,7 +733,15 @@ static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], co
         out.lut.insert(out.lut.end(), tru.begin(), tru.end());
         out.lut.push_back((uint32_t)cand.size());
         out.lut.insert(out.lut.end(), cand.begin(), cand.end());
-        out.lut.insert(out.lut.end(), locs.begin(), locs.end());
+        const size_t at = out.lut.size();
+        out.lut.resize(at + locs.size());
+        for (size_t r = 0; r < locs.size(); r++) {
+          const uint32_t *rec = &local[locs[r]];
+          const size_t len = 2 + 8 * (size_t)rec[0] + 2 * (size_t)(rec[1] & 0x7fffffffu);
+          out.lut[at + r] = (uint32_t)out.lut.size();
+          out.lut.insert(out.lut.end(), rec, rec + len);
+          out.local_words += (int64_t)len;
+        }
       } else {
         entry = encode_refs(c.refs, c.n, out.lut, &dedup);
       }
@@ -936,9 +947,10 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
   // shifted to level 30
   std::vector<Cell> cells;
+  std::vector<uint32_t> local;  // all sinks' records, embedded in the lookup table below
   auto gather = [&](const Sink &s) {
-    const uint64_t base = out.local.size();
-    out.local.insert(out.local.end(), s.local.begin(), s.local.end());
+    const uint64_t base = local.size();
+    local.insert(local.end(), s.local.begin(), s.local.end());
     for (const CellOut &c : s.cells)
       cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
                        quad_key(c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level)),
@@ -946,7 +958,7 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   };
   gather(top);
   for (const Sink &s : sinks) gather(s);
-  if (out.local.size() >= (1ull << 32)) {
+  if (local.size() >= (1ull << 32)) {
     err = "cell-local refinement records exceed 2^32 words";
     return ACT_E_RANGE;
   }
@@ -959,7 +971,7 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   face_ranges(cells, fc);
   int lp[6];
   const int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
-  const int rc = build_tries(cells, fc, lp, n_nodes, out, bp, err);
+  const int rc = build_tries(cells, fc, lp, n_nodes, local, out, bp, err);
   if (rc) return rc;
   out.build_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -11,7 +11,8 @@
 // Lookup table: one uint32 array; each list is
 //   n_true, true ids..., n_cand, candidate ids... (ids ascending per part);
 //   in exact mode a cell with candidates always has its own list, followed
-//   by n_cand offsets of cell-local refinement records.
+//   by n_cand word offsets (into the same array) of the candidates'
+//   cell-local refinement records, which follow right after.
 // Per face: a root node, the common prefix shared by every indexed cell on
 // the face (prefix level Lp), and the alignment of node levels: the root
 // covers levels Lp+1..Lp+4, its children Lp+5..Lp+8, and so on (the
@@ -70,10 +71,9 @@ struct HostIndex {
   std::vector<float> poly_m;           // largest |translated fp32 coordinate|
   std::vector<float> edges32;          // 4 per edge, translated, lower endpoint first
   std::vector<double> edges64;         // 4 per edge: ax ay bx by
-  // exact mode: cell-local refinement records (32-bit words); a candidate
-  // cell's lookup-table list n_true, true ids, n_cand, candidate ids is
-  // followed by one record offset per candidate
-  std::vector<uint32_t> local;
+  // exact mode: words of cell-local refinement records (stored in `lut`
+  // after their cell's list)
+  int64_t local_words = 0;
 
   // statistics
   int64_t n_cells = 0, n_cells_interior_only = 0;

@@ -64,7 +64,6 @@ struct DevImage {
   double2 *trig = nullptr;
   struct FaceDev *faces = nullptr;
   uint32_t *top32 = nullptr;
-  uint32_t *local = nullptr;
   size_t bytes = 0;
 };
 
@@ -135,7 +134,7 @@ struct ProbeParams {
   const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 as 32-bit entries
   int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
-  const uint32_t *local;  // cell-local refinement records (exact mode)
+  const uint32_t *local;  // exact mode: base of the cell-local records (the LUT)
   uint64_t *mask;         // exact mode: pending points of this pass, bit per point
   int64_t base;           // index of pts[0] in the caller's array (pair output)
   // batched joins: the batches laid end to end in a virtual point space,
@@ -925,7 +924,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
           const uint32_t loc = L.cand_loc(P, r);
           bool cov;
           if (loc != 0xffffffffu) {
-            cov = local_covers_dev(P.local + loc, pt.y, pt.x);
+            cov = local_record_covers(P.local + loc, pt.y, pt.x);
             if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
           } else {
             cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
@@ -1166,7 +1165,7 @@ struct DeviceGuard {
 
 static void free_image(DevImage &d) {
   void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
-                  d.e64,   d.trig,  d.faces, d.top32,  d.local};
+                  d.e64,   d.trig,  d.faces, d.top32};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -1285,10 +1284,10 @@ static int upload_image(act_index *x) {
   trig_table(trig);
   int rc;
   if ((rc = upload(d.nodes, h.nodes.data(), h.nodes.size() * 8, d.bytes))) return rc;
-  // device copies of the lookup table and the records carry zero padding
-  // for the resolve kernel's read-ahead (4 and 10 words)
+  // the device copy of the lookup table (with the records) carries zero
+  // padding for the resolve kernel's read-ahead (at most 10 words)
   std::vector<uint32_t> lut(h.lut);
-  lut.resize(lut.size() + 4, 0u);
+  lut.resize(lut.size() + 10, 0u);
   if ((rc = upload(d.lut, lut.data(), lut.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.eoff, h.poly_edge_off.data(), h.poly_edge_off.size() * 4, d.bytes))) return rc;
   if ((rc = upload(d.origin, h.poly_origin.data(), h.poly_origin.size() * 8, d.bytes))) return rc;
@@ -1304,9 +1303,6 @@ static int upload_image(act_index *x) {
   std::vector<uint32_t> top(n_top);
   for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
   if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
-  std::vector<uint32_t> local(h.local);
-  local.resize(local.size() + 10, 0u);
-  if ((rc = upload(d.local, local.data(), local.size() * 4, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -1356,7 +1352,7 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.top32 = x->dev.top32;
   P.n_lds_nodes = n_lds;
   P.refine = refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : refine;
-  P.local = x->dev.local;
+  P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
 }
 
 static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
@@ -1509,7 +1505,6 @@ static uint64_t index_digest(const HostIndex &h) {
   };
   mix(h.nodes.data(), h.nodes.size() * 8);
   mix(h.lut.data(), h.lut.size() * 4);
-  mix(h.local.data(), h.local.size() * 4);
   mix(h.edges64.data(), h.edges64.size() * 8);
   mix(&h.precision_m, sizeof h.precision_m);
   return d;
@@ -1862,9 +1857,11 @@ int act_index_stats(const act_index *x, act_stats *o) {
     o->n_faces += h.faces[f].root >= 0;
   }
   o->mode = h.mode;
+  const int depth = default_lds_depth(h);
+  o->lds_nodes = depth > 0 ? lds_nodes_for(h, depth) : 0;
   o->precision_m = h.precision_m;
   o->build_seconds = h.build_seconds;
-  o->local_words = (int64_t)h.local.size();
+  o->local_words = h.local_words;
   return ACT_OK;
 }
 
@@ -1880,13 +1877,13 @@ int act_refine_local_host(const act_index *x, int32_t face, uint32_t i, uint32_t
   if (!x || !covered) return fail(ACT_E_ARG, "bad argument");
   const HostIndex &h = x->host;
   const uint64_t e = host_lookup(h, face, i, j);
-  if ((e & kTagMask) != kTagLut || h.local.empty())
+  if ((e & kTagMask) != kTagLut || h.mode != ACT_EXACT)
     return fail(ACT_E_ARG, "no cell-local record for this cell");
   const uint32_t off = (uint32_t)(e >> 2);
   const uint32_t nt = h.lut[off], nc = h.lut[off + 1 + nt];
   for (uint32_t r = 0; r < nc; r++)
     if ((int32_t)h.lut[off + 2 + nt + r] == poly) {
-      *covered = local_record_covers(&h.local[h.lut[off + 2 + nt + nc + r]], lng, lat) ? 1 : 0;
+      *covered = local_record_covers(&h.lut[h.lut[off + 2 + nt + nc + r]], lng, lat) ? 1 : 0;
       return ACT_OK;
     }
   return fail(ACT_E_ARG, "polygon is not a candidate of this cell");
