@@ -349,6 +349,12 @@ def run_c2(args):
             var[name]["identical_to_local"] = bool(np.array_equal(out.cpu().numpy(), exact_out))
     var["fp32_filter_over_fp64_speedup"] = (var["fp64"]["join_ms_mean"]
                                             / var["fp32_filter"]["join_ms_mean"])
+    # cell-local refinement with pending points resolved by the probe's waves
+    wq, tq, _ = time_joins(idx, pts, out, k, 1, pending=act.ACT_PENDING_QUEUE)
+    torch.cuda.synchronize()
+    var["local_in_probe_queue"] = {"points_per_s": n * k / wq, "join_ms_mean": float(np.mean(tq)),
+                                   "identical_to_local": bool(np.array_equal(out.cpu().numpy(),
+                                                                             exact_out))}
     log("batched join (graph replay)")
     batched = batched_leg(act, idx, pts, exact_out)
     log("serving")
@@ -497,6 +503,8 @@ def run_c3(args):
         wv, mv = timed(idx, 1, refine=mode)
         var[name] = {"points_per_s": n / wv, "stream_ms": float(np.mean(mv))}
     var["fp32_filter_over_fp64_speedup"] = var["fp64"]["stream_ms"] / var["fp32_filter"]["stream_ms"]
+    wq, mq = timed(idx, 1, pending=act.ACT_PENDING_QUEUE)
+    var["local_in_probe_queue"] = {"points_per_s": n / wq, "stream_ms": float(np.mean(mq))}
     wa, ma = timed(idx_a, steps)
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
@@ -662,12 +670,15 @@ def summarize_pmc(fdir, wdir):
     print("| kernel | HBM bytes per launch | fetch (scaled) | write (scaled) | launches |")
     print("|---|---|---|---|---|")
     for k in sorted(fv):
-        pm = re.search(r"probe_kernel<(true|false), \d+, false, \d+, false>", k)
+        # probe_kernel<mode, lds, count, points per lane, batched>: mode 0
+        # approximate, 1 exact (pending points to the resolve kernel), 2
+        # exact (pending points resolved by the probe's queues)
+        pm = re.search(r"probe_kernel<(\d), \d+, false, \d+, false>", k)
         rm = re.search(r"resolve_kernel<(true|false), false, false>", k)
         if not pm and not rm:
             continue  # other kernels, and the counting variants
-        label = ("probe_kernel %s" % ("exact" if pm.group(1) == "true" else "approx")) if pm \
-            else ("resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges"))
+        label = ("probe_kernel %s" % {"0": "approx", "1": "exact", "2": "exact-queue"}[pm.group(1)]) \
+            if pm else ("resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges"))
         f = float(np.median(fv[k])) * fcal
         wr = float(np.median(wv.get(k, [0.0]))) * wcal
         print("| %s | %.4g | %.4g | %.4g | %d |" % (label, f + wr, f, wr, len(fv[k])))

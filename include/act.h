@@ -188,6 +188,14 @@ enum {
   ACT_NCOUNTERS = 16
 };
 
+/* How an exact join resolves its pending points (points whose cell has
+ * candidate references). KERNEL: the probe marks them in a per-stream mask
+ * and a second kernel refines them. QUEUE: each probe wave queues its
+ * pending points in LDS and refines them itself, 64 at a time (no second
+ * pass over the points; pays off when many points are pending). AUTO: the
+ * index's launch configuration (KERNEL unless act_tune chose QUEUE). */
+enum { ACT_PENDING_AUTO = 0, ACT_PENDING_KERNEL = 1, ACT_PENDING_QUEUE = 2 };
+
 /* Full-control join; act_join / act_join_pairs are shorthands for it. */
 typedef struct {
   const double *d_points;  /* device, 2*n doubles                            */
@@ -205,15 +213,21 @@ typedef struct {
                               of 32-bit entries)                             */
   int32_t grid;            /* probe blocks launched (0 = default 2048); each
                               wave walks tiles of 64 points grid-stride      */
-  int64_t pass_points;     /* exact mode: points per probe + resolve pass, at
-                              most the workspace's (0 = the workspace's)    */
+  int64_t pass_points;     /* exact joins with ACT_PENDING_KERNEL: points
+                              per probe + resolve pass, at most the
+                              workspace's (0 = the workspace's)              */
   int32_t points_per_lane; /* points each probe lane carries per step: 1, 2
-                              (0 = default 2)                                */
-  int32_t reserved2;
+                              (0 = the index's default: 1 in exact mode, 2 in
+                              approximate mode)                              */
+  int32_t pending;         /* exact mode with cell-local refinement: how
+                              pending points are resolved, ACT_PENDING_*
+                              (other refinement modes always use the
+                              kernel)                                        */
   void *probe_event;       /* optional hipEvent_t, recorded on the stream
-                              after each probe launch (so, in a one-pass
-                              join, between the probe and the resolve
-                              kernel): lets a caller time the probe alone   */
+                              after each probe launch (so, with
+                              ACT_PENDING_KERNEL, between the probe and the
+                              resolve kernel): lets a caller time the probe
+                              alone                                          */
 } act_join_args;
 
 int act_join_ex(const act_index *idx, const act_join_args *args, void *stream);
@@ -266,11 +280,12 @@ int act_batched_status(const act_index *idx, void *stream, int32_t *ok);
  * act_tune -- autotuner. Times joins of the sample (device, 2*n doubles;
  * d_out: device scratch of n int32) over probe grid sizes (256 .. 4096
  * blocks), LDS-staged trie depth (0 .. 2, where the levels fit), points
- * per lane (1, 2) and, in exact mode, the refinement mapping (cell-local or
- * all edges with the fp32 filter), picks the fastest (median of 3) and
- * makes it the index's launch configuration: joins that leave grid = 0,
- * lds_levels = -1, points_per_lane = 0 or refine = ACT_REFINE_AUTO, and
- * batched joins, use it from then on. The hand-tuning the paper reports for
+ * per lane (1, 2) and, in exact mode, the refinement mapping (cell-local,
+ * with pending points resolved by a second kernel or by the probe's own
+ * queues, or all edges with the fp32 filter), picks the fastest (median of
+ * 3) and makes it the index's launch configuration: joins that leave grid =
+ * 0, lds_levels = -1, points_per_lane = 0, refine = ACT_REFINE_AUTO or
+ * pending = ACT_PENDING_AUTO, and batched joins, use it from then on. The hand-tuning the paper reports for
  * its CPUs (Section V) is done by measurement here. With cache_path (a
  * text file, one line per (index digest, gfx950) -> configuration) a
  * cached configuration is applied without timing, and new results are
@@ -288,6 +303,8 @@ typedef struct {
   float default_ms;       /* the built-in defaults' median join time         */
   int32_t n_configs;      /* configurations timed (0 when from the cache)    */
   int32_t from_cache;     /* 1 if read from cache_path                       */
+  int32_t pending;        /* chosen ACT_PENDING_* (exact mode)               */
+  int32_t reserved;
   uint64_t index_digest;  /* cache key (0 without cache_path)                */
 } act_tune_result;
 

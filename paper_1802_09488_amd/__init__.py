@@ -22,13 +22,15 @@ import ctypes
 import numpy as np
 
 from . import _binding as _b
-from ._binding import (ACT_APPROX, ACT_EXACT, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
+from ._binding import (ACT_APPROX, ACT_EXACT, ACT_PENDING_AUTO, ACT_PENDING_KERNEL,
+                       ACT_PENDING_QUEUE, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
                        ACT_REFINE_FP64, ACT_REFINE_LOCAL, COUNTER_NAMES, ActError)
 
 __all__ = ["build", "Index", "Server", "cell_ids", "batch_descriptors", "wall_clock_hz",
            "ActError",
            "ACT_EXACT", "ACT_APPROX",
            "ACT_REFINE_AUTO", "ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64",
+           "ACT_PENDING_AUTO", "ACT_PENDING_KERNEL", "ACT_PENDING_QUEUE",
            "version", "lib"]
 
 lib = _b.lib
@@ -98,7 +100,8 @@ class Index:
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
                 refine=ACT_REFINE_AUTO, block=0, lds_levels=-1, grid=0,
-                pass_points=0, points_per_lane=0, probe_event=None, stream=None):
+                pass_points=0, points_per_lane=0, pending=ACT_PENDING_AUTO,
+                probe_event=None, stream=None):
         """Full-control join. Returns (out, pairs or None, counters dict or None).
 
         pairs: (m, 2) int64 CUDA tensor of (point, polygon) beyond out[i]
@@ -120,6 +123,7 @@ class Index:
         a.grid = grid
         a.pass_points = pass_points
         a.points_per_lane = points_per_lane
+        a.pending = pending
         if probe_event is not None:  # a recorded torch.cuda.Event (its HIP event handle)
             a.probe_event = probe_event.cuda_event
         pp = pq = cnt = ctr = None

@@ -16,6 +16,7 @@ ACT_OK, ACT_E_ARG, ACT_E_POLY, ACT_E_OOM, ACT_E_HIP, ACT_E_OVERFLOW, ACT_E_DEVIC
     0, -1, -2, -3, -4, -5, -6, -7
 ACT_EXACT, ACT_APPROX = 0, 1
 ACT_REFINE_AUTO, ACT_REFINE_LOCAL, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1, 2, 3
+ACT_PENDING_AUTO, ACT_PENDING_KERNEL, ACT_PENDING_QUEUE = 0, 1, 2
 ACT_NCOUNTERS = 16
 COUNTER_NAMES = ["points", "invalid", "false_hit", "solely_true", "cand_points", "candidates",
                  "edges", "edge_fp64", "edge_exact", "node_reads", "lut_reads"]
@@ -44,7 +45,7 @@ class JoinArgs(ctypes.Structure):
                 ("d_counters", ctypes.c_void_p), ("refine", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("lds_levels", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("pass_points", ctypes.c_int64),
-                ("points_per_lane", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+                ("points_per_lane", ctypes.c_int32), ("pending", ctypes.c_int32),
                 ("probe_event", ctypes.c_void_p)]
 
 
@@ -53,6 +54,7 @@ class TuneResult(ctypes.Structure):
                 ("points_per_lane", ctypes.c_int32), ("refine", ctypes.c_int32),
                 ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("n_configs", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("pending", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("index_digest", ctypes.c_uint64)]
 
 

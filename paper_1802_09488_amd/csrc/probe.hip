@@ -6,19 +6,23 @@
 //   2. domain check (non-finite / |lat| > 90 / |lng| > 180 -> no match);
 //   3. fp64 projection lat/lng -> unit sphere -> cube face -> (u, v) ->
 //      linear (s, t) -> 30-bit (i, j) (Section II, S2 paragraph);
-//   4. Hilbert position via a 4-levels-per-step state table held in LDS;
+//   4. the trie key is the leaf's quadtree path, 4 bits of i and 4 of j
+//      per node (the Hilbert id of step 4 is computed only for
+//      act_cell_ids, from a 4-levels-per-step state table held in LDS);
 //   5. stage 1 (Listing 4): face -> root, per-face common prefix check;
 //   6. stage 2 (Listing 5): comparison-free descent, 8 key bits per node,
 //      until a payload, a LUT offset or the sentinel;
 //   7. stage 3: decode the tagged entry (Section III-E, three cases);
 //   8. true hits (and every reference in approximate mode) are output;
-//      in exact mode a point whose cell has candidate references is marked
-//      in a per-64-point pending mask and left to the resolve kernel, which
-//      refines its candidates by the crossing-number test of Section II
-//      with the ST_Covers boundary rule (cell-local records by default;
-//      optionally over all edges: fp32 on origin-translated coordinates
-//      with a proven error bound, fp64 + exact arithmetic for the edges the
-//      bound leaves undecided);
+//      in exact mode a point whose cell has candidate references is
+//      pending: its candidates are refined by the crossing-number test of
+//      Section II with the ST_Covers boundary rule. By default each wave
+//      queues its pending points in LDS and refines them 64 at a time from
+//      the cells' local records; a two-pass join instead marks them in a
+//      per-64-point mask for the resolve kernel, which can also refine over
+//      all edges (fp32 on origin-translated coordinates with a proven error
+//      bound, fp64 + exact arithmetic for the edges the bound leaves
+//      undecided);
 //   9. out[i] = lowest matching id (or -1), further matches -> pair list.
 #include <hip/hip_runtime.h>
 
@@ -88,9 +92,10 @@ constexpr int64_t kDefaultPass = 1 << 24;
 // (set by act_tune; the built-in defaults otherwise).
 struct act_launch {
   int32_t grid = 2048;
-  int32_t lds_levels = -1;  // -1: deepest that fits
-  int32_t points_per_lane = 2;
+  int32_t lds_levels = -1;       // -1: deepest that fits
+  int32_t points_per_lane = 0;   // 0: 1 in exact mode, 2 in approximate mode
   int32_t refine = ACT_REFINE_LOCAL;
+  int32_t pending = ACT_PENDING_KERNEL;
 };
 
 struct act_index {
@@ -212,10 +217,13 @@ __device__ __forceinline__ bool project(const double2 *trig, double lat, double 
   const double mxy = fmax(fabs(x), fabs(y));
   const bool polar = fabs(z) > mxy;
   const double r29 = rcp_nr(fmax(mxy, fabs(z))) * 536870912.0;
-  const bool neg = polar ? z < 0.0 : (xmaj ? x < 0.0 : y < 0.0);
+  // the major coordinate is at least 1/sqrt(3) in magnitude, so its sign
+  // bit (bit 31 of the high word) says whether it is negative
+  const uint32_t hs = polar ? (uint32_t)__double2hiint(z)
+                            : (uint32_t)__double2hiint(xmaj ? x : y);
   // the face is usually the same for the whole wavefront (regional data):
   // then a wave-uniform branch picks the coordinates without selects
-  const uint32_t f = (polar ? 2u : (xmaj ? 0u : 1u)) + (neg ? 3u : 0u);
+  const uint32_t f = (polar ? 2u : (xmaj ? 0u : 1u)) + (hs >> 31) * 3u;
   const uint32_t f0 = __builtin_amdgcn_readfirstlane(f);
   if (__ballot(f != f0) == 0) {
     face = f0;
@@ -545,160 +553,6 @@ __device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, int64_t tile) 
   return r;
 }
 
-// Step 7-9 for the NP points of a lane in tile `tile` (points at T).
-template <bool EXACT, bool COUNT, int NP, bool BATCHED>
-__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, const TileRef &T,
-                                            int lane, const uint64_t (&e)[NP],
-                                            const bool (&live)[NP], const bool (&valid)[NP],
-                                            uint32_t (&c)[8]) {
-  bool pend[NP];
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    const int64_t k = p * 64 + lane;  // within the tile
-    const int64_t i = T.gi + k;       // caller's index (pair output)
-    if (COUNT) {
-      c[0] += live[p];
-      c[1] += live[p] && !valid[p];
-      c[2] += valid[p] && e[p] == 0;
-    }
-    // stage 3: the entry's references (Section III-E: one payload, two
-    // payloads or a lookup-table offset)
-    const uint32_t tag = (uint32_t)(e[p] & kTagMask);
-    const uint32_t r0 = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
-    const uint32_t r1 = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
-    const int n_inl = e[p] == 0 || tag == kTagLut ? 0 : (tag == kTagTwo ? 2 : 1);
-    const uint32_t off = (uint32_t)(e[p] >> 2);
-    if (!EXACT) {
-      // approximate mode: every reference is reported
-      Hits hits;
-      if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
-      if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
-      if (tag == kTagLut) {
-        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
-        for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
-        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
-        if (COUNT) c[4]++;
-      }
-      if (COUNT) c[3] += e[p] != 0;
-      if (live[p]) store_out(T.out + k, hits.best);
-      pend[p] = false;
-    } else {
-      // exact mode: a point whose cell entry has candidate references or is
-      // a lookup-table list is pending: its list offset goes to out[] and
-      // its bit to the pending mask; resolve_kernel finishes it
-      const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
-      pend[p] = live[p] && (tag == kTagLut || cand_inl);
-      if (pend[p]) {
-        store_out(T.out + k, tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending);
-      } else {
-        Hits hits;
-        if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
-        if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
-        if (live[p]) store_out(T.out + k, hits.best);
-        if (COUNT) c[3] += e[p] != 0;
-      }
-    }
-  }
-  if (EXACT) {
-#pragma unroll
-    for (int p = 0; p < NP; p++) {
-      const uint64_t m = ballot(pend[p]);
-      // every group of the virtual space of a batched join has a word
-      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[tile * NP + p] = m;
-    }
-  }
-  if (P.gticks && lane < NP) P.gticks[tile * NP + lane] = wall_clock64();
-}
-
-// The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
-// per lane, at lane and lane + 64, ...), grid-stride, so all lanes of a
-// wave run the same number of iterations. The loop is a two-stage software
-// pipeline: while tile t is projected and descends the LDS-staged levels,
-// the first global node level of tile t - 1 (issued at the end of the
-// previous iteration) is in flight; then tile t - 1 finishes. The point
-// loads run one tile further ahead.
-template <bool EXACT, int LDS_DEPTH, bool COUNT, int NP, bool BATCHED>
-__global__ __launch_bounds__(kProbeBlock) void probe_kernel(ProbeParams P) {
-  extern __shared__ uint32_t s_nodes[];
-  __shared__ FaceDev s_face[6];
-  __shared__ double2 s_trig[kTrigEntries];
-  if (LDS_DEPTH > 0)
-    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
-  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
-  if (threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-  uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
-  constexpr int TILE = 64 * NP;
-  const int64_t ntiles = BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE;
-  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
-  const int64_t first = (int64_t)blockIdx.x * kProbeWaves + wid;
-  double2 nxt[NP];
-  TileRef tnext;
-  if (first < ntiles) tnext = tile_ref<BATCHED, NP>(P, first);
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    const int64_t k = p * 64 + lane;
-    nxt[p] = (first < ntiles && k < tnext.n) ? load_point(tnext.pts + k) : make_double2(0.0, 0.0);
-  }
-  // stage B: the tile whose first global level is in flight
-  Descent<NP> B;
-  uint64_t xB[NP];
-  bool liveB[NP], validB[NP];
-  bool hasB = false;
-  int64_t tileB = 0;
-  TileRef TB, TA;
-  for (int64_t tile = first;; tile += nwaves) {
-    const bool hasA = tile < ntiles;  // wave-uniform
-    if (!hasA && !hasB) break;
-    Descent<NP> A;
-    bool liveA[NP], validA[NP];
-    if (hasA) {
-      TA = tnext;
-      const bool more = tile + nwaves < ntiles;
-      if (more) tnext = tile_ref<BATCHED, NP>(P, tile + nwaves);
-      uint32_t face[NP];
-#pragma unroll
-      for (int p = 0; p < NP; p++) {
-        const int64_t k = p * 64 + lane;
-        liveA[p] = k < TA.n;
-        const double lat = nxt[p].x, lng = nxt[p].y;
-        if (more && k < tnext.n) nxt[p] = load_point(tnext.pts + k);
-        face[p] = A.ci[p] = A.cj[p] = 0;
-        validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
-      }
-      descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, validA, A, c_reads);
-    }
-    if (hasB) {
-      take_level<NP>(B, xB, c_reads);
-      descend_rest<NP>(P, B, c_reads);
-      finish_tile<EXACT, COUNT, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c);
-    }
-    if (hasA) {
-      B = A;
-      TB = TA;
-#pragma unroll
-      for (int p = 0; p < NP; p++) {
-        liveB[p] = liveA[p];
-        validB[p] = validA[p];
-      }
-      issue_level<NP>(P, B, xB);
-    }
-    hasB = hasA;
-    tileB = tile;
-  }
-  if (COUNT) {
-    unsigned long long *C = P.counters;
-    atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c[0]);
-    atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c[1]);
-    atomicAdd(C + ACT_CNT_FALSE_HIT, (unsigned long long)c[2]);
-    atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c[3]);
-    atomicAdd(C + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
-    atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c[4]);
-  }
-}
-
 // References of a pending point's cell: true ids first, then candidates
 // (each with its cell-local record offset when the list carries one).
 struct RefList {
@@ -755,15 +609,9 @@ __device__ __forceinline__ bool local_covers_dev(const uint32_t *rec, double px,
   return par != 0;
 }
 
-// The pending point's references: from the list offset the probe left in
-// out[], or by repeating the lookup (inline entries).
-__device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t code, double lat,
-                                                double lng, uint32_t &reads) {
-  if (code <= -3) return lut_refs(P, (uint32_t)(-3 - code));
-  uint32_t face, ci, cj;
-  uint64_t e = 0;
-  if (project(P.trig, lat, lng, face, ci, cj))
-    e = lookup<0>(P, nullptr, P.faces[face], ci, cj, reads);
+// The references of a cell entry (a lookup-table list, or one or two inline
+// references, interior ones first).
+__device__ __forceinline__ RefList entry_refs(const ProbeParams &P, uint64_t e) {
   const uint32_t tag = (uint32_t)(e & kTagMask);
   if (e == 0 || tag == kTagPtr) return RefList();
   if (tag == kTagLut) return lut_refs(P, (uint32_t)(e >> 2));
@@ -781,6 +629,18 @@ __device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t co
   L.nt = (v0 & 1u) + (n > 1 ? (v1 & 1u) : 0u);
   L.nc = (uint32_t)n - L.nt;
   return L;
+}
+
+// The pending point's references in a two-pass join: from the list offset
+// the probe left in out[], or by repeating the lookup (inline entries).
+__device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t code, double lat,
+                                                double lng, uint32_t &reads) {
+  if (code <= -3) return lut_refs(P, (uint32_t)(-3 - code));
+  uint32_t face, ci, cj;
+  uint64_t e = 0;
+  if (project(P.trig, lat, lng, face, ci, cj))
+    e = lookup<0>(P, nullptr, P.faces[face], ci, cj, reads);
+  return entry_refs(P, e);
 }
 
 // All edges of a polygon tested by one lane in fp64 (+ exact): used only
@@ -896,12 +756,62 @@ __device__ __forceinline__ PointRef point_ref(const ProbeParams &P, int64_t v) {
   return r;
 }
 
-// Resolve the pending points, block range by block range. LOCAL: each
-// thread decides its point's candidates from their cell-local records.
-// Otherwise (refinement over all of a polygon's edges) lanes gather their
-// points' candidates and the whole wave tests one (point, polygon) pair at a
-// time (lanes over edges, see wave_covers); in every round each lane with
-// work offers its next candidate.
+// A batched join's group is complete once its last pending point is (the
+// probe stores each group's tick when its tile finishes; a pending point
+// resolved later raises it).
+template <bool BATCHED>
+__device__ __forceinline__ void point_done(const ProbeParams &P, int64_t v) {
+  if (BATCHED && P.gticks)
+    atomicMax((unsigned long long *)P.gticks + (v >> 6), (unsigned long long)wall_clock64());
+}
+
+// Step 8 with cell-local refinement for one pending point v (an index of
+// the pass, or of a batched join's virtual space) whose cell code is
+// `code`: true references are hits, and each candidate is decided from its
+// cell-local record (all of the polygon's edges for a candidate without
+// one). Counters go to c: solely-true, candidate points, candidates, edges,
+// fp64 edges, exact edges, lookup-table reads.
+// `entry`: the cell's entry when the caller has it (fused probe), else the
+// code the probe left in out[] (two-pass join).
+template <bool COUNT, bool BATCHED, bool ENTRY>
+__device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, uint64_t entry,
+                                              uint32_t (&c)[7], uint32_t &c_reads) {
+  const PointRef R = point_ref<BATCHED>(P, v);
+  const double2 pt = *R.pt;
+  const RefList L = ENTRY ? entry_refs(P, entry)
+                          : pending_refs(P, (int32_t)(uint32_t)entry, pt.x, pt.y, c_reads);
+  Hits hits;
+  for (uint32_t r = 0; r < L.nt; r++) hits.add(P, R.gi, (int32_t)L.true_id(P, r));
+  for (uint32_t r = 0; r < L.nc; r++) {
+    const int32_t poly = (int32_t)L.cand_id(P, r);
+    const uint32_t loc = L.cand_loc(P, r);
+    bool cov;
+    if (loc != 0xffffffffu) {
+      cov = local_record_covers(P.local + loc, pt.y, pt.x);
+      if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+    } else {
+      cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
+      if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+    }
+    if (cov) hits.add(P, R.gi, poly);
+  }
+  *R.out = hits.best;
+  point_done<BATCHED>(P, v);
+  if (COUNT) {
+    c[0] += L.nc == 0 && L.nt > 0;
+    c[1] += L.nc > 0;
+    c[2] += L.nc;
+    c[6] += L.lut;
+  }
+}
+
+// The second pass of a two-pass exact join: resolve the pending points of
+// the mask, block range by block range. LOCAL: each thread decides its
+// point's candidates from their cell-local records. Otherwise (refinement
+// over all of a polygon's edges) lanes gather their points' candidates and
+// the whole wave tests one (point, polygon) pair at a time (lanes over
+// edges, see wave_covers); in every round each lane with work offers its
+// next candidate.
 template <bool LOCAL, bool COUNT, bool BATCHED>
 __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
                                                                  int64_t nwords_arg) {
@@ -913,33 +823,9 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
     PendingIter it = gather_pending(P, blk, nwords, s_list, s_wave);
     int64_t v = 0;
     if (LOCAL) {
-      while (it.next(s_list, v)) {
-        const PointRef R = point_ref<BATCHED>(P, v);
-        const double2 pt = *R.pt;
-        const RefList L = pending_refs(P, *R.out, pt.x, pt.y, c_reads);
-        Hits hits;
-        for (uint32_t r = 0; r < L.nt; r++) hits.add(P, R.gi, (int32_t)L.true_id(P, r));
-        for (uint32_t r = 0; r < L.nc; r++) {
-          const int32_t poly = (int32_t)L.cand_id(P, r);
-          const uint32_t loc = L.cand_loc(P, r);
-          bool cov;
-          if (loc != 0xffffffffu) {
-            cov = local_record_covers(P.local + loc, pt.y, pt.x);
-            if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
-          } else {
-            cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
-            if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
-          }
-          if (cov) hits.add(P, R.gi, poly);
-        }
-        *R.out = hits.best;
-        if (COUNT) {
-          c[0] += L.nc == 0 && L.nt > 0;
-          c[1] += L.nc > 0;
-          c[2] += L.nc;
-          c[6] += L.lut;
-        }
-      }
+      while (it.next(s_list, v))
+        resolve_point<COUNT, BATCHED, false>(P, v, (uint32_t)*point_ref<BATCHED>(P, v).out, c,
+                                             c_reads);
     } else {
       const int lane = threadIdx.x & 63;
       bool have = false, more = true;
@@ -997,6 +883,234 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
   }
   flush_counters<COUNT>(P, c);
   if (COUNT && c_reads) atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+}
+
+// ------------------------------------------------------------------ probe
+
+// Probe modes: approximate (every reference of a cell is a hit); exact,
+// leaving pending points in a mask for resolve_kernel; exact, with pending
+// points resolved by the probe's own waves (cell-local refinement).
+enum ProbeMode { kApprox = 0, kExactMask = 1, kExactFused = 2 };
+
+// A wave's queue of pending points (kExactFused). The probe appends each
+// finished tile's pending points; whenever 64 have gathered, the wave
+// resolves them, one per lane, so refinement runs on full waves and needs no
+// second pass over the points. Entries are ring slots (head + k) mod
+// kQueueCap holding a point's index and its cell entry.
+constexpr int kQueueCap = 256;
+
+struct PendingQueue {
+  int64_t *v;
+  uint64_t *e;
+  uint32_t head, count;  // wave-uniform
+};
+
+// Resolves the first n (<= 64) queued points, lane l taking entry l.
+template <bool COUNT, bool BATCHED>
+__device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &Q, uint32_t n,
+                                            int lane, uint32_t (&rc)[7], uint32_t &c_reads) {
+  const bool on = (uint32_t)lane < n;
+  int64_t v = 0;
+  uint64_t e = 0;
+  if (on) {
+    const uint32_t slot = (Q.head + (uint32_t)lane) & (kQueueCap - 1);
+    v = Q.v[slot];
+    e = Q.e[slot];
+  }
+  wave_sync();  // read before later appends reuse the slots
+  Q.head += n;
+  Q.count -= n;
+  if (on) resolve_point<COUNT, BATCHED, true>(P, v, e, rc, c_reads);
+}
+
+// Step 7-9 for the NP points of a lane in tile `tile` (points at T).
+template <int MODE, bool COUNT, int NP, bool BATCHED>
+__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, const TileRef &T,
+                                            int lane, const uint64_t (&e)[NP],
+                                            const bool (&live)[NP], const bool (&valid)[NP],
+                                            uint32_t (&c)[8], PendingQueue &Q, uint32_t (&rc)[7],
+                                            uint32_t &c_reads) {
+  bool pend[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int64_t k = p * 64 + lane;  // within the tile
+    const int64_t i = T.gi + k;       // caller's index (pair output)
+    if (COUNT) {
+      c[0] += live[p];
+      c[1] += live[p] && !valid[p];
+      c[2] += valid[p] && e[p] == 0;
+    }
+    // stage 3: the entry's references (Section III-E: one payload, two
+    // payloads or a lookup-table offset)
+    const uint32_t tag = (uint32_t)(e[p] & kTagMask);
+    const uint32_t r0 = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
+    const uint32_t r1 = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
+    const int n_inl = e[p] == 0 || tag == kTagLut ? 0 : (tag == kTagTwo ? 2 : 1);
+    const uint32_t off = (uint32_t)(e[p] >> 2);
+    if (MODE == kApprox) {
+      // approximate mode: every reference is reported
+      Hits hits;
+      if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
+      if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
+      if (tag == kTagLut) {
+        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
+        for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
+        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
+        if (COUNT) c[4]++;
+      }
+      if (COUNT) c[3] += e[p] != 0;
+      if (live[p]) store_out(T.out + k, hits.best);
+      pend[p] = false;
+    } else {
+      // exact mode: a point whose cell entry has candidate references or is
+      // a lookup-table list is pending. Its list offset goes to out[]; then
+      // either its bit goes to the pending mask (resolve_kernel finishes
+      // it) or the point joins the wave's queue.
+      const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
+      pend[p] = live[p] && (tag == kTagLut || cand_inl);
+      const uint64_t m = MODE == kExactFused ? ballot(pend[p]) : 0ull;
+      if (pend[p]) {
+        const int32_t code = tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending;
+        store_out(T.out + k, code);
+        if (MODE == kExactFused) {
+          const uint32_t slot = (Q.head + Q.count + (uint32_t)lane_rank(m)) & (kQueueCap - 1);
+          Q.v[slot] = tile * (64 * NP) + k;
+          Q.e[slot] = e[p];
+        }
+      } else {
+        Hits hits;
+        if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
+        if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
+        if (live[p]) store_out(T.out + k, hits.best);
+        if (COUNT) c[3] += e[p] != 0;
+      }
+      if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
+    }
+  }
+  if (MODE == kExactMask) {
+#pragma unroll
+    for (int p = 0; p < NP; p++) {
+      const uint64_t m = ballot(pend[p]);
+      // every group of the virtual space of a batched join has a word
+      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[tile * NP + p] = m;
+    }
+  }
+  if (MODE == kExactFused && Q.count >= 64) {
+    wave_sync();  // appended before they are read
+    do {
+      drain_queue<COUNT, BATCHED>(P, Q, 64, lane, rc, c_reads);
+    } while (Q.count >= 64);
+  }
+  if (P.gticks && lane < NP) P.gticks[tile * NP + lane] = wall_clock64();
+}
+
+// The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
+// per lane, at lane and lane + 64, ...), grid-stride, so all lanes of a
+// wave run the same number of iterations. The loop is a two-stage software
+// pipeline: while tile t is projected and descends the LDS-staged levels,
+// the first global node level of tile t - 1 (issued at the end of the
+// previous iteration) is in flight; then tile t - 1 finishes. The point
+// loads run one tile further ahead.
+// Waves per SIMD the compiler must make room for. Eight (two 1024-thread
+// blocks per CU: at most 64 VGPRs and few SGPRs) where the probe fits
+// without spilling in its loop: one point per lane, or the approximate
+// probe; the exact probe with two points per lane, and the probe that
+// resolves its own queue, keep their registers (one block per CU).
+template <int MODE, int NP>
+constexpr int kProbeWavesPerEU = MODE != kExactFused && (NP == 1 || MODE == kApprox) ? 8 : 1;
+
+template <int MODE, int LDS_DEPTH, bool COUNT, int NP, bool BATCHED>
+__global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void probe_kernel(
+    ProbeParams P) {
+  constexpr bool FUSED = MODE == kExactFused;
+  extern __shared__ uint32_t s_nodes[];
+  __shared__ FaceDev s_face[6];
+  __shared__ double2 s_trig[kTrigEntries];
+  __shared__ int64_t s_qv[FUSED ? kProbeWaves * kQueueCap : 1];
+  __shared__ uint64_t s_qe[FUSED ? kProbeWaves * kQueueCap : 1];
+  if (LDS_DEPTH > 0)
+    for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
+  if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
+  if (threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
+  uint32_t rc[7] = {0, 0, 0, 0, 0, 0, 0};  // resolve counters (kExactFused)
+  PendingQueue Q{s_qv + (FUSED ? wid * kQueueCap : 0), s_qe + (FUSED ? wid * kQueueCap : 0), 0u, 0u};
+  constexpr int TILE = 64 * NP;
+  const int64_t ntiles = BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE;
+  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
+  const int64_t first = (int64_t)blockIdx.x * kProbeWaves + wid;
+  double2 nxt[NP];
+  TileRef tnext;
+  if (first < ntiles) tnext = tile_ref<BATCHED, NP>(P, first);
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    const int64_t k = p * 64 + lane;
+    nxt[p] = (first < ntiles && k < tnext.n) ? load_point(tnext.pts + k) : make_double2(0.0, 0.0);
+  }
+  // stage B: the tile whose first global level is in flight
+  Descent<NP> B;
+  uint64_t xB[NP];
+  bool liveB[NP], validB[NP];
+  bool hasB = false;
+  int64_t tileB = 0;
+  TileRef TB, TA;
+  for (int64_t tile = first;; tile += nwaves) {
+    const bool hasA = tile < ntiles;  // wave-uniform
+    if (!hasA && !hasB) break;
+    Descent<NP> A;
+    bool liveA[NP], validA[NP];
+    if (hasA) {
+      TA = tnext;
+      const bool more = tile + nwaves < ntiles;
+      if (more) tnext = tile_ref<BATCHED, NP>(P, tile + nwaves);
+      uint32_t face[NP];
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        const int64_t k = p * 64 + lane;
+        liveA[p] = k < TA.n;
+        const double lat = nxt[p].x, lng = nxt[p].y;
+        if (more && k < tnext.n) nxt[p] = load_point(tnext.pts + k);
+        face[p] = A.ci[p] = A.cj[p] = 0;
+        validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
+      }
+      descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, validA, A, c_reads);
+    }
+    if (hasB) {
+      take_level<NP>(B, xB, c_reads);
+      descend_rest<NP>(P, B, c_reads);
+      finish_tile<MODE, COUNT, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
+                                            c_reads);
+    }
+    if (hasA) {
+      B = A;
+      TB = TA;
+#pragma unroll
+      for (int p = 0; p < NP; p++) {
+        liveB[p] = liveA[p];
+        validB[p] = validA[p];
+      }
+      issue_level<NP>(P, B, xB);
+    }
+    hasB = hasA;
+    tileB = tile;
+  }
+  if (FUSED && Q.count > 0) {
+    wave_sync();
+    drain_queue<COUNT, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
+  }
+  if (FUSED) flush_counters<COUNT>(P, rc);
+  if (COUNT) {
+    unsigned long long *C = P.counters;
+    atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c[0]);
+    atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c[1]);
+    atomicAdd(C + ACT_CNT_FALSE_HIT, (unsigned long long)c[2]);
+    atomicAdd(C + ACT_CNT_SOLELY_TRUE, (unsigned long long)c[3]);
+    atomicAdd(C + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+    atomicAdd(C + ACT_CNT_LUT_READS, (unsigned long long)c[4]);
+  }
 }
 
 // ---------------------------------------------------------------- batches
@@ -1113,35 +1227,41 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
 }
 
 using ProbeFn = void (*)(ProbeParams);
-template <bool EXACT, int LDS, bool COUNT>
+template <int MODE, int LDS, bool COUNT>
 static ProbeFn probe_np(int np) {
-  return np == 1 ? probe_kernel<EXACT, LDS, COUNT, 1, false> : probe_kernel<EXACT, LDS, COUNT, 2, false>;
+  return np == 1 ? probe_kernel<MODE, LDS, COUNT, 1, false> : probe_kernel<MODE, LDS, COUNT, 2, false>;
 }
 
-static ProbeFn probe_fn(bool exact, int lds_depth, bool count, int np) {
+template <int MODE>
+static ProbeFn probe_mode_fn(int lds_depth, bool count, int np) {
   using F = ProbeFn (*)(int);
-  static const F tab[2][3][2] = {
-      {{probe_np<false, 0, false>, probe_np<false, 0, true>},
-       {probe_np<false, 1, false>, probe_np<false, 1, true>},
-       {probe_np<false, 2, false>, probe_np<false, 2, true>}},
-      {{probe_np<true, 0, false>, probe_np<true, 0, true>},
-       {probe_np<true, 1, false>, probe_np<true, 1, true>},
-       {probe_np<true, 2, false>, probe_np<true, 2, true>}}};
-  return tab[exact][lds_depth][count](np);
+  static const F tab[3][2] = {{probe_np<MODE, 0, false>, probe_np<MODE, 0, true>},
+                              {probe_np<MODE, 1, false>, probe_np<MODE, 1, true>},
+                              {probe_np<MODE, 2, false>, probe_np<MODE, 2, true>}};
+  return tab[lds_depth][count](np);
+}
+
+static ProbeFn probe_fn(int mode, int lds_depth, bool count, int np) {
+  return mode == kApprox      ? probe_mode_fn<kApprox>(lds_depth, count, np)
+         : mode == kExactMask ? probe_mode_fn<kExactMask>(lds_depth, count, np)
+                              : probe_mode_fn<kExactFused>(lds_depth, count, np);
 }
 
 // Batched joins: no counters.
-template <bool EXACT, int LDS>
+template <int MODE, int LDS>
 static ProbeFn probe_batched_np(int np) {
-  return np == 1 ? probe_kernel<EXACT, LDS, false, 1, true> : probe_kernel<EXACT, LDS, false, 2, true>;
+  return np == 1 ? probe_kernel<MODE, LDS, false, 1, true> : probe_kernel<MODE, LDS, false, 2, true>;
 }
 
-static ProbeFn probe_batched_fn(bool exact, int lds_depth, int np) {
+static ProbeFn probe_batched_fn(int mode, int lds_depth, int np) {
   using F = ProbeFn (*)(int);
-  static const F tab[2][3] = {
-      {probe_batched_np<false, 0>, probe_batched_np<false, 1>, probe_batched_np<false, 2>},
-      {probe_batched_np<true, 0>, probe_batched_np<true, 1>, probe_batched_np<true, 2>}};
-  return tab[exact][lds_depth](np);
+  static const F tab[3][3] = {
+      {probe_batched_np<kApprox, 0>, probe_batched_np<kApprox, 1>, probe_batched_np<kApprox, 2>},
+      {probe_batched_np<kExactMask, 0>, probe_batched_np<kExactMask, 1>,
+       probe_batched_np<kExactMask, 2>},
+      {probe_batched_np<kExactFused, 0>, probe_batched_np<kExactFused, 1>,
+       probe_batched_np<kExactFused, 2>}};
+  return tab[mode][lds_depth](np);
 }
 
 // ------------------------------------------------------------------ host
@@ -1355,6 +1475,15 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
 }
 
+// Points per probe lane when a join leaves it to the index: the tuned value,
+// else 1 in exact mode and 2 in approximate mode. One point per lane keeps
+// the exact probe under 64 VGPRs, so two blocks share a CU; the approximate
+// probe fits there with two.
+static int launch_np(const act_index *x) {
+  const int np = x->launch.points_per_lane;
+  return np > 0 ? np : (x->host.mode == ACT_EXACT ? 1 : 2);
+}
+
 static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
   if (!a) return fail(ACT_E_ARG, "args is NULL");
@@ -1371,6 +1500,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (a->pass_points < 0) return fail(ACT_E_ARG, "pass_points < 0");
   if (a->points_per_lane < 0 || a->points_per_lane > 2)
     return fail(ACT_E_ARG, "points_per_lane must be 0, 1 or 2");
+  if (a->pending < ACT_PENDING_AUTO || a->pending > ACT_PENDING_QUEUE)
+    return fail(ACT_E_ARG, "unknown pending mode");
   const HostIndex &h = x->host;
   const act_launch &L = x->launch;
   const int lds_req = a->lds_levels >= 0 ? a->lds_levels : L.lds_levels;
@@ -1392,19 +1523,25 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   P.n_pairs = a->d_n_pairs;
   P.counters = (unsigned long long *)a->d_counters;
   index_params(x, a->refine == ACT_REFINE_AUTO ? L.refine : a->refine, n_lds, P);
-  const int np = a->points_per_lane > 0 ? a->points_per_lane : L.points_per_lane;
+  const int np = a->points_per_lane > 0 ? a->points_per_lane : launch_np(x);
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
   const bool count = a->d_counters != nullptr;
+  // exact joins with cell-local refinement may resolve inside the probe;
+  // the other refinement modes always use the resolve kernel
+  const int pending = a->pending != ACT_PENDING_AUTO ? a->pending : L.pending;
+  const int mode = !exact ? kApprox
+                   : (P.refine == ACT_REFINE_LOCAL && pending == ACT_PENDING_QUEUE) ? kExactFused
+                                                                                    : kExactMask;
   int64_t pass = a->n;
-  if (exact) {
+  if (mode == kExactMask) {
     Workspace *w = nullptr;
     rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
     if (rc) return rc;
     P.mask = w->mask;
     pass = a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap;
   }
-  const ProbeFn probe = probe_fn(exact, depth, count, np);
+  const ProbeFn probe = probe_fn(mode, depth, count, np);
   using ResolveFn = void (*)(ProbeParams, int64_t);
   const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
                               ? (count ? resolve_kernel<true, true, false> : resolve_kernel<true, false, false>)
@@ -1424,7 +1561,7 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
-    if (!exact) continue;
+    if (mode != kExactMask) continue;
     const int64_t nwords = (n + 63) / 64;
     const int64_t ranges = (nwords + kRangeWords - 1) / kRangeWords;
     hipLaunchKernelGGL(resolve, dim3((unsigned)std::min<int64_t>(ranges, 65535)),
@@ -1464,15 +1601,16 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
                      w->vhdr, w->group_batch);
   ProbeParams P{};
   index_params(x, ACT_REFINE_LOCAL, n_lds, P);  // batched: cell-local refinement
-  P.mask = w->bmask;
   P.batches = d_batches;
   P.group_batch = w->group_batch;
   P.vstart = w->vstart;
   P.vhdr = w->vhdr;
   P.gticks = d_ticks ? w->gticks : nullptr;
-  hipLaunchKernelGGL(probe_batched_fn(exact, depth, L.points_per_lane), dim3(L.grid), dim3(kProbeBlock),
+  const int mode = !exact ? kApprox : (L.pending == ACT_PENDING_QUEUE ? kExactFused : kExactMask);
+  if (mode == kExactMask) P.mask = w->bmask;
+  hipLaunchKernelGGL(probe_batched_fn(mode, depth, launch_np(x)), dim3(L.grid), dim3(kProbeBlock),
                      (size_t)n_lds * 1024, st, P);
-  if (exact) {
+  if (mode == kExactMask) {
     void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
     hipLaunchKernelGGL(resolve, dim3(2048), dim3(kResolveBlock), 0, st, P, (int64_t)0);
   }
@@ -1516,14 +1654,15 @@ static bool cache_lookup(const char *path, uint64_t key, act_launch &L) {
   if (!f) return false;
   char arch[64];
   unsigned long long k;
-  int g, lds, np, rf;
+  int g, lds, np, rf, pd;
   bool hit = false;
-  while (std::fscanf(f, "%llx %63s %d %d %d %d", &k, arch, &g, &lds, &np, &rf) == 6)
+  while (std::fscanf(f, "%llx %63s %d %d %d %d %d", &k, arch, &g, &lds, &np, &rf, &pd) == 7)
     if (k == key && std::strcmp(arch, "gfx950") == 0) {
       L.grid = g;
       L.lds_levels = lds;
       L.points_per_lane = np;
       L.refine = rf;
+      L.pending = pd;
       hit = true;
     }
   std::fclose(f);
@@ -1534,8 +1673,8 @@ static void cache_store(const char *path, uint64_t key, const act_launch &L) {
   if (!path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%016llx gfx950 %d %d %d %d\n", (unsigned long long)key, L.grid, L.lds_levels,
-               L.points_per_lane, L.refine);
+  std::fprintf(f, "%016llx gfx950 %d %d %d %d %d\n", (unsigned long long)key, L.grid,
+               L.lds_levels, L.points_per_lane, L.refine, L.pending);
   std::fclose(f);
 }
 
@@ -1567,6 +1706,7 @@ static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d
       a.grid = L.grid;
       a.lds_levels = L.lds_levels;
       a.points_per_lane = L.points_per_lane;
+      a.pending = L.pending;
       int r = join_impl(x, &a, stream);  // warm
       if (r) return r;
       float t[3];
@@ -1582,7 +1722,8 @@ static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d
       ms = t[1];
       return ACT_OK;
     };
-    const act_launch defaults;
+    act_launch defaults;
+    defaults.points_per_lane = x->host.mode == ACT_EXACT ? 1 : 2;
     const act_launch saved = x->launch;
     x->launch = defaults;
     float ms;
@@ -1596,19 +1737,23 @@ static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d
       for (int lds = 0; lds <= 2 && !rc; lds++) {
         if (lds > 0 && lds_nodes_for(x->host, lds) < 0) continue;
         for (int np = 1; np <= 2 && !rc; np++)
-          for (int rf = ACT_REFINE_LOCAL; rf <= (exact ? ACT_REFINE_FP32_FILTER : ACT_REFINE_LOCAL) && !rc; rf++) {
-            act_launch L;
-            L.grid = grids[gi];
-            L.lds_levels = lds;
-            L.points_per_lane = np;
-            L.refine = rf;
-            rc = time_cfg(L, ms);
-            res->n_configs++;
-            if (!rc && ms < res->best_ms) {
-              res->best_ms = ms;
-              best = L;
+          for (int rf = ACT_REFINE_LOCAL; rf <= (exact ? ACT_REFINE_FP32_FILTER : ACT_REFINE_LOCAL) && !rc; rf++)
+            for (int pd = ACT_PENDING_KERNEL;
+                 pd <= (exact && rf == ACT_REFINE_LOCAL ? ACT_PENDING_QUEUE : ACT_PENDING_KERNEL) && !rc;
+                 pd++) {
+              act_launch L;
+              L.grid = grids[gi];
+              L.lds_levels = lds;
+              L.points_per_lane = np;
+              L.refine = rf;
+              L.pending = pd;
+              rc = time_cfg(L, ms);
+              res->n_configs++;
+              if (!rc && ms < res->best_ms) {
+                res->best_ms = ms;
+                best = L;
+              }
             }
-          }
       }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1623,6 +1768,7 @@ static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d
   res->lds_levels = best.lds_levels;
   res->points_per_lane = best.points_per_lane;
   res->refine = best.refine;
+  res->pending = best.pending;
   res->index_digest = key;
   return ACT_OK;
 }

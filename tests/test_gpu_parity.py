@@ -122,12 +122,16 @@ def test_c1_exact_edge_cases(act):
 REFINE_MODES = ["ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64"]
 
 
-@pytest.mark.parametrize("mode", REFINE_MODES)
-def test_c1_refine_modes_exact(act, mode):
-    """Every refinement mode gives the oracle's result, edge cases included."""
+@pytest.mark.parametrize("mode,pending", [("ACT_REFINE_LOCAL", "ACT_PENDING_QUEUE"),
+                                          ("ACT_REFINE_LOCAL", "ACT_PENDING_KERNEL"),
+                                          ("ACT_REFINE_FP32_FILTER", "ACT_PENDING_AUTO"),
+                                          ("ACT_REFINE_FP64", "ACT_PENDING_AUTO")])
+def test_c1_refine_modes_exact(act, mode, pending):
+    """Every refinement mode gives the oracle's result, edge cases included
+    (cell-local refinement inside the probe and in a second kernel)."""
     P, idx = index(act, "c1", "exact")
     pts = np.concatenate([synth.workload_points("c1"), edge_case_points(P, np.random.default_rng(4))])
-    out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+    out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode), pending=getattr(act, pending))
     assert_exact(P, pts, out, pairs, "c1-" + mode)
 
 
@@ -270,12 +274,14 @@ def overlapping_polygons(seed=12, n=9):
     return synth.Polygons.from_rings(polys)
 
 
-@pytest.mark.parametrize("pass_points,mode", [(0, "ACT_REFINE_LOCAL"), (1000, "ACT_REFINE_LOCAL"),
-                                              (4097, "ACT_REFINE_FP32_FILTER"),
-                                              (0, "ACT_REFINE_FP64")])
-def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode):
+@pytest.mark.parametrize("pass_points,mode,queue", [(0, "ACT_REFINE_LOCAL", True),
+                                                    (1000, "ACT_REFINE_LOCAL", False),
+                                                    (4097, "ACT_REFINE_FP32_FILTER", False),
+                                                    (0, "ACT_REFINE_FP64", False)])
+def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode, queue):
     """Exact parity where cells hold up to n references (long lookup-table
-    lists, several matches per point), in one pass and in many short passes
+    lists, several matches per point, most points pending), resolved inside
+    the probe, and by a second kernel in one pass and in many short passes
     (pair output then carries the pass offset)."""
     P = overlapping_polygons()
     idx = act.build(P, "exact", max_level=16)
@@ -285,7 +291,8 @@ def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode):
     pts = np.concatenate([
         np.stack([rng.uniform(40.68, 40.72, 200000), rng.uniform(-73.98, -73.92, 200000)], 1),
         P.verts])
-    kw = dict(pass_points=pass_points, refine=getattr(act, mode))
+    kw = dict(pass_points=pass_points, refine=getattr(act, mode),
+              pending=act.ACT_PENDING_QUEUE if queue else act.ACT_PENDING_KERNEL)
     out, pairs, ctr = gpu_join(idx, pts, counters=True, **kw)
     ref = assert_exact(P, pts, out, pairs, "overlap pass=%d %s" % (pass_points, mode))
     assert ref.cnt.max() >= 5
@@ -297,16 +304,34 @@ def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode):
 
 
 def test_workspace_reserve_and_passes(act):
-    """A reserved workspace smaller than the batch splits the join into
-    passes; results equal the single-pass join."""
+    """With pending points resolved by the second kernel, a reserved
+    workspace smaller than the batch splits the join into passes; results
+    equal the one-pass join and the join that resolves in the probe."""
     P, idx = index(act, "c2", "exact")
     pts = torch.from_numpy(synth.workload_points("c2", 0, 1_000_003)).cuda()
     one = idx.join(pts)
+    queued, _, _ = idx.join_ex(pts, pending=act.ACT_PENDING_QUEUE)
     idx2 = act.build(P, "exact")
     idx2.reserve(100_000)
-    many = idx2.join(pts)
+    many, _, _ = idx2.join_ex(pts, pending=act.ACT_PENDING_KERNEL)
     torch.cuda.synchronize()
-    assert torch.equal(one, many)
+    assert torch.equal(one, many) and torch.equal(one, queued)
+
+
+def test_pending_queue_and_kernel_agree(act):
+    """Pending points resolved inside the probe and by the resolve kernel:
+    identical outputs, pairs and counters, at both lane widths."""
+    P, idx = index(act, "c2", "exact")
+    pts = np.concatenate([synth.workload_points("c2", 0, 1_000_000),
+                          edge_case_points(P, np.random.default_rng(16))])
+    for npl in (1, 2):
+        o1, p1, c1 = gpu_join(idx, pts, counters=True, points_per_lane=npl,
+                              pending=act.ACT_PENDING_QUEUE)
+        o2, p2, c2 = gpu_join(idx, pts, counters=True, points_per_lane=npl,
+                              pending=act.ACT_PENDING_KERNEL)
+        assert np.array_equal(o1, o2) and np.array_equal(p1, p2)
+        assert c1 == c2, (c1, c2)
+        assert c1["cand_points"] > 1000
 
 
 def test_overlapping_polygons_approx(act):
