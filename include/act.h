@@ -217,8 +217,7 @@ typedef struct {
                               per probe + resolve pass, at most the
                               workspace's (0 = the workspace's)              */
   int32_t points_per_lane; /* points each probe lane carries per step: 1, 2
-                              (0 = the index's default: 1 in exact mode, 2 in
-                              approximate mode)                              */
+                              (0 = default 2)                                */
   int32_t pending;         /* exact mode with cell-local refinement: how
                               pending points are resolved, ACT_PENDING_*
                               (other refinement modes always use the

@@ -85,6 +85,9 @@ struct Workspace {
 };
 
 constexpr int64_t kDefaultPass = 1 << 24;
+// Points per probe launch at most: tile indices are 32-bit (2^31 tiles of
+// 64 points, plus the grid's waves, stay below 2^32).
+constexpr int64_t kMaxLaunchPoints = 1ll << 37;
 
 }  // namespace act
 
@@ -93,7 +96,7 @@ constexpr int64_t kDefaultPass = 1 << 24;
 struct act_launch {
   int32_t grid = 2048;
   int32_t lds_levels = -1;       // -1: deepest that fits
-  int32_t points_per_lane = 0;   // 0: 1 in exact mode, 2 in approximate mode
+  int32_t points_per_lane = 2;
   int32_t refine = ACT_REFINE_LOCAL;
   int32_t pending = ACT_PENDING_KERNEL;
 };
@@ -165,32 +168,38 @@ constexpr int kProbeWaves = kProbeBlock / 64;
 // 1e-9 degree margin. The pieces below are written for the argument ranges
 // that occur and cost far fewer instructions than general library routines.
 
-// Angles are split at the nearest whole degree b: x = b + d, |d| <= 1/2
+// Angles are split at the nearest whole degree b: x = b + u, |u| <= 1/2
 // degree. (cos b, sin b) come from a 361-entry table (b = -180 .. 180,
-// computed on the host with the C library), and sin d, cos d from short
-// Taylor series: the first omitted terms are below 4e-19 and 7e-16. The sum
-// formulas then give sin x and cos x to a few units of 1e-16, with no
+// computed on the host with the C library), and sin d, cos d (d = u pi/180)
+// from short Taylor series in u, the degree-to-radian factor folded into
+// the coefficients: the first omitted terms are below 8e-19 and 7e-16. The
+// sum formulas then give sin x and cos x to a few units of 1e-16, with no
 // quadrant logic. x - b is exact (Sterbenz's lemma, or b = 0).
 constexpr int kTrigEntries = 361;
+constexpr double kRad = 0.017453292519943295;  // pi / 180
+constexpr double kSin3 = -kRad * kRad * kRad / 6.0;
+constexpr double kSin5 = kRad * kRad * kRad * kRad * kRad / 120.0;
+constexpr double kCos2 = -kRad * kRad / 2.0;
+constexpr double kCos4 = kRad * kRad * kRad * kRad / 24.0;
 
 __device__ __forceinline__ void sincos_deg(const double2 *trig, double x, double &s, double &c) {
   const double b = rint(x);
   const double2 t = trig[(int)b + 180];  // (cos b, sin b)
-  const double d = (x - b) * 0.017453292519943295;
-  const double d2 = d * d;
-  const double sd = fma(d * d2, fma(d2, 1.0 / 120.0, -1.0 / 6.0), d);
-  const double cd = fma(d2, fma(d2, 1.0 / 24.0, -0.5), 1.0);
+  const double u = x - b;
+  const double u2 = u * u;
+  const double sd = u * fma(u2, fma(u2, kSin5, kSin3), kRad);
+  const double cd = fma(u2, fma(u2, kCos4, kCos2), 1.0);
   s = fma(t.y, cd, t.x * sd);
   c = fma(t.x, cd, -(t.y * sd));
 }
 
-// 1 / a for a in [1/sqrt(3), 1]: hardware estimate + two Newton steps.
+// 1 / a for a in [1/sqrt(3), 1]: hardware estimate + one Newton step. The
+// estimate's relative error was measured below 2^-24 over 2^24 inputs of
+// [0.5, 1], so the step leaves about 2^-48: the cell coordinates then err by
+// far less than the 1e-9 degree margin of the cell classification.
 __device__ __forceinline__ double rcp_nr(double a) {
-  double r = __builtin_amdgcn_rcp(a);
-  double e = fma(-a, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-a, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(a);
+  return fma(r, fma(-a, r, 1.0), r);
 }
 
 // Linear st transform of a face coordinate w = c / major, w in [-1, 1], as
@@ -291,7 +300,7 @@ __device__ __forceinline__ void wave_sync() {
 // the ray crosses it when the point lies left of the edge (orient > 0).
 // Strict comparisons of rounded values imply the same strict order of the
 // exact values; equal rounded values go to the exact test.
-template <bool COUNT>
+template <bool FULL>
 __device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e, float4 g,
                                                     float qx, float qy, float eta, double px,
                                                     double py, uint32_t &c_fp64,
@@ -302,19 +311,19 @@ __device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e,
     if (s != 0) return s > 0 ? 1 : 0;
   }
   const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
-  if (COUNT) {
+  if (FULL) {
     c_fp64++;
     if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
   }
   return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
 }
 
-template <bool COUNT>
+template <bool FULL>
 __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px, double py,
                                          uint32_t &c_fp64, uint32_t &c_exact) {
   const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
   if ((A.y > py && B.y > py) || (A.y < py && B.y < py)) return 0;
-  if (COUNT) {
+  if (FULL) {
     c_fp64++;
     if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
   }
@@ -326,7 +335,7 @@ __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px,
 // popcounts of the toggle ballots; any lane on an edge decides "covered".
 // The next chunk of edges is loaded while the current one is tested. Must be
 // called by all 64 lanes with wave-uniform arguments.
-template <bool COUNT>
+template <bool FULL>
 __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double lng, int lane,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
@@ -342,7 +351,7 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
       const int e = base + lane;
       const float4 g = nxt;
       if (e + 64 < e1) nxt = P.e32[e + 64];
-      const int r = e < e1 ? edge_fp32_then_exact<COUNT>(P, e, g, qx, qy, eta, px, py, c_fp64,
+      const int r = e < e1 ? edge_fp32_then_exact<FULL>(P, e, g, qx, qy, eta, px, py, c_fp64,
                                                          c_exact)
                            : 0;
       on |= ballot(r == 2) != 0;
@@ -351,7 +360,7 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
   } else {
     for (int base = e0; base < e1; base += 64) {
       const int e = base + lane;
-      const int r = e < e1 ? edge_fp64<COUNT>(P, e, px, py, c_fp64, c_exact) : 0;
+      const int r = e < e1 ? edge_fp64<FULL>(P, e, px, py, c_fp64, c_exact) : 0;
       on |= ballot(r == 2) != 0;
       par ^= (uint32_t)__popcll(ballot(r == 1));
     }
@@ -359,7 +368,10 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
   return on || (par & 1u) != 0;
 }
 
-// Lowest match goes to out[i]; every other match becomes a pair.
+// Lowest match goes to out[i]; every other match becomes a pair (PAIRS:
+// only kernels built with pair output emit them, so the lean kernels of
+// plain joins carry none of its registers).
+template <bool PAIRS>
 struct Hits {
   int32_t best = -1;
   __device__ __forceinline__ void add(const ProbeParams &P, int64_t i, int32_t poly) {
@@ -369,7 +381,7 @@ struct Hits {
     }
     const int32_t other = poly < best ? best : poly;
     best = poly < best ? poly : best;
-    if (P.pair_pt) {
+    if (PAIRS && P.pair_pt) {
       const unsigned long long k = atomicAdd((unsigned long long *)P.n_pairs, 1ull);
       if ((int64_t)k < P.cap) {
         P.pair_pt[k] = i;
@@ -519,37 +531,41 @@ __device__ __forceinline__ void store_out(int32_t *p, int32_t v) {
   __builtin_nontemporal_store(v, p);
 }
 
-// Where a tile's points live: its first point, its output, how many points
-// of the tile's 64 NP exist (may exceed 64 NP), and the caller's index of
-// its first point (pair output; single joins only). A single join's tiles
+// Where a tile's points live: its first point, its output, how many of
+// the tile's 64 NP points exist (0 .. 64 NP), and the caller's index of its
+// first point (pair output; single joins only). A single join's tiles
 // are consecutive; a batched join's tile lies inside one batch (batches
 // start at multiples of 128 virtual points).
 struct TileRef {
   const double2 *pts;
   int32_t *out;
-  int64_t n;
+  int32_t n;
   int64_t gi;
 };
 
+// Tile indices are 32-bit (a launch covers fewer than 2^32 tiles), so the
+// wave-uniform loop bookkeeping stays in scalar registers.
 template <bool BATCHED, int NP>
-__device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, int64_t tile) {
+__device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, uint32_t tile) {
   constexpr int TILE = 64 * NP;
   TileRef r;
+  int64_t rest;
   if (!BATCHED) {
-    const int64_t s = tile * TILE;
+    const int64_t s = (int64_t)tile * TILE;
     r.pts = P.pts + s;
     r.out = P.out + s;
-    r.n = P.n - s;
+    rest = P.n - s;
     r.gi = P.base + s;
   } else {
-    const int32_t b = P.group_batch[tile * NP];
-    const int64_t off = tile * TILE - P.vstart[b];
+    const int32_t b = P.group_batch[(int64_t)tile * NP];
+    const int64_t off = (int64_t)tile * TILE - P.vstart[b];
     const act_batch d = P.batches[b];
     r.pts = (const double2 *)d.d_points + off;
     r.out = d.d_out + off;
-    r.n = d.n - off;
+    rest = d.n - off;
     r.gi = -1;
   }
+  r.n = (int32_t)std::max<int64_t>(0, std::min<int64_t>(rest, TILE));
   return r;
 }
 
@@ -645,21 +661,21 @@ __device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t co
 
 // All edges of a polygon tested by one lane in fp64 (+ exact): used only
 // for a candidate without a cell-local record.
-template <bool COUNT>
+template <bool FULL>
 __device__ bool lane_covers(const ProbeParams &P, int poly, double lat, double lng,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   uint32_t par = 0;
   for (int e = P.eoff[poly]; e < P.eoff[poly + 1]; e++) {
-    const int r = edge_fp64<COUNT>(P, e, lng, lat, c_fp64, c_exact);
+    const int r = edge_fp64<FULL>(P, e, lng, lat, c_fp64, c_exact);
     if (r == 2) return true;
     par ^= (uint32_t)r;
   }
   return par != 0;
 }
 
-template <bool COUNT>
+template <bool FULL>
 __device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint32_t *c) {
-  if (!COUNT) return;
+  if (!FULL || !P.counters) return;
   static constexpr int ids[7] = {ACT_CNT_SOLELY_TRUE, ACT_CNT_CAND_POINTS, ACT_CNT_CANDIDATES,
                                  ACT_CNT_EDGES, ACT_CNT_EDGE_FP64, ACT_CNT_EDGE_EXACT,
                                  ACT_CNT_LUT_READS};
@@ -773,14 +789,14 @@ __device__ __forceinline__ void point_done(const ProbeParams &P, int64_t v) {
 // fp64 edges, exact edges, lookup-table reads.
 // `entry`: the cell's entry when the caller has it (fused probe), else the
 // code the probe left in out[] (two-pass join).
-template <bool COUNT, bool BATCHED, bool ENTRY>
+template <bool FULL, bool BATCHED, bool ENTRY>
 __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, uint64_t entry,
                                               uint32_t (&c)[7], uint32_t &c_reads) {
   const PointRef R = point_ref<BATCHED>(P, v);
   const double2 pt = *R.pt;
   const RefList L = ENTRY ? entry_refs(P, entry)
                           : pending_refs(P, (int32_t)(uint32_t)entry, pt.x, pt.y, c_reads);
-  Hits hits;
+  Hits<FULL> hits;
   for (uint32_t r = 0; r < L.nt; r++) hits.add(P, R.gi, (int32_t)L.true_id(P, r));
   for (uint32_t r = 0; r < L.nc; r++) {
     const int32_t poly = (int32_t)L.cand_id(P, r);
@@ -788,16 +804,16 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
     bool cov;
     if (loc != 0xffffffffu) {
       cov = local_record_covers(P.local + loc, pt.y, pt.x);
-      if (COUNT) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+      if (FULL) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
     } else {
-      cov = lane_covers<COUNT>(P, poly, pt.x, pt.y, c[4], c[5]);
-      if (COUNT) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+      cov = lane_covers<FULL>(P, poly, pt.x, pt.y, c[4], c[5]);
+      if (FULL) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
     }
     if (cov) hits.add(P, R.gi, poly);
   }
   *R.out = hits.best;
   point_done<BATCHED>(P, v);
-  if (COUNT) {
+  if (FULL) {
     c[0] += L.nc == 0 && L.nt > 0;
     c[1] += L.nc > 0;
     c[2] += L.nc;
@@ -812,7 +828,7 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
 // the whole wave tests one (point, polygon) pair at a time (lanes over
 // edges, see wave_covers); in every round each lane with work offers its
 // next candidate.
-template <bool LOCAL, bool COUNT, bool BATCHED>
+template <bool LOCAL, bool FULL, bool BATCHED>
 __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
                                                                  int64_t nwords_arg) {
   __shared__ uint16_t s_list[kListCap];
@@ -824,7 +840,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
     int64_t v = 0;
     if (LOCAL) {
       while (it.next(s_list, v))
-        resolve_point<COUNT, BATCHED, false>(P, v, (uint32_t)*point_ref<BATCHED>(P, v).out, c,
+        resolve_point<FULL, BATCHED, false>(P, v, (uint32_t)*point_ref<BATCHED>(P, v).out, c,
                                              c_reads);
     } else {
       const int lane = threadIdx.x & 63;
@@ -833,7 +849,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
       RefList L;
       PointRef R{nullptr, nullptr, 0};
       uint32_t r = 0;
-      Hits hits;
+      Hits<FULL> hits;
       for (;;) {
         if (!have && more) {
           more = it.next(s_list, v);
@@ -843,11 +859,11 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
             lat = pt.x;
             lng = pt.y;
             L = pending_refs(P, *R.out, lat, lng, c_reads);
-            hits = Hits();
+            hits = Hits<FULL>();
             for (uint32_t t = 0; t < L.nt; t++) hits.add(P, R.gi, (int32_t)L.true_id(P, t));
             r = 0;
             have = true;
-            if (COUNT) {
+            if (FULL) {
               c[0] += L.nc == 0 && L.nt > 0;
               c[1] += L.nc > 0;
               c[2] += L.nc;
@@ -870,8 +886,8 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
           todo &= todo - 1;
           const int32_t q = __shfl(poly, src);
           const double qlat = __shfl(lat, src), qlng = __shfl(lng, src);
-          if (COUNT && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
-          const bool cov = wave_covers<COUNT>(P, q, qlat, qlng, lane, c[4], c[5]);
+          if (FULL && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
+          const bool cov = wave_covers<FULL>(P, q, qlat, qlng, lane, c[4], c[5]);
           if (lane == src && cov) hits.add(P, R.gi, q);
         }
         if (have) r++;
@@ -881,8 +897,9 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
     if (P.gticks && threadIdx.x < kRangeWords && blk * kRangeWords + threadIdx.x < nwords)
       P.gticks[blk * kRangeWords + threadIdx.x] = wall_clock64();
   }
-  flush_counters<COUNT>(P, c);
-  if (COUNT && c_reads) atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+  flush_counters<FULL>(P, c);
+  if (FULL && c_reads && P.counters)
+    atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
 }
 
 // ------------------------------------------------------------------ probe
@@ -906,7 +923,7 @@ struct PendingQueue {
 };
 
 // Resolves the first n (<= 64) queued points, lane l taking entry l.
-template <bool COUNT, bool BATCHED>
+template <bool FULL, bool BATCHED>
 __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &Q, uint32_t n,
                                             int lane, uint32_t (&rc)[7], uint32_t &c_reads) {
   const bool on = (uint32_t)lane < n;
@@ -920,12 +937,12 @@ __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &
   wave_sync();  // read before later appends reuse the slots
   Q.head += n;
   Q.count -= n;
-  if (on) resolve_point<COUNT, BATCHED, true>(P, v, e, rc, c_reads);
+  if (on) resolve_point<FULL, BATCHED, true>(P, v, e, rc, c_reads);
 }
 
 // Step 7-9 for the NP points of a lane in tile `tile` (points at T).
-template <int MODE, bool COUNT, int NP, bool BATCHED>
-__device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, const TileRef &T,
+template <int MODE, bool FULL, int NP, bool BATCHED>
+__device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile, const TileRef &T,
                                             int lane, const uint64_t (&e)[NP],
                                             const bool (&live)[NP], const bool (&valid)[NP],
                                             uint32_t (&c)[8], PendingQueue &Q, uint32_t (&rc)[7],
@@ -933,9 +950,9 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
   bool pend[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    const int64_t k = p * 64 + lane;  // within the tile
-    const int64_t i = T.gi + k;       // caller's index (pair output)
-    if (COUNT) {
+    const int k = p * 64 + lane;  // within the tile
+    const int64_t i = T.gi + k;   // caller's index (pair output)
+    if (FULL) {
       c[0] += live[p];
       c[1] += live[p] && !valid[p];
       c[2] += valid[p] && e[p] == 0;
@@ -949,16 +966,25 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
     const uint32_t off = (uint32_t)(e[p] >> 2);
     if (MODE == kApprox) {
       // approximate mode: every reference is reported
-      Hits hits;
+      Hits<FULL> hits;
       if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
       if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
       if (tag == kTagLut) {
         const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
-        for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
-        for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
-        if (COUNT) c[4]++;
+        if (FULL && P.pair_pt) {
+          for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
+          for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
+        } else {
+          // each part of a list is sorted, so the lowest id heads a part
+          // (the device copy of the table is padded: the reads stay in
+          // bounds when a part is empty)
+          const uint32_t t0 = P.lut[off + 1], c0 = P.lut[off + 2 + nt];
+          if (nt) hits.add(P, i, (int32_t)t0);
+          if (nc) hits.add(P, i, (int32_t)c0);
+        }
+        if (FULL) c[4]++;
       }
-      if (COUNT) c[3] += e[p] != 0;
+      if (FULL) c[3] += e[p] != 0;
       if (live[p]) store_out(T.out + k, hits.best);
       pend[p] = false;
     } else {
@@ -974,15 +1000,15 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
         store_out(T.out + k, code);
         if (MODE == kExactFused) {
           const uint32_t slot = (Q.head + Q.count + (uint32_t)lane_rank(m)) & (kQueueCap - 1);
-          Q.v[slot] = tile * (64 * NP) + k;
+          Q.v[slot] = (int64_t)tile * (64 * NP) + k;
           Q.e[slot] = e[p];
         }
       } else {
-        Hits hits;
+        Hits<FULL> hits;
         if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
         if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
         if (live[p]) store_out(T.out + k, hits.best);
-        if (COUNT) c[3] += e[p] != 0;
+        if (FULL) c[3] += e[p] != 0;
       }
       if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
     }
@@ -992,16 +1018,16 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
     for (int p = 0; p < NP; p++) {
       const uint64_t m = ballot(pend[p]);
       // every group of the virtual space of a batched join has a word
-      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[tile * NP + p] = m;
+      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[(int64_t)tile * NP + p] = m;
     }
   }
   if (MODE == kExactFused && Q.count >= 64) {
     wave_sync();  // appended before they are read
     do {
-      drain_queue<COUNT, BATCHED>(P, Q, 64, lane, rc, c_reads);
+      drain_queue<FULL, BATCHED>(P, Q, 64, lane, rc, c_reads);
     } while (Q.count >= 64);
   }
-  if (P.gticks && lane < NP) P.gticks[tile * NP + lane] = wall_clock64();
+  if (P.gticks && lane < NP) P.gticks[(int64_t)tile * NP + lane] = wall_clock64();
 }
 
 // The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
@@ -1013,13 +1039,12 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, int64_t tile, 
 // loads run one tile further ahead.
 // Waves per SIMD the compiler must make room for. Eight (two 1024-thread
 // blocks per CU: at most 64 VGPRs and few SGPRs) where the probe fits
-// without spilling in its loop: one point per lane, or the approximate
-// probe; the exact probe with two points per lane, and the probe that
-// resolves its own queue, keep their registers (one block per CU).
+// without spilling in its loop; the probe that resolves its own queue keeps
+// its registers (one block per CU).
 template <int MODE, int NP>
-constexpr int kProbeWavesPerEU = MODE != kExactFused && (NP == 1 || MODE == kApprox) ? 8 : 1;
+constexpr int kProbeWavesPerEU = MODE != kExactFused ? 8 : 1;
 
-template <int MODE, int LDS_DEPTH, bool COUNT, int NP, bool BATCHED>
+template <int MODE, int LDS_DEPTH, bool FULL, int NP, bool BATCHED>
 __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void probe_kernel(
     ProbeParams P) {
   constexpr bool FUSED = MODE == kExactFused;
@@ -1039,15 +1064,15 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   uint32_t rc[7] = {0, 0, 0, 0, 0, 0, 0};  // resolve counters (kExactFused)
   PendingQueue Q{s_qv + (FUSED ? wid * kQueueCap : 0), s_qe + (FUSED ? wid * kQueueCap : 0), 0u, 0u};
   constexpr int TILE = 64 * NP;
-  const int64_t ntiles = BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE;
-  const int64_t nwaves = (int64_t)gridDim.x * kProbeWaves;
-  const int64_t first = (int64_t)blockIdx.x * kProbeWaves + wid;
+  const uint32_t ntiles = (uint32_t)(BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE);
+  const uint32_t nwaves = gridDim.x * kProbeWaves;
+  const uint32_t first = blockIdx.x * kProbeWaves + wid;
   double2 nxt[NP];
   TileRef tnext;
   if (first < ntiles) tnext = tile_ref<BATCHED, NP>(P, first);
 #pragma unroll
   for (int p = 0; p < NP; p++) {
-    const int64_t k = p * 64 + lane;
+    const int k = p * 64 + lane;
     nxt[p] = (first < ntiles && k < tnext.n) ? load_point(tnext.pts + k) : make_double2(0.0, 0.0);
   }
   // stage B: the tile whose first global level is in flight
@@ -1055,24 +1080,33 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   uint64_t xB[NP];
   bool liveB[NP], validB[NP];
   bool hasB = false;
-  int64_t tileB = 0;
+  uint32_t tileB = 0;
   TileRef TB, TA;
-  for (int64_t tile = first;; tile += nwaves) {
+  for (uint32_t tile = first;; tile += nwaves) {
     const bool hasA = tile < ntiles;  // wave-uniform
     if (!hasA && !hasB) break;
     Descent<NP> A;
     bool liveA[NP], validA[NP];
     if (hasA) {
       TA = tnext;
-      const bool more = tile + nwaves < ntiles;
+      const bool more = tile + nwaves < ntiles;  // no wrap: ntiles + nwaves < 2^32
       if (more) tnext = tile_ref<BATCHED, NP>(P, tile + nwaves);
+      // with one point per lane every lane loads (lanes past the end of
+      // the next tile its last point; after the wave's last tile, this tile
+      // again): the load is always issued, which keeps the compiler's
+      // waits for the node level in flight exact
+      const int kmax = max(tnext.n - 1, 0);
+      const double2 *src = tnext.n > 0 ? tnext.pts : TA.pts;
       uint32_t face[NP];
 #pragma unroll
       for (int p = 0; p < NP; p++) {
-        const int64_t k = p * 64 + lane;
+        const int k = p * 64 + lane;
         liveA[p] = k < TA.n;
         const double lat = nxt[p].x, lng = nxt[p].y;
-        if (more && k < tnext.n) nxt[p] = load_point(tnext.pts + k);
+        if (NP == 1)
+          nxt[p] = load_point(src + min(k, kmax));
+        else if (more && k < tnext.n)
+          nxt[p] = load_point(tnext.pts + k);
         face[p] = A.ci[p] = A.cj[p] = 0;
         validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
       }
@@ -1081,7 +1115,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     if (hasB) {
       take_level<NP>(B, xB, c_reads);
       descend_rest<NP>(P, B, c_reads);
-      finish_tile<MODE, COUNT, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
+      finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
                                             c_reads);
     }
     if (hasA) {
@@ -1099,10 +1133,10 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   }
   if (FUSED && Q.count > 0) {
     wave_sync();
-    drain_queue<COUNT, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
+    drain_queue<FULL, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
   }
-  if (FUSED) flush_counters<COUNT>(P, rc);
-  if (COUNT) {
+  if (FUSED) flush_counters<FULL>(P, rc);
+  if (FULL && P.counters) {
     unsigned long long *C = P.counters;
     atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c[0]);
     atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c[1]);
@@ -1227,9 +1261,9 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
 }
 
 using ProbeFn = void (*)(ProbeParams);
-template <int MODE, int LDS, bool COUNT>
+template <int MODE, int LDS, bool FULL>
 static ProbeFn probe_np(int np) {
-  return np == 1 ? probe_kernel<MODE, LDS, COUNT, 1, false> : probe_kernel<MODE, LDS, COUNT, 2, false>;
+  return np == 1 ? probe_kernel<MODE, LDS, FULL, 1, false> : probe_kernel<MODE, LDS, FULL, 2, false>;
 }
 
 template <int MODE>
@@ -1332,6 +1366,8 @@ static int get_batch_workspace(const act_index *x, void *stream, int32_t nb, int
   std::lock_guard<std::mutex> lk(x->ws_mu);
   Workspace &w = x->ws[stream];
   const int64_t groups = (points + 128 * (int64_t)nb) / 64 + 2;
+  if (groups * 64 > kMaxLaunchPoints)
+    return fail(ACT_E_RANGE, "batched join larger than 2^37 points (with padding)");
   if (w.cap_groups < groups || w.cap_batches < nb) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
@@ -1475,14 +1511,8 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
 }
 
-// Points per probe lane when a join leaves it to the index: the tuned value,
-// else 1 in exact mode and 2 in approximate mode. One point per lane keeps
-// the exact probe under 64 VGPRs, so two blocks share a CU; the approximate
-// probe fits there with two.
-static int launch_np(const act_index *x) {
-  const int np = x->launch.points_per_lane;
-  return np > 0 ? np : (x->host.mode == ACT_EXACT ? 1 : 2);
-}
+// Points per probe lane when a join leaves it to the index.
+static int launch_np(const act_index *x) { return x->launch.points_per_lane; }
 
 static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
@@ -1526,20 +1556,22 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   const int np = a->points_per_lane > 0 ? a->points_per_lane : launch_np(x);
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
-  const bool count = a->d_counters != nullptr;
+  // counters or pair output: the full kernels (plain joins run lean ones)
+  const bool count = a->d_counters != nullptr || pairs;
   // exact joins with cell-local refinement may resolve inside the probe;
   // the other refinement modes always use the resolve kernel
   const int pending = a->pending != ACT_PENDING_AUTO ? a->pending : L.pending;
   const int mode = !exact ? kApprox
                    : (P.refine == ACT_REFINE_LOCAL && pending == ACT_PENDING_QUEUE) ? kExactFused
                                                                                     : kExactMask;
-  int64_t pass = a->n;
+  int64_t pass = std::min(a->n, kMaxLaunchPoints);
   if (mode == kExactMask) {
     Workspace *w = nullptr;
     rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
     if (rc) return rc;
     P.mask = w->mask;
-    pass = a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap;
+    pass = std::min(a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap,
+                    kMaxLaunchPoints);
   }
   const ProbeFn probe = probe_fn(mode, depth, count, np);
   using ResolveFn = void (*)(ProbeParams, int64_t);
@@ -1722,8 +1754,7 @@ static int tune_impl(act_index *x, const double *d_sample, int64_t n, int32_t *d
       ms = t[1];
       return ACT_OK;
     };
-    act_launch defaults;
-    defaults.points_per_lane = x->host.mode == ACT_EXACT ? 1 : 2;
+    const act_launch defaults;
     const act_launch saved = x->launch;
     x->launch = defaults;
     float ms;
