@@ -211,7 +211,7 @@ typedef struct {
   int32_t lds_levels;      /* top trie node levels staged in LDS: 0, 1, 2, or
                               -1 for the default (deepest that fits 64 KiB
                               of 32-bit entries)                             */
-  int32_t grid;            /* probe blocks launched (0 = default 2048); each
+  int32_t grid;            /* probe blocks launched (0 = default 1024); each
                               wave walks tiles of 64 points grid-stride      */
   int64_t pass_points;     /* exact joins with ACT_PENDING_KERNEL: points
                               per probe + resolve pass, at most the

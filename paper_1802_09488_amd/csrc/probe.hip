@@ -68,6 +68,7 @@ struct DevImage {
   double2 *trig = nullptr;
   struct FaceDev *faces = nullptr;
   uint32_t *top32 = nullptr;
+  uint64_t *sink = nullptr;  // 64 bytes that the probe's idle lanes store to
   size_t bytes = 0;
 };
 
@@ -94,7 +95,7 @@ constexpr int64_t kMaxLaunchPoints = 1ll << 37;
 // Launch configuration used when a join leaves a knob at its default
 // (set by act_tune; the built-in defaults otherwise).
 struct act_launch {
-  int32_t grid = 2048;
+  int32_t grid = 1024;
   int32_t lds_levels = -1;       // -1: deepest that fits
   int32_t points_per_lane = 2;
   int32_t refine = ACT_REFINE_LOCAL;
@@ -145,6 +146,7 @@ struct ProbeParams {
   const uint32_t *local;  // exact mode: base of the cell-local records (the LUT)
   uint64_t *mask;         // exact mode: pending points of this pass, bit per point
   int64_t base;           // index of pts[0] in the caller's array (pair output)
+  uint64_t *sink;         // target of the stores of lanes without a point
   // batched joins: the batches laid end to end in a virtual point space,
   // each starting at a multiple of 128 points
   const act_batch *batches;
@@ -985,7 +987,9 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         if (FULL) c[4]++;
       }
       if (FULL) c[3] += e[p] != 0;
-      if (live[p]) store_out(T.out + k, hits.best);
+      // every lane stores (lanes without a point to the sink), so the
+      // store is always issued and the compiler's waits stay exact
+      store_out(live[p] ? T.out + k : (int32_t *)P.sink, hits.best);
       pend[p] = false;
     } else {
       // exact mode: a point whose cell entry has candidate references or is
@@ -995,9 +999,9 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
       const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
       pend[p] = live[p] && (tag == kTagLut || cand_inl);
       const uint64_t m = MODE == kExactFused ? ballot(pend[p]) : 0ull;
+      int32_t v;
       if (pend[p]) {
-        const int32_t code = tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending;
-        store_out(T.out + k, code);
+        v = tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending;
         if (MODE == kExactFused) {
           const uint32_t slot = (Q.head + Q.count + (uint32_t)lane_rank(m)) & (kQueueCap - 1);
           Q.v[slot] = (int64_t)tile * (64 * NP) + k;
@@ -1007,9 +1011,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         Hits<FULL> hits;
         if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
         if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
-        if (live[p]) store_out(T.out + k, hits.best);
+        v = hits.best;
         if (FULL) c[3] += e[p] != 0;
       }
+      // one store from every lane (lanes without a point to the sink)
+      store_out(live[p] ? T.out + k : (int32_t *)P.sink, v);
       if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
     }
   }
@@ -1017,8 +1023,10 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
 #pragma unroll
     for (int p = 0; p < NP; p++) {
       const uint64_t m = ballot(pend[p]);
-      // every group of the virtual space of a batched join has a word
-      if (lane == 0 && (BATCHED || p * 64 < T.n)) P.mask[(int64_t)tile * NP + p] = m;
+      // every lane stores the word (the same value), a word past the pass
+      // to the sink; every group of a batched join's virtual space has one
+      uint64_t *word = BATCHED || p * 64 < T.n ? P.mask + (int64_t)tile * NP + p : P.sink + 1;
+      *word = m;
     }
   }
   if (MODE == kExactFused && Q.count >= 64) {
@@ -1028,6 +1036,42 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
     } while (Q.count >= 64);
   }
   if (P.gticks && lane < NP) P.gticks[(int64_t)tile * NP + lane] = wall_clock64();
+}
+
+// Loads the points of tile T into v. Every lane loads, so the load is
+// always issued: lanes past the tile's end load its last point. A batched
+// join's padding tile has no points: it loads those of `alt` instead, or
+// nothing when `alt` has none either (a single join's tiles all have
+// points, and `alt` is then a tile of the same join).
+template <bool BATCHED, int NP>
+__device__ __forceinline__ void load_tile(const TileRef &T, const TileRef &alt, int lane,
+                                          double2 (&v)[NP]) {
+  const TileRef &S = T.n > 0 ? T : alt;
+  if (BATCHED && S.n <= 0) {
+#pragma unroll
+    for (int p = 0; p < NP; p++) v[p] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int kmax = S.n - 1;
+#pragma unroll
+  for (int p = 0; p < NP; p++) v[p] = load_point(S.pts + min(p * 64 + lane, kmax));
+}
+
+// Steps 2-5 and the LDS-staged part of step 6 for the points of tile T.
+template <int LDS_DEPTH, int NP>
+__device__ __forceinline__ void project_tile(const double2 *s_trig, const uint32_t *s_nodes,
+                                             const FaceDev *s_face, const TileRef &T, int lane,
+                                             const double2 (&pts)[NP], Descent<NP> &D,
+                                             bool (&live)[NP], bool (&valid)[NP],
+                                             uint32_t &c_reads) {
+  uint32_t face[NP];
+#pragma unroll
+  for (int p = 0; p < NP; p++) {
+    live[p] = p * 64 + lane < T.n;
+    face[p] = D.ci[p] = D.cj[p] = 0;
+    valid[p] = live[p] && project(s_trig, pts[p].x, pts[p].y, face[p], D.ci[p], D.cj[p]);
+  }
+  descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, valid, D, c_reads);
 }
 
 // The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
@@ -1067,60 +1111,45 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   const uint32_t ntiles = (uint32_t)(BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE);
   const uint32_t nwaves = gridDim.x * kProbeWaves;
   const uint32_t first = blockIdx.x * kProbeWaves + wid;
-  double2 nxt[NP];
-  TileRef tnext;
-  if (first < ntiles) tnext = tile_ref<BATCHED, NP>(P, first);
-#pragma unroll
-  for (int p = 0; p < NP; p++) {
-    const int k = p * 64 + lane;
-    nxt[p] = (first < ntiles && k < tnext.n) ? load_point(tnext.pts + k) : make_double2(0.0, 0.0);
-  }
-  // stage B: the tile whose first global level is in flight
-  Descent<NP> B;
-  uint64_t xB[NP];
-  bool liveB[NP], validB[NP];
-  bool hasB = false;
-  uint32_t tileB = 0;
-  TileRef TB, TA;
-  for (uint32_t tile = first;; tile += nwaves) {
-    const bool hasA = tile < ntiles;  // wave-uniform
-    if (!hasA && !hasB) break;
-    Descent<NP> A;
-    bool liveA[NP], validA[NP];
-    if (hasA) {
-      TA = tnext;
-      const bool more = tile + nwaves < ntiles;  // no wrap: ntiles + nwaves < 2^32
-      if (more) tnext = tile_ref<BATCHED, NP>(P, tile + nwaves);
-      // with one point per lane every lane loads (lanes past the end of
-      // the next tile its last point; after the wave's last tile, this tile
-      // again): the load is always issued, which keeps the compiler's
-      // waits for the node level in flight exact
-      const int kmax = max(tnext.n - 1, 0);
-      const double2 *src = tnext.n > 0 ? tnext.pts : TA.pts;
-      uint32_t face[NP];
-#pragma unroll
-      for (int p = 0; p < NP; p++) {
-        const int k = p * 64 + lane;
-        liveA[p] = k < TA.n;
-        const double lat = nxt[p].x, lng = nxt[p].y;
-        if (NP == 1)
-          nxt[p] = load_point(src + min(k, kmax));
-        else if (more && k < tnext.n)
-          nxt[p] = load_point(tnext.pts + k);
-        face[p] = A.ci[p] = A.cj[p] = 0;
-        validA[p] = liveA[p] && project(s_trig, lat, lng, face[p], A.ci[p], A.cj[p]);
-      }
-      descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, validA, A, c_reads);
+  if (first < ntiles) {
+    // stage B: the tile whose first global level is in flight; nxt: the
+    // points of the tile after the one being projected
+    Descent<NP> B;
+    uint64_t xB[NP];
+    bool liveB[NP], validB[NP];
+    TileRef TB = tile_ref<BATCHED, NP>(P, first), TN;
+    uint32_t tileB = first;
+    double2 nxt[NP];
+    {  // prologue: the wave's first tile
+      double2 cur[NP];
+      load_tile<BATCHED, NP>(TB, TB, lane, cur);
+      TN = first + nwaves < ntiles ? tile_ref<BATCHED, NP>(P, first + nwaves) : TB;
+      load_tile<BATCHED, NP>(TN, TB, lane, nxt);
+      project_tile<LDS_DEPTH, NP>(s_trig, s_nodes, s_face, TB, lane, cur, B, liveB, validB,
+                                  c_reads);
+      issue_level<NP>(P, B, xB);
     }
-    if (hasB) {
+    // steady state: no wave-uniform branches around memory operations, so
+    // the compiler's waits for the node level in flight and for the next
+    // tile's points stay exact
+    for (uint32_t tile = first + nwaves; tile < ntiles; tile += nwaves) {
+      const TileRef TA = TN;
+      TN = tile + nwaves < ntiles ? tile_ref<BATCHED, NP>(P, tile + nwaves) : TA;
+      double2 cur[NP];
+#pragma unroll
+      for (int p = 0; p < NP; p++) cur[p] = nxt[p];
+      load_tile<BATCHED, NP>(TN, TA, lane, nxt);
+      Descent<NP> A;
+      bool liveA[NP], validA[NP];
+      project_tile<LDS_DEPTH, NP>(s_trig, s_nodes, s_face, TA, lane, cur, A, liveA, validA,
+                                  c_reads);
       take_level<NP>(B, xB, c_reads);
       descend_rest<NP>(P, B, c_reads);
       finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
                                             c_reads);
-    }
-    if (hasA) {
       B = A;
       TB = TA;
+      tileB = tile;
 #pragma unroll
       for (int p = 0; p < NP; p++) {
         liveB[p] = liveA[p];
@@ -1128,8 +1157,11 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
       }
       issue_level<NP>(P, B, xB);
     }
-    hasB = hasA;
-    tileB = tile;
+    // epilogue: the wave's last tile
+    take_level<NP>(B, xB, c_reads);
+    descend_rest<NP>(P, B, c_reads);
+    finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
+                                          c_reads);
   }
   if (FUSED && Q.count > 0) {
     wave_sync();
@@ -1319,7 +1351,7 @@ struct DeviceGuard {
 
 static void free_image(DevImage &d) {
   void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
-                  d.e64,   d.trig,  d.faces, d.top32};
+                  d.e64,   d.trig,  d.faces, d.top32, d.sink};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -1459,6 +1491,8 @@ static int upload_image(act_index *x) {
   std::vector<uint32_t> top(n_top);
   for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
   if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
+  const uint64_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if ((rc = upload(d.sink, zeros, sizeof zeros, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -1509,6 +1543,7 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.n_lds_nodes = n_lds;
   P.refine = refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : refine;
   P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
+  P.sink = x->dev.sink;
 }
 
 // Points per probe lane when a join leaves it to the index.
