@@ -303,6 +303,32 @@ def test_overlapping_polygons_long_candidate_lists(act, pass_points, mode, queue
     assert np.array_equal(np.unique(pairs2, axis=0), np.unique(pairs, axis=0))
 
 
+@pytest.mark.parametrize("mode", ["exact", "approx"])
+def test_small_and_ragged_lengths(act, mode):
+    """Joins whose length leaves waves with no tile, one tile, or a ragged
+    last tile (lanes without a point), at both lane widths and at grids that
+    give every wave many tiles or none, through the lean kernels (plain
+    joins) and the full ones (pairs): every out equals the same points'
+    share of the reference (the oracle in exact mode, the full kernel's
+    large join, checked against the oracle elsewhere, in approximate mode)."""
+    P, idx = index(act, "c2", mode, 0.0 if mode == "exact" else 4.0)
+    pts = np.concatenate([synth.workload_points("c2", 0, 70_000),
+                          edge_case_points(P, np.random.default_rng(18))[:5000]])
+    full, full_pairs, _ = gpu_join(idx, pts)
+    if mode == "exact":
+        assert np.array_equal(full, oracle.join(P, pts).out)
+    t = torch.from_numpy(pts).cuda()
+    for n in (1, 2, 63, 64, 65, 127, 128, 129, 1000, 4097, 70_001):
+        for npl in (1, 2):
+            for grid in (1, 3, 0, 4096):
+                lean, _, _ = idx.join_ex(t[:n], points_per_lane=npl, grid=grid)
+                torch.cuda.synchronize()
+                assert np.array_equal(lean.cpu().numpy(), full[:n]), (n, npl, grid)
+            o, pr, _ = gpu_join(idx, pts[:n], points_per_lane=npl)
+            assert np.array_equal(o, full[:n]), (n, npl)
+            assert np.array_equal(pr, full_pairs[full_pairs[:, 0] < n]), (n, npl)
+
+
 def test_workspace_reserve_and_passes(act):
     """With pending points resolved by the second kernel, a reserved
     workspace smaller than the batch splits the join into passes; results
@@ -331,6 +357,11 @@ def test_pending_queue_and_kernel_agree(act):
                               pending=act.ACT_PENDING_KERNEL)
         assert np.array_equal(o1, o2) and np.array_equal(p1, p2)
         assert c1 == c2, (c1, c2)
+        t = torch.from_numpy(pts).cuda()
+        for pend in (act.ACT_PENDING_QUEUE, act.ACT_PENDING_KERNEL):  # lean kernels
+            lean, _, _ = idx.join_ex(t, points_per_lane=npl, pending=pend)
+            torch.cuda.synchronize()
+            assert np.array_equal(lean.cpu().numpy(), o1), (npl, pend)
         assert c1["cand_points"] > 1000
 
 
