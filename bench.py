@@ -672,14 +672,21 @@ def summarize_pmc(fdir, wdir):
     print("|---|---|---|---|---|")
     for k in sorted(fv):
         # probe_kernel<mode, lds, count, points per lane, batched>: mode 0
-        # approximate, 1 exact (pending points to the resolve kernel), 2
-        # exact (pending points resolved by the probe's queues)
+        # approximate, 1 exact (pending points in a mask for resolve_kernel),
+        # 2 exact (pending points resolved by the probe's queues), 3 exact
+        # (per-wave pending lists for resolve_list_kernel, the default)
         pm = re.search(r"probe_kernel<(\d), \d+, false, \d+, false>", k)
         rm = re.search(r"resolve_kernel<(true|false), false, false>", k)
-        if not pm and not rm:
+        lm = re.search(r"resolve_list_kernel<false>", k)
+        if not pm and not rm and not lm:
             continue  # other kernels, and the counting variants
-        label = ("probe_kernel %s" % {"0": "approx", "1": "exact", "2": "exact-queue"}[pm.group(1)]) \
-            if pm else ("resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges"))
+        if pm:
+            label = "probe_kernel %s" % {"0": "approx", "1": "exact-mask", "2": "exact-queue",
+                                         "3": "exact"}[pm.group(1)]
+        elif rm:
+            label = "resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges")
+        else:
+            label = "resolve_list_kernel"
         f = float(np.median(fv[k])) * fcal
         wr = float(np.median(wv.get(k, [0.0]))) * wcal
         print("| %s | %.4g | %.4g | %.4g | %d |" % (label, f + wr, f, wr, len(fv[k])))

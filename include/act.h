@@ -160,9 +160,10 @@ int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
 
 /*
- * act_workspace_reserve -- exact-mode joins mark the points that need
- * refinement in a per-stream pending mask owned by the index (one bit per
- * point of a pass). The first exact join on a stream allocates it for
+ * act_workspace_reserve -- exact-mode joins record the points that need
+ * refinement in a per-stream pending workspace owned by the index: a mask
+ * (one bit per point of a pass) and per-wave pending lists (8 bytes per
+ * point of a pass, plus 64 MiB). The first exact join on a stream allocates it for
  * max(n, 16 Mi) points; a later, longer join runs in passes of that many
  * points (no allocation). Call this beforehand to size it for `points`
  * points per pass, e.g. before capturing joins into a HIP graph, where
@@ -189,8 +190,9 @@ enum {
 };
 
 /* How an exact join resolves its pending points (points whose cell has
- * candidate references). KERNEL: the probe marks them in a per-stream mask
- * and a second kernel refines them. QUEUE: each probe wave queues its
+ * candidate references). KERNEL: the probe records them in the stream's
+ * workspace (per-wave lists with cell-local refinement, else a mask) and a
+ * second kernel refines them. QUEUE: each probe wave queues its
  * pending points in LDS and refines them itself, 64 at a time (no second
  * pass over the points; pays off when many points are pending). AUTO: the
  * index's launch configuration (KERNEL unless act_tune chose QUEUE). */

@@ -77,6 +77,11 @@ struct DevImage {
 struct Workspace {
   uint64_t *mask = nullptr;
   int64_t cap = 0;  // points
+  // the probe waves' pending lists (cell-local refinement): room for cap
+  // points plus the ragged ends of up to kListWavesMax waves' regions
+  uint2 *plist = nullptr;
+  int64_t plist_cap = 0;
+  uint32_t *pcount = nullptr;
   // batched joins: virtual point space of up to cap_groups 64-point groups
   uint64_t *bmask = nullptr, *gticks = nullptr;
   int32_t *group_batch = nullptr;
@@ -86,6 +91,9 @@ struct Workspace {
 };
 
 constexpr int64_t kDefaultPass = 1 << 24;
+// Probe waves whose pending lists a workspace holds (grids up to 4096
+// blocks; larger grids fall back to the pending mask).
+constexpr int64_t kListWavesMax = 4096 * 16;
 // Points per probe launch at most: tile indices are 32-bit (2^31 tiles of
 // 64 points, plus the grid's waves, stay below 2^32).
 constexpr int64_t kMaxLaunchPoints = 1ll << 37;
@@ -145,6 +153,9 @@ struct ProbeParams {
   int32_t refine;
   const uint32_t *local;  // exact mode: base of the cell-local records (the LUT)
   uint64_t *mask;         // exact mode: pending points of this pass, bit per point
+  uint2 *plist;           // or: each probe wave's pending points (index, code)
+  uint32_t *pcount;       //   and how many each wave has
+  uint32_t region;        //   entries per wave
   int64_t base;           // index of pts[0] in the caller's array (pair output)
   uint64_t *sink;         // target of the stores of lanes without a point
   // batched joins: the batches laid end to end in a virtual point space,
@@ -904,12 +915,37 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
     atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
 }
 
+// The second pass after a probe that listed its pending points per wave
+// (kExactList): wave w of this kernel resolves the entries of probe wave w,
+// one per lane, 64 at a time. The entry carries the point's code, so the
+// lookup-table read can start beside the point's.
+constexpr int kListBlock = 256;
+
+template <bool FULL>
+__global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
+                                                                  uint32_t nwaves) {
+  const uint32_t w = blockIdx.x * (kListBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
+  if (w < nwaves) {
+    const uint32_t cnt = P.pcount[w];
+    const uint2 *list = P.plist + (size_t)w * P.region;
+    for (uint32_t e = lane; e < cnt; e += 64) {
+      const uint2 ent = list[e];
+      resolve_point<FULL, false, false>(P, ent.x, ent.y, c, c_reads);
+    }
+  }
+  flush_counters<FULL>(P, c);
+  if (FULL && c_reads && P.counters)
+    atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
+}
+
 // ------------------------------------------------------------------ probe
 
 // Probe modes: approximate (every reference of a cell is a hit); exact,
 // leaving pending points in a mask for resolve_kernel; exact, with pending
 // points resolved by the probe's own waves (cell-local refinement).
-enum ProbeMode { kApprox = 0, kExactMask = 1, kExactFused = 2 };
+enum ProbeMode { kApprox = 0, kExactMask = 1, kExactFused = 2, kExactList = 3 };
 
 // A wave's queue of pending points (kExactFused). The probe appends each
 // finished tile's pending points; whenever 64 have gathered, the wave
@@ -922,6 +958,7 @@ struct PendingQueue {
   int64_t *v;
   uint64_t *e;
   uint32_t head, count;  // wave-uniform
+  uint2 *list;           // kExactList: this wave's region of the pending list
 };
 
 // Resolves the first n (<= 64) queued points, lane l taking entry l.
@@ -1017,6 +1054,14 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
       // one store from every lane (lanes without a point to the sink)
       store_out(live[p] ? T.out + k : (int32_t *)P.sink, v);
       if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
+      if (MODE == kExactList) {
+        // the wave appends its pending points (index in the pass, code) to
+        // its region of the list; other lanes store to the sink
+        const uint64_t pm = ballot(pend[p]);
+        uint2 *dst = pend[p] ? Q.list + Q.count + lane_rank(pm) : (uint2 *)(P.sink + 2);
+        *dst = make_uint2(tile * (uint32_t)(64 * NP) + (uint32_t)k, (uint32_t)v);
+        Q.count += (uint32_t)__popcll(pm);
+      }
     }
   }
   if (MODE == kExactMask) {
@@ -1106,7 +1151,10 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
   uint32_t rc[7] = {0, 0, 0, 0, 0, 0, 0};  // resolve counters (kExactFused)
-  PendingQueue Q{s_qv + (FUSED ? wid * kQueueCap : 0), s_qe + (FUSED ? wid * kQueueCap : 0), 0u, 0u};
+  PendingQueue Q{s_qv + (FUSED ? wid * kQueueCap : 0), s_qe + (FUSED ? wid * kQueueCap : 0), 0u, 0u,
+                 MODE == kExactList
+                     ? P.plist + (size_t)(blockIdx.x * kProbeWaves + wid) * P.region
+                     : nullptr};
   constexpr int TILE = 64 * NP;
   const uint32_t ntiles = (uint32_t)(BATCHED ? P.vhdr[0] / NP : (P.n + TILE - 1) / TILE);
   const uint32_t nwaves = gridDim.x * kProbeWaves;
@@ -1163,6 +1211,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
                                           c_reads);
   }
+  if (MODE == kExactList) P.pcount[blockIdx.x * kProbeWaves + wid] = Q.count;
   if (FUSED && Q.count > 0) {
     wave_sync();
     drain_queue<FULL, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
@@ -1310,6 +1359,7 @@ static ProbeFn probe_mode_fn(int lds_depth, bool count, int np) {
 static ProbeFn probe_fn(int mode, int lds_depth, bool count, int np) {
   return mode == kApprox      ? probe_mode_fn<kApprox>(lds_depth, count, np)
          : mode == kExactMask ? probe_mode_fn<kExactMask>(lds_depth, count, np)
+         : mode == kExactList ? probe_mode_fn<kExactList>(lds_depth, count, np)
                               : probe_mode_fn<kExactFused>(lds_depth, count, np);
 }
 
@@ -1386,6 +1436,8 @@ static void free_batch_workspace(Workspace &w) {
 
 static void free_workspace(Workspace &w) {
   if (w.mask) (void)hipFree(w.mask);
+  if (w.plist) (void)hipFree(w.plist);
+  if (w.pcount) (void)hipFree(w.pcount);
   free_batch_workspace(w);
   w = Workspace();
 }
@@ -1439,11 +1491,15 @@ static int get_workspace(const act_index *x, void *stream, int64_t cap, bool gro
     if (w.mask && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
       return fail(ACT_E_HIP, "cannot synchronise the stream to enlarge its workspace");
     free_workspace(w);
-    if (hipMalloc((void **)&w.mask, (size_t)cap / 8) != hipSuccess) {
+    const int64_t plist_cap = cap + kListWavesMax * 128;
+    if (hipMalloc((void **)&w.mask, (size_t)cap / 8) != hipSuccess ||
+        hipMalloc((void **)&w.plist, 8 * (size_t)plist_cap) != hipSuccess ||
+        hipMalloc((void **)&w.pcount, 4 * (size_t)kListWavesMax) != hipSuccess) {
       free_workspace(w);
-      return fail(ACT_E_OOM, "cannot allocate the pending mask");
+      return fail(ACT_E_OOM, "cannot allocate the pending workspace");
     }
     w.cap = cap;
+    w.plist_cap = plist_cap;
   }
   out = &w;
   return ACT_OK;
@@ -1600,19 +1656,22 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
                    : (P.refine == ACT_REFINE_LOCAL && pending == ACT_PENDING_QUEUE) ? kExactFused
                                                                                     : kExactMask;
   int64_t pass = std::min(a->n, kMaxLaunchPoints);
+  Workspace *w = nullptr;
   if (mode == kExactMask) {
-    Workspace *w = nullptr;
     rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
     if (rc) return rc;
     P.mask = w->mask;
+    P.plist = w->plist;
+    P.pcount = w->pcount;
     pass = std::min(a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap,
                     kMaxLaunchPoints);
   }
-  const ProbeFn probe = probe_fn(mode, depth, count, np);
   using ResolveFn = void (*)(ProbeParams, int64_t);
   const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
                               ? (count ? resolve_kernel<true, true, false> : resolve_kernel<true, false, false>)
                               : (count ? resolve_kernel<false, true, false> : resolve_kernel<false, false, false>);
+  using ListFn = void (*)(ProbeParams, uint32_t);
+  const ListFn resolve_list = count ? resolve_list_kernel<true> : resolve_list_kernel<false>;
   for (int64_t s0 = 0; s0 < a->n; s0 += pass) {
     const int64_t n = std::min(pass, a->n - s0);
     P.pts = (const double2 *)a->d_points + s0;
@@ -1622,12 +1681,30 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
     const int64_t tile_blocks = (n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : L.grid,
                                                                   tile_blocks));
-    hipLaunchKernelGGL(probe, dim3(grid), dim3(kProbeBlock), (size_t)n_lds * 1024,
-                       (hipStream_t)stream, P);
+    // cell-local refinement: the probe waves list their pending points when
+    // the pass's indices fit 32 bits and the regions fit the workspace
+    int pmode = mode;
+    const int64_t nwaves = (int64_t)grid * kProbeWaves, tile_pts = 64 * (int64_t)np;
+    const int64_t region = ((n + tile_pts - 1) / tile_pts + nwaves - 1) / nwaves * tile_pts;
+    if (mode == kExactMask && P.refine == ACT_REFINE_LOCAL && n < (1ll << 32) &&
+        nwaves <= kListWavesMax && region * nwaves <= w->plist_cap) {
+      pmode = kExactList;
+      P.region = (uint32_t)region;
+    }
+    hipLaunchKernelGGL(probe_fn(pmode, depth, count, np), dim3(grid), dim3(kProbeBlock),
+                       (size_t)n_lds * 1024, (hipStream_t)stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
+    if (pmode == kExactList) {
+      hipLaunchKernelGGL(resolve_list, dim3((unsigned)((nwaves + 3) / 4)), dim3(kListBlock), 0,
+                         (hipStream_t)stream, P, (uint32_t)nwaves);
+      e = hipGetLastError();
+      if (e != hipSuccess)
+        return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
+      continue;
+    }
     if (mode != kExactMask) continue;
     const int64_t nwords = (n + 63) / 64;
     const int64_t ranges = (nwords + kRangeWords - 1) / kRangeWords;

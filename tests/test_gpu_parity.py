@@ -365,6 +365,37 @@ def test_pending_queue_and_kernel_agree(act):
         assert c1["cand_points"] > 1000
 
 
+def test_pending_lists_and_mask_agree(act):
+    """Exact joins record pending points in per-wave lists unless the probe
+    grid has more waves than the lists hold (grid > 4096): then in the
+    pending mask. Both routes give identical outputs, pairs and counters,
+    lean and counting, and a sample of points matches the oracle."""
+    P, idx = index(act, "c2", "exact")
+    pts = np.concatenate([synth.workload_points("c2", 0, 10_700_000),
+                          edge_case_points(P, np.random.default_rng(17))])
+    t = torch.from_numpy(pts).cuda()
+    for npl in (1, 2):
+        # grid 5200 has 83,200 waves (mask); with two points per lane it
+        # still gets 5200 blocks of tiles (10.7e6 / 2048 > 5200)
+        o1, p1, c1 = gpu_join(idx, pts, counters=True, points_per_lane=npl, grid=1024,
+                              pending=act.ACT_PENDING_KERNEL)
+        o2, p2, c2 = gpu_join(idx, pts, counters=True, points_per_lane=npl, grid=5200,
+                              pending=act.ACT_PENDING_KERNEL)
+        assert np.array_equal(o1, o2) and np.array_equal(p1, p2), npl
+        assert c1 == c2, (c1, c2)
+        for g in (1024, 5200):  # lean kernels
+            lean, _, _ = idx.join_ex(t, points_per_lane=npl, grid=g,
+                                     pending=act.ACT_PENDING_KERNEL)
+            torch.cuda.synchronize()
+            assert np.array_equal(lean.cpu().numpy(), o1), (npl, g)
+        assert c1["cand_points"] > 10000
+    rng = np.random.default_rng(18)
+    sample = np.concatenate([rng.choice(len(pts), 20000, replace=False),
+                             np.arange(len(pts) - 300, len(pts))])
+    ref = oracle.join(P, pts[sample])
+    assert np.array_equal(o1[sample], ref.out)
+
+
 def test_overlapping_polygons_approx(act):
     P = overlapping_polygons(seed=14)
     idx = act.build(P, "approx", 2.0)
