@@ -179,7 +179,8 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
     import threading
 
     import numpy as np
-    srv = act.Server(indexes, slots=slots, arena_bytes=arena_bytes, max_request_points=max_points)
+    # requests are at most max_points long; a launch group joins up to 2^20
+    srv = act.Server(indexes, slots=slots, arena_bytes=arena_bytes, max_request_points=1 << 20)
     g = np.random.default_rng(seed)
     res = []
     for qps in qps_list:
@@ -222,7 +223,8 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
     srv.close()
     return {"slots": slots, "arena_bytes": int(arena_bytes),
             "request_points": "floor(exp(U(0, ln %d))), seed %d" % (max_points, seed),
-            "runs": res, "failed": st["failed"]}
+            "runs": res, "failed": st["failed"], "requests": st["completed"],
+            "launch_groups": st["launches"]}
 
 
 def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
@@ -590,7 +592,7 @@ def run_c4(args):
 
 
 def run_c5(args):
-    """Serving: Poisson arrivals at 1e3, 1e4 and 5e4 requests/s of
+    """Serving: Poisson arrivals at 1e3, 1e4, 5e4 and 1e5 requests/s of
     floor(exp(U(0, ln 65536))) points, each aimed at the 290-polygon
     approx@4m index or the 40,000-polygon exact index."""
     import synth
@@ -599,7 +601,7 @@ def run_c5(args):
     ie = act.build(synth.workload_polygons("c3"), "exact")
     pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
     sec = args.serve_seconds or 10.0
-    srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4], sec)
+    srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4, 1e5], sec)
     srv["indexes"] = "c2 approx@4m, c3 exact"
     best = max(r["points_per_s"] for r in srv["runs"])
     _line(best, len(srv["runs"]), 0, 1000.0 * sec,

@@ -318,9 +318,14 @@ int act_tune(act_index *idx, const double *d_sample, int64_t n, int32_t *d_out, 
  * GPU. A scheduler thread admits requests in arrival order when one of
  * `slots` streams is free and the request's buffers (20 bytes per point)
  * fit a device arena and a pinned host arena of `arena_bytes` each
- * (allocated once; 0 = 90% of free HBM, at most 4 GiB). An admitted request
- * is staged into pinned memory, copied to the GPU, joined (act_join) and
- * copied back on its stream; its result lands in the caller's h_out.
+ * (allocated once; 0 = 90% of free HBM, at most 4 GiB). When a slot frees
+ * up, the request at the front of the queue is admitted together with the
+ * requests for the same index waiting behind it (continuous batching: up to
+ * max_request_points points in all, or the front request alone if it is
+ * longer; up to 1024 requests). The group is staged into pinned memory,
+ * copied to the GPU, joined (one act_join) and copied back on the slot's
+ * stream; each request's results land in its caller's h_out. A request's
+ * result does not depend on the group it ran in.
  * Exact-mode workspaces for every (index, stream) are reserved at creation
  * for max_request_points (longer requests run in passes), so serving
  * allocates nothing. The indexes must outlive the server.
@@ -331,7 +336,8 @@ typedef struct {
   int32_t slots;               /* concurrent requests on the GPU (default 4)  */
   int32_t device;              /* HIP device (default 0)                      */
   int64_t arena_bytes;         /* per-arena bytes (default 0, see above)      */
-  int64_t max_request_points;  /* workspace sizing (default 2^20)             */
+  int64_t max_request_points;  /* workspace sizing and launch-group points
+                                  (default 2^20)                              */
 } act_server_opts;
 
 typedef struct {
@@ -342,6 +348,7 @@ typedef struct {
 typedef struct {
   int64_t submitted, admitted, completed, failed, queued, points, arena_bytes;
   int32_t slots, reserved;
+  int64_t launches;  /* launch groups (joins) started                        */
 } act_server_stats;
 
 void act_server_opts_init(act_server_opts *opts);

@@ -73,7 +73,7 @@ class ServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("points", ctypes.c_int64),
                 ("arena_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("launches", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):

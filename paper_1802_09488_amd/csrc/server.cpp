@@ -6,14 +6,17 @@
 // uneven size aimed at different polygon sets. This runtime keeps the
 // indexes resident and runs a scheduler thread:
 //   * requests wait in FIFO order;
-//   * a request is admitted when one of `slots` streams is free and its
-//     buffers fit both arenas (device memory for points and results, and
-//     pinned host memory for staging) -- memory is the admission budget;
-//   * an admitted request is staged into pinned memory, copied to the GPU,
-//     joined and copied back on its own stream, so admitted requests
+//   * when one of `slots` streams is free, the front request is admitted
+//     together with the requests for the same index waiting behind it, as
+//     one launch group of up to max_request_points points whose buffers fit
+//     both arenas (device memory for points and results, and pinned host
+//     memory for staging) -- memory is the admission budget, and under load
+//     one launch serves many requests (continuous batching);
+//   * an admitted group is staged into pinned memory, copied to the GPU,
+//     joined and copied back on its slot's stream, so admitted groups
 //     overlap on the device; completions are found by polling stream events;
-//   * results are copied to the caller's buffer and the request's times are
-//     kept (arrival, admission, completion).
+//   * results are copied to the callers' buffers and each request's times
+//     are kept (arrival, admission, completion).
 // Arenas are allocated once at creation; the hot loop allocates nothing.
 #include <hip/hip_runtime.h>
 
@@ -90,20 +93,33 @@ struct Request {
   int64_t n;
   int32_t *h_out;
   double arrival, admitted = 0, done = 0;
-  int64_t dev_off = -1, pin_off = -1, bytes = 0;
-  int slot = -1;
+  int64_t offset = 0;  // first point in its launch group
   int status = ACT_OK;
+};
+
+// Requests for one index joined in one launch on one slot: their points
+// sit back to back in one device and one pinned buffer (20 bytes a point:
+// 16 in, 4 out).
+struct Group {
+  std::vector<Request *> reqs;
+  int32_t index = 0;
+  int64_t n = 0, dev_off = 0, pin_off = 0, bytes = 0;
+  bool busy() const { return !reqs.empty(); }
 };
 
 }  // namespace
 
+// Ownership: the queue, the ticket map, the statistics and the requests'
+// status and times are shared and guarded by `mu`. The slots (`running`),
+// the arenas and the requests taken from the queue belong to the scheduler
+// thread, which stages and launches without holding `mu`.
 struct act_server {
   std::vector<const act_index *> indexes;
   int device = 0;
   int64_t max_request = 0;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;
-  std::vector<Request *> running;  // per slot
+  std::vector<Group> running;  // per slot
   char *dev_base = nullptr;
   char *pin_base = nullptr;
   Arena dev_arena, pin_arena;
@@ -127,103 +143,161 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
-// Start an admitted request on its slot's stream (scheduler thread).
-int launch(act_server *s, Request *r) {
-  const int64_t n = r->n;
-  char *pin = s->pin_base + r->pin_off;
-  char *dev = s->dev_base + r->dev_off;
+// A launch group takes at most this many waiting requests.
+constexpr size_t kGroupMax = 1024;
+// How far down the queue the scheduler looks for requests of the front
+// request's index.
+constexpr size_t kGroupScan = 4096;
+
+// Stage a group into pinned memory and start its copies and join on its
+// slot's stream (scheduler thread, `mu` not held).
+int launch(act_server *s, int slot, const Group &g) {
+  const int64_t n = g.n;
+  char *pin = s->pin_base + g.pin_off;
+  char *dev = s->dev_base + g.dev_off;
   double *pin_pts = (double *)pin;
   int32_t *pin_out = (int32_t *)(pin + 16 * n);
   double *dev_pts = (double *)dev;
   int32_t *dev_out = (int32_t *)(dev + 16 * n);
-  hipStream_t st = s->streams[r->slot];
-  std::memcpy(pin_pts, r->h_points, 16 * (size_t)n);
+  hipStream_t st = s->streams[slot];
+  for (const Request *r : g.reqs)
+    if (r->n) std::memcpy(pin_pts + 2 * r->offset, r->h_points, 16 * (size_t)r->n);
   if (hipMemcpyAsync(dev_pts, pin_pts, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
     return ACT_E_HIP;
-  int rc = act_join(s->indexes[r->index], dev_pts, n, dev_out, st);
+  int rc = act_join(s->indexes[g.index], dev_pts, n, dev_out, st);
   if (rc) return rc;
   if (hipMemcpyAsync(pin_out, dev_out, 4 * (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess)
     return ACT_E_HIP;
-  if (hipEventRecord(s->events[r->slot], st) != hipSuccess) return ACT_E_HIP;
+  if (hipEventRecord(s->events[slot], st) != hipSuccess) return ACT_E_HIP;
   return ACT_OK;
 }
 
-void finish(act_server *s, Request *r, int status) {
-  if (status == ACT_OK && r->n > 0)
-    std::memcpy(r->h_out, s->pin_base + r->pin_off + 16 * r->n, 4 * (size_t)r->n);
-  r->status = status;
-  r->done = now_s();
-  if (r->bytes) {
-    s->dev_arena.release(r->dev_off, r->bytes);
-    s->pin_arena.release(r->pin_off, r->bytes);
+// Copy a finished group's results out, free its buffers and complete its
+// requests (scheduler thread, `mu` not held on entry).
+void finish(act_server *s, Group &g, int status) {
+  if (status == ACT_OK)
+    for (const Request *r : g.reqs)
+      if (r->n)
+        std::memcpy(r->h_out, s->pin_base + g.pin_off + 16 * g.n + 4 * r->offset,
+                    4 * (size_t)r->n);
+  if (g.bytes) {
+    s->dev_arena.release(g.dev_off, g.bytes);
+    s->pin_arena.release(g.pin_off, g.bytes);
   }
-  if (r->slot >= 0) s->running[r->slot] = nullptr;
-  s->stats.completed++;
-  s->stats.points += r->n;
-  if (status != ACT_OK) s->stats.failed++;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const double t = now_s();
+    for (Request *r : g.reqs) {
+      r->status = status;
+      r->done = t;
+      s->stats.completed++;
+      s->stats.points += r->n;
+      if (status != ACT_OK) s->stats.failed++;
+    }
+  }
+  s->cv_done.notify_all();
+  g = Group();
+}
+
+// Take the front request and the waiting requests of its index behind it
+// (in arrival order, up to max_request points in all, or the front request
+// alone if it is longer) whose buffers fit both arenas. `mu` held. False if
+// even the front request does not fit yet.
+bool take_group(act_server *s, Group &g) {
+  Request *r0 = s->queue.front();
+  g.index = r0->index;
+  g.reqs.assign(1, r0);
+  g.n = r0->n;
+  std::vector<size_t> picked;
+  const size_t scan = std::min(s->queue.size(), kGroupScan);
+  for (size_t k = 1; k < scan && g.reqs.size() < kGroupMax; k++) {
+    Request *r = s->queue[k];
+    if (r->index != g.index || g.n + r->n > s->max_request) continue;
+    g.reqs.push_back(r);
+    picked.push_back(k);
+    g.n += r->n;
+  }
+  for (int attempt = 0; attempt < 2; attempt++) {
+    if (attempt == 1) {  // the group does not fit: try the front request alone
+      if (g.reqs.size() == 1) break;
+      g.reqs.resize(1);
+      picked.clear();
+      g.n = r0->n;
+    }
+    g.bytes = 20 * g.n;
+    if (g.n == 0) {
+      g.bytes = 0;
+    } else {
+      if (!s->dev_arena.alloc(g.bytes, g.dev_off)) continue;
+      if (!s->pin_arena.alloc(g.bytes, g.pin_off)) {
+        s->dev_arena.release(g.dev_off, g.bytes);
+        continue;
+      }
+    }
+    // remove the picked requests (back to front), then the front one
+    for (auto it = picked.rbegin(); it != picked.rend(); ++it)
+      s->queue.erase(s->queue.begin() + (std::ptrdiff_t)*it);
+    s->queue.pop_front();
+    int64_t off = 0;
+    const double t = now_s();
+    for (Request *r : g.reqs) {
+      r->offset = off;
+      off += r->n;
+      r->admitted = t;
+    }
+    s->stats.admitted += (int64_t)g.reqs.size();
+    s->stats.launches++;
+    return true;
+  }
+  g = Group();
+  return false;
 }
 
 void worker_loop(act_server *s) {
   (void)hipSetDevice(s->device);
-  std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     bool progress = false;
     // completions
     for (size_t k = 0; k < s->running.size(); k++) {
-      Request *r = s->running[k];
-      if (!r) continue;
+      Group &g = s->running[k];
+      if (!g.busy()) continue;
       const hipError_t q = hipEventQuery(s->events[k]);
       if (q == hipErrorNotReady) continue;
-      finish(s, r, q == hipSuccess ? ACT_OK : ACT_E_HIP);
+      finish(s, g, q == hipSuccess ? ACT_OK : ACT_E_HIP);
       progress = true;
     }
-    if (progress) s->cv_done.notify_all();
-    // admissions, in arrival order
-    while (!s->queue.empty()) {
-      Request *r = s->queue.front();
+    // admissions, front of the queue first
+    for (;;) {
       int slot = -1;
       for (size_t k = 0; k < s->running.size(); k++)
-        if (!s->running[k]) {
+        if (!s->running[k].busy()) {
           slot = (int)k;
           break;
         }
       if (slot < 0) break;
-      r->bytes = 20 * r->n;
-      if (r->n > 0) {
-        int64_t d, p;
-        if (!s->dev_arena.alloc(r->bytes, d)) break;
-        if (!s->pin_arena.alloc(r->bytes, p)) {
-          s->dev_arena.release(d, r->bytes);
-          break;
-        }
-        r->dev_off = d;
-        r->pin_off = p;
-      } else {
-        r->bytes = 0;
-      }
-      s->queue.pop_front();
-      r->slot = slot;
-      r->admitted = now_s();
-      s->running[slot] = r;
-      s->stats.admitted++;
-      const int rc = r->n > 0 ? launch(s, r) : ACT_OK;
-      if (rc != ACT_OK || r->n == 0) {
-        // whatever was enqueued must finish before the buffers are reused
-        if (rc != ACT_OK) (void)hipStreamSynchronize(s->streams[slot]);
-        finish(s, r, rc);
-        s->cv_done.notify_all();
+      Group g;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->queue.empty() || !take_group(s, g)) break;
       }
       progress = true;
+      const int rc = g.n > 0 ? launch(s, slot, g) : ACT_OK;
+      if (rc != ACT_OK || g.n == 0) {
+        // whatever was enqueued must finish before the buffers are reused
+        if (rc != ACT_OK) (void)hipStreamSynchronize(s->streams[slot]);
+        finish(s, g, rc);
+        continue;
+      }
+      s->running[slot] = std::move(g);
     }
     bool busy = false;
-    for (Request *r : s->running) busy |= r != nullptr;
-    if (s->stop && !busy && s->queue.empty()) break;
+    for (const Group &g : s->running) busy |= g.busy();
     if (!progress) {
-      if (busy) {  // poll the in-flight requests' events
-        lk.unlock();
+      if (busy) {  // poll the in-flight groups' events
         std::this_thread::yield();
-        lk.lock();
       } else {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->stop && s->queue.empty()) break;
         s->cv_work.wait(lk, [s] { return s->stop || !s->queue.empty(); });
       }
     }
@@ -295,7 +369,7 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
     act_server_destroy(s);
     return rc;
   }
-  s->running.assign(s->streams.size(), nullptr);
+  s->running.resize(s->streams.size());
   s->stats.arena_bytes = arena;
   s->stats.slots = (int32_t)s->streams.size();
   s->worker = std::thread(worker_loop, s);

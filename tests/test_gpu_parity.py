@@ -555,6 +555,45 @@ def test_server_results_same_alone_and_in_mix(act):
             assert np.array_equal(out, oracle.join(P1, p).out)
     st = srv.stats()
     assert st["completed"] == 300 and st["failed"] == 0 and st["queued"] == 0
+    # the burst queues up behind 4 slots: waiting requests for one index
+    # share launches
+    assert 0 < st["launches"] < 300, st
+    srv.close()
+
+
+def test_server_groups_keep_results_apart(act):
+    """Many tiny and empty requests for two indexes submitted at once (one
+    slot, so they queue): they are joined in shared launches, each result
+    equals the oracle's for its own points, in its own buffer, and no
+    group exceeds max_request_points points."""
+    P1, i1 = index(act, "c1", "exact")
+    P2, i2 = index(act, "c1", "approx", 4.0)
+    pts = synth.workload_points("c1", 0, 100_000)
+    srv = act.Server([i1, i2], slots=1, arena_bytes=8 << 20, max_request_points=5000)
+    rng = np.random.default_rng(43)
+    reqs, a = [], 0
+    for k in range(400):
+        n = int(rng.choice([0, 1, 2, 63, 64, 65, 700, 4999, 5000]))
+        if a + n > len(pts):
+            a = 0
+        reqs.append((int(rng.integers(0, 2)), pts[a:a + n]))
+        a += n
+    tickets = [srv.submit(w, p) for w, p in reqs]
+    ref1 = oracle.join(P1, pts).out
+    for (w, p), t in zip(reqs, tickets):
+        out, tm = srv.wait(t)
+        assert len(out) == len(p) and tm["n"] == len(p)
+        if len(p) == 0:
+            continue
+        off = int((p.ctypes.data - pts.ctypes.data) // 16)
+        if w == 0:
+            assert np.array_equal(out, ref1[off:off + len(p)])
+        else:
+            alone = i2.join(torch.from_numpy(p).cuda()).cpu().numpy()
+            assert np.array_equal(out, alone)
+    st = srv.stats()
+    assert st["completed"] == 400 and st["failed"] == 0
+    assert st["launches"] < 200, st
     srv.close()
 
 
