@@ -16,13 +16,15 @@
 //   8. true hits (and every reference in approximate mode) are output;
 //      in exact mode a point whose cell has candidate references is
 //      pending: its candidates are refined by the crossing-number test of
-//      Section II with the ST_Covers boundary rule. By default each wave
-//      queues its pending points in LDS and refines them 64 at a time from
-//      the cells' local records; a two-pass join instead marks them in a
-//      per-64-point mask for the resolve kernel, which can also refine over
+//      Section II with the ST_Covers boundary rule. By default the join
+//      has two passes: each probe wave lists its pending points (index and
+//      cell entry) in its own region of a workspace list, and a second
+//      kernel refines them from the cells' local records. Refinement over
 //      all edges (fp32 on origin-translated coordinates with a proven error
 //      bound, fp64 + exact arithmetic for the edges the bound leaves
-//      undecided);
+//      undecided) and batched joins mark pending points in a per-64-point
+//      mask for the resolve kernel instead; or each wave queues its pending
+//      points in LDS and refines them itself, 64 at a time;
 //   9. out[i] = lowest matching id (or -1), further matches -> pair list.
 #include <hip/hip_runtime.h>
 
@@ -238,7 +240,8 @@ __device__ __forceinline__ bool project(const double2 *trig, double lat, double 
   const bool xmaj = fabs(x) >= fabs(y);
   const double mxy = fmax(fabs(x), fabs(y));
   const bool polar = fabs(z) > mxy;
-  const double r29 = rcp_nr(fmax(mxy, fabs(z))) * 536870912.0;
+  // (a select, not fmax: fmax would first quiet NaNs, which cannot occur)
+  const double r29 = rcp_nr(polar ? fabs(z) : mxy) * 536870912.0;
   // the major coordinate is at least 1/sqrt(3) in magnitude, so its sign
   // bit (bit 31 of the high word) says whether it is negative
   const uint32_t hs = polar ? (uint32_t)__double2hiint(z)
@@ -944,7 +947,9 @@ __global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
 
 // Probe modes: approximate (every reference of a cell is a hit); exact,
 // leaving pending points in a mask for resolve_kernel; exact, with pending
-// points resolved by the probe's own waves (cell-local refinement).
+// points resolved by the probe's own waves (cell-local refinement); exact,
+// with pending points listed per wave for resolve_list_kernel (cell-local
+// refinement).
 enum ProbeMode { kApprox = 0, kExactMask = 1, kExactFused = 2, kExactList = 3 };
 
 // A wave's queue of pending points (kExactFused). The probe appends each
