@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -107,6 +108,104 @@ struct Group {
   bool busy() const { return !reqs.empty(); }
 };
 
+// Host copies shared by the scheduler thread and a few helper threads that
+// only copy (every HIP call stays on the scheduler thread). Idle helpers
+// sleep; a batch of pieces is split between the caller and them.
+class CopyPool {
+ public:
+  struct Piece {
+    void *dst;
+    const void *src;
+    size_t n;
+  };
+  explicit CopyPool(int helpers) {
+    for (int k = 0; k < helpers; k++) th_.emplace_back([this] { helper(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto &t : th_) t.join();
+  }
+  // Runs every piece; returns when all are copied.
+  void run(const std::vector<Piece> &pieces) {
+    if (pieces.empty()) return;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      jobs_ = &pieces;
+      next_ = 0;
+      remaining_ = pieces.size();
+      gen_++;
+    }
+    cv_.notify_all();
+    const size_t done = drain(pieces);
+    std::unique_lock<std::mutex> lk(mu_);
+    remaining_ -= done;
+    done_.wait(lk, [this] { return remaining_ == 0 && busy_ == 0; });
+    jobs_ = nullptr;
+  }
+
+ private:
+  size_t drain(const std::vector<Piece> &J) {
+    size_t done = 0;
+    for (size_t k; (k = next_.fetch_add(1)) < J.size(); done++)
+      std::memcpy(J[k].dst, J[k].src, J[k].n);
+    return done;
+  }
+  void helper() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      if (!jobs_) continue;  // that batch has already finished
+      const std::vector<Piece> *J = jobs_;
+      busy_++;
+      lk.unlock();
+      const size_t done = drain(*J);
+      lk.lock();
+      remaining_ -= done;
+      busy_--;
+      if (remaining_ == 0 && busy_ == 0) done_.notify_all();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  const std::vector<Piece> *jobs_ = nullptr;
+  std::atomic<size_t> next_{0};
+  size_t remaining_ = 0;  // pieces not yet copied (guarded by mu_)
+  int busy_ = 0;          // helpers inside the current batch (guarded by mu_)
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+// Copies of a group below this many bytes run on the scheduler thread
+// alone (waking the helpers costs more); larger ones are cut into pieces.
+constexpr size_t kParallelCopyBytes = 1 << 20;
+constexpr size_t kCopyPiece = 256 << 10;
+constexpr int kCopyHelpers = 3;
+
+// Run the copies (dst, src, bytes) of a group, in pieces on the pool if
+// they are large (`pieces` is the caller's scratch list).
+void group_copies(CopyPool &pool, const std::vector<CopyPool::Piece> &work,
+                  std::vector<CopyPool::Piece> &pieces) {
+  size_t total = 0;
+  for (const auto &w : work) total += w.n;
+  if (total < kParallelCopyBytes) {
+    for (const auto &w : work) std::memcpy(w.dst, w.src, w.n);
+    return;
+  }
+  pieces.clear();
+  for (const auto &w : work)
+    for (size_t o = 0; o < w.n; o += kCopyPiece)
+      pieces.push_back({(char *)w.dst + o, (const char *)w.src + o, std::min(kCopyPiece, w.n - o)});
+  pool.run(pieces);
+}
+
 }  // namespace
 
 // Ownership: the queue, the ticket map, the statistics and the requests'
@@ -130,6 +229,8 @@ struct act_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
+  CopyPool copies{kCopyHelpers};
+  std::vector<CopyPool::Piece> copy_work, copy_pieces;  // scheduler thread's scratch
   act_server_stats stats{};
   std::string err;
 };
@@ -160,8 +261,10 @@ int launch(act_server *s, int slot, const Group &g) {
   double *dev_pts = (double *)dev;
   int32_t *dev_out = (int32_t *)(dev + 16 * n);
   hipStream_t st = s->streams[slot];
+  s->copy_work.clear();
   for (const Request *r : g.reqs)
-    if (r->n) std::memcpy(pin_pts + 2 * r->offset, r->h_points, 16 * (size_t)r->n);
+    if (r->n) s->copy_work.push_back({pin_pts + 2 * r->offset, r->h_points, 16 * (size_t)r->n});
+  group_copies(s->copies, s->copy_work, s->copy_pieces);
   if (hipMemcpyAsync(dev_pts, pin_pts, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
     return ACT_E_HIP;
   int rc = act_join(s->indexes[g.index], dev_pts, n, dev_out, st);
@@ -175,11 +278,14 @@ int launch(act_server *s, int slot, const Group &g) {
 // Copy a finished group's results out, free its buffers and complete its
 // requests (scheduler thread, `mu` not held on entry).
 void finish(act_server *s, Group &g, int status) {
-  if (status == ACT_OK)
+  if (status == ACT_OK) {
+    s->copy_work.clear();
     for (const Request *r : g.reqs)
       if (r->n)
-        std::memcpy(r->h_out, s->pin_base + g.pin_off + 16 * g.n + 4 * r->offset,
-                    4 * (size_t)r->n);
+        s->copy_work.push_back(
+            {r->h_out, s->pin_base + g.pin_off + 16 * g.n + 4 * r->offset, 4 * (size_t)r->n});
+    group_copies(s->copies, s->copy_work, s->copy_pieces);
+  }
   if (g.bytes) {
     s->dev_arena.release(g.dev_off, g.bytes);
     s->pin_arena.release(g.pin_off, g.bytes);
