@@ -18,6 +18,9 @@ text summaries kept under profiles/):
                                               --output-format csv -d DIR)
   python bench.py --summarize-pmc FDIR WDIR  (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
                                               --output-format csv -d FDIR / WDIR)
+  python bench.py --summarize-counters [--points-per-launch N] DIR...
+                                             (rocprofv3 --pmc <SQ_/TCC_ counters>
+                                              --output-format csv -d DIR, one per set)
 """
 from __future__ import annotations
 
@@ -275,11 +278,16 @@ def main():
                     help="seconds per serving rate (default 2 in c2, 10 in c5)")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR")
+    ap.add_argument("--points-per-launch", type=float, default=0.0,
+                    help="with --summarize-counters: points one launch processes")
     args = ap.parse_args()
     if args.summarize_trace:
         return summarize_trace(args.summarize_trace)
     if args.summarize_pmc:
         return summarize_pmc(*args.summarize_pmc)
+    if args.summarize_counters:
+        return summarize_counters(args.summarize_counters, args.points_per_launch)
     if args.gpus != 1:
         print("bench.py measures one GPU: the probe replicates the immutable index per GPU and "
               "splits the points, and this benchmark runs and reports the single-GPU case only "
@@ -642,6 +650,62 @@ def summarize_trace(d):
         v = np.asarray(v)
         print("| %s | %d | %d | %d | %.1f | %.1f | %.1f | %.2f |" % (
             name, grid, blk, len(v), v.mean(), v.min(), v.max(), v.sum() / 1e3))
+
+
+def _lean_act_kernel(name):
+    """This library's kernels without counters and pair output (the FULL
+    template argument: third of probe_kernel, second of resolve_kernel,
+    first of resolve_list_kernel)."""
+    m = re.match(r"(probe_kernel|resolve_kernel|resolve_list_kernel)<([^>]*)>", name)
+    if not m:
+        return False
+    a = [x.strip() for x in m.group(2).split(",")]
+    full = {"probe_kernel": 2, "resolve_kernel": 1, "resolve_list_kernel": 0}[m.group(1)]
+    return a[full] == "false"
+
+
+def summarize_counters(dirs, points_per_launch):
+    """Issue and L2 counters of the largest launches of each lean kernel
+    (medians over those launches; counting kernels and small grids left
+    out): VALU and SALU instructions (per 64 points when the points per
+    launch are given), VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x
+    GRBM_GUI_ACTIVE / 8), the share of wave time waiting on instruction
+    issue (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) and the L2 hit rate
+    (TCC_HIT_sum / TCC_REQ_sum)."""
+    import numpy as np
+    vals, grids = {}, {}
+    for d in dirs:
+        for r in _csv_rows(d, "counter_collection.csv"):
+            k, g = _short(r["Kernel_Name"]), int(r["Grid_Size"])
+            if not _lean_act_kernel(k):
+                continue  # torch's and the runtime's kernels, the counting kernels
+            if g > grids.get(k, -1):
+                grids[k], vals[k] = g, {}
+            if g == grids[k]:
+                vals[k].setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    print("kernel sources sha256/16: `%s`" % kernel_source_hash())
+    print()
+    unit = "per 64 points" if points_per_launch else "per launch"
+    print("| kernel | grid | VALU instr. %s | SALU instr. %s | VALU busy | issue wait | "
+          "L2 hit rate |" % (unit, unit))
+    print("|---|---|---|---|---|---|---|")
+    for k in sorted(vals):
+        m = {c: float(np.median(v)) for c, v in vals[k].items()}
+        div = points_per_launch / 64.0 if points_per_launch else 1.0
+        cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+
+        def f(x, fmt):
+            return fmt % x if x is not None else "-"
+        print("| %s | %d | %s | %s | %s | %s | %s |" % (
+            k, grids[k],
+            f(m["SQ_INSTS_VALU"] / div if "SQ_INSTS_VALU" in m else None, "%.4g"),
+            f(m["SQ_INSTS_SALU"] / div if "SQ_INSTS_SALU" in m else None, "%.4g"),
+            f(100 * m["SQ_INSTS_VALU"] * 4 / (1024 * cyc) if cyc and "SQ_INSTS_VALU" in m
+              else None, "%.0f%%"),
+            f(100 * m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"]
+              if "SQ_WAIT_INST_ANY" in m and m.get("SQ_WAVE_CYCLES") else None, "%.0f%%"),
+            f(100 * m["TCC_HIT_sum"] / m["TCC_REQ_sum"]
+              if "TCC_HIT_sum" in m and m.get("TCC_REQ_sum") else None, "%.0f%%")))
 
 
 def summarize_pmc(fdir, wdir):

@@ -597,6 +597,26 @@ def test_server_groups_keep_results_apart(act):
     srv.close()
 
 
+def test_server_large_groups_share_copies(act):
+    """A burst of 30,000-point requests for one index behind one slot: the
+    launch groups reach about 2^20 points (16 MiB of staging), whose copies
+    are cut into pieces shared with helper threads; every result equals the
+    oracle's for its own points."""
+    P, idx = index(act, "c1", "exact")
+    pts = synth.workload_points("c1", 0, 100_000)
+    ref = oracle.join(P, pts).out
+    srv = act.Server([idx], slots=1, arena_bytes=64 << 20, max_request_points=1 << 20)
+    rng = np.random.default_rng(44)
+    starts = rng.integers(0, len(pts) - 30_000, 96)
+    tickets = [srv.submit(0, pts[a:a + 30_000]) for a in starts]
+    for a, t in zip(starts, tickets):
+        out, _ = srv.wait(t)
+        assert np.array_equal(out, ref[a:a + 30_000]), a
+    st = srv.stats()
+    assert st["completed"] == 96 and st["failed"] == 0 and st["launches"] < 48, st
+    srv.close()
+
+
 def test_server_admission_by_memory(act):
     """Requests that each need most of the arena are admitted one at a time
     (memory, not slots, is the limit) and all complete; a request that can
