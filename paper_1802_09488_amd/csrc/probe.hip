@@ -1806,7 +1806,9 @@ static bool cache_lookup(const char *path, uint64_t key, act_launch &L) {
   int g, lds, np, rf, pd;
   bool hit = false;
   while (std::fscanf(f, "%llx %63s %d %d %d %d %d", &k, arch, &g, &lds, &np, &rf, &pd) == 7)
-    if (k == key && std::strcmp(arch, "gfx950") == 0) {
+    if (k == key && std::strcmp(arch, "gfx950") == 0 && g >= 1 && g <= 65536 && lds >= -1 &&
+        lds <= 2 && (np == 1 || np == 2) && rf >= ACT_REFINE_LOCAL && rf <= ACT_REFINE_FP64 &&
+        pd >= ACT_PENDING_KERNEL && pd <= ACT_PENDING_QUEUE) {  // other lines are skipped
       L.grid = g;
       L.lds_levels = lds;
       L.points_per_lane = np;

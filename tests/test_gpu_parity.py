@@ -318,7 +318,7 @@ def test_small_and_ragged_lengths(act, mode):
     if mode == "exact":
         assert np.array_equal(full, oracle.join(P, pts).out)
     t = torch.from_numpy(pts).cuda()
-    for n in (1, 2, 63, 64, 65, 127, 128, 129, 1000, 4097, 70_001):
+    for n in (1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 4097, 70_001):
         for npl in (1, 2):
             for grid in (1, 3, 0, 4096):
                 lean, _, _ = idx.join_ex(t[:n], points_per_lane=npl, grid=grid)
