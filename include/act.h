@@ -256,6 +256,9 @@ typedef struct {
  * (setup, probe, resolve in exact mode, optional finish); the host reads
  * nothing back, so the call can be captured into a HIP graph once the
  * stream's workspace is large enough (act_batched_reserve) and replayed.
+ * Batches are processed smallest first (by the bit length of their size;
+ * input order within one length), so small batches complete early; the
+ * results do not depend on the order.
  * d_ticks (optional, device, nb + 1 uint64): [0] the wall-clock tick at
  * which the join started on the GPU, [1 + b] the tick at which batch b was
  * complete (act_wall_clock_hz gives the tick rate). Extra matches of

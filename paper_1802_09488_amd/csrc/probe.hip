@@ -88,6 +88,8 @@ struct Workspace {
   uint64_t *bmask = nullptr, *gticks = nullptr;
   int32_t *group_batch = nullptr;
   int64_t *vstart = nullptr, *vhdr = nullptr;
+  int64_t *vsorted = nullptr;  // batches' virtual starts in virtual order
+  int32_t *vorder = nullptr;   // the batch at each position of that order
   int64_t cap_groups = 0;
   int32_t cap_batches = 0;
 };
@@ -1238,80 +1240,154 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
 // A batched join lays its batches end to end in a virtual point space,
 // each starting at a multiple of 128 points (so no probe tile spans two
 // batches), and runs the probe and resolve kernels over that space once.
-// The setup kernel (one block) scans the batch sizes; the fill kernel
-// records the batch of every 64-point group; the finish kernel turns the
-// groups' completion ticks into per-batch completion ticks. None of them
-// needs the host to know the sizes, so the whole call can be captured.
+// The probe walks the space in order, so a batch's completion time grows
+// with the points laid out before it: the batches are laid out smallest
+// first, by size class (the bit length of the batch's 128-point blocks;
+// input order within a class), which lets the many small batches of an
+// uneven mix complete early without delaying the total. The setup kernel
+// (one block) computes the layout; the fill kernel records the batch of
+// every 64-point group; the finish kernel turns the groups' completion
+// ticks into per-batch completion ticks. None of them needs the host to
+// know the sizes, so the whole call can be captured.
 constexpr int kSetupBlock = 1024;
+constexpr int kSizeClasses = 40;  // bit lengths of 128-point block counts (< 2^37 points)
+
+__device__ __forceinline__ int64_t batch_span(int64_t n) { return n > 0 ? (n + 127) / 128 * 128 : 0; }
+
+__device__ __forceinline__ int size_class(int64_t span) {
+  return span > 0 ? 64 - __clzll((unsigned long long)(span / 128)) : 0;
+}
 
 __global__ __launch_bounds__(kSetupBlock) void batch_setup_kernel(const act_batch *batches,
                                                                   int32_t nb, int64_t cap_groups,
-                                                                  int64_t *vstart, int64_t *vhdr,
+                                                                  int64_t *vstart, int64_t *vsorted,
+                                                                  int32_t *vorder, int64_t *vhdr,
                                                                   uint64_t *ticks) {
+  __shared__ unsigned long long s_cls_pts[kSizeClasses];
+  __shared__ unsigned int s_cls_cnt[kSizeClasses];
   __shared__ int64_t s_part[kSetupBlock / 64];
+  __shared__ int32_t s_cpart[kSetupBlock / 64];
   __shared__ int64_t s_carry;
-  if (threadIdx.x == 0) {
-    s_carry = 0;
-    if (ticks) ticks[0] = wall_clock64();
+  __shared__ int32_t s_ccarry;
+  if (threadIdx.x < kSizeClasses) {
+    s_cls_pts[threadIdx.x] = 0;
+    s_cls_cnt[threadIdx.x] = 0;
   }
+  if (threadIdx.x == 0 && ticks) ticks[0] = wall_clock64();
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // points and batches per size class
   bool bad = false;
-  for (int32_t b0 = 0; b0 < nb; b0 += kSetupBlock) {
-    const int32_t b = b0 + (int32_t)threadIdx.x;
-    int64_t sz = 0;
-    if (b < nb) {
-      const int64_t n = batches[b].n;
-      bad |= n < 0;
-      sz = n > 0 ? (n + 127) / 128 * 128 : 0;
-    }
-    int64_t incl = sz;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int64_t v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
-    if (lane == 63) s_part[wid] = incl;
-    __syncthreads();
-    int64_t before = s_carry, total = 0;
-    for (int k = 0; k < kSetupBlock / 64; k++) {
-      if (k < wid) before += s_part[k];
-      total += s_part[k];
-    }
-    if (b < nb) vstart[b] = before + incl - sz;
-    __syncthreads();
-    if (threadIdx.x == 0) s_carry += total;
-    __syncthreads();
+  for (int32_t b = threadIdx.x; b < nb; b += kSetupBlock) {
+    const int64_t n = batches[b].n;
+    bad |= n < 0 || n >= (1ll << 37);
+    const int64_t sp = (n < 0 || n >= (1ll << 37)) ? 0 : batch_span(n);
+    const int c = size_class(sp);
+    atomicAdd(&s_cls_pts[c], (unsigned long long)sp);
+    atomicAdd(&s_cls_cnt[c], 1u);
   }
   bad = __syncthreads_or(bad);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t vbase = 0;
+  int32_t cbase = 0;
+  // each class in turn: an exclusive scan of its batches' spans (and
+  // counts), in input order, from the class's first virtual point (and
+  // first position of the order)
+  for (int c = 0; c < kSizeClasses; c++) {
+    const int64_t cls_pts = (int64_t)s_cls_pts[c];
+    const int32_t cls_cnt = (int32_t)s_cls_cnt[c];
+    if (cls_cnt == 0) continue;  // block-uniform
+    if (threadIdx.x == 0) {
+      s_carry = 0;
+      s_ccarry = 0;
+    }
+    __syncthreads();
+    for (int32_t b0 = 0; b0 < nb; b0 += kSetupBlock) {
+      const int32_t b = b0 + (int32_t)threadIdx.x;
+      int64_t sp = 0;
+      int32_t one = 0;
+      if (b < nb) {
+        const int64_t n = batches[b].n;
+        const int64_t s0 = (n < 0 || n >= (1ll << 37)) ? 0 : batch_span(n);
+        if (size_class(s0) == c) {
+          sp = s0;
+          one = 1;
+        }
+      }
+      int64_t incl = sp;
+      int32_t cincl = one;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t v = __shfl_up(incl, d);
+        const int32_t w = __shfl_up(cincl, d);
+        if (lane >= d) {
+          incl += v;
+          cincl += w;
+        }
+      }
+      if (lane == 63) {
+        s_part[wid] = incl;
+        s_cpart[wid] = cincl;
+      }
+      __syncthreads();
+      int64_t before = s_carry, total = 0;
+      int32_t cbefore = s_ccarry, ctotal = 0;
+      for (int k = 0; k < kSetupBlock / 64; k++) {
+        if (k < wid) {
+          before += s_part[k];
+          cbefore += s_cpart[k];
+        }
+        total += s_part[k];
+        ctotal += s_cpart[k];
+      }
+      if (one) {
+        const int64_t v = vbase + before + incl - sp;
+        const int32_t pos = cbase + cbefore + cincl - 1;
+        vstart[b] = v;
+        vsorted[pos] = v;
+        vorder[pos] = b;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        s_carry += total;
+        s_ccarry += ctotal;
+      }
+      __syncthreads();
+    }
+    vbase += cls_pts;
+    cbase += cls_cnt;
+  }
   if (threadIdx.x == 0) {
-    vstart[nb] = s_carry;
-    const int64_t groups = s_carry / 64;
+    vstart[nb] = vbase;
+    vsorted[nb] = vbase;
+    const int64_t groups = vbase / 64;
     vhdr[0] = (bad || groups > cap_groups) ? 0 : groups;  // 0: the join does nothing
     vhdr[1] = (bad || groups > cap_groups) ? 1 : 0;
   }
 }
 
-__global__ __launch_bounds__(256) void batch_fill_kernel(const int64_t *vstart, int32_t nb,
+__global__ __launch_bounds__(256) void batch_fill_kernel(const int64_t *vsorted,
+                                                         const int32_t *vorder, int32_t nb,
                                                          const int64_t *vhdr,
                                                          int32_t *group_batch) {
   const int64_t ng = vhdr[0];
   for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < ng;
        g += (int64_t)gridDim.x * 256) {
-    // last batch whose first point is at or before the group's
+    // the last batch in virtual order whose first point is at or before the
+    // group's (empty batches, all of class 0, come first)
     int32_t lo = 0, hi = nb - 1;
     const int64_t v = g * 64;
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) >> 1;
-      if (vstart[mid] <= v) lo = mid; else hi = mid - 1;
+      if (vsorted[mid] <= v) lo = mid; else hi = mid - 1;
     }
-    group_batch[g] = lo;
+    group_batch[g] = vorder[lo];
   }
 }
 
 // Completion tick of each batch: the latest tick of its groups (the resolve
 // kernel's, in exact mode, which runs after the probe).
-__global__ __launch_bounds__(256) void batch_finish_kernel(const int64_t *vstart, int32_t nb,
+__global__ __launch_bounds__(256) void batch_finish_kernel(const act_batch *batches,
+                                                           const int64_t *vstart, int32_t nb,
                                                            const int64_t *vhdr,
                                                            const uint64_t *gticks,
                                                            uint64_t *ticks) {
@@ -1321,8 +1397,10 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(const int64_t *vstart
   const bool ok = vhdr[0] > 0 || vstart[nb] == 0;
   for (int64_t b = wave; b < nb; b += nwaves) {
     uint64_t t = 0;
-    if (ok)
-      for (int64_t g = vstart[b] / 64 + lane; g < vstart[b + 1] / 64; g += 64) t = max(t, gticks[g]);
+    if (ok) {
+      const int64_t g0 = vstart[b] / 64, g1 = g0 + batch_span(batches[b].n) / 64;
+      for (int64_t g = g0 + lane; g < g1; g += 64) t = max(t, gticks[g]);
+    }
     for (int d = 32; d > 0; d >>= 1) t = max(t, (uint64_t)__shfl_xor(t, d));
     if (lane == 0) ticks[1 + b] = ok ? (t ? t : ticks[0]) : 0;
   }
@@ -1429,12 +1507,13 @@ static int upload(T *&dst, const void *src, size_t bytes, size_t &total) {
 }
 
 static void free_batch_workspace(Workspace &w) {
-  void *ptrs[] = {w.bmask, w.gticks, w.group_batch, w.vstart, w.vhdr};
+  void *ptrs[] = {w.bmask, w.gticks, w.group_batch, w.vstart, w.vhdr, w.vsorted, w.vorder};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   w.bmask = w.gticks = nullptr;
   w.group_batch = nullptr;
-  w.vstart = w.vhdr = nullptr;
+  w.vstart = w.vhdr = w.vsorted = nullptr;
+  w.vorder = nullptr;
   w.cap_groups = 0;
   w.cap_batches = 0;
 }
@@ -1472,6 +1551,8 @@ static int get_batch_workspace(const act_index *x, void *stream, int32_t nb, int
               hipMalloc((void **)&w.gticks, 8 * (size_t)g) == hipSuccess &&
               hipMalloc((void **)&w.group_batch, 4 * (size_t)g) == hipSuccess &&
               hipMalloc((void **)&w.vstart, 8 * ((size_t)b + 1)) == hipSuccess &&
+              hipMalloc((void **)&w.vsorted, 8 * ((size_t)b + 1)) == hipSuccess &&
+              hipMalloc((void **)&w.vorder, 4 * ((size_t)b + 1)) == hipSuccess &&
               hipMalloc((void **)&w.vhdr, 64) == hipSuccess;
     if (!ok) {
       free_batch_workspace(w);
@@ -1745,9 +1826,9 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   const bool exact = h.mode == ACT_EXACT;
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(batch_setup_kernel, dim3(1), dim3(kSetupBlock), 0, st, d_batches, nb,
-                     w->cap_groups, w->vstart, w->vhdr, d_ticks);
-  hipLaunchKernelGGL(batch_fill_kernel, dim3(kBatchGrid), dim3(256), 0, st, w->vstart, nb,
-                     w->vhdr, w->group_batch);
+                     w->cap_groups, w->vstart, w->vsorted, w->vorder, w->vhdr, d_ticks);
+  hipLaunchKernelGGL(batch_fill_kernel, dim3(kBatchGrid), dim3(256), 0, st, w->vsorted, w->vorder,
+                     nb, w->vhdr, w->group_batch);
   ProbeParams P{};
   index_params(x, ACT_REFINE_LOCAL, n_lds, P);  // batched: cell-local refinement
   P.batches = d_batches;
@@ -1765,7 +1846,7 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   }
   if (d_ticks)
     hipLaunchKernelGGL(batch_finish_kernel, dim3((unsigned)std::min<int64_t>(((int64_t)nb + 3) / 4, 4096)),
-                       dim3(256), 0, st, w->vstart, nb, w->vhdr, w->gticks, d_ticks);
+                       dim3(256), 0, st, d_batches, w->vstart, nb, w->vhdr, w->gticks, d_ticks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return fail(ACT_E_HIP, std::string("batched join launch: ") + hipGetErrorString(e));

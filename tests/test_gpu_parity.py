@@ -446,6 +446,38 @@ def test_batched_matches_oracle_and_single(act, mode, prec):
     assert act.wall_clock_hz(0) > 1e6
 
 
+def test_batched_small_batches_complete_first(act):
+    """Batches are laid out smallest size class first: in an uneven mix the
+    smallest quarter of the batches completes well before the largest
+    quarter, and every output still equals the single join's. (Approximate
+    mode: batches complete as their tiles do; in exact mode with the
+    resolve kernel, batches with a pending point complete after it.)"""
+    P, idx = index(act, "c2", "approx", 4.0)
+    rng = np.random.default_rng(33)
+    n_all = 24_000_000
+    pts_all = synth.workload_points("c2", 0, n_all)
+    spans = _uneven_batches(pts_all, rng, 1500, 2e5)
+    rng.shuffle(spans)  # input order unrelated to size
+    dev = torch.from_numpy(pts_all).cuda()
+    batches = [(dev[a:b], torch.full((b - a,), -7, dtype=torch.int32, device="cuda"))
+               for a, b in spans]
+    desc, total = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    idx.join_batched(desc, total, ticks=ticks)
+    torch.cuda.synchronize()
+    assert idx.batched_ok()
+    single = idx.join(dev).cpu().numpy()
+    for (a, b), (_, o) in zip(spans, batches):
+        assert np.array_equal(o.cpu().numpy(), single[a:b]), (a, b)
+    t = ticks.cpu().numpy().view(np.uint64).astype(np.float64)
+    done = t[1:] - t[0]
+    size = np.array([b - a for a, b in spans])
+    order = np.argsort(size, kind="stable")
+    q = len(order) // 4
+    small, large = np.median(done[order[:q]]), np.median(done[order[-q:]])
+    assert small < 0.5 * large, (small, large)
+
+
 def test_batched_graph_replays(act):
     """The batched join captured once into a HIP graph (through torch) and
     replayed three times, with eager joins and output clearing between the
