@@ -557,6 +557,15 @@ def test_autotuner_keeps_results_and_caches(act, tmp_path):
         (r["grid"], r["lds_levels"], r["points_per_lane"], r["refine"])
     assert np.array_equal(idx2.join(pts).cpu().numpy(), before)
     assert np.array_equal(oracle.join(P, pts[:200000].cpu().numpy()).out, before[:200000])
+    # a cache line that is not a valid launch (three points per lane) is
+    # skipped: the tuner times the sweep instead of applying it
+    bad = str(tmp_path / "act_tune_bad.txt")
+    with open(bad, "w") as f:
+        f.write("%x gfx950 1024 2 3 1 1\n" % r["index_digest"])
+    idx3 = act.build(P, "exact")
+    r3 = idx3.tune(pts, cache_path=bad)
+    assert not r3["from_cache"] and r3["n_configs"] >= 20 and r3["points_per_lane"] in (1, 2)
+    assert np.array_equal(idx3.join(pts).cpu().numpy(), before)
 
 
 def test_server_results_same_alone_and_in_mix(act):
