@@ -396,6 +396,29 @@ def test_pending_lists_and_mask_agree(act):
     assert np.array_equal(o1[sample], ref.out)
 
 
+def test_concurrent_streams_share_an_index(act):
+    """Joins of one exact index enqueued on two streams at once (each stream
+    has its own pending workspace), with the pending points listed and
+    resolved by a second kernel on one and resolved in the probe on the
+    other: every result equals the one-stream join's."""
+    P, idx = index(act, "c2", "exact")
+    a = torch.from_numpy(synth.workload_points("c2", 0, 2_000_000)).cuda()
+    b = torch.from_numpy(synth.workload_points("c2", 2_000_000, 3_500_000)).cuda()
+    ref_a, ref_b = idx.join(a).cpu().numpy(), idx.join(b).cpu().numpy()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            oa, _, _ = idx.join_ex(a, pending=act.ACT_PENDING_KERNEL, stream=s1)
+        with torch.cuda.stream(s2):
+            ob, _, _ = idx.join_ex(b, pending=act.ACT_PENDING_QUEUE, stream=s2)
+            ob2, _, _ = idx.join_ex(a, pending=act.ACT_PENDING_KERNEL, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(oa.cpu().numpy(), ref_a)
+        assert np.array_equal(ob.cpu().numpy(), ref_b)
+        assert np.array_equal(ob2.cpu().numpy(), ref_a)
+
+
 def test_overlapping_polygons_approx(act):
     P = overlapping_polygons(seed=14)
     idx = act.build(P, "approx", 2.0)
