@@ -204,16 +204,22 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
                 lat[k] = tm["done_s"] - tm["arrival_s"]
                 done_t[k] = tm["done_s"]
 
+        # the request views and arrival times are made before the clock
+        # starts; the submit loop paces itself on time.monotonic, the clock
+        # act_server_clock reads (CLOCK_MONOTONIC), without a library call
+        views = [pools[t][a:a + n] for t, a, n in zip(target, starts, sizes)]
+        idxs = [int(t) for t in target]
+        t0 = act.Server.clock() + 0.05
+        arrival = (t0 + np.cumsum(gaps)).tolist()
+        off = act.Server.clock() - time.monotonic()
         th = threading.Thread(target=waiter)
         th.start()
-        t0 = act.Server.clock() + 0.05
-        arrival = t0 + np.cumsum(gaps)
+        mono = time.monotonic
         for k in range(nreq):
-            while act.Server.clock() < arrival[k]:
+            due = arrival[k] - off
+            while mono() < due:
                 pass
-            p = pools[target[k]]
-            tickets[k] = srv.submit(int(target[k]), p[starts[k]:starts[k] + sizes[k]],
-                                    arrival=float(arrival[k]))
+            tickets[k] = srv.submit(idxs[k], views[k], arrival=arrival[k])
             ready.release()
         th.join()
         span = float(done_t.max() - arrival[0])
