@@ -160,6 +160,27 @@ int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
 
 /*
+ * act_join_noalloc -- act_join for callers that cannot allocate device
+ * memory: code being captured into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments and results as act_join;
+ * it calls no hipMalloc, hipFree or other allocating routine, on any call.
+ * Exact-mode joins keep their pending mask (one bit per point) in a static
+ * device array of 16 MiB that the library holds on every device it runs on
+ * until the process ends, instead of the stream's workspace, so:
+ *   - n may be at most 2^27 (134,217,728) points per call; larger n returns
+ *     ACT_E_RANGE before anything is launched;
+ *   - all act_join_noalloc calls on one GPU share that array: calls that
+ *     overlap in time on one GPU (different streams or host threads) race
+ *     and must be serialised by the caller. Sequential calls need no
+ *     clearing between them (each join writes every mask word it reads).
+ * Pending points are always resolved by the mask's resolve kernel (or in
+ * the probe's queues, when act_tune chose ACT_PENDING_QUEUE), never by the
+ * per-wave lists. Errors as act_join, plus ACT_E_RANGE.
+ */
+int act_join_noalloc(const act_index *idx, const double *d_points, int64_t n,
+                     int32_t *d_out, void *stream);
+
+/*
  * act_workspace_reserve -- exact-mode joins record the points that need
  * refinement in a per-stream pending workspace owned by the index: a mask
  * (one bit per point of a pass) and per-wave pending lists (8 bytes per

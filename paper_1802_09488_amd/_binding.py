@@ -105,6 +105,7 @@ def _load():
         "act_free": ([p], None),
         "act_join": ([p, p, i64, p, p], ctypes.c_int),
         "act_join_pairs": ([p, p, i64, p, p, p, i64, p, p], ctypes.c_int),
+        "act_join_noalloc": ([p, p, i64, p, p], ctypes.c_int),
         "act_join_ex": ([p, p, p], ctypes.c_int),
         "act_workspace_reserve": ([p, p, i64], ctypes.c_int),
         "act_cell_ids": ([p, i64, p, p], ctypes.c_int),

@@ -1591,6 +1591,37 @@ static int get_workspace(const act_index *x, void *stream, int64_t cap, bool gro
   return ACT_OK;
 }
 
+// ------------------------------------------------ joins that allocate nothing
+//
+// act_join_noalloc keeps the pending mask of its exact joins (one bit per
+// point) in this file-scope device array instead of a per-stream workspace.
+// Every device the library runs on holds its own copy for the life of the
+// process. In host code the array's name is not a device address: the
+// address is looked up once per device, with that device current, and only
+// that pointer is handed to kernels. The mask needs no clearing: every probe
+// writes each mask word its resolve kernel reads.
+constexpr int64_t kNoAllocMaxPoints = 1ll << 27;  // points per call (16 MiB of mask)
+static __device__ __align__(256) uint64_t scratch[kNoAllocMaxPoints / 64];
+
+constexpr int kMaxDevices = 64;
+
+static int noalloc_scratch(int dev, uint64_t *&ptr) {
+  static std::mutex mu;
+  static uint64_t *ptrs[kMaxDevices] = {nullptr};
+  if (dev < 0 || dev >= kMaxDevices) return fail(ACT_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    DeviceGuard g(dev);
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ACT_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    ptrs[dev] = (uint64_t *)p;
+  }
+  ptr = ptrs[dev];
+  return ACT_OK;
+}
+
 static void face_table(const HostIndex &h, FaceDev f[6]) {
   for (int k = 0; k < 6; k++) {
     const FaceRoot &F = h.faces[k];
@@ -1691,7 +1722,10 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
 // Points per probe lane when a join leaves it to the index.
 static int launch_np(const act_index *x) { return x->launch.points_per_lane; }
 
-static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
+// `ext`: a caller-provided pending workspace (its mask only; cap points per
+// pass) used instead of the stream's, so that the join allocates nothing.
+static int join_impl(const act_index *x, const act_join_args *a, void *stream,
+                     Workspace *ext = nullptr) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
   if (!a) return fail(ACT_E_ARG, "args is NULL");
   if (a->n < 0) return fail(ACT_E_ARG, "n < 0");
@@ -1744,8 +1778,12 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream) {
   int64_t pass = std::min(a->n, kMaxLaunchPoints);
   Workspace *w = nullptr;
   if (mode == kExactMask) {
-    rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
-    if (rc) return rc;
+    if (ext) {
+      w = ext;
+    } else {
+      rc = get_workspace(x, stream, std::max<int64_t>(a->n, kDefaultPass), false, w);
+      if (rc) return rc;
+    }
     P.mask = w->mask;
     P.plist = w->plist;
     P.pcount = w->pcount;
@@ -2156,6 +2194,28 @@ int act_join(const act_index *x, const double *d_points, int64_t n, int32_t *d_o
   a.d_out = d_out;
   a.lds_levels = -1;
   return join_impl(x, &a, stream);
+}
+
+int act_join_noalloc(const act_index *x, const double *d_points, int64_t n, int32_t *d_out,
+                     void *stream) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (n > kNoAllocMaxPoints)
+    return fail(ACT_E_RANGE, "act_join_noalloc: " + std::to_string(n) +
+                                 " points exceed its limit of " +
+                                 std::to_string(kNoAllocMaxPoints) + " per call");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  uint64_t *mask = nullptr;
+  int rc = noalloc_scratch(x->device, mask);
+  if (rc) return rc;
+  Workspace w;
+  w.mask = mask;
+  w.cap = kNoAllocMaxPoints;
+  act_join_args a{};
+  a.d_points = d_points;
+  a.n = n;
+  a.d_out = d_out;
+  a.lds_levels = -1;
+  return join_impl(x, &a, stream, &w);
 }
 
 int act_join_pairs(const act_index *x, const double *d_points, int64_t n, int32_t *d_out,
