@@ -486,6 +486,13 @@ int act_orient_fp32_host(const double *a, const double *b, const double *p,
  * tier (host evaluation, tests). */
 int act_orient_exact_host(const double *a, const double *b, const double *p);
 
+/* Many orientation tests at once on the host (tests): abp holds n rows
+ * (ax, ay, bx, by, px, py) as (x = lng, y = lat). tier 0: out[k] = the exact
+ * sign (act_orient_exact_host); tier 1: out[k] = the fp32 tier's decision
+ * (act_orient_fp32_host with origin[2k..2k+1] and m_poly[k]). */
+int act_orient_host_n(const double *abp, const double *origin, const float *m_poly, int64_t n,
+                      int32_t tier, int8_t *out);
+
 /* Message of the last failure on the calling thread ("" if none). */
 /*
  * act_abi_sizes -- sizeof(act_build_opts), sizeof(act_join_args) and

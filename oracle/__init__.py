@@ -39,6 +39,8 @@ def _load():
         lib.oracle_orient_sign.restype = ctypes.c_int
         lib.oracle_orient_sign_exact.argtypes = [d] * 6
         lib.oracle_orient_sign_exact.restype = ctypes.c_int
+        lib.oracle_orient_sign_n.argtypes = [p, i64, ctypes.c_int, p]
+        lib.oracle_orient_sign_n.restype = None
         lib.oracle_covers.argtypes = [p, p, p, i32, i32, d, d, ctypes.c_int]
         lib.oracle_covers.restype = ctypes.c_int
         lib.oracle_join.argtypes = [p, p, p, i32, p, i64, p, p, p, p, i64, p,
@@ -67,6 +69,15 @@ def orient_sign(a, b, p, exact_only: bool = False) -> int:
     """Exact sign of orient2d with points given as (x, y)."""
     f = _load().oracle_orient_sign_exact if exact_only else _load().oracle_orient_sign
     return int(f(float(a[0]), float(a[1]), float(b[0]), float(b[1]), float(p[0]), float(p[1])))
+
+
+def orient_signs(abp: np.ndarray, exact_only: bool = False) -> np.ndarray:
+    """Exact orientation signs of the rows (ax, ay, bx, by, px, py) of an
+    (n, 6) fp64 array, as int8."""
+    abp = np.ascontiguousarray(abp, dtype=np.float64).reshape(-1, 6)
+    out = np.empty(abp.shape[0], np.int8)
+    _load().oracle_orient_sign_n(_ptr(abp), abp.shape[0], int(exact_only), _ptr(out))
+    return out
 
 
 def covers(polys, p: int, lat: float, lng: float, use_bbox: bool = True) -> bool:

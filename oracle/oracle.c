@@ -120,6 +120,16 @@ int oracle_orient_sign_exact(double ax, double ay, double bx, double by,
   return or_orient_exact(ax, ay, bx, by, px, py);
 }
 
+/* Signs of n orientation tests (tests call this to check many cases at
+ * once); abp holds (ax, ay, bx, by, px, py) for each test. */
+void oracle_orient_sign_n(const double *abp, int64_t n, int exact_only, int8_t *out) {
+  for (int64_t k = 0; k < n; k++) {
+    const double *q = abp + 6 * k;
+    out[k] = (int8_t)(exact_only ? or_orient_exact(q[0], q[1], q[2], q[3], q[4], q[5])
+                                 : oracle_orient_sign(q[0], q[1], q[2], q[3], q[4], q[5]));
+  }
+}
+
 /* ---- point in polygon ---------------------------------------------------- */
 
 /* verts: interleaved (lat, lng). Returns 1 if polygon p covers (lat, lng).

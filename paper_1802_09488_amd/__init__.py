@@ -371,6 +371,19 @@ def orient_fp32_host(a, b, p, origin, m_poly) -> int:
     return int(lib.act_orient_fp32_host(*[_np_ptr(x) for x in arr], ctypes.c_float(m_poly)))
 
 
+def orient_host_n(abp, tier, origin=None, m_poly=None) -> np.ndarray:
+    """Signs of the rows (ax, ay, bx, by, px, py) of an (n, 6) array by the
+    library's exact tier (tier 0) or its fp32 tier (tier 1: 0 = undecided)."""
+    abp = np.ascontiguousarray(abp, dtype=np.float64).reshape(-1, 6)
+    n = abp.shape[0]
+    out = np.empty(n, np.int8)
+    o = np.ascontiguousarray(origin if origin is not None else np.zeros((n, 2)), dtype=np.float64)
+    m = np.ascontiguousarray(m_poly if m_poly is not None else np.zeros(n), dtype=np.float32)
+    _b.check(lib.act_orient_host_n(_np_ptr(abp), _np_ptr(o), _np_ptr(m), n, int(tier),
+                                   _np_ptr(out)))
+    return out
+
+
 def orient_exact_host(a, b, p) -> int:
     arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (a, b, p)]
     return int(lib.act_orient_exact_host(*[_np_ptr(x) for x in arr]))

@@ -133,6 +133,7 @@ def _load():
         "act_encode_refs_host": ([p, i32, p, i64, p, p], ctypes.c_int),
         "act_orient_fp32_host": ([p, p, p, p, ctypes.c_float], ctypes.c_int),
         "act_orient_exact_host": ([p, p, p], ctypes.c_int),
+        "act_orient_host_n": ([p, p, p, i64, i32, p], ctypes.c_int),
         "act_last_error": ([], ctypes.c_char_p),
         "act_version": ([], ctypes.c_char_p),
     }

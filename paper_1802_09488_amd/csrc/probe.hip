@@ -2380,6 +2380,19 @@ int act_orient_exact_host(const double *a, const double *b, const double *p) {
   return orient_sign_exact(a[0], a[1], b[0], b[1], p[0], p[1]);
 }
 
+int act_orient_host_n(const double *abp, const double *origin, const float *m_poly, int64_t n,
+                      int32_t tier, int8_t *out) {
+  if (n < 0 || (n > 0 && (!abp || !out)) || tier < 0 || tier > 1 ||
+      (tier == 1 && n > 0 && (!origin || !m_poly)))
+    return fail(ACT_E_ARG, "bad argument");
+  for (int64_t k = 0; k < n; k++) {
+    const double *q = abp + 6 * k;
+    out[k] = (int8_t)(tier == 0 ? orient_sign_exact(q[0], q[1], q[2], q[3], q[4], q[5])
+                                : act_orient_fp32_host(q, q + 2, q + 4, origin + 2 * k, m_poly[k]));
+  }
+  return ACT_OK;
+}
+
 int act_abi_sizes(int64_t *sizes) {
   if (!sizes) return fail(ACT_E_ARG, "sizes is NULL");
   sizes[0] = (int64_t)sizeof(act_build_opts);

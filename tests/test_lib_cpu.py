@@ -177,35 +177,69 @@ def _frac_sign(a, b, p):
     return (d > 0) - (d < 0)
 
 
+def _fp32_cases(rng, n):
+    """(rows, origins, m_poly): near-degenerate lat/lng orientation tests of
+    a polygon with origin o (points within 1e-16 .. 1e-6 degrees of an
+    edge, edges from 1e-7 to 1e-3 degrees long)."""
+    o = np.stack([rng.uniform(-74.2, -73.7, n), rng.uniform(40.5, 40.9, n)], 1)
+    a = o + rng.uniform(-0.05, 0.05, (n, 2))
+    b = a + rng.uniform(-1e-3, 1e-3, (n, 2)) * 10.0 ** rng.integers(-4, 1, (n, 1))
+    t = rng.uniform(-0.2, 1.2, (n, 1))
+    off = rng.uniform(-1, 1, (n, 2)) * 10.0 ** rng.integers(-16, -5, (n, 1))
+    p = a + t * (b - a) + off
+    m = np.max(np.abs(np.concatenate([(a - o), (b - o)], 1).astype(np.float32)), 1)
+    return np.concatenate([a, b, p], 1), o, m
+
+
 def test_fp32_tier_never_decides_wrong(act):
-    """Invariant fuzz of the fp32 tier's error bound: whenever it decides,
-    the sign equals the exact one (near-degenerate lat/lng cases)."""
+    """Invariant fuzz of the fp32 tier's error bound over 1e7 near-degenerate
+    cases: whenever it decides, the sign equals the exact one (the oracle's
+    exact sign, pinned against integer arithmetic in test_oracle.py; the
+    first 20,000 decided cases also against fractions.Fraction)."""
     rng = np.random.default_rng(21)
-    decided = 0
-    n = 30000
-    for k in range(n):
-        o = np.array([rng.uniform(-74.2, -73.7), rng.uniform(40.5, 40.9)])
-        a = o + rng.uniform(-0.05, 0.05, 2)
-        b = a + rng.uniform(-1e-3, 1e-3, 2) * 10.0 ** rng.integers(-4, 1)
-        t = rng.uniform(-0.2, 1.2)
-        off = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-16, -5)
-        p = a + t * (b - a) + off
-        m = float(np.max(np.abs(np.float32(np.concatenate([a - o, b - o])))))
-        s = act.orient_fp32_host(a, b, p, o, m)
-        if s != 0:
-            decided += 1
-            assert s == _frac_sign(a, b, p), (a, b, p, o)
-    assert decided > n // 10
+    decided = fr = 0
+    n = 10_000_000
+    for c0 in range(0, n, 1_000_000):
+        rows, o, m = _fp32_cases(rng, 1_000_000)
+        # rows are (x, y) = (lng, lat) pairs; the tier sees them the same way
+        got = act.orient_host_n(rows, 1, o, m)
+        want = oracle.orient_signs(rows)
+        dec = got != 0
+        decided += int(dec.sum())
+        bad = np.nonzero(dec & (got != want))[0]
+        assert bad.size == 0, (rows[bad[:3]], o[bad[:3]], m[bad[:3]])
+        if fr < 20000:
+            for k in np.nonzero(dec)[0][:20000 - fr]:
+                assert got[k] == _frac_sign(rows[k, 0:2], rows[k, 2:4], rows[k, 4:6])
+                fr += 1
+    assert decided > n // 10 and decided < n  # both outcomes occur
+    # the single-call entry gives the same decisions
+    rows, o, m = _fp32_cases(np.random.default_rng(5), 3000)
+    got = act.orient_host_n(rows, 1, o, m)
+    for k in range(3000):
+        assert act.orient_fp32_host(rows[k, 0:2], rows[k, 2:4], rows[k, 4:6], o[k], m[k]) == got[k]
 
 
 def test_exact_orient_matches_rationals(act):
+    """The library's exact orientation (the builder's predicates and the last
+    refinement tier) on 1e6 near-collinear cases and the oracle's adversarial
+    set equals the oracle's pinned exact sign (and Fraction on 20,000)."""
+    from test_oracle import adversarial_triples
     rng = np.random.default_rng(22)
-    for k in range(20000):
-        a = rng.uniform(-75, -73, 2)
-        b = rng.uniform(-75, -73, 2)
-        t = rng.uniform(-1, 2)
-        p = a + t * (b - a) + rng.integers(-2, 3, 2) * np.spacing(a)
-        assert act.orient_exact_host(a, b, p) == _frac_sign(a, b, p)
+    n = 500_000
+    a = rng.uniform(-75, -73, (n, 2))
+    b = rng.uniform(-75, -73, (n, 2))
+    p = a + rng.uniform(-1, 2, (n, 1)) * (b - a) + rng.integers(-2, 3, (n, 2)) * np.spacing(a)
+    rows = np.concatenate([np.concatenate([a, b, p], 1), adversarial_triples(rng, 500_000)])
+    got = act.orient_host_n(rows, 0)
+    want = oracle.orient_signs(rows)
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, rows[bad[:3]]
+    assert (want == 0).sum() > 10000
+    for k in range(0, 1_000_000, 50):
+        assert got[k] == _frac_sign(rows[k, 0:2], rows[k, 2:4], rows[k, 4:6])
+    for k in range(2000):
+        assert act.orient_exact_host(rows[k, 0:2], rows[k, 2:4], rows[k, 4:6]) == got[k]
 
 
 def _raw_build(act, verts, ring_off, poly_ring_off, mode=0, prec=0.0, device=-1):

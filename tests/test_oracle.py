@@ -25,46 +25,69 @@ def frac_orient(a, b, p):
     return (d > 0) - (d < 0)
 
 
-def _adversarial_triples(rng, n):
-    out = []
-    for _ in range(n):
-        kind = rng.integers(0, 5)
-        if kind == 0:  # generic
-            a, b, p = rng.uniform(-180, 180, (3, 2))
-        elif kind == 1:  # point on the line through a, b (rounded), nudged by ulps
-            a, b = rng.uniform(-75, -73, (2, 2))
-            t = rng.uniform(-0.5, 1.5)
-            p = a + t * (b - a)
-            p = p + rng.integers(-3, 4, 2) * np.spacing(p)
-        elif kind == 2:  # exactly collinear dyadic points
-            a = rng.integers(-2**20, 2**20, 2) / 2.0**10
-            d = rng.integers(-2**10, 2**10, 2) / 2.0**12
-            k = rng.integers(-4, 5)
-            b = a + d
-            p = a + k * d
-        elif kind == 3:  # lat/lng-like, tiny offsets from an edge
-            a = np.array([rng.uniform(-74.3, -73.6), rng.uniform(40.4, 41.0)])
-            b = a + rng.uniform(-1e-3, 1e-3, 2)
-            t = rng.uniform(0, 1)
-            p = a + t * (b - a) + rng.uniform(-1e-15, 1e-15, 2)
-        else:  # widely different magnitudes
-            a = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-30, 3, 2)
-            b = rng.uniform(-1, 1, 2) * 10.0 ** rng.integers(-30, 3, 2)
-            p = a + rng.uniform(0, 1) * (b - a)
-        out.append((tuple(a), tuple(b), tuple(p)))
+def int_orient(a, b, p):
+    """Exact sign by integer arithmetic: every finite double is an integer
+    multiple of 2^-1074, so scaling all six coordinates by 2^1074 turns the
+    determinant into an exact integer expression."""
+    def sc(v):
+        num, den = float(v).as_integer_ratio()
+        return num << (1075 - den.bit_length())
+    ax, ay, bx, by, px, py = (sc(v) for v in (*a, *b, *p))
+    d = (bx - ax) * (py - ay) - (by - ay) * (px - ax)
+    return (d > 0) - (d < 0)
+
+
+def adversarial_triples(rng, n):
+    """(n, 6) rows (ax, ay, bx, by, px, py) of five kinds: generic; near the
+    line through a and b (rounded, nudged by ulps); exactly collinear dyadic;
+    lat/lng-like with tiny offsets from an edge; widely different
+    magnitudes."""
+    kind = rng.integers(0, 5, n)
+    out = np.empty((n, 6))
+    k = kind == 0
+    out[k] = rng.uniform(-180, 180, (k.sum(), 6))
+    k = kind == 1
+    m = k.sum()
+    a, b = rng.uniform(-75, -73, (m, 2)), rng.uniform(-75, -73, (m, 2))
+    p = a + rng.uniform(-0.5, 1.5, (m, 1)) * (b - a)
+    p = p + rng.integers(-3, 4, (m, 2)) * np.spacing(p)
+    out[k] = np.concatenate([a, b, p], 1)
+    k = kind == 2
+    m = k.sum()
+    a = rng.integers(-2**20, 2**20, (m, 2)) / 2.0**10
+    d = rng.integers(-2**10, 2**10, (m, 2)) / 2.0**12
+    out[k] = np.concatenate([a, a + d, a + rng.integers(-4, 5, (m, 1)) * d], 1)
+    k = kind == 3
+    m = k.sum()
+    a = np.stack([rng.uniform(-74.3, -73.6, m), rng.uniform(40.4, 41.0, m)], 1)
+    b = a + rng.uniform(-1e-3, 1e-3, (m, 2))
+    p = a + rng.uniform(0, 1, (m, 1)) * (b - a) + rng.uniform(-1e-15, 1e-15, (m, 2))
+    out[k] = np.concatenate([a, b, p], 1)
+    k = kind == 4
+    m = k.sum()
+    a = rng.uniform(-1, 1, (m, 2)) * 10.0 ** rng.integers(-30, 3, (m, 2))
+    b = rng.uniform(-1, 1, (m, 2)) * 10.0 ** rng.integers(-30, 3, (m, 2))
+    out[k] = np.concatenate([a, b, a + rng.uniform(0, 1, (m, 1)) * (b - a)], 1)
     return out
 
 
 def test_orient_sign_matches_rationals():
+    """1e6 adversarial triples: the oracle's filtered and exact-only signs
+    equal the sign of the exact integer determinant (and, on the first
+    20,000, of the same determinant in fractions.Fraction)."""
     rng = np.random.default_rng(11)
-    cases = _adversarial_triples(rng, 60000)
-    zeros = 0
-    for a, b, p in cases:
-        want = frac_orient(a, b, p)
-        zeros += want == 0
-        assert oracle.orient_sign(a, b, p) == want, (a, b, p)
-        assert oracle.orient_sign(a, b, p, exact_only=True) == want, (a, b, p)
-    assert zeros > 1000  # the adversarial set really exercises the exact path
+    rows = adversarial_triples(rng, 1_000_000)
+    want = np.array([int_orient(r[0:2], r[2:4], r[4:6]) for r in rows], dtype=np.int8)
+    for r, w in zip(rows[:20000], want[:20000]):
+        assert frac_orient(r[0:2], r[2:4], r[4:6]) == w
+    got = oracle.orient_signs(rows)
+    got_exact = oracle.orient_signs(rows, exact_only=True)
+    bad = np.nonzero((got != want) | (got_exact != want))[0]
+    assert bad.size == 0, rows[bad[:3]]
+    assert (want == 0).sum() > 20000  # the adversarial set really exercises the exact path
+    # the single-call entry agrees with the batched one
+    for r, w in zip(rows[:2000], want[:2000]):
+        assert oracle.orient_sign(r[0:2], r[2:4], r[4:6]) == w
 
 
 def _P(*rings_xy):

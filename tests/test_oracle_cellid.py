@@ -46,6 +46,9 @@ def test_hilbert_roundtrip_level30():
 
 def test_st_transform():
     assert C.st_from_uv(np.array([-1.0, 0.0, 1.0])).tolist() == [0.0, 0.5, 1.0]
+    # the linear reading s = (1 + u) / 2 at interior points (a quadratic or
+    # tangent transform gives 0.79 / 0.85 at u = 1/2)
+    assert C.st_from_uv(np.array([-0.5, 0.5, 0.25])).tolist() == [0.25, 0.75, 0.625]
     w = np.linspace(-1, 1, 10001)
     s = C.st_from_uv(w)
     assert np.all(np.diff(s) > 0)
@@ -109,3 +112,33 @@ def test_cell_centre_roundtrip():
     lat2 = np.degrees(np.arctan2(c[2], np.hypot(c[0], c[1])))
     lng2 = np.degrees(np.arctan2(c[1], c[0]))
     assert np.array_equal(C.cell_ids(lat2, lng2), ids)
+
+
+def test_closed_form_leaf_off_centre():
+    """A point off the face centre, derived by hand: on the equator at
+    lng = atan(u) with u = 1/2 + 2^-30, the x axis dominates (face 0), u is
+    y/x = tan(lng) and v = z/x = 0. The linear transform gives
+    s = 3/4 + 2^-31, the middle of leaf column i = 3 * 2^28 (fp64 rounding
+    moves s by about 1e-16, far from the column's edges), and t = 1/2, so
+    j = 2^29 exactly. The Hilbert digits of that leaf follow from the curve's
+    definition: level 1 has (i, j) bits (1, 1) -> digit 2; level 2 has bits
+    (1, 0) -> digit 3, and that quadrant is reflected and transposed, which
+    maps the remaining all-zero (i, j) bits to all ones -> digit 2 at every
+    further level."""
+    u = 0.5 + 2.0 ** -30
+    lng = np.degrees(np.arctan(u))
+    face, uu, vv, s, t = C.project(np.array([0.0]), np.array([lng]))
+    assert face[0] == 0 and vv[0] == 0.0
+    i, j = C.leaf_ij(s, t)
+    assert (int(i[0]), int(j[0])) == (3 << 28, 1 << 29)
+    d = 2
+    d = (d << 2) | 3
+    for _ in range(28):
+        d = (d << 2) | 2
+    ids = C.cell_ids(np.array([0.0]), np.array([lng]))
+    assert int(ids[0]) == (0 << 61) | (d << 1) | 1
+    # the same leaf on the v axis: lat = atan(v) at lng = 0 gives (i, j) =
+    # (2^29, 3 * 2^28) on face 0
+    face, _, _, s, t = C.project(np.array([np.degrees(np.arctan(u))]), np.array([0.0]))
+    i, j = C.leaf_ij(s, t)
+    assert face[0] == 0 and (int(i[0]), int(j[0])) == (1 << 29, 3 << 28)
