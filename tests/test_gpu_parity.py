@@ -5,6 +5,8 @@ set of further (point, polygon) pairs. Approximate mode must respect its
 guarantee: no covering polygon missed, and every extra pair's point lies
 within precision_m of that polygon's boundary.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -197,7 +199,12 @@ def test_c2_exact_sample(act):
                           edge_case_points(P, np.random.default_rng(6))])
     out, pairs, ctr = gpu_join(idx, pts, counters=True)
     assert_exact(P, pts, out, pairs, "c2")
-    assert ctr["candidates"] > 0 and ctr["edge_fp64"] < ctr["edges"]
+    assert ctr["candidates"] > 0 and ctr["cand_points"] > 0
+    # over all edges with the fp32 filter: some edges, not all, go to fp64
+    out2, pairs2, ctr2 = gpu_join(idx, pts, counters=True, refine=act.ACT_REFINE_FP32_FILTER)
+    assert np.array_equal(out2, out) and np.array_equal(pairs2, pairs)
+    assert 0 < ctr2["edge_fp64"] < ctr2["edges"], ctr2
+    assert ctr2["edge_exact"] <= ctr2["edge_fp64"]
 
 
 def test_c2_approx_sample(act):
@@ -733,3 +740,221 @@ def test_c3_approx_1m_guarantee(act):
     n_extra, n_pairs = assert_approx(P, pts, out, pairs, 1.0, "c3-approx1m")
     assert n_extra < 0.05 * n_pairs
     del idx
+
+
+# ----------------------------------------------------- tuned launch paths
+
+def set_launch(act, idx, path, grid, lds, np_, refine, pending):
+    """Make (grid, LDS depth, points per lane, refinement, pending mode) the
+    index's launch configuration through a tuning-cache line, as act_tune
+    would after choosing it."""
+    with open(path, "w") as f:
+        f.write("%016x gfx950 %d %d %d %d %d\n" % (idx.digest(), grid, lds, np_, refine, pending))
+    sample = torch.from_numpy(synth.workload_points("c1", 0, 1024)).cuda()
+    r = idx.tune(sample, cache_path=str(path))
+    assert r["from_cache"] == 1
+    assert (r["grid"], r["lds_levels"], r["points_per_lane"], r["refine"], r["pending"]) == \
+        (grid, lds, np_, refine, pending)
+
+
+def run_batched(act, idx, dev, spans, stream=None):
+    outs = [torch.full((b - a,), -7, dtype=torch.int32, device="cuda") for a, b in spans]
+    desc, total = act.batch_descriptors([(dev[a:b], o) for (a, b), o in zip(spans, outs)])
+    ticks = torch.zeros(len(spans) + 1, dtype=torch.int64, device="cuda")
+    idx.join_batched(desc, total, ticks=ticks, stream=stream)
+    torch.cuda.synchronize()
+    assert idx.batched_ok(stream=stream)
+    t = ticks.cpu().numpy().view(np.uint64)
+    assert t[0] > 0 and np.all(t[1:] >= t[0])
+    return outs
+
+
+def test_batched_every_tuned_launch(act, tmp_path):
+    """Batched joins in every launch configuration act_tune can pick (exact:
+    pending points resolved by the mask's kernel or in the probe's queues,
+    one or two points per lane, LDS depth 0-2, several grids; approximate:
+    points per lane x LDS depth): every batch's output equals the oracle's
+    (exact) or the single join's (approximate)."""
+    P, idx = index(act, "c2", "exact")
+    rng = np.random.default_rng(61)
+    pts_all = synth.workload_points("c2", 0, 1_200_000)
+    spans = _uneven_batches(pts_all, rng, 300, 2e4)
+    n = spans[-1][1]
+    ref = oracle.join(P, pts_all[:n]).out
+    dev = torch.from_numpy(pts_all).cuda()
+    grids = [256, 512, 1024, 2048, 4096]
+    k = 0
+    for pending in (act.ACT_PENDING_KERNEL, act.ACT_PENDING_QUEUE):
+        for np_ in (1, 2):
+            for lds in (0, 1, 2):
+                g = grids[k % len(grids)]
+                k += 1
+                print("batched exact pending=%d np=%d lds=%d grid=%d" % (pending, np_, lds, g),
+                      flush=True)
+                set_launch(act, idx, tmp_path / "l.txt", g, lds, np_, act.ACT_REFINE_LOCAL,
+                           pending)
+                outs = run_batched(act, idx, dev, spans)
+                got = np.concatenate([o.cpu().numpy() for o in outs])
+                bad = np.nonzero(got != ref)[0]
+                assert bad.size == 0, (pending, np_, lds, g, bad[:5])
+    Pa, ia = index(act, "c2", "approx", 4.0)
+    single = ia.join(dev[:n]).cpu().numpy()
+    for np_ in (1, 2):
+        for lds in (0, 1, 2):
+            print("batched approx np=%d lds=%d" % (np_, lds), flush=True)
+            set_launch(act, ia, tmp_path / "la.txt", 2048, lds, np_, act.ACT_REFINE_LOCAL,
+                       act.ACT_PENDING_KERNEL)
+            got = np.concatenate([o.cpu().numpy() for o in run_batched(act, ia, dev, spans)])
+            assert np.array_equal(got, single), (np_, lds)
+    # the indexes are shared with other tests: back to the built-in defaults
+    for x in (idx, ia):
+        set_launch(act, x, tmp_path / "d.txt", 1024, -1, 2, act.ACT_REFINE_LOCAL,
+                   act.ACT_PENDING_KERNEL)
+
+
+@pytest.mark.timeout(900)
+def test_c4_batches_on_c3_index(act):
+    """The C4 configuration: 10,000 batches of floor(exp(U(0, ln 1e6)))
+    points (seed 3004) of the C3 stream against the 40,000-polygon exact
+    index, in one batched join, with pending points resolved in the probe's
+    queues (the autotuner's pick for this workload) and by the mask's
+    kernel. The two agree on every point; the oracle checks 1% of the
+    batches (seeded) and every batch under 1,000 points."""
+    P, idx = index(act, "c3", "exact")
+    sizes = synth.batch_sizes(10_000, 3004)
+    total = int(sizes.sum())
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    print("c4: staging %d points" % total, flush=True)
+    dev = torch.empty((total, 2), dtype=torch.float64, device="cuda")
+    step = 1 << 24
+    for s0 in range(0, total, step):
+        s1 = min(total, s0 + step)
+        dev[s0:s1].copy_(torch.from_numpy(synth.workload_points("c3", s0, s1)))
+    spans = list(zip(bounds[:-1].tolist(), bounds[1:].tolist()))
+    import tempfile
+    outs = {}
+    with tempfile.TemporaryDirectory() as td:
+        for pending in (act.ACT_PENDING_QUEUE, act.ACT_PENDING_KERNEL):
+            print("c4: pending=%d" % pending, flush=True)
+            set_launch(act, idx, os.path.join(td, "c4.txt"), 256, 2, 2, act.ACT_REFINE_LOCAL,
+                       pending)
+            outs[pending] = run_batched(act, idx, dev, spans)
+        set_launch(act, idx, os.path.join(td, "d.txt"), 1024, -1, 2, act.ACT_REFINE_LOCAL,
+                   act.ACT_PENDING_KERNEL)
+    for a, b in zip(outs[act.ACT_PENDING_QUEUE], outs[act.ACT_PENDING_KERNEL]):
+        assert torch.equal(a, b)
+    rng = np.random.default_rng(3005)
+    pick = set(rng.choice(len(spans), len(spans) // 100, replace=False).tolist())
+    pick |= set(np.nonzero(sizes < 1000)[0].tolist())
+    pick = sorted(pick)
+    print("c4: oracle on %d batches, %d points" % (len(pick), int(sizes[pick].sum())),
+          flush=True)
+    sel = np.concatenate([np.arange(*spans[b]) for b in pick])
+    ref = oracle.join(P, dev[torch.from_numpy(sel).cuda()].cpu().numpy()).out
+    got = np.concatenate([outs[act.ACT_PENDING_QUEUE][b].cpu().numpy() for b in pick])
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, (bad.size, sel[bad[:5]])
+    del dev
+
+
+def test_server_with_c3_exact_index(act):
+    """Serving over the two indexes of the C5 configuration (C2 approx@4m,
+    C3 exact): 300 requests of 1 .. 2e4 points submitted as a burst to a
+    4-slot server; every result equals the request joined alone, and the
+    C3-exact results equal the oracle's."""
+    P2, ia = index(act, "c2", "approx", 4.0)
+    P3, ie = index(act, "c3", "exact")
+    rng = np.random.default_rng(45)
+    pools = [synth.workload_points("c2", 0, 1_000_000), synth.workload_points("c3", 0, 1_000_000)]
+    srv = act.Server([ia, ie], slots=4, arena_bytes=4_000_000, max_request_points=1 << 16)
+    reqs = []
+    for k in range(300):
+        n = int(np.floor(np.exp(rng.uniform(0, np.log(2e4)))))
+        w = int(rng.integers(0, 2))
+        a = int(rng.integers(0, len(pools[w]) - n))
+        reqs.append((w, pools[w][a:a + n]))
+    tickets = [srv.submit(w, p, arrival=act.Server.clock()) for w, p in reqs]
+    exact_pts, exact_out = [], []
+    for (w, p), t in zip(reqs, tickets):
+        out, tm = srv.wait(t)
+        assert tm["n"] == len(p)
+        alone = (ia if w == 0 else ie).join(torch.from_numpy(p).cuda()).cpu().numpy()
+        assert np.array_equal(out, alone)
+        if w == 1:
+            exact_pts.append(p)
+            exact_out.append(out)
+    ref = oracle.join(P3, np.concatenate(exact_pts)).out
+    assert np.array_equal(np.concatenate(exact_out), ref)
+    st = srv.stats()
+    assert st["completed"] == 300 and st["failed"] == 0
+    srv.close()
+
+
+@pytest.mark.timeout(900)
+def test_c3_exact_pin_sample(act):
+    """C3 exact at the pinned sample size: the first 1e6 points of batch 0
+    plus 1e6 seeded random positions of the 1e9-point stream (drawn within 64
+    seeded 2^20-point chunks spread over all 60 batches), bit-exact against
+    the oracle, with the pair sets."""
+    P, idx = index(act, "c3", "exact")
+    rng = np.random.default_rng(54)
+    N = synth.WORKLOADS["c3"]["n_points"]
+    chunk = 1 << 20
+    parts = [synth.workload_points("c3", 0, 1_000_000)]
+    for c in np.sort(rng.choice(N // chunk, 64, replace=False)):
+        pts = synth.workload_points("c3", int(c) * chunk, int(c + 1) * chunk)
+        parts.append(pts[np.sort(rng.choice(chunk, 1_000_000 // 64 + 1, replace=False))])
+    pts = np.concatenate(parts)[:2_000_000]
+    out, pairs, _ = gpu_join(idx, pts)
+    assert_exact(P, pts, out, pairs, "c3-pin")
+
+
+def _cell_corner_points(P, rng, n, levels):
+    """Points within a few ulps of cell corners and cell edges at the given
+    quadtree levels, in the cells met by polygon edges: a point on a random
+    polygon edge gives a cell; its corners (and edge midpoints) are mapped
+    back to lat/lng by inverting the projection, then moved by -2 .. 2 ulps
+    in each coordinate."""
+    v = P.verts
+    a = rng.integers(0, len(v) - 1, n)
+    t = rng.uniform(0, 1, (n, 1))
+    on_edge = v[a] + t * (v[a + 1] - v[a])
+    face, _, _, s, tt = C.project(on_edge[:, 0], on_edge[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    lvl = rng.choice(levels, n)
+    sh = 30 - lvl
+    # corner offsets: 0 or 1 cell in each axis, or half a cell along an edge
+    oi = rng.choice([0.0, 1.0, 0.5], n)
+    oj = np.where(oi == 0.5, rng.choice([0.0, 1.0], n), rng.choice([0.0, 1.0, 0.5], n))
+    si = (((i >> sh) + oi) * (2.0 ** sh)) / C.N
+    sj = (((j >> sh) + oj) * (2.0 ** sh)) / C.N
+    u, w = C.uv_from_st(si), C.uv_from_st(sj)
+    ax = face % 3
+    sign = np.where(face >= 3, -1.0, 1.0)
+    c = np.zeros((3, n))
+    k = np.arange(n)
+    c[ax, k] = sign
+    c[(ax + 1) % 3, k] = u
+    c[(ax + 2) % 3, k] = w
+    lat = np.degrees(np.arctan2(c[2], np.hypot(c[0], c[1])))
+    lng = np.degrees(np.arctan2(c[1], c[0]))
+    pts = np.stack([lat, lng], 1)
+    return pts + rng.integers(-2, 3, (n, 2)) * np.spacing(pts)
+
+
+@pytest.mark.parametrize("w", ["c2", "c3"])
+def test_points_at_cell_edges(act, w):
+    """Points within rounding of cell corners and edges at the covering's
+    levels (reading: the cell boxes' 1e-9 degree margin absorbs the
+    difference between the GPU's projection and any other): exact parity
+    with the oracle, pairs included, in every refinement mode."""
+    P, idx = index(act, w, "exact")
+    st = idx.stats()
+    top = st["max_cell_level"]
+    pts = _cell_corner_points(P, np.random.default_rng(71), 150_000,
+                              np.arange(max(1, top - 6), top + 1))
+    ids = C.cell_ids(pts[:, 0], pts[:, 1])
+    assert len(np.unique(ids)) > 50_000
+    for mode in REFINE_MODES:
+        out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+        assert_exact(P, pts, out, pairs, "%s-cell-edges-%s" % (w, mode))
