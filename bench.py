@@ -239,11 +239,14 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
             "launch_groups": st["launches"]}
 
 
-def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
+def cpu_baseline_and_parity(P, workload, n_sample, gpu_out, gpu_pairs=None, gpu_counts=None,
+                            one_thread_points=1_000_000):
     """The oracle (brute force: bbox prefilter + exact point-in-polygon
     against every polygon, OpenMP over points) on the host's cores over the
     first n_sample points of the stream; its output is compared with the
-    GPU's exact-mode output for those points."""
+    GPU's exact-mode output for those points: out[], and, when given, the
+    GPU's further (point, polygon) pairs and per-polygon counts. The oracle
+    is also timed on one thread over the first one_thread_points points."""
     import numpy as np
 
     import oracle
@@ -253,6 +256,8 @@ def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
     step = 1 << 24
     dt = 0.0
     mism = 0
+    ref_pairs = []
+    counts = np.zeros(P.n_polys, np.int64)
     for s in range(0, n_sample, step):
         e = min(n_sample, s + step)
         pts = synth.workload_points(workload, s, e)
@@ -260,12 +265,134 @@ def cpu_baseline_and_parity(P, workload, n_sample, gpu_out):
         ref = oracle.join(P, pts, nthreads=cores)
         dt += time.perf_counter() - t0
         mism += int(np.count_nonzero(ref.out != gpu_out[s:e]))
+        if len(ref.pairs):
+            ref_pairs.append(ref.pairs + np.array([s, 0]))
+        counts += np.bincount(ref.pair_set()[:, 1], minlength=P.n_polys)
     base = {"value": n_sample / dt, "unit": "points/s", "cores": cores, "kind": "oracle",
             "sample": "points 0..%d of the %s stream (%s), exact join, %d threads, %.1f s"
                       % (n_sample, workload, "the whole workload" if n_sample == len(gpu_out)
                          else "a prefix", cores, dt)}
+    n1 = min(one_thread_points, n_sample)
+    pts = synth.workload_points(workload, 0, n1)
+    t0 = time.perf_counter()
+    oracle.join(P, pts, nthreads=1)
+    d1 = time.perf_counter() - t0
+    base["one_thread"] = {"value": n1 / d1, "unit": "points/s", "cores": 1,
+                          "sample": "points 0..%d of the %s stream, exact join, 1 thread, %.1f s"
+                                    % (n1, workload, d1)}
     parity = {"points_checked": n_sample, "out_mismatches": mism}
+    if gpu_pairs is not None:
+        rp = np.concatenate(ref_pairs) if ref_pairs else np.zeros((0, 2), np.int64)
+        rp = rp[np.lexsort((rp[:, 1], rp[:, 0]))]
+        gp = gpu_pairs[(gpu_pairs[:, 0] < n_sample)]
+        gp = gp[np.lexsort((gp[:, 1], gp[:, 0]))]
+        parity["pairs_checked"] = int(len(rp))
+        parity["pairs_identical"] = bool(np.array_equal(rp, gp))
+    if gpu_counts is not None and n_sample == len(gpu_out):
+        parity["counts_identical"] = bool(np.array_equal(counts, gpu_counts))
+        parity["count_pairs_total"] = int(counts.sum())
     return base, parity
+
+
+def precomputed_ids_leg(act, indexes, pts, steps, exact_out):
+    """Joins of points that arrive with their level-30 cell ids (the paper's
+    probe input): the ids are computed once (act_cell_ids, timed too), then
+    act_join_ids is timed per index; its algorithmic traffic is 12 B per
+    point (8 B id in, 4 B id out) plus 16 B per pending point in exact
+    mode."""
+    import numpy as np
+    import torch
+    n = pts.shape[0]
+    ids = torch.empty(n, dtype=torch.int64, device="cuda")
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ms = []
+    for k in range(steps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        act.cell_ids(pts, out=ids)
+        b.record()
+        torch.cuda.synchronize()
+        if k:
+            ms.append(a.elapsed_time(b))
+    res = {"cell_ids_ms_median": float(np.median(ms))}
+    for name, idx in indexes:
+        exact = idx.mode == act.ACT_EXACT
+        ms = []
+        for k in range(steps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            idx.join_ids(ids, pts if exact else None, out=out)
+            b.record()
+            torch.cuda.synchronize()
+            if k:
+                ms.append(a.elapsed_time(b))
+        med = float(np.median(ms))
+        r = {"join_ms_median": med, "points_per_s": n / (med * 1e-3),
+             "roofline_frac_12B": 12 * n / (med * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        if exact:
+            r["identical_to_join"] = bool(np.array_equal(out.cpu().numpy(), exact_out))
+        res[name] = r
+    del ids, out
+    return res
+
+
+def pairs_and_counts_leg(act, indexes, pts, steps):
+    """Timed pair-emitting joins (act_join_pairs: out[] plus every further
+    (point, polygon) pair) and per-polygon count joins (act_join_count) over
+    the resident points, for each (name, index); buffers are allocated once
+    and the counters zeroed before each timed call. Returns the timings and
+    the exact index's pairs and counts (host) for the oracle check."""
+    import ctypes
+
+    import numpy as np
+    import torch
+    n = pts.shape[0]
+    lib = act.lib
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    cap = n // 8
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    pp = torch.empty(cap, dtype=torch.int64, device="cuda")
+    pq = torch.empty(cap, dtype=torch.int32, device="cuda")
+    npairs = torch.zeros(1, dtype=torch.int64, device="cuda")
+    P_ = ctypes.c_void_p
+    res, keep = {}, {}
+    for name, idx in indexes:
+        npoly = idx.n_polys
+        counts = torch.zeros(npoly, dtype=torch.int64, device="cuda")
+
+        def pairs_call():
+            act._b.check(lib.act_join_pairs(idx.handle, P_(pts.data_ptr()), n, P_(out.data_ptr()),
+                                            P_(pp.data_ptr()), P_(pq.data_ptr()), cap,
+                                            P_(npairs.data_ptr()), st))
+
+        def count_call():
+            act._b.check(lib.act_join_count(idx.handle, P_(pts.data_ptr()), n,
+                                            P_(counts.data_ptr()), st))
+        r = {}
+        for what, call, zero in (("pairs", pairs_call, npairs), ("count", count_call, counts)):
+            ms = []
+            for k in range(steps + 1):
+                zero.zero_()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                call()
+                b.record()
+                torch.cuda.synchronize()
+                if k:
+                    ms.append(a.elapsed_time(b))
+            med = float(np.median(ms))
+            r[what] = {"join_ms_median": med, "points_per_s": n / (med * 1e-3)}
+        m = int(npairs.item())
+        r["pairs"]["extra_pairs"] = m
+        r["pairs"]["complete"] = m <= cap
+        r["count"]["pairs_counted"] = int(counts.sum().item())
+        res[name] = r
+        if name == "exact":
+            keep["pairs"] = torch.stack([pp[:min(m, cap)],
+                                         pq[:min(m, cap)].to(torch.int64)], 1).cpu().numpy()
+            keep["counts"] = counts.cpu().numpy()
+    del out, pp, pq
+    return res, keep
 
 
 def main():
@@ -369,12 +496,22 @@ def run_c2(args):
             var[name]["identical_to_local"] = bool(np.array_equal(out.cpu().numpy(), exact_out))
     var["fp32_filter_over_fp64_speedup"] = (var["fp64"]["join_ms_mean"]
                                             / var["fp32_filter"]["join_ms_mean"])
+    # the fp32 tier's share of edges left to the fp64 re-test (and to the
+    # exact expansion after it)
+    _, _, c32 = idx.join_ex(pts, out, counters=True, refine=act.ACT_REFINE_FP32_FILTER)
+    var["fp32_filter"]["edges_tested"] = c32["edges"]
+    var["fp32_filter"]["fp64_retest_share"] = c32["edge_fp64"] / max(1, c32["edges"])
+    var["fp32_filter"]["exact_share"] = c32["edge_exact"] / max(1, c32["edges"])
     # cell-local refinement with pending points resolved by the probe's waves
     wq, tq, _ = time_joins(idx, pts, out, k, 1, pending=act.ACT_PENDING_QUEUE)
     torch.cuda.synchronize()
     var["local_in_probe_queue"] = {"points_per_s": n * k / wq, "join_ms_mean": float(np.mean(tq)),
                                    "identical_to_local": bool(np.array_equal(out.cpu().numpy(),
                                                                              exact_out))}
+    log("pair output and per-polygon counts")
+    pc, pc_keep = pairs_and_counts_leg(act, [("exact", idx), ("approx4m", idx_a)], pts, k)
+    log("joins of precomputed cell ids")
+    ids_leg = precomputed_ids_leg(act, [("exact", idx), ("approx4m", idx_a)], pts, k, exact_out)
     log("batched join (graph replay)")
     batched = batched_leg(act, idx, pts, exact_out)
     log("serving")
@@ -424,6 +561,8 @@ def run_c2(args):
                      / PEAK_HBM_GBS,
                      "traffic": traffic["approx"] if traffic and "approx" in traffic else None},
         "refine_variants": var,
+        "pairs_and_counts": pc,
+        "precomputed_ids": ids_leg,
         "counters_exact": ctr,
         "counters_approx4m": ctr_a,
         "index": {"exact": {k2: st[k2] for k2 in ("n_cells", "n_nodes", "node_bytes", "lut_words",
@@ -441,7 +580,7 @@ def run_c2(args):
         log("cpu baseline (oracle)")
         ns = min(args.cpu_sample or n, n)
         res["cpu_baseline"], res["parity_vs_oracle"] = cpu_baseline_and_parity(
-            P, args.workload, ns, exact_out)
+            P, args.workload, ns, exact_out, pc_keep.get("pairs"), pc_keep.get("counts"))
     print(json.dumps(res), flush=True)
 
 

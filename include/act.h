@@ -53,7 +53,14 @@ enum {
   ACT_E_RANGE = -7     /* request beyond a documented limit                  */
 };
 
-enum { ACT_EXACT = 0, ACT_APPROX = 1 };
+/* ACT_AUTO: the paper's policy for a memory budget and a precision
+ * (Section III-A): the approximate index at precision_m when its device
+ * image fits act_build_opts.memory_budget, otherwise the exact index,
+ * trained with the options' training points within the budget (Section
+ * III-D); if even the untrained exact index does not fit, its covering
+ * level is lowered (by two levels at a time) until it does. The built
+ * index reports the mode it took (act_stats.mode). */
+enum { ACT_EXACT = 0, ACT_APPROX = 1, ACT_AUTO = 2 };
 
 /* Refinement of candidate hits in exact mode. All modes give identical,
  * exact results; they differ in cost. */
@@ -92,6 +99,22 @@ typedef struct {
   double margin_deg;   /* conservative inflation of every cell's lat/lng box
                           before classification (default 1e-9 deg, which
                           covers fp64 projection rounding by >1e3x)          */
+  /* Training (Section III-D), exact mode only: the index adapts to the
+   * expected points. Each training point, in order, that falls into an
+   * expensive cell (one with a candidate reference) splits that cell into
+   * its four children, classified against the cell's references, until
+   * the points run out or the next split would take the index's device
+   * image beyond memory_budget. Ignored in approximate mode. */
+  const double *train_points; /* host, 2 * n_train doubles (lat, lng); the
+                                 array is read during act_build only       */
+  int64_t n_train;            /* 0 (default): no training                  */
+  int64_t memory_budget;      /* bytes of the device image (as
+                                 act_stats.device_bytes); 0 = no limit.
+                                 With ACT_AUTO also the approximate
+                                 index's limit                             */
+  int32_t train_max_level;    /* finest level training splits to (default
+                                 30)                                       */
+  int32_t reserved0;
 } act_build_opts;
 
 /* Fills *opts with the defaults (the values act_build uses for NULL). */
@@ -107,7 +130,8 @@ void act_build_opts_init(act_build_opts *opts);
  *               poly_ring_off[p] .. poly_ring_off[p+1]-1; the first is the
  *               outer ring, the rest are holes. Orientation is arbitrary.
  *               Polygons may overlap (a point then matches several).
- * mode          ACT_EXACT or ACT_APPROX.
+ * mode          ACT_EXACT, ACT_APPROX or ACT_AUTO (needs a memory budget
+ *               in opts).
  * precision_m   approx mode: every reported pair is a true containment or
  *               the point lies within precision_m metres of the polygon's
  *               boundary (cells are split until their diagonal is below
@@ -119,7 +143,8 @@ void act_build_opts_init(act_build_opts *opts);
  * Consecutive duplicate vertices are dropped.
  * Errors: ACT_E_ARG, ACT_E_POLY (fewer than 3 distinct vertices in a ring,
  * non-finite or out-of-range coordinates, more than 2^30 polygons),
- * ACT_E_OOM, ACT_E_HIP, ACT_E_DEVICE.
+ * ACT_E_OOM, ACT_E_HIP, ACT_E_DEVICE, ACT_E_RANGE (ACT_AUTO: no index fits
+ * the budget).
  */
 int act_build(const double *verts_latlng, const int64_t *ring_off,
               const int32_t *poly_ring_off, int32_t n_polys, int32_t mode,
@@ -129,6 +154,22 @@ int act_build(const double *verts_latlng, const int64_t *ring_off,
 /* Release an index and its device memory. NULL is a no-op. The caller must
  * make sure no join on it is still running. */
 void act_free(act_index *idx);
+
+/*
+ * act_save / act_load -- an index as a file, so that a built (and trained,
+ * and tuned) index can be reused without rebuilding. The file holds the
+ * host image (trie, lookup table with the cell-local records, polygon
+ * store, statistics) and the launch configuration act_tune chose, in a
+ * little-endian binary layout with a version and a 64-bit digest.
+ * act_load checks the digest and that every child pointer, list offset,
+ * record and polygon id stays inside the image before uploading it to
+ * `device` (-1: host only, as act_build_opts.device). The loaded index
+ * equals the saved one (act_index_digest). Errors: ACT_E_ARG (NULL, cannot
+ * open or write, not an index file, truncated or corrupt), ACT_E_OOM,
+ * ACT_E_DEVICE, ACT_E_HIP.
+ */
+int act_save(const act_index *idx, const char *path);
+int act_load(const char *path, int32_t device, act_index **out);
 
 /*
  * act_join -- probe n points (Section III-E, Listing 3).
@@ -158,6 +199,50 @@ int act_join(const act_index *idx, const double *d_points, int64_t n,
 int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int32_t *d_out, int64_t *d_pair_point, int32_t *d_pair_poly,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
+
+/*
+ * act_join_ids -- act_join for points that arrive with their level-30 cell
+ * ids, as the points of the paper's probe do (Listing 3: each point carries
+ * its cell id; the projection is not part of the probe there).
+ *
+ * d_ids     device, n uint64: the points' leaf cell ids in this library's
+ *           layout (act_cell_ids): 3 face bits, the 60-bit Hilbert position,
+ *           marker bit 1. An id that names no leaf (face above 5, bit 0
+ *           clear, e.g. 0 for an invalid point) matches nothing.
+ * d_points  device, 2*n doubles (lat, lng) of the same points: exact mode
+ *           reads the points whose cells have candidates, to refine them;
+ *           may be NULL in approximate mode.
+ * d_out     device, n int32, as act_join.
+ * The probe decodes each id to its leaf (face, i, j) and descends the trie
+ * as act_join does; ids computed by any projection whose error stays within
+ * the build's margin (act_build_opts.margin_deg) give act_join's results
+ * (exact mode). Exact mode uses the stream's pending workspace. Errors as
+ * act_join.
+ */
+int act_join_ids(const act_index *idx, const uint64_t *d_ids, const double *d_points,
+                 int64_t n, int32_t *d_out, void *stream);
+
+/*
+ * act_join_count -- the paper's evaluation query, the number of points per
+ * polygon (Section V: a count grouped by polygon id over the join pairs;
+ * the aggregation follows the probe as in Section IV-B2, "produce output").
+ *
+ * d_points  device, 2*n doubles (lat, lng).
+ * d_counts  device, n_polys int64 (NULL allowed only for an empty polygon
+ *           set): the call ADDS to counts[p] the number of the points that
+ *           polygon p covers (exact mode: every covering polygon of a point
+ *           counts, overlaps and shared boundaries included, i.e. the pair
+ *           set of act_join_pairs) or that reference p (approx mode: every
+ *           reference of the point's cell). Zero it first for a plain
+ *           count; repeated calls accumulate (streaming).
+ * Writes no per-point output. Refinement is cell-local; in exact mode the
+ * stream's pending workspace is used (allocated on first use, see
+ * act_workspace_reserve). Counts are accumulated with atomics, so the
+ * values are deterministic; the order of their updates is not. Errors as
+ * act_join.
+ */
+int act_join_count(const act_index *idx, const double *d_points, int64_t n,
+                   int64_t *d_counts, void *stream);
 
 /*
  * act_join_noalloc -- act_join for callers that cannot allocate device
@@ -430,6 +515,12 @@ typedef struct {
   double precision_m;
   double build_seconds;
   int64_t local_words;      /* cell-local refinement records (32-bit words)   */
+  int64_t train_splits;     /* cells split by training (Section III-D)        */
+  int64_t train_points_used; /* training points consumed before the budget
+                               ran out (n_train if it did not)               */
+  int64_t image_bytes;      /* device bytes the index's image needs (equal to
+                               device_bytes once uploaded; also for
+                               host-only builds)                            */
 } act_stats;
 
 int act_index_stats(const act_index *idx, act_stats *out);

@@ -22,13 +22,13 @@ import ctypes
 import numpy as np
 
 from . import _binding as _b
-from ._binding import (ACT_APPROX, ACT_EXACT, ACT_PENDING_AUTO, ACT_PENDING_KERNEL,
+from ._binding import (ACT_APPROX, ACT_AUTO, ACT_EXACT, ACT_PENDING_AUTO, ACT_PENDING_KERNEL,
                        ACT_PENDING_QUEUE, ACT_REFINE_AUTO, ACT_REFINE_FP32_FILTER,
                        ACT_REFINE_FP64, ACT_REFINE_LOCAL, COUNTER_NAMES, ActError)
 
-__all__ = ["build", "Index", "Server", "cell_ids", "batch_descriptors", "wall_clock_hz",
-           "ActError",
-           "ACT_EXACT", "ACT_APPROX",
+__all__ = ["build", "load", "Index", "Server", "cell_ids", "batch_descriptors",
+           "wall_clock_hz", "ActError",
+           "ACT_EXACT", "ACT_APPROX", "ACT_AUTO",
            "ACT_REFINE_AUTO", "ACT_REFINE_LOCAL", "ACT_REFINE_FP32_FILTER", "ACT_REFINE_FP64",
            "ACT_PENDING_AUTO", "ACT_PENDING_KERNEL", "ACT_PENDING_QUEUE",
            "version", "lib"]
@@ -82,6 +82,10 @@ class Index:
     def handle(self):
         return self._h
 
+    def save(self, path):
+        """Write the index (host image and launch configuration) to a file."""
+        _b.check(lib.act_save(self._h, str(path).encode()))
+
     def stats(self) -> dict:
         st = _b.Stats()
         _b.check(lib.act_index_stats(self._h, ctypes.byref(st)))
@@ -97,6 +101,45 @@ class Index:
         _b.check(lib.act_join(self._h, ctypes.c_void_p(points.data_ptr()), n,
                               ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
         return out
+
+    def join_ids(self, ids, points=None, out=None, stream=None):
+        """Join points given by their level-30 cell ids (int64 CUDA tensor of
+        the uint64 bit patterns, as cell_ids() returns); `points` (the same
+        points' (n, 2) float64 lat/lng) is required in exact mode."""
+        import torch
+        if not isinstance(ids, torch.Tensor) or not ids.is_cuda or ids.dtype != torch.int64 \
+                or ids.dim() != 1 or not ids.is_contiguous():
+            raise TypeError("ids must be a contiguous 1-D int64 CUDA tensor")
+        n = ids.shape[0]
+        if points is not None:
+            _check_points(points)
+            if points.shape[0] != n:
+                raise ValueError("ids and points differ in length")
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device=ids.device)
+        _b.check(lib.act_join_ids(self._h, ctypes.c_void_p(ids.data_ptr()),
+                                  ctypes.c_void_p(points.data_ptr() if points is not None else 0),
+                                  n, ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def join_count(self, points, counts=None, stream=None):
+        """Per-polygon number of covering points (int64 CUDA tensor of
+        n_polys), added to `counts` when given (streaming), else to zeros."""
+        import torch
+        _check_points(points)
+        if counts is None:
+            counts = torch.zeros(self.n_polys, dtype=torch.int64, device=points.device)
+        elif counts.dtype != torch.int64 or counts.numel() < self.n_polys or \
+                not counts.is_contiguous():
+            raise TypeError("counts must be a contiguous int64 tensor of n_polys elements")
+        _b.check(lib.act_join_count(self._h, ctypes.c_void_p(points.data_ptr()),
+                                    points.shape[0], ctypes.c_void_p(counts.data_ptr()),
+                                    _stream_ptr(stream)))
+        return counts
+
+    @property
+    def n_polys(self) -> int:
+        return int(self.stats()["n_polys"])
 
     def join_ex(self, points, out=None, *, capacity=None, counters=False,
                 refine=ACT_REFINE_AUTO, block=0, lds_levels=-1, grid=0,
@@ -233,20 +276,42 @@ class Index:
 
 def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
           device: int = 0, threads: int = 0, margin_deg: float = 0.0,
-          prefix_level: int = -1) -> Index:
+          prefix_level: int = -1, train_points=None, memory_budget: int = 0,
+          train_max_level: int = 30) -> Index:
     """Build an index (host) and upload it to `device` (-1: host only).
-    prefix_level -1 lets the builder choose the trie's prefix level."""
-    m = {"exact": ACT_EXACT, "approx": ACT_APPROX}.get(mode, mode)
+    prefix_level -1 lets the builder choose the trie's prefix level.
+    train_points: optional (n, 2) float64 (lat, lng) host array the exact
+    index is trained with (Section III-D) within memory_budget bytes of
+    device image (0: no limit)."""
+    m = {"exact": ACT_EXACT, "approx": ACT_APPROX, "auto": ACT_AUTO}.get(mode, mode)
     v = np.ascontiguousarray(polys.verts, dtype=np.float64)
     ro = np.ascontiguousarray(polys.ring_off, dtype=np.int64)
     pro = np.ascontiguousarray(polys.poly_ring_off, dtype=np.int32)
     n_polys = pro.shape[0] - 1
+    tp = None if train_points is None else \
+        np.ascontiguousarray(train_points, dtype=np.float64).reshape(-1, 2)
     opts = _b.BuildOpts(max_level=max_level, device=device, threads=threads,
-                        prefix_level=prefix_level, margin_deg=margin_deg)
+                        prefix_level=prefix_level, margin_deg=margin_deg,
+                        train_points=tp.ctypes.data if tp is not None else None,
+                        n_train=0 if tp is None else tp.shape[0],
+                        memory_budget=int(memory_budget), train_max_level=train_max_level)
     h = ctypes.c_void_p()
     _b.check(lib.act_build(_np_ptr(v), _np_ptr(ro), _np_ptr(pro), n_polys, m, float(precision_m),
                            ctypes.byref(opts), ctypes.byref(h)))
-    return Index(h, m, precision_m, device)
+    idx = Index(h, m, precision_m, device)
+    if m == ACT_AUTO:  # the mode the budget policy took
+        idx.mode = idx.stats()["mode"]
+    return idx
+
+
+def load(path, device: int = 0) -> Index:
+    """An index saved with Index.save, uploaded to `device` (-1: host only)."""
+    h = ctypes.c_void_p()
+    _b.check(lib.act_load(str(path).encode(), int(device), ctypes.byref(h)))
+    idx = Index(h, ACT_EXACT, 0.0, device)
+    st = idx.stats()
+    idx.mode, idx.precision_m = st["mode"], st["precision_m"]
+    return idx
 
 
 def batch_descriptors(batches):

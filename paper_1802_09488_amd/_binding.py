@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libact.so")
 
 ACT_OK, ACT_E_ARG, ACT_E_POLY, ACT_E_OOM, ACT_E_HIP, ACT_E_OVERFLOW, ACT_E_DEVICE, ACT_E_RANGE = \
     0, -1, -2, -3, -4, -5, -6, -7
-ACT_EXACT, ACT_APPROX = 0, 1
+ACT_EXACT, ACT_APPROX, ACT_AUTO = 0, 1, 2
 ACT_REFINE_AUTO, ACT_REFINE_LOCAL, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1, 2, 3
 ACT_PENDING_AUTO, ACT_PENDING_KERNEL, ACT_PENDING_QUEUE = 0, 1, 2
 ACT_NCOUNTERS = 16
@@ -35,7 +35,9 @@ class ActError(RuntimeError):
 class BuildOpts(ctypes.Structure):
     _fields_ = [("max_level", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("threads", ctypes.c_int32), ("prefix_level", ctypes.c_int32),
-                ("margin_deg", ctypes.c_double)]
+                ("margin_deg", ctypes.c_double), ("train_points", ctypes.c_void_p),
+                ("n_train", ctypes.c_int64), ("memory_budget", ctypes.c_int64),
+                ("train_max_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class JoinArgs(ctypes.Structure):
@@ -86,7 +88,8 @@ class Stats(ctypes.Structure):
                 ("n_faces", ctypes.c_int32), ("face_prefix_level", ctypes.c_int32 * 6),
                 ("mode", ctypes.c_int32), ("lds_nodes", ctypes.c_int32),
                 ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double),
-                ("local_words", ctypes.c_int64)]
+                ("local_words", ctypes.c_int64), ("train_splits", ctypes.c_int64),
+                ("train_points_used", ctypes.c_int64), ("image_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -103,9 +106,13 @@ def _load():
     sig = {
         "act_build": ([p, p, p, i32, i32, d, p, p], ctypes.c_int),
         "act_free": ([p], None),
+        "act_save": ([p, ctypes.c_char_p], ctypes.c_int),
+        "act_load": ([ctypes.c_char_p, i32, p], ctypes.c_int),
         "act_join": ([p, p, i64, p, p], ctypes.c_int),
         "act_join_pairs": ([p, p, i64, p, p, p, i64, p, p], ctypes.c_int),
         "act_join_noalloc": ([p, p, i64, p, p], ctypes.c_int),
+        "act_join_count": ([p, p, i64, p, p], ctypes.c_int),
+        "act_join_ids": ([p, p, p, i64, p, p], ctypes.c_int),
         "act_join_ex": ([p, p, p], ctypes.c_int),
         "act_workspace_reserve": ([p, p, i64], ctypes.c_int),
         "act_cell_ids": ([p, i64, p, p], ctypes.c_int),

@@ -34,9 +34,11 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "cellid.hpp"
@@ -251,6 +253,8 @@ struct Ctx {
   BuildParams bp;
   std::atomic<bool> failed{false};
   std::string err;
+  int err_code = ACT_E_ARG;
+  std::atomic<int64_t> cells_out{0};  // cells emitted so far (for bp.cell_limit)
 };
 
 // Classify a child box given the parent's candidates.
@@ -330,7 +334,12 @@ static uint32_t local_record(const Prep &P, int p, const Box &b, std::vector<uin
   return off;
 }
 
-void emit(const Ctx &C, const Work &w, Sink &s) {
+void emit(Ctx &C, const Work &w, Sink &s) {
+  if (C.bp.cell_limit > 0 && C.cells_out.fetch_add(1, std::memory_order_relaxed) >= C.bp.cell_limit &&
+      !C.failed.exchange(true)) {
+    C.err = "the covering exceeds the memory budget";
+    C.err_code = ACT_E_RANGE;
+  }
   CellOut c;
   c.face = w.face;
   c.level = w.level;
@@ -656,6 +665,228 @@ static int64_t choose_prefix(const std::vector<Cell> &cells, const FaceCells fc[
   return n_al;
 }
 
+// ------------------------------------------------------------- training
+//
+// Section III-D: when a training point hits an expensive cell (one whose
+// reference list has a candidate), that cell is replaced by its four
+// children, each classified against the cell's references (a polygon
+// interior to the parent stays interior; a candidate polygon becomes
+// interior, candidate or absent per child), and the index is updated. This
+// is repeated, one split per hit, over the training points in their order
+// until the memory budget is used up. The image's size is tracked as the
+// training goes: the trie nodes (with the faces' prefix levels fixed before
+// training) and an upper bound of the lookup-table words each cell needs.
+
+// Leaf cell (face, i, j) of a point, by the projection of cellid.hpp (host
+// trigonometry). Training only chooses which cells to split, so the host's
+// rounding does not matter for the join's results.
+static bool host_leaf(double lat, double lng, int &face, uint32_t &i, uint32_t &j) {
+  if (!(std::fabs(lat) <= 90.0 && std::fabs(lng) <= 180.0)) return false;
+  const double phi = lat / kDeg, lam = lng / kDeg;
+  const double c[3] = {std::cos(phi) * std::cos(lam), std::cos(phi) * std::sin(lam), std::sin(phi)};
+  const double ax = std::fabs(c[0]), ay = std::fabs(c[1]), az = std::fabs(c[2]);
+  const int a = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+  const double m = std::fabs(c[a]);
+  face = a + (c[a] < 0 ? 3 : 0);
+  auto coord = [](double w) {
+    const double v = std::floor(kTwo30 * st_from_uv(w));
+    return (uint32_t)std::min(std::max(v, 0.0), kTwo30 - 1.0);
+  };
+  i = coord(c[(a + 1) % 3] / m);
+  j = coord(c[(a + 2) % 3] / m);
+  return true;
+}
+
+// Unique key of a cell (coordinates at its level): face, quadtree path and
+// a marker bit, laid out like a cell id.
+static uint64_t cell_code(int face, int level, uint32_t i, uint32_t j) {
+  const int sh = 2 * (kMaxLevel - level);
+  return ((uint64_t)face << 61) | (quad_key(i, j) << (sh + 1)) | (1ull << sh);
+}
+
+// Lookup-table words a cell needs at most (deduplication can only save);
+// `top`: the cell lies in the top two node levels, whose 32-bit copy moves
+// inline references to the table.
+static int64_t cell_lut_words(const Cell &c, const std::vector<uint32_t> &local, bool exact,
+                              bool top) {
+  int nt = 0, nc = 0;
+  int64_t rec = 0;
+  for (int r = 0; r < c.n; r++) {
+    if (c.refs[r] & 1u) {
+      nt++;
+    } else {
+      nc++;
+      if (exact) {
+        const uint32_t *w = &local[c.local_base + c.locs[r]];
+        rec += 2 + 8 * (int64_t)w[0] + 2 * (int64_t)(w[1] & 0x7fffffffu);
+      }
+    }
+  }
+  if (exact && nc > 0) return 2 + nt + 2 * (int64_t)nc + rec;
+  return c.n >= 3 || top ? 2 + c.n : 0;
+}
+
+// Node level of a cell at level l under prefix level lp.
+static int node_depth(int l, int lp) { return l <= lp ? 0 : (l - lp - 1) / 4; }
+
+struct Trainer {
+  Ctx &C;
+  const Prep &P;
+  std::vector<Cell> &cells;
+  std::vector<uint32_t> &local;
+  std::deque<std::vector<uint32_t>> &store;  // refs and locs of cells made by splits
+  std::unordered_map<uint64_t, size_t> where;  // cell code -> index in cells
+  std::unordered_set<uint64_t> nodes;          // (face, ancestor at lp + 4d) of every node
+  int64_t top_nodes = 0;                       // nodes at depths 0 and 1
+  int lp[6];
+  int lcap[6];  // finest level a face's node alignment allows
+  uint32_t levels = 0;  // bit l: some cell has level l
+
+  Trainer(Ctx &c, const Prep &p, std::vector<Cell> &cs, std::vector<uint32_t> &lc,
+          std::deque<std::vector<uint32_t>> &st)
+      : C(c), P(p), cells(cs), local(lc), store(st) {}
+
+  void add_nodes(const Cell &c) {
+    const int l = c.level, f = c.face;
+    for (int d = 0; d <= node_depth(l, lp[f]); d++) {
+      const int L = lp[f] + 4 * d;
+      const int sh = kMaxLevel - L;
+      if (nodes.insert(cell_code(f, L, c.I >> sh, c.J >> sh)).second && d <= 1) top_nodes++;
+    }
+  }
+
+  // Index of the cell containing leaf (face, i, j), or SIZE_MAX.
+  size_t find(int face, uint32_t i, uint32_t j) const {
+    for (int l = kMaxLevel; l >= 0; l--) {
+      if (!((levels >> l) & 1u)) continue;
+      const int sh = kMaxLevel - l;
+      auto it = where.find(cell_code(face, l, i >> sh, j >> sh));
+      if (it != where.end()) return it->second;
+    }
+    return SIZE_MAX;
+  }
+
+  // Children of cell k (their cells appended to `kids`, records to local).
+  void split(size_t k, std::vector<Cell> &kids) {
+    const Cell c = cells[k];
+    const int sh = kMaxLevel - c.level;
+    Work w;
+    w.face = c.face;
+    w.level = c.level;
+    w.i = c.I >> sh;
+    w.j = c.J >> sh;
+    w.box = inflate(cell_bounds(w.face, w.level, w.i, w.j), C.bp.margin_deg);
+    for (int r = 0; r < c.n; r++) {
+      const int32_t p = (int32_t)(c.refs[r] >> 1);
+      if (c.refs[r] & 1u) {
+        w.interior.push_back(p);
+      } else {
+        const int32_t off = (int32_t)w.edges.size();
+        for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) w.edges.push_back(e);
+        w.bnd.push_back({p, off, P.e_off[p + 1] - P.e_off[p]});
+      }
+    }
+    Sink tmp;
+    Work ch;
+    for (int q = 0; q < 4; q++) {
+      make_child(C, w, q, ch);
+      if (ch.bnd.empty() && ch.interior.empty()) continue;  // outside every polygon
+      emit(C, ch, tmp);
+    }
+    const uint64_t base = local.size();
+    local.insert(local.end(), tmp.local.begin(), tmp.local.end());
+    for (const CellOut &o : tmp.cells) {
+      store.emplace_back(tmp.refs.begin() + o.ref_off, tmp.refs.begin() + o.ref_off + o.ref_cnt);
+      const uint32_t *refs = store.back().data();
+      std::vector<uint32_t> locs(tmp.locs.begin() + o.ref_off,
+                                 tmp.locs.begin() + o.ref_off + o.ref_cnt);
+      for (uint32_t &v : locs)
+        if (v != UINT32_MAX) v = (uint32_t)(base + v);
+      store.push_back(std::move(locs));
+      const int s2 = kMaxLevel - o.level;
+      kids.push_back({o.face, o.level, o.i << s2, o.j << s2, quad_key(o.i << s2, o.j << s2), refs,
+                      store.back().data(), 0, o.ref_cnt});
+    }
+  }
+};
+
+// `store` receives the reference arrays of the cells the splits make (the
+// cells point into it, so it must outlive the trie build).
+static void train_index(Ctx &C, const Prep &P, std::vector<Cell> &cells,
+                        std::vector<uint32_t> &local, std::deque<std::vector<uint32_t>> &store,
+                        const int lp[6], int64_t fixed_bytes, HostIndex &out) {
+  const BuildParams &bp = C.bp;
+  const bool exact = bp.mode == ACT_EXACT;
+  Trainer T(C, P, cells, local, store);
+  int64_t lut_words = 10;  // the device copy's padding
+  for (int f = 0; f < 6; f++) {
+    T.lp[f] = lp[f];
+    T.lcap[f] = std::min(bp.train_max_level, lp[f] + 4 * ((kMaxLevel - lp[f]) / 4));
+  }
+  for (size_t k = 0; k < cells.size(); k++) {
+    const Cell &c = cells[k];
+    T.where[cell_code(c.face, c.level, c.I >> (kMaxLevel - c.level), c.J >> (kMaxLevel - c.level))] = k;
+    T.levels |= 1u << c.level;
+    T.add_nodes(c);
+    lut_words += cell_lut_words(c, local, exact, node_depth(c.level, T.lp[c.face]) <= 1);
+  }
+  auto bytes = [&](int64_t n_nodes, int64_t top, int64_t words) {
+    return fixed_bytes + (n_nodes + 1) * 2048 + top * 1024 + 4 * words;
+  };
+  if (bp.memory_budget > 0 &&
+      bytes((int64_t)T.nodes.size(), T.top_nodes, lut_words) > bp.memory_budget)
+    return;  // the untrained index already uses the budget
+  std::vector<Cell> kids;
+  int64_t used = 0;
+  for (; used < bp.n_train; used++) {
+    int face;
+    uint32_t i, j;
+    if (!host_leaf(bp.train_points[2 * used], bp.train_points[2 * used + 1], face, i, j)) continue;
+    const size_t k = T.find(face, i, j);
+    if (k == SIZE_MAX) continue;  // a false hit
+    const Cell c = cells[k];
+    bool expensive = false;
+    for (int r = 0; r < c.n; r++) expensive |= !(c.refs[r] & 1u);
+    if (!expensive || c.level >= T.lcap[face]) continue;
+    kids.clear();
+    T.split(k, kids);
+    // what the split adds: a new node when the children start a node level,
+    // and the children's lists in place of the parent's
+    const int lpf = T.lp[face];
+    int64_t words = lut_words - cell_lut_words(c, local, exact, node_depth(c.level, lpf) <= 1);
+    for (const Cell &q : kids)
+      words += cell_lut_words(q, local, exact, node_depth(q.level, lpf) <= 1);
+    const bool new_node = node_depth(c.level + 1, T.lp[face]) > node_depth(c.level, T.lp[face]);
+    const uint64_t nkey = cell_code(face, c.level, c.I >> (kMaxLevel - c.level),
+                                    c.J >> (kMaxLevel - c.level));
+    const bool adds = new_node && !T.nodes.count(nkey);
+    const int64_t top = T.top_nodes + (adds && node_depth(c.level + 1, T.lp[face]) <= 1);
+    if (bp.memory_budget > 0 &&
+        bytes((int64_t)T.nodes.size() + (adds ? 1 : 0), top, words) > bp.memory_budget)
+      break;  // the budget is used up
+    if (adds) {
+      T.nodes.insert(nkey);
+      T.top_nodes = top;
+    }
+    lut_words = words;
+    T.where.erase(cell_code(face, c.level, c.I >> (kMaxLevel - c.level), c.J >> (kMaxLevel - c.level)));
+    cells[k].n = -1;  // replaced by its children
+    for (const Cell &q : kids) {
+      T.where[cell_code(q.face, q.level, q.I >> (kMaxLevel - q.level), q.J >> (kMaxLevel - q.level))] =
+          cells.size();
+      T.levels |= 1u << q.level;
+      cells.push_back(q);
+    }
+    out.train_splits++;
+  }
+  out.train_points_used = used;
+  std::vector<Cell> live;  // without the cells that were split
+  live.reserve(cells.size());
+  for (const Cell &c : cells)
+    if (c.n >= 0) live.push_back(c);
+  cells.swap(live);
+}
+
 // Builds the faces' tries and lookup table from the sorted cells into
 // out.nodes / out.lut / out.faces (and the trie statistics), with prefix
 // level lp[face].
@@ -776,6 +1007,241 @@ static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], co
   if (out.nodes.size() / 256 >= (1ull << 30)) {  // pointer entries carry 30-bit node indices
     err = "trie exceeds 2^30 nodes";
     return ACT_E_RANGE;
+  }
+  return ACT_OK;
+}
+
+int64_t image_fixed_bytes(int64_t n_polys, int64_t n_edges) {
+  auto up = [](int64_t b) { return std::max<int64_t>(b, 16); };  // each upload is at least 16 B
+  return up(4 * (n_polys + 1)) + up(16 * n_polys) + up(4 * n_polys) + up(16 * n_edges) +
+         up(32 * n_edges) + up(361 * 16) + up(6 * 16) + up(64);
+}
+
+int64_t image_bytes(const HostIndex &h) {
+  return image_fixed_bytes(h.n_polys, (int64_t)h.edges64.size() / 4) +
+         std::max<int64_t>(16, (int64_t)h.nodes.size() * 8) + 4 * ((int64_t)h.lut.size() + 10) +
+         std::max<int64_t>(16, (int64_t)(h.n_d0 + h.n_d1) * 1024);
+}
+
+// ------------------------------------------------------------ index files
+
+namespace {
+
+constexpr char kFileMagic[8] = {'A', 'C', 'T', 'I', 'D', 'X', '0', '1'};
+constexpr uint32_t kFileVersion = 1;
+
+// Running digest of the bytes written or read (FNV-style mixing).
+struct Digest {
+  uint64_t d = 0xcbf29ce484222325ull;
+  void mix(const void *p, size_t n) {
+    const uint8_t *b = (const uint8_t *)p;
+    for (size_t k = 0; k < n; k++) d = (d ^ b[k]) * 0x100000001b3ull;
+  }
+};
+
+struct Writer {
+  FILE *f;
+  Digest dg;
+  bool ok = true;
+  void raw(const void *p, size_t n) {
+    if (n && std::fwrite(p, 1, n, f) != n) ok = false;
+    dg.mix(p, n);
+  }
+  template <typename T> void val(const T &v) { raw(&v, sizeof v); }
+  template <typename T> void vec(const std::vector<T> &v) {
+    const uint64_t n = v.size();
+    val(n);
+    raw(v.data(), n * sizeof(T));
+  }
+};
+
+struct Reader {
+  FILE *f;
+  Digest dg;
+  bool ok = true;
+  uint64_t left;  // bytes of the file not read yet
+  void raw(void *p, size_t n) {
+    if (!ok || n > left || (n && std::fread(p, 1, n, f) != n)) {
+      ok = false;
+      return;
+    }
+    left -= n;
+    dg.mix(p, n);
+  }
+  template <typename T> void val(T &v) { raw(&v, sizeof v); }
+  template <typename T> void vec(std::vector<T> &v) {
+    uint64_t n = 0;
+    val(n);
+    if (!ok || n > left / sizeof(T)) {
+      ok = false;
+      return;
+    }
+    v.resize(n);
+    raw(v.data(), n * sizeof(T));
+  }
+};
+
+template <typename IO, typename H>
+void scalars(IO &io, H &h) {
+  io.val(h.mode);
+  io.val(h.precision_m);
+  io.val(h.max_level);
+  io.val(h.n_polys);
+  for (int f = 0; f < 6; f++) {
+    io.val(h.faces[f].root);
+    io.val(h.faces[f].plevel);
+    io.val(h.faces[f].pi);
+    io.val(h.faces[f].pj);
+    io.val(h.faces[f].depth);
+  }
+  io.val(h.local_words);
+  io.val(h.n_cells);
+  io.val(h.n_cells_interior_only);
+  io.val(h.max_depth);
+  io.val(h.max_refs);
+  io.val(h.max_cell_level);
+  io.val(h.n_d0);
+  io.val(h.n_d1);
+  io.val(h.build_seconds);
+  io.val(h.train_splits);
+  io.val(h.train_points_used);
+}
+
+template <typename IO, typename H>
+void arrays(IO &io, H &h) {
+  io.vec(h.nodes);
+  io.vec(h.lut);
+  io.vec(h.poly_edge_off);
+  io.vec(h.poly_origin);
+  io.vec(h.poly_m);
+  io.vec(h.edges32);
+  io.vec(h.edges64);
+}
+
+}  // namespace
+
+// Every reference the probe follows stays inside the image: child pointers
+// name existing nodes, lookup-table lists and the cell-local records they
+// point to lie inside the table, polygon ids are below n_polys, and the
+// faces' roots and prefix levels are valid.
+static bool image_consistent(const HostIndex &h) {
+  const uint64_t n_nodes = h.nodes.size() / 256, n_lut = h.lut.size();
+  const uint32_t np = (uint32_t)h.n_polys;
+  if (n_nodes == 0 || (uint64_t)h.n_d0 + (uint64_t)h.n_d1 >= n_nodes || h.n_d0 < 0 || h.n_d1 < 0)
+    return false;
+  for (int f = 0; f < 6; f++) {
+    const FaceRoot &F = h.faces[f];
+    if (F.root != -1 && (F.root <= 0 || (uint64_t)F.root >= n_nodes)) return false;
+    if (F.plevel < 0 || F.plevel > kMaxLevel) return false;
+  }
+  const bool exact = h.mode == ACT_EXACT;
+  uint64_t last_ok = UINT64_MAX;
+  for (uint64_t k = 256; k < h.nodes.size(); k++) {
+    const uint64_t e = h.nodes[k];
+    if (e == 0) continue;
+    switch (e & kTagMask) {
+      case kTagPtr:
+        if ((e >> 2) == 0 || (e >> 2) >= n_nodes) return false;
+        break;
+      case kTagTwo:
+        if ((((e >> 33) & 0x7fffffffu) >> 1) >= np) return false;
+        [[fallthrough]];
+      case kTagOne:
+        if ((((e >> 2) & 0x7fffffffu) >> 1) >= np) return false;
+        break;
+      default: {
+        const uint64_t off = e >> 2;
+        if (off == last_ok) break;
+        if (off + 2 > n_lut) return false;
+        const uint64_t nt = h.lut[off];
+        if (off + 2 + nt > n_lut) return false;
+        const uint64_t nc = h.lut[off + 1 + nt];
+        const uint64_t end = off + 2 + nt + nc + (exact && nc ? nc : 0);
+        if (end > n_lut) return false;
+        for (uint64_t r = 0; r < nt; r++)
+          if (h.lut[off + 1 + r] >= np) return false;
+        for (uint64_t r = 0; r < nc; r++) {
+          if (h.lut[off + 2 + nt + r] >= np) return false;
+          if (!exact) continue;
+          const uint64_t rec = h.lut[off + 2 + nt + nc + r];
+          if (rec + 2 > n_lut) return false;
+          const uint64_t len = 2 + 8 * (uint64_t)h.lut[rec] + 2 * (uint64_t)(h.lut[rec + 1] & 0x7fffffffu);
+          if (rec + len > n_lut) return false;
+        }
+        last_ok = off;
+      }
+    }
+  }
+  for (uint64_t k = 0; k < (uint64_t)h.n_polys; k++)
+    if (h.poly_edge_off[k] > h.poly_edge_off[k + 1]) return false;
+  return h.poly_edge_off.empty() || (h.poly_edge_off[0] == 0 &&
+         (uint64_t)h.poly_edge_off[h.n_polys] == h.edges64.size() / 4);
+}
+
+int save_host_index(const HostIndex &h, const void *extra, uint32_t extra_bytes, const char *path,
+                    std::string &err) {
+  FILE *f = std::fopen(path, "wb");
+  if (!f) {
+    err = std::string("cannot open ") + path + " for writing";
+    return ACT_E_ARG;
+  }
+  Writer w{f};
+  w.raw(kFileMagic, sizeof kFileMagic);
+  w.val(kFileVersion);
+  w.val(extra_bytes);
+  scalars(w, h);
+  arrays(w, h);
+  w.raw(extra, extra_bytes);
+  const uint64_t d = w.dg.d;
+  w.val(d);
+  const bool ok = w.ok && std::fclose(f) == 0;
+  if (!ok) {
+    err = std::string("writing ") + path + " failed";
+    return ACT_E_ARG;
+  }
+  return ACT_OK;
+}
+
+int load_host_index(const char *path, HostIndex &h, void *extra, uint32_t extra_bytes,
+                    std::string &err) {
+  FILE *f = std::fopen(path, "rb");
+  if (!f) {
+    err = std::string("cannot open ") + path;
+    return ACT_E_ARG;
+  }
+  std::fseek(f, 0, SEEK_END);
+  const long size = std::ftell(f);
+  std::fseek(f, 0, SEEK_SET);
+  Reader r{f};
+  r.left = size > 0 ? (uint64_t)size : 0;
+  char magic[8];
+  uint32_t version = 0, xb = 0;
+  r.raw(magic, sizeof magic);
+  r.val(version);
+  r.val(xb);
+  if (!r.ok || std::memcmp(magic, kFileMagic, 8) != 0 || version != kFileVersion ||
+      xb != extra_bytes) {
+    std::fclose(f);
+    err = std::string(path) + " is not an index file of this version";
+    return ACT_E_ARG;
+  }
+  h = HostIndex();
+  scalars(r, h);
+  arrays(r, h);
+  r.raw(extra, extra_bytes);
+  const uint64_t want = r.dg.d;
+  uint64_t got = 0;
+  r.val(got);
+  std::fclose(f);
+  const bool shape_ok = h.n_polys >= 0 && h.poly_edge_off.size() == (size_t)h.n_polys + 1 &&
+                        h.nodes.size() % 256 == 0 && h.poly_origin.size() == 2 * (size_t)h.n_polys &&
+                        h.poly_m.size() == (size_t)h.n_polys && h.edges64.size() % 4 == 0 &&
+                        h.edges32.size() == h.edges64.size() &&
+                        (h.mode == ACT_EXACT || h.mode == ACT_APPROX);
+  if (!r.ok || got != want || r.left != 0 || !shape_ok || !image_consistent(h)) {
+    h = HostIndex();
+    err = std::string(path) + ": truncated or corrupt index file";
+    return ACT_E_ARG;
   }
   return ACT_OK;
 }
@@ -942,7 +1408,7 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   tasks.clear();
   if (C.failed) {
     err = C.err;
-    return ACT_E_ARG;
+    return C.err_code;
   }
   // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
   // shifted to level 30
@@ -962,15 +1428,33 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     err = "cell-local refinement records exceed 2^32 words";
     return ACT_E_RANGE;
   }
-  std::sort(cells.begin(), cells.end(), [](const Cell &a, const Cell &b) {
+  auto by_key = [](const Cell &a, const Cell &b) {
     return a.face != b.face ? a.face < b.face : a.key < b.key;
-  });
-  out.n_cells = (int64_t)cells.size();
+  };
+  std::sort(cells.begin(), cells.end(), by_key);
   // ------------------------------------------------------------- tries
   FaceCells fc[6];
   face_ranges(cells, fc);
   int lp[6];
-  const int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
+  int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
+  std::deque<std::vector<uint32_t>> trained;  // reference arrays of cells made by training
+  if (bp.mode == ACT_EXACT && bp.n_train > 0) {
+    // training keeps the faces' prefix levels: the trie grows only below them
+    train_index(C, P, cells, local, trained, lp,
+                image_fixed_bytes(n_polys, (int64_t)(P.ex.size() / 4)), out);
+    if (local.size() >= (1ull << 32)) {
+      err = "cell-local refinement records exceed 2^32 words";
+      return ACT_E_RANGE;
+    }
+    std::sort(cells.begin(), cells.end(), by_key);
+    face_ranges(cells, fc);
+    n_nodes = 1;
+    for (int f = 0; f < 6; f++) {
+      int64_t d1;
+      if (fc[f].c1 > fc[f].c0) n_nodes += count_nodes(cells, fc[f], lp[f], d1);
+    }
+  }
+  out.n_cells = (int64_t)cells.size();
   const int rc = build_tries(cells, fc, lp, n_nodes, local, out, bp, err);
   if (rc) return rc;
   out.build_seconds =

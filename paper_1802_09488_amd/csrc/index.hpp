@@ -84,6 +84,8 @@ struct HostIndex {
   // 32-bit entries.
   int32_t n_d0 = 0, n_d1 = 0;
   double build_seconds = 0;
+  // training (Section III-D): cells split and training points consumed
+  int64_t train_splits = 0, train_points_used = 0;
 };
 
 // Trie nodes the probe stages in LDS (the top two node levels, as 32-bit
@@ -97,7 +99,33 @@ struct BuildParams {
   int32_t threads;
   int32_t prefix_level;  // -1: automatic
   double margin_deg;
+  // training (exact mode): points (lat, lng) and the device-image budget
+  const double *train_points = nullptr;
+  int64_t n_train = 0;
+  int64_t memory_budget = 0;  // bytes, 0 = none
+  int32_t train_max_level = 30;
+  // stop early (ACT_E_RANGE) once the covering has more cells than this
+  // (0 = no limit): a budget check that need not finish the covering
+  int64_t cell_limit = 0;
 };
+
+// Device bytes of an index image besides its trie nodes and lookup table
+// (the polygon store, tables, the LDS copy of the top levels at its largest),
+// as the runtime uploads it: an upper bound used by the training budget.
+int64_t image_fixed_bytes(int64_t n_polys, int64_t n_edges);
+
+// Device bytes the runtime uploads for this index.
+int64_t image_bytes(const HostIndex &h);
+
+// Index files: the host image in a little-endian binary layout (magic,
+// version, scalars, then each array as a length and its elements), followed
+// by `extra` caller bytes (the launch configuration) and a 64-bit digest of
+// everything before it. load_host_index checks the magic, version, lengths
+// and digest.
+int save_host_index(const HostIndex &h, const void *extra, uint32_t extra_bytes, const char *path,
+                    std::string &err);
+int load_host_index(const char *path, HostIndex &h, void *extra, uint32_t extra_bytes,
+                    std::string &err);
 
 // Builds the host index. Returns ACT_OK or an error code with `err` set.
 int build_host_index(const double *verts_latlng, const int64_t *ring_off,

@@ -71,6 +71,7 @@ struct DevImage {
   struct FaceDev *faces = nullptr;
   uint32_t *top32 = nullptr;
   uint64_t *sink = nullptr;  // 64 bytes that the probe's idle lanes store to
+  uint16_t *hinv = nullptr;  // inverse Hilbert table (joins of precomputed ids)
   size_t bytes = 0;
 };
 
@@ -169,6 +170,15 @@ struct ProbeParams {
   const int64_t *vstart;       // first virtual point of each batch, [nb] = end
   const int64_t *vhdr;         // [0] virtual groups in use (0 on a bad call)
   uint64_t *gticks;            // optional: completion tick of each group
+  // count joins: per-polygon number of covering points, accumulated in
+  // `counts` (device, one per polygon), through a per-block LDS histogram of
+  // hist_bins bins when the polygons fit it (0: straight to `counts`)
+  unsigned long long *counts;
+  int32_t hist_bins;
+  // joins of precomputed cell ids: the level-30 ids of the points (the
+  // points themselves, pts, are then read only to refine pending ones)
+  const uint64_t *ids;
+  const uint16_t *hinv;  // inverse Hilbert table, 1024 entries (device)
 };
 
 
@@ -409,6 +419,15 @@ struct Hits {
   }
 };
 
+// One (point, polygon) match of a count join: a histogram bin in LDS, or
+// the polygon's global counter.
+__device__ __forceinline__ void count_add(const ProbeParams &P, uint32_t *s_hist, uint32_t poly) {
+  if (s_hist)
+    atomicAdd(s_hist + poly, 1u);
+  else
+    atomicAdd(P.counts + poly, 1ull);
+}
+
 // Steps 5-6: prefix check (Listing 4) and comparison-free descent
 // (Listing 5). Each node consumes 4 levels of the cell's quadtree path, its
 // key byte being (4 bits of i, 4 bits of j). The first LDS_DEPTH node levels
@@ -559,6 +578,7 @@ struct TileRef {
   int32_t *out;
   int32_t n;
   int64_t gi;
+  const uint64_t *ids;  // joins of precomputed ids: the tile's first id
 };
 
 // Tile indices are 32-bit (a launch covers fewer than 2^32 tiles), so the
@@ -574,6 +594,7 @@ __device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, uint32_t tile)
     r.out = P.out + s;
     rest = P.n - s;
     r.gi = P.base + s;
+    r.ids = P.ids + s;
   } else {
     const int32_t b = P.group_batch[(int64_t)tile * NP];
     const int64_t off = (int64_t)tile * TILE - P.vstart[b];
@@ -582,6 +603,7 @@ __device__ __forceinline__ TileRef tile_ref(const ProbeParams &P, uint32_t tile)
     r.out = d.d_out + off;
     rest = d.n - off;
     r.gi = -1;
+    r.ids = nullptr;
   }
   r.n = (int32_t)std::max<int64_t>(0, std::min<int64_t>(rest, TILE));
   return r;
@@ -807,7 +829,9 @@ __device__ __forceinline__ void point_done(const ProbeParams &P, int64_t v) {
 // fp64 edges, exact edges, lookup-table reads.
 // `entry`: the cell's entry when the caller has it (fused probe), else the
 // code the probe left in out[] (two-pass join).
-template <bool FULL, bool BATCHED, bool ENTRY>
+// COUNT: a count join's resolve, which adds each match to the polygon's
+// counter instead of writing out[].
+template <bool FULL, bool BATCHED, bool ENTRY, bool COUNT = false>
 __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, uint64_t entry,
                                               uint32_t (&c)[7], uint32_t &c_reads) {
   const PointRef R = point_ref<BATCHED>(P, v);
@@ -815,7 +839,12 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
   const RefList L = ENTRY ? entry_refs(P, entry)
                           : pending_refs(P, (int32_t)(uint32_t)entry, pt.x, pt.y, c_reads);
   Hits<FULL> hits;
-  for (uint32_t r = 0; r < L.nt; r++) hits.add(P, R.gi, (int32_t)L.true_id(P, r));
+  for (uint32_t r = 0; r < L.nt; r++) {
+    if (COUNT)
+      count_add(P, nullptr, L.true_id(P, r));
+    else
+      hits.add(P, R.gi, (int32_t)L.true_id(P, r));
+  }
   for (uint32_t r = 0; r < L.nc; r++) {
     const int32_t poly = (int32_t)L.cand_id(P, r);
     const uint32_t loc = L.cand_loc(P, r);
@@ -827,9 +856,14 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
       cov = lane_covers<FULL>(P, poly, pt.x, pt.y, c[4], c[5]);
       if (FULL) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
     }
-    if (cov) hits.add(P, R.gi, poly);
+    if (cov) {
+      if (COUNT)
+        count_add(P, nullptr, (uint32_t)poly);
+      else
+        hits.add(P, R.gi, poly);
+    }
   }
-  *R.out = hits.best;
+  if (!COUNT) *R.out = hits.best;
   point_done<BATCHED>(P, v);
   if (FULL) {
     c[0] += L.nc == 0 && L.nt > 0;
@@ -926,7 +960,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
 // lookup-table read can start beside the point's.
 constexpr int kListBlock = 256;
 
-template <bool FULL>
+template <bool FULL, bool COUNT = false>
 __global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
                                                                   uint32_t nwaves) {
   const uint32_t w = blockIdx.x * (kListBlock / 64) + (threadIdx.x >> 6);
@@ -937,7 +971,7 @@ __global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
     const uint2 *list = P.plist + (size_t)w * P.region;
     for (uint32_t e = lane; e < cnt; e += 64) {
       const uint2 ent = list[e];
-      resolve_point<FULL, false, false>(P, ent.x, ent.y, c, c_reads);
+      resolve_point<FULL, false, false, COUNT>(P, ent.x, ent.y, c, c_reads);
     }
   }
   flush_counters<FULL>(P, c);
@@ -952,7 +986,16 @@ __global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
 // points resolved by the probe's own waves (cell-local refinement); exact,
 // with pending points listed per wave for resolve_list_kernel (cell-local
 // refinement).
-enum ProbeMode { kApprox = 0, kExactMask = 1, kExactFused = 2, kExactList = 3 };
+// Count joins (per-polygon number of covering points, no out[]) have modes
+// of their own: approximate, and exact with per-wave pending lists.
+enum ProbeMode {
+  kApprox = 0,
+  kExactMask = 1,
+  kExactFused = 2,
+  kExactList = 3,
+  kApproxCount = 4,
+  kExactCount = 5
+};
 
 // A wave's queue of pending points (kExactFused). The probe appends each
 // finished tile's pending points; whenever 64 have gathered, the wave
@@ -992,7 +1035,7 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
                                             int lane, const uint64_t (&e)[NP],
                                             const bool (&live)[NP], const bool (&valid)[NP],
                                             uint32_t (&c)[8], PendingQueue &Q, uint32_t (&rc)[7],
-                                            uint32_t &c_reads) {
+                                            uint32_t &c_reads, uint32_t *s_hist) {
   bool pend[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
@@ -1010,7 +1053,20 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
     const uint32_t r1 = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
     const int n_inl = e[p] == 0 || tag == kTagLut ? 0 : (tag == kTagTwo ? 2 : 1);
     const uint32_t off = (uint32_t)(e[p] >> 2);
-    if (MODE == kApprox) {
+    if (MODE == kApproxCount) {
+      // approximate count join: every reference of the cell is a match
+      if (live[p]) {
+        if (n_inl > 0) count_add(P, s_hist, r0 >> 1);
+        if (n_inl > 1) count_add(P, s_hist, r1 >> 1);
+        if (tag == kTagLut) {
+          const uint32_t nt = P.lut[off];
+          for (uint32_t r = 0; r < nt; r++) count_add(P, s_hist, P.lut[off + 1 + r]);
+          const uint32_t nc = P.lut[off + 1 + nt];
+          for (uint32_t r = 0; r < nc; r++) count_add(P, s_hist, P.lut[off + 2 + nt + r]);
+        }
+      }
+      pend[p] = false;
+    } else if (MODE == kApprox) {
       // approximate mode: every reference is reported
       Hits<FULL> hits;
       if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
@@ -1051,6 +1107,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
           Q.v[slot] = (int64_t)tile * (64 * NP) + k;
           Q.e[slot] = e[p];
         }
+      } else if (MODE == kExactCount) {
+        // a cell without candidates: its inline references are true hits
+        if (live[p] && n_inl > 0) count_add(P, s_hist, r0 >> 1);
+        if (live[p] && n_inl > 1) count_add(P, s_hist, r1 >> 1);
+        v = 0;
       } else {
         Hits<FULL> hits;
         if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
@@ -1058,10 +1119,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         v = hits.best;
         if (FULL) c[3] += e[p] != 0;
       }
-      // one store from every lane (lanes without a point to the sink)
-      store_out(live[p] ? T.out + k : (int32_t *)P.sink, v);
+      // one store from every lane (lanes without a point to the sink); a
+      // count join writes no out[]
+      if (MODE != kExactCount) store_out(live[p] ? T.out + k : (int32_t *)P.sink, v);
       if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
-      if (MODE == kExactList) {
+      if (MODE == kExactList || MODE == kExactCount) {
         // the wave appends its pending points (index in the pass, code) to
         // its region of the list; other lanes store to the sink
         const uint64_t pm = ballot(pend[p]);
@@ -1095,7 +1157,9 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
 // join's padding tile has no points: it loads those of `alt` instead, or
 // nothing when `alt` has none either (a single join's tiles all have
 // points, and `alt` is then a tile of the same join).
-template <bool BATCHED, int NP>
+// IDS: the tile's precomputed cell ids are loaded instead (8 bytes each,
+// carried in the x half).
+template <bool BATCHED, int NP, bool IDS = false>
 __device__ __forceinline__ void load_tile(const TileRef &T, const TileRef &alt, int lane,
                                           double2 (&v)[NP]) {
   const TileRef &S = T.n > 0 ? T : alt;
@@ -1106,22 +1170,58 @@ __device__ __forceinline__ void load_tile(const TileRef &T, const TileRef &alt, 
   }
   const int kmax = S.n - 1;
 #pragma unroll
-  for (int p = 0; p < NP; p++) v[p] = load_point(S.pts + min(p * 64 + lane, kmax));
+  for (int p = 0; p < NP; p++) {
+    if (IDS) {
+      const unsigned long long id =
+          __builtin_nontemporal_load((const unsigned long long *)S.ids + min(p * 64 + lane, kmax));
+      v[p] = make_double2(__longlong_as_double((long long)id), 0.0);
+    } else {
+      v[p] = load_point(S.pts + min(p * 64 + lane, kmax));
+    }
+  }
+}
+
+// Leaf coordinates of a level-30 cell id (face, 60-bit Hilbert position,
+// marker bit): the position is read 4 levels (8 bits) at a time through the
+// inverse of the curve's 4-level state table, from the two padding levels
+// of the 32-level frame down. Ids of no leaf (face above 5, no marker at
+// bit 0, including 0) are invalid.
+__device__ __forceinline__ bool decode_leaf(const uint16_t *hinv, uint64_t id, uint32_t &face,
+                                            uint32_t &i, uint32_t &j) {
+  face = (uint32_t)(id >> 61);
+  const uint64_t pos = (id >> 1) & ((1ull << 60) - 1);
+  uint32_t st = 0, ii = 0, jj = 0;
+#pragma unroll
+  for (int sh = 56; sh >= 0; sh -= 8) {
+    const uint32_t e = hinv[(st << 8) | (uint32_t)((pos >> sh) & 255u)];
+    ii = (ii << 4) | ((e >> 4) & 15u);
+    jj = (jj << 4) | (e & 15u);
+    st = e >> 8;
+  }
+  i = ii;
+  j = jj;
+  return face <= 5u && (id & 1ull);
 }
 
 // Steps 2-5 and the LDS-staged part of step 6 for the points of tile T.
-template <int LDS_DEPTH, int NP>
+template <int LDS_DEPTH, int NP, bool IDS = false>
 __device__ __forceinline__ void project_tile(const double2 *s_trig, const uint32_t *s_nodes,
                                              const FaceDev *s_face, const TileRef &T, int lane,
                                              const double2 (&pts)[NP], Descent<NP> &D,
                                              bool (&live)[NP], bool (&valid)[NP],
-                                             uint32_t &c_reads) {
+                                             uint32_t &c_reads, const uint16_t *s_hinv) {
   uint32_t face[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     live[p] = p * 64 + lane < T.n;
     face[p] = D.ci[p] = D.cj[p] = 0;
-    valid[p] = live[p] && project(s_trig, pts[p].x, pts[p].y, face[p], D.ci[p], D.cj[p]);
+    if (IDS) {
+      valid[p] = live[p] && decode_leaf(s_hinv, (uint64_t)__double_as_longlong(pts[p].x), face[p],
+                                        D.ci[p], D.cj[p]);
+      face[p] = valid[p] ? face[p] : 0u;
+    } else {
+      valid[p] = live[p] && project(s_trig, pts[p].x, pts[p].y, face[p], D.ci[p], D.cj[p]);
+    }
   }
   descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, valid, D, c_reads);
 }
@@ -1140,26 +1240,35 @@ __device__ __forceinline__ void project_tile(const double2 *s_trig, const uint32
 template <int MODE, int NP>
 constexpr int kProbeWavesPerEU = MODE != kExactFused ? 8 : 1;
 
-template <int MODE, int LDS_DEPTH, bool FULL, int NP, bool BATCHED>
+// IDS: the points arrive as level-30 cell ids (Listing 3's input), decoded
+// instead of projected.
+template <int MODE, int LDS_DEPTH, bool FULL, int NP, bool BATCHED, bool IDS = false>
 __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void probe_kernel(
     ProbeParams P) {
   constexpr bool FUSED = MODE == kExactFused;
   extern __shared__ uint32_t s_nodes[];
   __shared__ FaceDev s_face[6];
-  __shared__ double2 s_trig[kTrigEntries];
+  __shared__ double2 s_trig[IDS ? 1 : kTrigEntries];
+  __shared__ uint16_t s_hinv[IDS ? 1024 : 1];
   __shared__ int64_t s_qv[FUSED ? kProbeWaves * kQueueCap : 1];
   __shared__ uint64_t s_qe[FUSED ? kProbeWaves * kQueueCap : 1];
   if (LDS_DEPTH > 0)
     for (int k = threadIdx.x; k < P.n_lds_nodes * 256; k += kProbeBlock) s_nodes[k] = P.top32[k];
   if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
-  if (threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
+  if (!IDS && threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
+  if (IDS) s_hinv[threadIdx.x] = P.hinv[threadIdx.x];  // 1024 threads, 1024 entries
+  // count joins: a per-block histogram of the polygons after the trie levels
+  constexpr bool COUNTING = MODE == kApproxCount || MODE == kExactCount;
+  uint32_t *s_hist = COUNTING && P.hist_bins > 0 ? s_nodes + P.n_lds_nodes * 256 : nullptr;
+  if (s_hist)
+    for (int k = threadIdx.x; k < P.hist_bins; k += kProbeBlock) s_hist[k] = 0u;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
   uint32_t rc[7] = {0, 0, 0, 0, 0, 0, 0};  // resolve counters (kExactFused)
   PendingQueue Q{s_qv + (FUSED ? wid * kQueueCap : 0), s_qe + (FUSED ? wid * kQueueCap : 0), 0u, 0u,
-                 MODE == kExactList
+                 MODE == kExactList || MODE == kExactCount
                      ? P.plist + (size_t)(blockIdx.x * kProbeWaves + wid) * P.region
                      : nullptr};
   constexpr int TILE = 64 * NP;
@@ -1177,11 +1286,11 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     double2 nxt[NP];
     {  // prologue: the wave's first tile
       double2 cur[NP];
-      load_tile<BATCHED, NP>(TB, TB, lane, cur);
+      load_tile<BATCHED, NP, IDS>(TB, TB, lane, cur);
       TN = first + nwaves < ntiles ? tile_ref<BATCHED, NP>(P, first + nwaves) : TB;
-      load_tile<BATCHED, NP>(TN, TB, lane, nxt);
-      project_tile<LDS_DEPTH, NP>(s_trig, s_nodes, s_face, TB, lane, cur, B, liveB, validB,
-                                  c_reads);
+      load_tile<BATCHED, NP, IDS>(TN, TB, lane, nxt);
+      project_tile<LDS_DEPTH, NP, IDS>(s_trig, s_nodes, s_face, TB, lane, cur, B, liveB, validB,
+                                       c_reads, s_hinv);
       issue_level<NP>(P, B, xB);
     }
     // steady state: no wave-uniform branches around memory operations, so
@@ -1193,15 +1302,15 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
       double2 cur[NP];
 #pragma unroll
       for (int p = 0; p < NP; p++) cur[p] = nxt[p];
-      load_tile<BATCHED, NP>(TN, TA, lane, nxt);
+      load_tile<BATCHED, NP, IDS>(TN, TA, lane, nxt);
       Descent<NP> A;
       bool liveA[NP], validA[NP];
-      project_tile<LDS_DEPTH, NP>(s_trig, s_nodes, s_face, TA, lane, cur, A, liveA, validA,
-                                  c_reads);
+      project_tile<LDS_DEPTH, NP, IDS>(s_trig, s_nodes, s_face, TA, lane, cur, A, liveA, validA,
+                                       c_reads, s_hinv);
       take_level<NP>(B, xB, c_reads);
       descend_rest<NP>(P, B, c_reads);
       finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
-                                            c_reads);
+                                            c_reads, s_hist);
       B = A;
       TB = TA;
       tileB = tile;
@@ -1216,9 +1325,17 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     take_level<NP>(B, xB, c_reads);
     descend_rest<NP>(P, B, c_reads);
     finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
-                                          c_reads);
+                                          c_reads, s_hist);
   }
-  if (MODE == kExactList) P.pcount[blockIdx.x * kProbeWaves + wid] = Q.count;
+  if (MODE == kExactList || MODE == kExactCount)
+    P.pcount[blockIdx.x * kProbeWaves + wid] = Q.count;
+  if (s_hist) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < P.hist_bins; k += kProbeBlock) {
+      const uint32_t v = s_hist[k];
+      if (v) atomicAdd(P.counts + k, (unsigned long long)v);
+    }
+  }
   if (FUSED && Q.count > 0) {
     wave_sync();
     drain_queue<FULL, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
@@ -1446,6 +1563,38 @@ static ProbeFn probe_fn(int mode, int lds_depth, bool count, int np) {
                               : probe_mode_fn<kExactFused>(lds_depth, count, np);
 }
 
+// Count joins: lean kernels only.
+template <int MODE, int LDS>
+static ProbeFn probe_count_np(int np) {
+  return np == 1 ? probe_kernel<MODE, LDS, false, 1, false> : probe_kernel<MODE, LDS, false, 2, false>;
+}
+
+static ProbeFn probe_count_fn(bool exact, int lds_depth, int np) {
+  using F = ProbeFn (*)(int);
+  static const F tab[2][3] = {
+      {probe_count_np<kApproxCount, 0>, probe_count_np<kApproxCount, 1>,
+       probe_count_np<kApproxCount, 2>},
+      {probe_count_np<kExactCount, 0>, probe_count_np<kExactCount, 1>,
+       probe_count_np<kExactCount, 2>}};
+  return tab[exact ? 1 : 0][lds_depth](np);
+}
+
+// Joins of precomputed cell ids: lean kernels, approximate or with the
+// per-wave pending lists.
+template <int MODE, int LDS>
+static ProbeFn probe_ids_np(int np) {
+  return np == 1 ? probe_kernel<MODE, LDS, false, 1, false, true>
+                 : probe_kernel<MODE, LDS, false, 2, false, true>;
+}
+
+static ProbeFn probe_ids_fn(bool exact, int lds_depth, int np) {
+  using F = ProbeFn (*)(int);
+  static const F tab[2][3] = {
+      {probe_ids_np<kApprox, 0>, probe_ids_np<kApprox, 1>, probe_ids_np<kApprox, 2>},
+      {probe_ids_np<kExactList, 0>, probe_ids_np<kExactList, 1>, probe_ids_np<kExactList, 2>}};
+  return tab[exact ? 1 : 0][lds_depth](np);
+}
+
 // Batched joins: no counters.
 template <int MODE, int LDS>
 static ProbeFn probe_batched_np(int np) {
@@ -1484,7 +1633,7 @@ struct DeviceGuard {
 
 static void free_image(DevImage &d) {
   void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
-                  d.e64,   d.trig,  d.faces, d.top32, d.sink};
+                  d.e64,   d.trig,  d.faces, d.top32, d.sink, d.hinv};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -1666,6 +1815,16 @@ static int upload_image(act_index *x) {
   if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
   const uint64_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if ((rc = upload(d.sink, zeros, sizeof zeros, d.bytes))) return rc;
+  // the inverse of the 4-level Hilbert table: (state, 8 position bits) ->
+  // (i nibble << 4 | j nibble) | next state << 8
+  uint16_t fwd[1024], inv[1024];
+  hilbert_table4(fwd);
+  for (int st = 0; st < 4; st++)
+    for (int b = 0; b < 256; b++) {
+      const uint16_t e = fwd[st * 256 + b];
+      inv[st * 256 + (e & 255)] = (uint16_t)(b | (e & 0x300));
+    }
+  if ((rc = upload(d.hinv, inv, sizeof inv, d.bytes))) return rc;
   return ACT_OK;
 }
 
@@ -1717,6 +1876,7 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.refine = refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : refine;
   P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
   P.sink = x->dev.sink;
+  P.hinv = x->dev.hinv;
 }
 
 // Points per probe lane when a join leaves it to the index.
@@ -1724,13 +1884,25 @@ static int launch_np(const act_index *x) { return x->launch.points_per_lane; }
 
 // `ext`: a caller-provided pending workspace (its mask only; cap points per
 // pass) used instead of the stream's, so that the join allocates nothing.
+// `counts`: a count join (per-polygon number of covering points added to
+// counts[], no out[]); always with cell-local refinement and, in exact mode,
+// the per-wave pending lists.
+constexpr int64_t kCountPass = 1ll << 31;  // points per pass of a count join
+constexpr int kCountGridMax = 4096;        // so that the pending lists always fit
+constexpr int kLdsDynamicMax = 65536;      // dynamic LDS per probe block
+
+// `ids`: the points' level-30 cell ids (a->d_points then only for pending
+// points of exact joins, which use the per-wave lists).
 static int join_impl(const act_index *x, const act_join_args *a, void *stream,
-                     Workspace *ext = nullptr) {
+                     Workspace *ext = nullptr, unsigned long long *counts = nullptr,
+                     const uint64_t *ids = nullptr) {
   if (!x) return fail(ACT_E_ARG, "index is NULL");
   if (!a) return fail(ACT_E_ARG, "args is NULL");
   if (a->n < 0) return fail(ACT_E_ARG, "n < 0");
   if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
-  if (a->n > 0 && (!a->d_points || !a->d_out)) return fail(ACT_E_ARG, "points/out is NULL");
+  if (a->n > 0 && (!a->d_out && !counts)) return fail(ACT_E_ARG, "out is NULL");
+  if (a->n > 0 && !a->d_points && !(ids && x->host.mode == ACT_APPROX))
+    return fail(ACT_E_ARG, "points is NULL");
   bool pairs = a->d_pair_point || a->d_pair_poly || a->d_n_pairs;
   if (pairs && (!a->d_pair_point || !a->d_pair_poly || !a->d_n_pairs || a->pair_capacity < 0))
     return fail(ACT_E_ARG, "pair output needs point, poly, counter arrays and capacity >= 0");
@@ -1772,12 +1944,23 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
   // exact joins with cell-local refinement may resolve inside the probe;
   // the other refinement modes always use the resolve kernel
   const int pending = a->pending != ACT_PENDING_AUTO ? a->pending : L.pending;
-  const int mode = !exact ? kApprox
+  if (counts || ids) P.refine = ACT_REFINE_LOCAL;
+  const int mode = counts ? (exact ? kExactCount : kApproxCount)
+                   : ids ? (exact ? kExactList : kApprox)
+                   : !exact ? kApprox
                    : (P.refine == ACT_REFINE_LOCAL && pending == ACT_PENDING_QUEUE) ? kExactFused
                                                                                     : kExactMask;
-  int64_t pass = std::min(a->n, kMaxLaunchPoints);
+  int64_t pass = std::min(a->n, counts ? kCountPass : kMaxLaunchPoints);
   Workspace *w = nullptr;
-  if (mode == kExactMask) {
+  size_t lds_bytes = (size_t)n_lds * 1024;
+  if (counts) {
+    P.counts = counts;
+    // the polygons' histogram joins the trie levels in LDS when it fits
+    const int64_t hist = (int64_t)h.n_polys * 4;
+    P.hist_bins = lds_bytes + hist <= (size_t)kLdsDynamicMax ? (int32_t)h.n_polys : 0;
+    lds_bytes += (size_t)P.hist_bins * 4;
+  }
+  if (mode == kExactMask || mode == kExactCount || (ids && exact)) {
     if (ext) {
       w = ext;
     } else {
@@ -1788,8 +1971,9 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
     P.plist = w->plist;
     P.pcount = w->pcount;
     pass = std::min(a->pass_points > 0 ? std::min(a->pass_points, w->cap) : w->cap,
-                    kMaxLaunchPoints);
+                    counts || ids ? kCountPass : kMaxLaunchPoints);
   }
+  if (ids) pass = std::min(pass, kCountPass);
   using ResolveFn = void (*)(ProbeParams, int64_t);
   const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
                               ? (count ? resolve_kernel<true, true, false> : resolve_kernel<true, false, false>)
@@ -1798,13 +1982,15 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
   const ListFn resolve_list = count ? resolve_list_kernel<true> : resolve_list_kernel<false>;
   for (int64_t s0 = 0; s0 < a->n; s0 += pass) {
     const int64_t n = std::min(pass, a->n - s0);
-    P.pts = (const double2 *)a->d_points + s0;
-    P.out = a->d_out + s0;
+    P.pts = a->d_points ? (const double2 *)a->d_points + s0 : nullptr;
+    P.ids = ids ? ids + s0 : nullptr;
+    P.out = counts ? nullptr : a->d_out + s0;
     P.n = n;
     P.base = s0;
     const int64_t tile_blocks = (n + (int64_t)kProbeBlock * np - 1) / ((int64_t)kProbeBlock * np);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : L.grid,
-                                                                  tile_blocks));
+    int grid = (int)std::max<int64_t>(1, std::min<int64_t>(a->grid > 0 ? a->grid : L.grid,
+                                                            tile_blocks));
+    if (counts || ids) grid = std::min(grid, kCountGridMax);
     // cell-local refinement: the probe waves list their pending points when
     // the pass's indices fit 32 bits and the regions fit the workspace
     int pmode = mode;
@@ -1815,14 +2001,22 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
       pmode = kExactList;
       P.region = (uint32_t)region;
     }
-    hipLaunchKernelGGL(probe_fn(pmode, depth, count, np), dim3(grid), dim3(kProbeBlock),
-                       (size_t)n_lds * 1024, (hipStream_t)stream, P);
+    if (mode == kExactCount || (ids && exact)) {
+      if (!(n < (1ll << 32) && nwaves <= kListWavesMax && region * nwaves <= w->plist_cap))
+        return fail(ACT_E_RANGE, "pending lists do not fit the workspace");
+      P.region = (uint32_t)region;
+    }
+    const ProbeFn probe = counts ? probe_count_fn(exact, depth, np)
+                          : ids  ? probe_ids_fn(exact, depth, np)
+                                 : probe_fn(pmode, depth, count, np);
+    hipLaunchKernelGGL(probe, dim3(grid), dim3(kProbeBlock), lds_bytes, (hipStream_t)stream, P);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
       return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
-    if (pmode == kExactList) {
-      hipLaunchKernelGGL(resolve_list, dim3((unsigned)((nwaves + 3) / 4)), dim3(kListBlock), 0,
+    if (pmode == kExactList || pmode == kExactCount) {
+      const ListFn list_fn = pmode == kExactCount ? resolve_list_kernel<false, true> : resolve_list;
+      hipLaunchKernelGGL(list_fn, dim3((unsigned)((nwaves + 3) / 4)), dim3(kListBlock), 0,
                          (hipStream_t)stream, P, (uint32_t)nwaves);
       e = hipGetLastError();
       if (e != hipSuccess)
@@ -2057,6 +2251,50 @@ void act_build_opts_init(act_build_opts *o) {
   o->threads = 0;
   o->prefix_level = -1;
   o->margin_deg = 1e-9;
+  o->train_points = nullptr;
+  o->n_train = 0;
+  o->memory_budget = 0;
+  o->train_max_level = 30;
+  o->reserved0 = 0;
+}
+
+// Builds the host index and, for a device, uploads it. ACT_AUTO follows the
+// paper's policy (Section III-A): the approximate index at precision_m if
+// its image fits opts->memory_budget, else the exact index trained within
+// the budget, with the covering level lowered until the untrained image
+// fits.
+static int build_impl(const double *verts_latlng, const int64_t *ring_off,
+                      const int32_t *poly_ring_off, int32_t n_polys, BuildParams bp,
+                      act_index *x, std::string &err) {
+  static const int32_t zero = 0;
+  const int32_t *pro = n_polys > 0 ? poly_ring_off : &zero;
+  int rc;
+  try {
+    if (bp.mode != ACT_AUTO) return build_host_index(verts_latlng, ring_off, pro, n_polys, bp, x->host, err);
+    const int64_t budget = bp.memory_budget;
+    BuildParams ap = bp;
+    ap.mode = ACT_APPROX;
+    ap.n_train = 0;
+    // each cell of the covering takes at least one 8-byte trie entry
+    ap.cell_limit = budget > 0 ? budget / 8 + 1 : 0;
+    rc = build_host_index(verts_latlng, ring_off, pro, n_polys, ap, x->host, err);
+    if (rc == ACT_OK && (budget == 0 || image_bytes(x->host) <= budget)) return ACT_OK;
+    if (rc != ACT_OK && rc != ACT_E_RANGE) return rc;
+    BuildParams ep = bp;
+    ep.mode = ACT_EXACT;
+    ep.precision_m = 0.0;
+    for (int ml = bp.max_level; ml >= 1; ml -= 2) {
+      ep.max_level = ml;
+      rc = build_host_index(verts_latlng, ring_off, pro, n_polys, ep, x->host, err);
+      if (rc) return rc;
+      if (image_bytes(x->host) <= budget) return ACT_OK;
+    }
+    err = "no index fits the memory budget of " + std::to_string(budget) + " bytes";
+    return ACT_E_RANGE;
+  } catch (const std::bad_alloc &) {
+    err = "out of host memory during build";
+    return ACT_E_OOM;
+  }
 }
 
 int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t *poly_ring_off,
@@ -2067,19 +2305,31 @@ int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t
   if (n_polys < 0) return fail(ACT_E_ARG, "n_polys < 0");
   if (n_polys > 0 && (!verts_latlng || !ring_off || !poly_ring_off))
     return fail(ACT_E_ARG, "polygon arrays are NULL");
-  if (mode != ACT_EXACT && mode != ACT_APPROX) return fail(ACT_E_ARG, "mode must be ACT_EXACT or ACT_APPROX");
-  if (mode == ACT_APPROX && !(precision_m >= 0.05))
+  if (mode != ACT_EXACT && mode != ACT_APPROX && mode != ACT_AUTO)
+    return fail(ACT_E_ARG, "mode must be ACT_EXACT, ACT_APPROX or ACT_AUTO");
+  if (mode != ACT_EXACT && !(precision_m >= 0.05))
     return fail(ACT_E_ARG, "approximate mode needs precision_m >= 0.05");
   act_build_opts o;
   act_build_opts_init(&o);
   if (opts) o = *opts;
   BuildParams bp;
   bp.mode = mode;
-  bp.precision_m = mode == ACT_APPROX ? precision_m : 0.0;
+  bp.precision_m = mode != ACT_EXACT ? precision_m : 0.0;
   bp.max_level = o.max_level ? o.max_level : 20;
   bp.threads = o.threads;
   bp.prefix_level = o.prefix_level;
   bp.margin_deg = o.margin_deg > 0 ? o.margin_deg : 1e-9;
+  bp.train_points = o.train_points;
+  bp.n_train = o.n_train;
+  bp.memory_budget = o.memory_budget;
+  bp.train_max_level = o.train_max_level ? o.train_max_level : 30;
+  if (bp.n_train < 0 || (bp.n_train > 0 && !bp.train_points))
+    return fail(ACT_E_ARG, "training needs n_train >= 0 points");
+  if (bp.memory_budget < 0) return fail(ACT_E_ARG, "memory_budget < 0");
+  if (mode == ACT_AUTO && bp.memory_budget <= 0)
+    return fail(ACT_E_ARG, "ACT_AUTO needs a memory_budget");
+  if (bp.train_max_level < 1 || bp.train_max_level > kMaxLevel)
+    return fail(ACT_E_ARG, "train_max_level must be 1..30");
   const int device = o.device;
   if (bp.max_level < 1 || bp.max_level > kMaxLevel) return fail(ACT_E_ARG, "max_level must be 1..30");
   if (bp.prefix_level < -1 || bp.prefix_level > kMaxLevel)
@@ -2090,19 +2340,57 @@ int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t
   act_index *x = new (std::nothrow) act_index;
   if (!x) return fail(ACT_E_OOM, "out of host memory");
   std::string err;
-  static const int32_t zero = 0;
+  int rc = build_impl(verts_latlng, ring_off, poly_ring_off, n_polys, bp, x, err);
+  if (rc) {
+    delete x;
+    return fail(rc, err);
+  }
+  x->device = device;
+  if (device >= 0) {
+    DeviceGuard g(device);
+    rc = upload_image(x);
+    if (rc) {
+      free_image(x->dev);
+      delete x;
+      return rc;
+    }
+  }
+  *out = x;
+  return ACT_OK;
+}
+
+int act_save(const act_index *x, const char *path) {
+  if (!x || !path) return fail(ACT_E_ARG, "index or path is NULL");
+  std::string err;
+  const int rc = save_host_index(x->host, &x->launch, sizeof(act_launch), path, err);
+  return rc ? fail(rc, err) : ACT_OK;
+}
+
+int act_load(const char *path, int32_t device, act_index **out) {
+  if (!path || !out) return fail(ACT_E_ARG, "path or out is NULL");
+  *out = nullptr;
+  if (device >= 0 && device >= device_count())
+    return fail(ACT_E_DEVICE, "HIP device " + std::to_string(device) + " not available");
+  act_index *x = new (std::nothrow) act_index;
+  if (!x) return fail(ACT_E_OOM, "out of host memory");
+  std::string err;
+  act_launch L;
   int rc;
   try {
-    rc = build_host_index(verts_latlng, ring_off, n_polys > 0 ? poly_ring_off : &zero, n_polys,
-                          bp, x->host, err);
+    rc = load_host_index(path, x->host, &L, sizeof L, err);
   } catch (const std::bad_alloc &) {
     rc = ACT_E_OOM;
-    err = "out of host memory during build";
+    err = "out of host memory while loading";
   }
   if (rc) {
     delete x;
     return fail(rc, err);
   }
+  const bool launch_ok = L.grid >= 1 && L.grid <= 65536 && L.lds_levels >= -1 &&
+                         L.lds_levels <= 2 && (L.points_per_lane == 1 || L.points_per_lane == 2) &&
+                         L.refine >= ACT_REFINE_LOCAL && L.refine <= ACT_REFINE_FP64 &&
+                         L.pending >= ACT_PENDING_KERNEL && L.pending <= ACT_PENDING_QUEUE;
+  x->launch = launch_ok ? L : act_launch();
   x->device = device;
   if (device >= 0) {
     DeviceGuard g(device);
@@ -2218,6 +2506,29 @@ int act_join_noalloc(const act_index *x, const double *d_points, int64_t n, int3
   return join_impl(x, &a, stream, &w);
 }
 
+int act_join_ids(const act_index *x, const uint64_t *d_ids, const double *d_points, int64_t n,
+                 int32_t *d_out, void *stream) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (n > 0 && !d_ids) return fail(ACT_E_ARG, "ids is NULL");
+  act_join_args a{};
+  a.d_points = d_points;
+  a.n = n;
+  a.d_out = d_out;
+  a.lds_levels = -1;
+  return join_impl(x, &a, stream, nullptr, nullptr, d_ids);
+}
+
+int act_join_count(const act_index *x, const double *d_points, int64_t n, int64_t *d_counts,
+                   void *stream) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (!d_counts && x->host.n_polys > 0) return fail(ACT_E_ARG, "counts is NULL");
+  act_join_args a{};
+  a.d_points = d_points;
+  a.n = n;
+  a.lds_levels = -1;
+  return join_impl(x, &a, stream, nullptr, (unsigned long long *)d_counts);
+}
+
 int act_join_pairs(const act_index *x, const double *d_points, int64_t n, int32_t *d_out,
                    int64_t *d_pair_point, int32_t *d_pair_poly, int64_t capacity,
                    int64_t *d_n_pairs, void *stream) {
@@ -2299,6 +2610,9 @@ int act_index_stats(const act_index *x, act_stats *o) {
   o->precision_m = h.precision_m;
   o->build_seconds = h.build_seconds;
   o->local_words = h.local_words;
+  o->train_splits = h.train_splits;
+  o->train_points_used = h.train_points_used;
+  o->image_bytes = image_bytes(h);
   return ACT_OK;
 }
 

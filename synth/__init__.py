@@ -419,6 +419,16 @@ def workload_points(name: str, start: int = 0, stop: int | None = None) -> np.nd
     return mixture_points(start, stop, w["point_seed"], Mixture.make(w["mixture_seed"]))
 
 
+def training_points(name: str, n: int) -> np.ndarray:
+    """Historical points for training a workload's index: the workload's own
+    point distribution, drawn from a different seed (point seed + 5000)."""
+    w = WORKLOADS[name]
+    seed = w["point_seed"] + 5000
+    if w["points"] == "uniform":
+        return uniform_points(0, n, seed)
+    return mixture_points(0, n, seed, Mixture.make(w["mixture_seed"]))
+
+
 def batch_sizes(n_batches: int, seed: int, hi: float = 1e6) -> np.ndarray:
     """Uneven batch sizes floor(exp(U(0, ln hi))), at least 1."""
     g = _rng(seed)

@@ -1,0 +1,93 @@
+"""GPU parity of joins on precomputed cell ids (act_join_ids): points that
+arrive with their level-30 cell ids, as in the paper's probe.
+
+Ids from the library's own projection (act_cell_ids) give act_join's output
+exactly; ids computed on the host by the oracle's numpy projection (a
+different sin/cos) give the oracle's exact output too, since the cells'
+classification boxes carry a margin far above either projection's error.
+Ids that name no leaf match nothing.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cellid as C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def act():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1802_09488_amd as act
+    return act
+
+
+_IDX = {}
+
+
+def index(act, w, mode, prec=0.0):
+    key = (w, mode, prec)
+    if key not in _IDX:
+        P = synth.workload_polygons(w)
+        _IDX[key] = (P, act.build(P, mode, prec))
+    return _IDX[key]
+
+
+def near_edges(P, rng, n=20000):
+    v = P.verts
+    k = rng.choice(len(v) - 1, min(len(v) - 1, n), replace=False)
+    t = rng.uniform(0, 1, (len(k), 1))
+    on = v[k] + t * (v[k + 1] - v[k])
+    return np.concatenate([v[k], on + rng.integers(-2, 3, on.shape) * np.spacing(on)])
+
+
+@pytest.mark.parametrize("w,mode,prec,n", [("c1", "exact", 0.0, 100_000),
+                                           ("c2", "exact", 0.0, 2_000_000),
+                                           ("c2", "approx", 4.0, 2_000_000),
+                                           ("c3", "exact", 0.0, 300_000)])
+def test_ids_from_the_library_match_join(act, w, mode, prec, n):
+    P, idx = index(act, w, mode, prec)
+    pts = np.concatenate([synth.workload_points(w, 0, n), near_edges(P, np.random.default_rng(3))])
+    t = torch.from_numpy(pts).cuda()
+    ids = act.cell_ids(t)
+    got = idx.join_ids(ids, t if mode == "exact" else None).cpu().numpy()
+    want = idx.join(t).cpu().numpy()
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad.size, bad[:5])
+    if mode == "exact":
+        assert np.array_equal(got[:200_000], oracle.join(P, pts[:200_000]).out)
+
+
+@pytest.mark.parametrize("w", ["c1", "c2"])
+def test_host_ids_give_the_oracle(act, w):
+    P, idx = index(act, w, "exact")
+    rng = np.random.default_rng(4)
+    pts = np.concatenate([synth.workload_points(w, 0, 300_000), near_edges(P, rng)])
+    ids = C.cell_ids(pts[:, 0], pts[:, 1]).view(np.int64)
+    got = idx.join_ids(torch.from_numpy(ids).cuda(), torch.from_numpy(pts).cuda()).cpu().numpy()
+    assert np.array_equal(got, oracle.join(P, pts).out)
+
+
+def test_invalid_ids_match_nothing(act):
+    P, idx = index(act, "c1", "exact")
+    pts = synth.workload_points("c1", 0, 4096)
+    ids = C.cell_ids(pts[:, 0], pts[:, 1]).view(np.int64).copy()
+    good = idx.join_ids(torch.from_numpy(ids).cuda(), torch.from_numpy(pts).cuda()).cpu().numpy()
+    assert (good >= 0).mean() > 0.5
+    bad = ids.copy()
+    bad[0::3] = 0                                   # the invalid-point id
+    bad[1::3] = (ids[1::3].view(np.uint64) | np.uint64(7 << 61)).view(np.int64)  # face 7
+    bad[2::3] = ids[2::3] & ~np.int64(1)            # no marker at bit 0
+    got = idx.join_ids(torch.from_numpy(bad).cuda(), torch.from_numpy(pts).cuda()).cpu().numpy()
+    assert np.all(got == -1)
+    # approximate mode needs no points; empty input is a no-op
+    Pa, ia = index(act, "c1", "approx", 4.0)
+    t = torch.from_numpy(ids).cuda()
+    assert np.array_equal(ia.join_ids(t).cpu().numpy(),
+                          ia.join(torch.from_numpy(pts).cuda()).cpu().numpy())
+    assert ia.join_ids(t[:0]).shape[0] == 0

@@ -958,3 +958,66 @@ def test_points_at_cell_edges(act, w):
     for mode in REFINE_MODES:
         out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
         assert_exact(P, pts, out, pairs, "%s-cell-edges-%s" % (w, mode))
+
+
+# ------------------------------------------------------------ trained indexes
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("w,n_train,max_level", [("c2", 1_000_000, 20), ("c2", 300_000, 16),
+                                                 ("c3", 1_000_000, 20)])
+def test_trained_index_exact(act, w, n_train, max_level):
+    """Indexes trained with points of the workload's distribution (Section
+    III-D; cells split below the covering level where training points hit
+    candidates) stay bit-exact against the oracle in every refinement mode:
+    workload points, training points (which lie in the split cells), edge
+    cases and points at the corners of the trained cells."""
+    P = synth.workload_polygons(w)
+    tp = synth.training_points(w, n_train)
+    idx = act.build(P, "exact", max_level=max_level, train_points=tp)
+    st = idx.stats()
+    assert st["train_splits"] > 0 and st["max_cell_level"] > max_level
+    rng = np.random.default_rng(91)
+    pts = np.concatenate([synth.workload_points(w, 0, 100_000), tp[:50_000],
+                          edge_case_points(P, rng)[:20_000],
+                          _cell_corner_points(P, rng, 30_000,
+                                              np.arange(max_level, st["max_cell_level"] + 1))])
+    for mode in REFINE_MODES:
+        out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+        assert_exact(P, pts, out, pairs, "%s-trained-%s" % (w, mode))
+    # the trained index's count join agrees with its pairs
+    t = torch.from_numpy(pts).cuda()
+    cnt = idx.join_count(t).cpu().numpy()
+    ref = oracle.join(P, pts)
+    assert np.array_equal(cnt, np.bincount(ref.pair_set()[:, 1], minlength=P.n_polys))
+
+
+def test_saved_and_auto_indexes(act, tmp_path):
+    """An index written with act_save and read back with act_load joins
+    exactly like the original (which keeps its tuned launch); ACT_AUTO
+    indexes, approximate under a large budget and exact and trained under
+    a smaller one, meet their modes' bars against the oracle."""
+    P = synth.workload_polygons("c2")
+    tp = synth.training_points("c2", 200_000)
+    idx = act.build(P, "exact", train_points=tp)
+    set_launch(act, idx, tmp_path / "q.txt", 512, 2, 1, act.ACT_REFINE_LOCAL,
+               act.ACT_PENDING_QUEUE)
+    path = tmp_path / "c2.act"
+    idx.save(path)
+    got = act.load(path)
+    assert got.digest() == idx.digest()
+    pts = np.concatenate([synth.workload_points("c2", 0, 400_000),
+                          edge_case_points(P, np.random.default_rng(93))])
+    t = torch.from_numpy(pts).cuda()
+    a, b = idx.join(t).cpu().numpy(), got.join(t).cpu().numpy()
+    assert np.array_equal(a, b)
+    out, pairs, _ = gpu_join(got, pts)
+    assert_exact(P, pts, out, pairs, "c2-loaded")
+    approx = act.build(P, "approx", 4.0, device=-1).stats()["image_bytes"]
+    big = act.build(P, "auto", 4.0, memory_budget=approx, train_points=tp)
+    assert big.mode == act.ACT_APPROX
+    out, pairs, _ = gpu_join(big, pts[:200_000])
+    assert_approx(P, pts[:200_000], out, pairs, 4.0, "c2-auto-approx")
+    small = act.build(P, "auto", 4.0, memory_budget=approx - 1, train_points=tp)
+    assert small.mode == act.ACT_EXACT and small.stats()["device_bytes"] <= approx - 1
+    out, pairs, _ = gpu_join(small, pts)
+    assert_exact(P, pts, out, pairs, "c2-auto-exact")

@@ -298,3 +298,161 @@ def test_empty_polygon_set(act):
     st = idx.stats()
     assert st["n_cells"] == 0 and st["n_faces"] == 0
     assert idx.lookup_host([4], [5], [7]).tolist() == [0]
+
+
+def _cand_fraction(idx, pts):
+    """Share of points whose cell has a candidate reference (host lookups)."""
+    face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    ent = idx.lookup_host(face, i, j)
+    lut = idx.lut_host()
+    return np.mean([any(not inter for _, inter in _decode(e, lut)) for e in ent])
+
+
+def test_training_refines_expensive_cells(act):
+    """Training (Section III-D) with points of the workload's distribution:
+    cells are split, the index stays conservative (every covering polygon
+    referenced, interior references true, checked against the oracle on
+    fresh points and on the training points), fewer fresh points land in
+    expensive cells, and the build is deterministic."""
+    P = synth.workload_polygons("c2")
+    tp = synth.training_points("c2", 300_000)
+    base = act.build(P, "exact", device=-1, max_level=16)
+    idx = act.build(P, "exact", device=-1, max_level=16, train_points=tp)
+    st = idx.stats()
+    assert st["train_splits"] > 1000 and st["train_points_used"] == len(tp)
+    assert st["max_cell_level"] > 16 and st["n_cells"] > base.stats()["n_cells"]
+    pts = np.concatenate([synth.workload_points("c2", 0, 20000), tp[:5000], P.verts[::7]])
+    _structural_check(act, P, idx, pts)
+    fresh = synth.workload_points("c2", 50_000, 70_000)
+    assert _cand_fraction(idx, fresh) < 0.8 * _cand_fraction(base, fresh)
+    again = act.build(P, "exact", device=-1, max_level=16, train_points=tp, threads=3)
+    assert again.digest() == idx.digest()
+    # the local records of split cells decide like the oracle
+    face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    ent = idx.lookup_host(face, i, j)
+    lut = idx.lut_host()
+    checked = 0
+    for k in range(0, len(pts), 3):
+        for p, interior in _decode(ent[k], lut):
+            if not interior:
+                got = idx.refine_local_host(face[k], i[k], j[k], pts[k, 0], pts[k, 1], p)
+                assert got == oracle.covers(P, p, pts[k, 0], pts[k, 1])
+                checked += 1
+    assert checked > 100
+
+
+def test_training_respects_memory_budget(act):
+    """Training stops when the next split would take the device image past
+    the budget: the image stays within it and not every training point was
+    used; a budget below the untrained image trains nothing; approximate
+    indexes ignore training."""
+    P = synth.workload_polygons("c2")
+    tp = synth.training_points("c2", 300_000)
+    base = act.build(P, "exact", device=-1, max_level=16).stats()
+    budget = base["image_bytes"] + 200_000
+    st = act.build(P, "exact", device=-1, max_level=16, train_points=tp,
+                   memory_budget=budget).stats()
+    assert 0 < st["train_splits"] and st["train_points_used"] < len(tp)
+    assert base["image_bytes"] < st["image_bytes"] <= budget
+    st0 = act.build(P, "exact", device=-1, max_level=16, train_points=tp,
+                    memory_budget=base["image_bytes"] - 1).stats()
+    assert st0["train_splits"] == 0 and st0["image_bytes"] == base["image_bytes"]
+    sa = act.build(P, "approx", 8.0, device=-1, train_points=tp).stats()
+    assert sa["train_splits"] == 0
+    cap = act.build(P, "exact", device=-1, max_level=16, train_points=tp,
+                    train_max_level=17).stats()
+    assert cap["max_cell_level"] == 17
+
+
+def test_auto_policy_follows_the_budget(act):
+    """ACT_AUTO (Section III-A): the approximate index when it fits the
+    budget; else the exact index, its covering level lowered until the
+    untrained image fits, then trained within the budget; an error when
+    nothing fits."""
+    P = synth.workload_polygons("c2")
+    tp = synth.training_points("c2", 200_000)
+    approx = act.build(P, "approx", 4.0, device=-1).stats()
+    big = act.build(P, "auto", 4.0, device=-1, memory_budget=approx["image_bytes"],
+                    train_points=tp)
+    assert big.mode == act.ACT_APPROX and big.stats()["image_bytes"] == \
+        approx["image_bytes"]
+    budget = approx["image_bytes"] - 1
+    small = act.build(P, "auto", 4.0, device=-1, memory_budget=budget, train_points=tp)
+    st = small.stats()
+    assert small.mode == act.ACT_EXACT and st["image_bytes"] <= budget
+    assert st["train_splits"] > 0
+    pts = synth.workload_points("c2", 0, 5000)
+    _structural_check(act, P, small, pts)
+    with pytest.raises(act.ActError) as e:
+        act.build(P, "auto", 4.0, device=-1, memory_budget=100_000)
+    assert e.value.code == -7
+    with pytest.raises(act.ActError):
+        act.build(P, "auto", 4.0, device=-1)  # no budget
+
+
+def test_save_load_roundtrip(act, tmp_path):
+    """An index file reproduces the index (digest, statistics, lookups); a
+    corrupt, truncated or foreign file is refused."""
+    P = synth.workload_polygons("c2")
+    for mode, prec, kw in (("exact", 0.0, {"train_points": synth.training_points("c2", 50_000)}),
+                           ("approx", 4.0, {})):
+        idx = act.build(P, mode, prec, device=-1, **kw)
+        path = tmp_path / ("%s.act" % mode)
+        idx.save(path)
+        got = act.load(path, device=-1)
+        assert got.digest() == idx.digest()
+        a, b = idx.stats(), got.stats()
+        for k in ("n_cells", "n_nodes", "lut_words", "local_words", "max_depth", "mode",
+                  "precision_m", "train_splits", "image_bytes", "face_prefix_level"):
+            assert a[k] == b[k], k
+        pts = synth.workload_points("c2", 0, 20000)
+        face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+        i, j = C.leaf_ij(s, tt)
+        assert np.array_equal(idx.lookup_host(face, i, j), got.lookup_host(face, i, j))
+    raw = bytearray(path.read_bytes())
+    for label, data in (("flip", raw[:1000] + bytes([raw[1000] ^ 1]) + raw[1001:]),
+                        ("truncated", raw[:-9]), ("foreign", b"not an index" + raw[12:])):
+        bad = tmp_path / ("bad_%s.act" % label)
+        bad.write_bytes(bytes(data))
+        with pytest.raises(act.ActError) as e:
+            act.load(bad, device=-1)
+        assert e.value.code == -1, label
+    with pytest.raises(act.ActError):
+        act.load(tmp_path / "missing.act", device=-1)
+
+
+def _fnv(data: bytes) -> int:
+    d = 0xcbf29ce484222325
+    for b in data:
+        d = ((d ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return d
+
+
+def test_load_refuses_out_of_range_references(act, tmp_path):
+    """A file whose digest is right but whose trie points outside the image
+    (a child pointer past the last node, a list offset past the table) is
+    refused: the loader checks every reference the probe would follow."""
+    import struct
+    sq = [np.array([[40.70, -74.00], [40.70, -73.99], [40.71, -73.99], [40.71, -74.00]])]
+    P = synth.Polygons.from_rings([sq])
+    idx = act.build(P, "exact", device=-1)
+    path = tmp_path / "sq.act"
+    idx.save(path)
+    raw = bytearray(path.read_bytes())
+    assert _fnv(bytes(raw[:-8])) == struct.unpack("<Q", raw[-8:])[0]  # the documented digest
+    assert act.load(path, device=-1).digest() == idx.digest()
+    n_nodes = struct.unpack("<Q", raw[224:232])[0] // 256
+    ent = np.frombuffer(bytes(raw[232:232 + 8 * 256 * n_nodes]), dtype=np.uint64)
+    for label, want_tag, value in (("pointer", 0, (n_nodes + 5) << 2),
+                                   ("list", 3, ((1 << 29) << 2) | 3)):
+        k = int(np.nonzero((ent != 0) & ((ent & np.uint64(3)) == np.uint64(want_tag)))[0][0])
+        bad = bytearray(raw)
+        bad[232 + 8 * k:240 + 8 * k] = struct.pack("<Q", value)
+        bad[-8:] = struct.pack("<Q", _fnv(bytes(bad[:-8])))
+        p = tmp_path / ("bad_%s.act" % label)
+        p.write_bytes(bytes(bad))
+        with pytest.raises(act.ActError) as e:
+            act.load(p, device=-1)
+        assert "corrupt" in str(e.value), label
