@@ -400,9 +400,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"],
-                    help="c2 (default): 290 polygons, 1e8 points; c3: 40k polygons, 1e9 "
-                         "points in 2^24 batches; c4: 10,000 uneven batches, one graph "
+    ap.add_argument("--workload", default="all", choices=["all", "c2", "c3", "c4", "c5"],
+                    help="all (default): the c2 headline (290 polygons, 1e8 points) plus "
+                         "compact c3/c4/c5 legs; c2: the headline alone; c3: 40k polygons, "
+                         "1e9 points in 2^24 batches; c4: 10,000 uneven batches, one graph "
                          "replay; c5: serving sweep")
     ap.add_argument("--points", type=int, default=0, help="override the point count")
     ap.add_argument("--cpu-sample", type=int, default=0,
@@ -429,16 +430,26 @@ def main():
               "splits the points, and this benchmark runs and reports the single-GPU case only "
               "(--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    {"c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)
+    {"all": run_all, "c2": run_c2, "c3": run_c3, "c4": run_c4, "c5": run_c5}[args.workload](args)
 
 
-def run_c2(args):
+def run_all(args):
+    """The c2 headline line, with compact c3, c4 and c5 legs in it."""
+    res, keep = run_c2(args, emit=False)
+    if res is None:
+        return
+    res["legs"] = compact_legs(args, keep)
+    print(json.dumps(res), flush=True)
+
+
+def run_c2(args, emit=True):
     import numpy as np
     import torch
 
     import synth
     import paper_1802_09488_amd as act
 
+    args.workload = "c2"
     w = synth.WORKLOADS[args.workload]
     n = args.points or w["n_points"]
     log("polygons", args.workload)
@@ -482,7 +493,7 @@ def run_c2(args):
                "approx_probe_ms": float(np.mean(prb_a)),
                "kernel_sources_sha256_16": kernel_source_hash()}
         print(json.dumps(res), flush=True)
-        return
+        return None, None
     log("timing refinement variants")
     k = max(3, args.steps // 2)
     var = {}
@@ -581,7 +592,173 @@ def run_c2(args):
         ns = min(args.cpu_sample or n, n)
         res["cpu_baseline"], res["parity_vs_oracle"] = cpu_baseline_and_parity(
             P, args.workload, ns, exact_out, pc_keep.get("pairs"), pc_keep.get("counts"))
-    print(json.dumps(res), flush=True)
+    if emit:
+        print(json.dumps(res), flush=True)
+    return res, {"approx4m": idx_a}
+
+
+def _timed_stream(idx, pts, out, bsz, steps, **kw):
+    """Joins of pts in batches of bsz (one step = all batches): wall clock
+    over the steps and HIP-event time of each."""
+    import torch
+    n = pts.shape[0]
+
+    def once():
+        for s in range(0, n, bsz):
+            idx.join_ex(pts[s:s + bsz], out[s:s + bsz], **kw)
+    once()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        once()
+        b.record()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t, [a.elapsed_time(b) for a, b in ev]
+
+
+def _index_metrics(ctr):
+    """The paper's index metrics (Tables III and IV) from join counters:
+    false hits, solely true hits, and candidates per point that needs
+    refinement."""
+    pts = max(1, ctr["points"])
+    return {"false_hit_pct": 100.0 * ctr["false_hit"] / pts,
+            "solely_true_hit_pct": 100.0 * ctr["solely_true"] / pts,
+            "refined_point_pct": 100.0 * ctr["cand_points"] / pts,
+            "candidates_per_refined_point": ctr["candidates"] / max(1, ctr["cand_points"])}
+
+
+def compact_legs(args, keep):
+    """Compact forms of the other workloads, in the default run:
+    c3: 2^26 points of the 40,000-polygon stream in 2^24 batches, exact
+    (untrained, and trained with 4e6 points: the Table IV analogue) and
+    approx@1m, with an oracle sample; c4: the first 1,000 batches of the
+    uneven-batch mix on the c3 exact index, tuned, one graph replay per
+    step, oracle on 1% of the batches plus every batch under 1,000 points;
+    c5: the serving sweep at 1e3, 1e4 and 5e4 requests/s over the c2
+    approx@4m and c3 exact indexes."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    import paper_1802_09488_amd as act
+    legs = {}
+    cores = len(os.sched_getaffinity(0))
+    log("c3: polygons and indexes")
+    P = synth.workload_polygons("c3")
+    t0 = time.perf_counter()
+    ie = act.build(P, "exact")
+    tb_e = time.perf_counter() - t0
+    tp = synth.training_points("c3", 4_000_000)
+    t0 = time.perf_counter()
+    it = act.build(P, "exact", train_points=tp)
+    tb_t = time.perf_counter() - t0
+    del tp
+    n, bsz = 1 << 26, 1 << 24
+    log("c3: staging %d points" % n)
+    pts = _stage_points("c3", n)
+    out = torch.empty(n, dtype=torch.int32, device="cuda")
+    ie.reserve(bsz)
+    it.reserve(bsz)
+    steps = 3
+    c3 = {"n_points": n, "batch": bsz, "steps": steps}
+    sample = synth.workload_points("c3", 0, 200_000)
+    ref = oracle.join(P, sample, nthreads=cores)
+    for name, ix, tb in (("exact", ie, tb_e), ("exact_trained_4e6", it, tb_t)):
+        wall, ms = _timed_stream(ix, pts, out, bsz, steps)
+        _, _, ctr = ix.join_ex(pts[:bsz], out[:bsz], counters=True)
+        st = ix.stats()
+        ok = bool(np.array_equal(out[:200_000].cpu().numpy(), ref.out))
+        c3[name] = {"points_per_s": n * steps / wall, "stream_ms": float(np.median(ms)),
+                    "roofline_frac": BYTES_PER_POINT * n * steps / wall / 1e9 / PEAK_HBM_GBS,
+                    "index_metrics": dict(_index_metrics(ctr), tree_nodes=st["n_nodes"],
+                                          image_bytes=st["image_bytes"],
+                                          train_splits=st["train_splits"]),
+                    "build_s": tb, "oracle_sample_identical": ok}
+    wq, _ = _timed_stream(ie, pts, out, bsz, 1, pending=act.ACT_PENDING_QUEUE)
+    c3["exact_in_probe_queue_points_per_s"] = n / wq
+    t0 = time.perf_counter()
+    oracle.join(P, sample, nthreads=cores)
+    dt = time.perf_counter() - t0
+    c3["cpu_baseline"] = {"value": len(sample) / dt, "unit": "points/s", "cores": cores,
+                          "kind": "oracle", "sample": "first 200,000 points of the c3 stream, "
+                                                      "exact, %.1f s" % dt}
+    del it
+    log("c3: approx@1m")
+    t0 = time.perf_counter()
+    ia = act.build(P, "approx", 1.0)
+    tb_a = time.perf_counter() - t0
+    wall, ms = _timed_stream(ia, pts, out, bsz, steps)
+    oa, pa = ia.join_pairs(pts[:200_000])
+    got = set(map(tuple, pa.cpu().numpy().tolist()))
+    oa = oa.cpu().numpy()
+    got |= {(i, int(o)) for i, o in enumerate(oa) if o >= 0}
+    missing = len(set(map(tuple, ref.pair_set().tolist())) - got)
+    c3["approx1m"] = {"points_per_s": n * steps / wall, "stream_ms": float(np.median(ms)),
+                      "build_s": tb_a, "image_bytes": ia.stats()["image_bytes"],
+                      "oracle_pairs_missing_in_sample": missing}
+    del ia, pts, out
+    torch.cuda.empty_cache()
+    legs["c3"] = c3
+
+    log("c4: 1,000 uneven batches")
+    sizes = synth.batch_sizes(10_000, 3004)[:1000]
+    total = int(sizes.sum())
+    pts = _stage_points("c3", total)
+    tune = ie.tune(pts[:min(total, 1 << 25)])
+    out = torch.full((total,), -9, dtype=torch.int32, device="cuda")
+    bounds = np.concatenate([[0], np.cumsum(sizes)])
+    batches = [(pts[a:b], out[a:b]) for a, b in zip(bounds[:-1], bounds[1:])]
+    desc, tot = act.batch_descriptors(batches)
+    ticks = torch.zeros(len(batches) + 1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    ie.batched_reserve(len(batches), tot, stream=s)
+    with torch.cuda.stream(s):
+        ie.join_batched(desc, tot, ticks=ticks)
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ie.join_batched(desc, tot, ticks=ticks)
+    hz = act.wall_clock_hz(0)
+    ms, p50, p99 = [], [], []
+    for _ in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+        t = ticks.cpu().numpy().view(np.uint64).astype(np.float64)
+        lat = (t[1:] - t[0]) / hz * 1e3
+        p50.append(float(np.percentile(lat, 50)))
+        p99.append(float(np.percentile(lat, 99)))
+    rng = np.random.default_rng(3005)
+    pick = sorted(set(rng.choice(len(sizes), 10, replace=False).tolist())
+                  | set(np.nonzero(sizes < 1000)[0].tolist()))
+    sel = np.concatenate([np.arange(bounds[b], bounds[b + 1]) for b in pick])
+    sel_t = torch.from_numpy(sel).cuda()
+    okc4 = bool(np.array_equal(out[sel_t].cpu().numpy(),
+                               oracle.join(P, pts[sel_t].cpu().numpy(), nthreads=cores).out))
+    med = float(np.median(ms[1:]))
+    legs["c4"] = {"batches": len(sizes), "n_points": total, "graph_replay_ms": med,
+                  "points_per_s": total / (med * 1e-3),
+                  "batch_latency_ms": {"p50": float(np.median(p50)), "p99": float(np.median(p99)),
+                                       "what": "per-batch completion tick minus the join's "
+                                               "start tick"},
+                  "tuner": tune, "oracle": {"batches_checked": len(pick),
+                                            "points_checked": int(len(sel)), "identical": okc4}}
+    del g, pts, out, batches, desc
+    torch.cuda.empty_cache()
+
+    log("c5: serving sweep")
+    pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
+    srv = serving_leg(act, [keep["approx4m"], ie], pools, [1e3, 1e4, 5e4], 2.0)
+    srv["indexes"] = "c2 approx@4m, c3 exact"
+    legs["c5"] = srv
+    return legs
 
 
 def _stage_points(workload, n, step=1 << 24):

@@ -328,7 +328,7 @@ __device__ __forceinline__ void wave_sync() {
 // the ray crosses it when the point lies left of the edge (orient > 0).
 // Strict comparisons of rounded values imply the same strict order of the
 // exact values; equal rounded values go to the exact test.
-template <bool FULL>
+template <int FULL>
 __device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e, float4 g,
                                                     float qx, float qy, float eta, double px,
                                                     double py, uint32_t &c_fp64,
@@ -339,19 +339,19 @@ __device__ __forceinline__ int edge_fp32_then_exact(const ProbeParams &P, int e,
     if (s != 0) return s > 0 ? 1 : 0;
   }
   const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
-  if (FULL) {
+  if (FULL == 2) {
     c_fp64++;
     if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
   }
   return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
 }
 
-template <bool FULL>
+template <int FULL>
 __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px, double py,
                                          uint32_t &c_fp64, uint32_t &c_exact) {
   const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];
   if ((A.y > py && B.y > py) || (A.y < py && B.y < py)) return 0;
-  if (FULL) {
+  if (FULL == 2) {
     c_fp64++;
     if (orient_sign_fp64_filter(A.x, A.y, B.x, B.y, px, py) == 0) c_exact++;
   }
@@ -363,7 +363,7 @@ __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px,
 // popcounts of the toggle ballots; any lane on an edge decides "covered".
 // The next chunk of edges is loaded while the current one is tested. Must be
 // called by all 64 lanes with wave-uniform arguments.
-template <bool FULL>
+template <int FULL>
 __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double lng, int lane,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   const int e0 = P.eoff[poly], e1 = P.eoff[poly + 1];
@@ -418,6 +418,24 @@ struct Hits {
     }
   }
 };
+
+// Slots for k pairs of each lane in the pair list, one atomic per wave:
+// returns the lane's first slot. Must be reached by all 64 lanes.
+__device__ __forceinline__ uint64_t reserve_pairs(const ProbeParams &P, int lane, uint32_t k) {
+  uint32_t incl = k;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    if (lane >= d) incl += v;
+  }
+  const uint32_t total = __shfl(incl, 63);
+  unsigned long long base = 0;
+  if (total != 0) {  // wave-uniform
+    if (lane == 0) base = atomicAdd((unsigned long long *)P.n_pairs, (unsigned long long)total);
+    base = __shfl(base, 0);
+  }
+  return base + incl - k;
+}
 
 // One (point, polygon) match of a count join: a histogram bin in LDS, or
 // the polygon's global counter.
@@ -701,7 +719,7 @@ __device__ __forceinline__ RefList pending_refs(const ProbeParams &P, int32_t co
 
 // All edges of a polygon tested by one lane in fp64 (+ exact): used only
 // for a candidate without a cell-local record.
-template <bool FULL>
+template <int FULL>
 __device__ bool lane_covers(const ProbeParams &P, int poly, double lat, double lng,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   uint32_t par = 0;
@@ -713,9 +731,9 @@ __device__ bool lane_covers(const ProbeParams &P, int poly, double lat, double l
   return par != 0;
 }
 
-template <bool FULL>
+template <int FULL>
 __device__ __forceinline__ void flush_counters(const ProbeParams &P, const uint32_t *c) {
-  if (!FULL || !P.counters) return;
+  if (FULL != 2 || !P.counters) return;
   static constexpr int ids[7] = {ACT_CNT_SOLELY_TRUE, ACT_CNT_CAND_POINTS, ACT_CNT_CANDIDATES,
                                  ACT_CNT_EDGES, ACT_CNT_EDGE_FP64, ACT_CNT_EDGE_EXACT,
                                  ACT_CNT_LUT_READS};
@@ -831,17 +849,18 @@ __device__ __forceinline__ void point_done(const ProbeParams &P, int64_t v) {
 // code the probe left in out[] (two-pass join).
 // COUNT: a count join's resolve, which adds each match to the polygon's
 // counter instead of writing out[].
-template <bool FULL, bool BATCHED, bool ENTRY, bool COUNT = false>
+template <int FULL, bool BATCHED, bool ENTRY, bool COUNT = false>
 __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, uint64_t entry,
-                                              uint32_t (&c)[7], uint32_t &c_reads) {
+                                              uint32_t (&c)[7], uint32_t &c_reads,
+                                              uint32_t *s_hist = nullptr) {
   const PointRef R = point_ref<BATCHED>(P, v);
   const double2 pt = *R.pt;
   const RefList L = ENTRY ? entry_refs(P, entry)
                           : pending_refs(P, (int32_t)(uint32_t)entry, pt.x, pt.y, c_reads);
-  Hits<FULL> hits;
+  Hits<(FULL >= 1)> hits;
   for (uint32_t r = 0; r < L.nt; r++) {
     if (COUNT)
-      count_add(P, nullptr, L.true_id(P, r));
+      count_add(P, s_hist, L.true_id(P, r));
     else
       hits.add(P, R.gi, (int32_t)L.true_id(P, r));
   }
@@ -851,21 +870,21 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
     bool cov;
     if (loc != 0xffffffffu) {
       cov = local_record_covers(P.local + loc, pt.y, pt.x);
-      if (FULL) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
+      if (FULL == 2) c[3] += P.local[loc] + (P.local[loc + 1] & 0x7fffffffu);
     } else {
       cov = lane_covers<FULL>(P, poly, pt.x, pt.y, c[4], c[5]);
-      if (FULL) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
+      if (FULL == 2) c[3] += (uint32_t)(P.eoff[poly + 1] - P.eoff[poly]);
     }
     if (cov) {
       if (COUNT)
-        count_add(P, nullptr, (uint32_t)poly);
+        count_add(P, s_hist, (uint32_t)poly);
       else
         hits.add(P, R.gi, poly);
     }
   }
   if (!COUNT) *R.out = hits.best;
   point_done<BATCHED>(P, v);
-  if (FULL) {
+  if (FULL == 2) {
     c[0] += L.nc == 0 && L.nt > 0;
     c[1] += L.nc > 0;
     c[2] += L.nc;
@@ -880,7 +899,7 @@ __device__ __forceinline__ void resolve_point(const ProbeParams &P, int64_t v, u
 // the whole wave tests one (point, polygon) pair at a time (lanes over
 // edges, see wave_covers); in every round each lane with work offers its
 // next candidate.
-template <bool LOCAL, bool FULL, bool BATCHED>
+template <bool LOCAL, int FULL, bool BATCHED>
 __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
                                                                  int64_t nwords_arg) {
   __shared__ uint16_t s_list[kListCap];
@@ -901,7 +920,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
       RefList L;
       PointRef R{nullptr, nullptr, 0};
       uint32_t r = 0;
-      Hits<FULL> hits;
+      Hits<(FULL >= 1)> hits;
       for (;;) {
         if (!have && more) {
           more = it.next(s_list, v);
@@ -911,11 +930,11 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
             lat = pt.x;
             lng = pt.y;
             L = pending_refs(P, *R.out, lat, lng, c_reads);
-            hits = Hits<FULL>();
+            hits = Hits<(FULL >= 1)>();
             for (uint32_t t = 0; t < L.nt; t++) hits.add(P, R.gi, (int32_t)L.true_id(P, t));
             r = 0;
             have = true;
-            if (FULL) {
+            if (FULL == 2) {
               c[0] += L.nc == 0 && L.nt > 0;
               c[1] += L.nc > 0;
               c[2] += L.nc;
@@ -938,7 +957,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
           todo &= todo - 1;
           const int32_t q = __shfl(poly, src);
           const double qlat = __shfl(lat, src), qlng = __shfl(lng, src);
-          if (FULL && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
+          if (FULL == 2 && lane == 0) c[3] += (uint32_t)(P.eoff[q + 1] - P.eoff[q]);
           const bool cov = wave_covers<FULL>(P, q, qlat, qlng, lane, c[4], c[5]);
           if (lane == src && cov) hits.add(P, R.gi, q);
         }
@@ -950,7 +969,7 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
       P.gticks[blk * kRangeWords + threadIdx.x] = wall_clock64();
   }
   flush_counters<FULL>(P, c);
-  if (FULL && c_reads && P.counters)
+  if (FULL == 2 && c_reads && P.counters)
     atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
 }
 
@@ -960,22 +979,39 @@ __global__ __launch_bounds__(kResolveBlock) void resolve_kernel(ProbeParams P,
 // lookup-table read can start beside the point's.
 constexpr int kListBlock = 256;
 
-template <bool FULL, bool COUNT = false>
+// COUNT: a count join's resolve; its blocks keep a histogram of the
+// polygons in LDS when the probe's did (hist_bins), so that the matches of
+// pending points meet few global atomics; the grid then takes several probe
+// waves' lists per wave.
+template <int FULL, bool COUNT = false>
 __global__ __launch_bounds__(kListBlock) void resolve_list_kernel(ProbeParams P,
                                                                   uint32_t nwaves) {
-  const uint32_t w = blockIdx.x * (kListBlock / 64) + (threadIdx.x >> 6);
+  extern __shared__ uint32_t s_counts[];
+  uint32_t *s_hist = COUNT && P.hist_bins > 0 ? s_counts : nullptr;
+  if (s_hist) {
+    for (int k = threadIdx.x; k < P.hist_bins; k += kListBlock) s_hist[k] = 0u;
+    __syncthreads();
+  }
   const int lane = threadIdx.x & 63;
   uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0}, c_reads = 0;
-  if (w < nwaves) {
+  const uint32_t stride = gridDim.x * (kListBlock / 64);
+  for (uint32_t w = blockIdx.x * (kListBlock / 64) + (threadIdx.x >> 6); w < nwaves; w += stride) {
     const uint32_t cnt = P.pcount[w];
     const uint2 *list = P.plist + (size_t)w * P.region;
     for (uint32_t e = lane; e < cnt; e += 64) {
       const uint2 ent = list[e];
-      resolve_point<FULL, false, false, COUNT>(P, ent.x, ent.y, c, c_reads);
+      resolve_point<FULL, false, false, COUNT>(P, ent.x, ent.y, c, c_reads, s_hist);
+    }
+  }
+  if (s_hist) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < P.hist_bins; k += kListBlock) {
+      const uint32_t v = s_hist[k];
+      if (v) atomicAdd(P.counts + k, (unsigned long long)v);
     }
   }
   flush_counters<FULL>(P, c);
-  if (FULL && c_reads && P.counters)
+  if (FULL == 2 && c_reads && P.counters)
     atomicAdd(P.counters + ACT_CNT_NODE_READS, (unsigned long long)c_reads);
 }
 
@@ -1012,7 +1048,7 @@ struct PendingQueue {
 };
 
 // Resolves the first n (<= 64) queued points, lane l taking entry l.
-template <bool FULL, bool BATCHED>
+template <int FULL, bool BATCHED>
 __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &Q, uint32_t n,
                                             int lane, uint32_t (&rc)[7], uint32_t &c_reads) {
   const bool on = (uint32_t)lane < n;
@@ -1030,7 +1066,7 @@ __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &
 }
 
 // Step 7-9 for the NP points of a lane in tile `tile` (points at T).
-template <int MODE, bool FULL, int NP, bool BATCHED>
+template <int MODE, int FULL, int NP, bool BATCHED>
 __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile, const TileRef &T,
                                             int lane, const uint64_t (&e)[NP],
                                             const bool (&live)[NP], const bool (&valid)[NP],
@@ -1041,7 +1077,7 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
   for (int p = 0; p < NP; p++) {
     const int k = p * 64 + lane;  // within the tile
     const int64_t i = T.gi + k;   // caller's index (pair output)
-    if (FULL) {
+    if (FULL == 2) {
       c[0] += live[p];
       c[1] += live[p] && !valid[p];
       c[2] += valid[p] && e[p] == 0;
@@ -1067,26 +1103,43 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
       }
       pend[p] = false;
     } else if (MODE == kApprox) {
-      // approximate mode: every reference is reported
-      Hits<FULL> hits;
+      // approximate mode: every reference is reported, the lowest in out[]
+      Hits<false> hits;
       if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
       if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
+      uint32_t nt = 0, nc = 0;
       if (tag == kTagLut) {
-        const uint32_t nt = P.lut[off], nc = P.lut[off + 1 + nt];
-        if (FULL && P.pair_pt) {
-          for (uint32_t r = 0; r < nt; r++) hits.add(P, i, (int32_t)P.lut[off + 1 + r]);
-          for (uint32_t r = 0; r < nc; r++) hits.add(P, i, (int32_t)P.lut[off + 2 + nt + r]);
-        } else {
-          // each part of a list is sorted, so the lowest id heads a part
-          // (the device copy of the table is padded: the reads stay in
-          // bounds when a part is empty)
-          const uint32_t t0 = P.lut[off + 1], c0 = P.lut[off + 2 + nt];
-          if (nt) hits.add(P, i, (int32_t)t0);
-          if (nc) hits.add(P, i, (int32_t)c0);
-        }
-        if (FULL) c[4]++;
+        nt = P.lut[off];
+        nc = P.lut[off + 1 + nt];
+        // each part of a list is sorted, so the lowest id heads a part
+        // (the device copy of the table is padded: the reads stay in
+        // bounds when a part is empty)
+        const uint32_t t0 = P.lut[off + 1], c0 = P.lut[off + 2 + nt];
+        if (nt) hits.add(P, i, (int32_t)t0);
+        if (nc) hits.add(P, i, (int32_t)c0);
+        if (FULL == 2) c[4]++;
       }
-      if (FULL) c[3] += e[p] != 0;
+      if (FULL >= 1 && P.pair_pt) {
+        // every other reference is a pair; the wave reserves the slots of
+        // all its lanes' pairs with one atomic
+        const uint32_t total = live[p] ? (uint32_t)n_inl + nt + nc : 0u;
+        uint64_t slot = reserve_pairs(P, lane, total > 0 ? total - 1 : 0u);
+        auto put = [&](int32_t poly) {
+          if (poly == hits.best) return;
+          if ((int64_t)slot < P.cap) {
+            P.pair_pt[slot] = i;
+            P.pair_poly[slot] = poly;
+          }
+          slot++;
+        };
+        if (live[p]) {
+          if (n_inl > 0) put((int32_t)(r0 >> 1));
+          if (n_inl > 1) put((int32_t)(r1 >> 1));
+          for (uint32_t r = 0; r < nt; r++) put((int32_t)P.lut[off + 1 + r]);
+          for (uint32_t r = 0; r < nc; r++) put((int32_t)P.lut[off + 2 + nt + r]);
+        }
+      }
+      if (FULL == 2) c[3] += e[p] != 0;
       // every lane stores (lanes without a point to the sink), so the
       // store is always issued and the compiler's waits stay exact
       store_out(live[p] ? T.out + k : (int32_t *)P.sink, hits.best);
@@ -1113,11 +1166,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         if (live[p] && n_inl > 1) count_add(P, s_hist, r1 >> 1);
         v = 0;
       } else {
-        Hits<FULL> hits;
+        Hits<(FULL >= 1)> hits;
         if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
         if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
         v = hits.best;
-        if (FULL) c[3] += e[p] != 0;
+        if (FULL == 2) c[3] += e[p] != 0;
       }
       // one store from every lane (lanes without a point to the sink); a
       // count join writes no out[]
@@ -1242,7 +1295,7 @@ constexpr int kProbeWavesPerEU = MODE != kExactFused ? 8 : 1;
 
 // IDS: the points arrive as level-30 cell ids (Listing 3's input), decoded
 // instead of projected.
-template <int MODE, int LDS_DEPTH, bool FULL, int NP, bool BATCHED, bool IDS = false>
+template <int MODE, int LDS_DEPTH, int FULL, int NP, bool BATCHED, bool IDS = false>
 __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void probe_kernel(
     ProbeParams P) {
   constexpr bool FUSED = MODE == kExactFused;
@@ -1341,7 +1394,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     drain_queue<FULL, BATCHED>(P, Q, Q.count, lane, rc, c_reads);
   }
   if (FUSED) flush_counters<FULL>(P, rc);
-  if (FULL && P.counters) {
+  if (FULL == 2 && P.counters) {
     unsigned long long *C = P.counters;
     atomicAdd(C + ACT_CNT_POINTS, (unsigned long long)c[0]);
     atomicAdd(C + ACT_CNT_INVALID, (unsigned long long)c[1]);
@@ -1542,21 +1595,23 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
 }
 
 using ProbeFn = void (*)(ProbeParams);
-template <int MODE, int LDS, bool FULL>
+template <int MODE, int LDS, int FULL>
 static ProbeFn probe_np(int np) {
   return np == 1 ? probe_kernel<MODE, LDS, FULL, 1, false> : probe_kernel<MODE, LDS, FULL, 2, false>;
 }
 
 template <int MODE>
-static ProbeFn probe_mode_fn(int lds_depth, bool count, int np) {
+// full: 0 = lean, 1 = pair output, 2 = pair output and counters
+static ProbeFn probe_mode_fn(int lds_depth, int full, int np) {
   using F = ProbeFn (*)(int);
-  static const F tab[3][2] = {{probe_np<MODE, 0, false>, probe_np<MODE, 0, true>},
-                              {probe_np<MODE, 1, false>, probe_np<MODE, 1, true>},
-                              {probe_np<MODE, 2, false>, probe_np<MODE, 2, true>}};
-  return tab[lds_depth][count](np);
+  static const F tab[3][3] = {
+      {probe_np<MODE, 0, 0>, probe_np<MODE, 0, 1>, probe_np<MODE, 0, 2>},
+      {probe_np<MODE, 1, 0>, probe_np<MODE, 1, 1>, probe_np<MODE, 1, 2>},
+      {probe_np<MODE, 2, 0>, probe_np<MODE, 2, 1>, probe_np<MODE, 2, 2>}};
+  return tab[lds_depth][full](np);
 }
 
-static ProbeFn probe_fn(int mode, int lds_depth, bool count, int np) {
+static ProbeFn probe_fn(int mode, int lds_depth, int count, int np) {
   return mode == kApprox      ? probe_mode_fn<kApprox>(lds_depth, count, np)
          : mode == kExactMask ? probe_mode_fn<kExactMask>(lds_depth, count, np)
          : mode == kExactList ? probe_mode_fn<kExactList>(lds_depth, count, np)
@@ -1566,7 +1621,7 @@ static ProbeFn probe_fn(int mode, int lds_depth, bool count, int np) {
 // Count joins: lean kernels only.
 template <int MODE, int LDS>
 static ProbeFn probe_count_np(int np) {
-  return np == 1 ? probe_kernel<MODE, LDS, false, 1, false> : probe_kernel<MODE, LDS, false, 2, false>;
+  return np == 1 ? probe_kernel<MODE, LDS, 0, 1, false> : probe_kernel<MODE, LDS, 0, 2, false>;
 }
 
 static ProbeFn probe_count_fn(bool exact, int lds_depth, int np) {
@@ -1583,8 +1638,8 @@ static ProbeFn probe_count_fn(bool exact, int lds_depth, int np) {
 // per-wave pending lists.
 template <int MODE, int LDS>
 static ProbeFn probe_ids_np(int np) {
-  return np == 1 ? probe_kernel<MODE, LDS, false, 1, false, true>
-                 : probe_kernel<MODE, LDS, false, 2, false, true>;
+  return np == 1 ? probe_kernel<MODE, LDS, 0, 1, false, true>
+                 : probe_kernel<MODE, LDS, 0, 2, false, true>;
 }
 
 static ProbeFn probe_ids_fn(bool exact, int lds_depth, int np) {
@@ -1598,7 +1653,7 @@ static ProbeFn probe_ids_fn(bool exact, int lds_depth, int np) {
 // Batched joins: no counters.
 template <int MODE, int LDS>
 static ProbeFn probe_batched_np(int np) {
-  return np == 1 ? probe_kernel<MODE, LDS, false, 1, true> : probe_kernel<MODE, LDS, false, 2, true>;
+  return np == 1 ? probe_kernel<MODE, LDS, 0, 1, true> : probe_kernel<MODE, LDS, 0, 2, true>;
 }
 
 static ProbeFn probe_batched_fn(int mode, int lds_depth, int np) {
@@ -1940,7 +1995,8 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
   DeviceGuard g(x->device);
   const bool exact = h.mode == ACT_EXACT;
   // counters or pair output: the full kernels (plain joins run lean ones)
-  const bool count = a->d_counters != nullptr || pairs;
+  // 0: lean kernels, 1: pair output, 2: pair output and counters
+  const int count = a->d_counters != nullptr ? 2 : (pairs ? 1 : 0);
   // exact joins with cell-local refinement may resolve inside the probe;
   // the other refinement modes always use the resolve kernel
   const int pending = a->pending != ACT_PENDING_AUTO ? a->pending : L.pending;
@@ -1976,10 +2032,16 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
   if (ids) pass = std::min(pass, kCountPass);
   using ResolveFn = void (*)(ProbeParams, int64_t);
   const ResolveFn resolve = P.refine == ACT_REFINE_LOCAL
-                              ? (count ? resolve_kernel<true, true, false> : resolve_kernel<true, false, false>)
-                              : (count ? resolve_kernel<false, true, false> : resolve_kernel<false, false, false>);
+                              ? (count == 2   ? resolve_kernel<true, 2, false>
+                                 : count == 1 ? resolve_kernel<true, 1, false>
+                                              : resolve_kernel<true, 0, false>)
+                              : (count == 2   ? resolve_kernel<false, 2, false>
+                                 : count == 1 ? resolve_kernel<false, 1, false>
+                                              : resolve_kernel<false, 0, false>);
   using ListFn = void (*)(ProbeParams, uint32_t);
-  const ListFn resolve_list = count ? resolve_list_kernel<true> : resolve_list_kernel<false>;
+  const ListFn resolve_list = count == 2   ? resolve_list_kernel<2>
+                              : count == 1 ? resolve_list_kernel<1>
+                                           : resolve_list_kernel<0>;
   for (int64_t s0 = 0; s0 < a->n; s0 += pass) {
     const int64_t n = std::min(pass, a->n - s0);
     P.pts = a->d_points ? (const double2 *)a->d_points + s0 : nullptr;
@@ -2015,9 +2077,13 @@ static int join_impl(const act_index *x, const act_join_args *a, void *stream,
       return fail(ACT_E_HIP, std::string("probe launch: ") + hipGetErrorString(e));
     if (a->probe_event) HIP_TRY(hipEventRecord((hipEvent_t)a->probe_event, (hipStream_t)stream));
     if (pmode == kExactList || pmode == kExactCount) {
-      const ListFn list_fn = pmode == kExactCount ? resolve_list_kernel<false, true> : resolve_list;
-      hipLaunchKernelGGL(list_fn, dim3((unsigned)((nwaves + 3) / 4)), dim3(kListBlock), 0,
-                         (hipStream_t)stream, P, (uint32_t)nwaves);
+      const bool cnt = pmode == kExactCount;
+      const ListFn list_fn = cnt ? resolve_list_kernel<0, true> : resolve_list;
+      // a count join's resolve blocks each flush a histogram: fewer blocks
+      const int64_t lgrid = std::min<int64_t>((nwaves + 3) / 4, cnt && P.hist_bins > 0 ? 1024 : 1ll << 30);
+      hipLaunchKernelGGL(list_fn, dim3((unsigned)lgrid), dim3(kListBlock),
+                         cnt ? (size_t)P.hist_bins * 4 : 0, (hipStream_t)stream, P,
+                         (uint32_t)nwaves);
       e = hipGetLastError();
       if (e != hipSuccess)
         return fail(ACT_E_HIP, std::string("resolve launch: ") + hipGetErrorString(e));
@@ -2073,7 +2139,7 @@ static int join_batched_impl(const act_index *x, const act_batch *d_batches, int
   hipLaunchKernelGGL(probe_batched_fn(mode, depth, launch_np(x)), dim3(L.grid), dim3(kProbeBlock),
                      (size_t)n_lds * 1024, st, P);
   if (mode == kExactMask) {
-    void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, false, true>;
+    void (*resolve)(ProbeParams, int64_t) = resolve_kernel<true, 0, true>;
     hipLaunchKernelGGL(resolve, dim3(2048), dim3(kResolveBlock), 0, st, P, (int64_t)0);
   }
   if (d_ticks)
