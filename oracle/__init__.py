@@ -46,6 +46,12 @@ def _load():
         lib.oracle_join.argtypes = [p, p, p, i32, p, i64, p, p, p, p, i64, p,
                                     ctypes.c_int, ctypes.c_int]
         lib.oracle_join.restype = ctypes.c_int
+        lib.oracle_covers_sphere.argtypes = [p, p, p, i32, i32, d, d]
+        lib.oracle_covers_sphere.restype = ctypes.c_int
+        lib.oracle_join_sphere.argtypes = [p, p, p, i32, p, i64, p, p, p, p, i64, p, ctypes.c_int]
+        lib.oracle_join_sphere.restype = ctypes.c_int
+        lib.oracle_boundary_dist_sphere_pairs.argtypes = [p, p, p, p, p, p, i64, p]
+        lib.oracle_boundary_dist_sphere_pairs.restype = None
         lib.oracle_boundary_dist_m.argtypes = [p, p, p, i32, d, d]
         lib.oracle_boundary_dist_m.restype = d
         lib.oracle_boundary_dist_pairs.argtypes = [p, p, p, p, p, p, i64, p]
@@ -125,6 +131,50 @@ def join(polys, pts: np.ndarray, nthreads: int = 0, use_bbox: bool = True) -> Jo
     m = m.value
     pairs = np.stack([pp[:m], pq[:m].astype(np.int64)], 1) if m else np.zeros((0, 2), np.int64)
     return JoinResult(out, cnt, pairs)
+
+
+def covers_sphere(polys, p: int, lat: float, lng: float) -> bool:
+    """Spherical model (great-circle edges): does polygon p cover the point."""
+    v, ro, pro = _poly_args(polys)
+    return bool(_load().oracle_covers_sphere(_ptr(v), _ptr(ro), _ptr(pro), polys.n_polys, int(p),
+                                             float(lat), float(lng)))
+
+
+def join_sphere(polys, pts: np.ndarray, nthreads: int = 0) -> JoinResult:
+    """Brute-force join in the spherical model (great-circle edges)."""
+    lib = _load()
+    v, ro, pro = _poly_args(polys)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    out = np.empty(n, np.int32)
+    cnt = np.empty(n, np.int32)
+    cap = max(1024, n // 8)
+    while True:
+        pp = np.empty(cap, np.int64)
+        pq = np.empty(cap, np.int32)
+        m = ctypes.c_int64(0)
+        lib.oracle_join_sphere(_ptr(v), _ptr(ro), _ptr(pro), polys.n_polys, _ptr(pts), n,
+                               _ptr(out), _ptr(cnt), _ptr(pp), _ptr(pq), cap, ctypes.byref(m),
+                               int(nthreads))
+        if m.value <= cap:
+            break
+        cap = m.value
+    m = m.value
+    pairs = np.stack([pp[:m], pq[:m].astype(np.int64)], 1) if m else np.zeros((0, 2), np.int64)
+    return JoinResult(out, cnt, pairs)
+
+
+def boundary_dist_sphere_pairs(polys, pts: np.ndarray, pairs: np.ndarray) -> np.ndarray:
+    """Great-circle distance in metres from each pair's point to its
+    polygon's boundary (edges as minor arcs)."""
+    v, ro, pro = _poly_args(polys)
+    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    pp = np.ascontiguousarray(pairs[:, 0], dtype=np.int64)
+    pq = np.ascontiguousarray(pairs[:, 1], dtype=np.int32)
+    dist = np.empty(pairs.shape[0])
+    _load().oracle_boundary_dist_sphere_pairs(_ptr(v), _ptr(ro), _ptr(pro), _ptr(pts), _ptr(pp),
+                                              _ptr(pq), pairs.shape[0], _ptr(dist))
+    return dist
 
 
 def boundary_dist_m(polys, p: int, lat: float, lng: float) -> float:

@@ -246,6 +246,181 @@ int oracle_join(const double *verts, const int64_t *ring_off,
   return 0;
 }
 
+/* ---- the spherical model ------------------------------------------------ */
+/*
+ * The paper refines candidates with S2's point-in-polygon test, which works
+ * on the sphere (Section III-A). Reading of that model: a polygon's edges
+ * are the minor great-circle arcs between consecutive vertices (unit
+ * vectors of the vertices' lat/lng, by the C library's sin and cos); a
+ * point lies within the polygon if it is a vertex, lies on an edge, or has
+ * odd crossing parity along the arc from the point north on its meridian to
+ * the pole (polygons contain no pole, so the pole is outside). The meridian
+ * of the point meets edge (a, b) when the point's longitude is in the
+ * edge's half-open longitude range [min, max) (edges along a meridian are
+ * never crossed, only touched); it crosses the edge when the point and the
+ * north pole lie on opposite sides of the edge's great circle, i.e. when
+ * det(a, b, p) = p . (a x b) has the sign opposite to that of
+ * det(a, b, N), which is the sign of lng_b - lng_a for edges shorter than
+ * 180 degrees of longitude. det(a, b, p) = 0 with the point's longitude in
+ * the closed range means the point is on the edge. det is evaluated in
+ * fp64 on the computed unit vectors; points within rounding of an edge may
+ * be decided either way (parity with the GPU is judged away from edges).
+ */
+static void or_unit(double lat, double lng, double v[3]) {
+  const double d = 3.14159265358979323846 / 180.0;
+  const double cp = cos(lat * d), sp = sin(lat * d), cl = cos(lng * d), sl = sin(lng * d);
+  v[0] = cp * cl;
+  v[1] = cp * sl;
+  v[2] = sp;
+}
+
+static int or_covers_sphere(const double *verts, const int64_t *ring_off,
+                            const int32_t *poly_ring_off, const double *bbox, int p,
+                            double lat, double lng) {
+  const double *bb = bbox + 4 * (size_t)p; /* arcs stay inside their longitude range */
+  if (lng < bb[2] || lng > bb[3]) return 0;
+  double q[3];
+  or_unit(lat, lng, q);
+  int inside = 0;
+  for (int r = poly_ring_off[p]; r < poly_ring_off[p + 1]; r++) {
+    int64_t k0 = ring_off[r], k1 = ring_off[r + 1];
+    for (int64_t k = k0; k < k1; k++) {
+      int64_t kn = (k + 1 < k1) ? k + 1 : k0;
+      double alat = verts[2 * k], alng = verts[2 * k + 1];
+      double blat = verts[2 * kn], blng = verts[2 * kn + 1];
+      if ((lat == alat && lng == alng) || (lat == blat && lng == blng)) return 1; /* vertex */
+      if (alng == blng) { /* along a meridian: touched, never crossed */
+        if (lng == alng && lat >= fmin(alat, blat) && lat <= fmax(alat, blat)) return 1;
+        continue;
+      }
+      double lo = fmin(alng, blng), hi = fmax(alng, blng);
+      if (lng < lo || lng > hi) continue;
+      double a[3], b[3];
+      or_unit(alat, alng, a);
+      or_unit(blat, blng, b);
+      const double n0 = a[1] * b[2] - a[2] * b[1];
+      const double n1 = a[2] * b[0] - a[0] * b[2];
+      const double n2 = a[0] * b[1] - a[1] * b[0];
+      const double det = q[0] * n0 + q[1] * n1 + q[2] * n2;
+      if (det == 0.0) return 1; /* on the edge's great circle, inside its range */
+      if (lng == hi) continue;  /* half-open longitude range */
+      const int s_pole = blng > alng ? 1 : -1;
+      if ((det > 0 ? 1 : -1) == -s_pole) inside ^= 1;
+    }
+  }
+  return inside;
+}
+
+int oracle_covers_sphere(const double *verts, const int64_t *ring_off,
+                         const int32_t *poly_ring_off, int32_t n_polys, int32_t p,
+                         double lat, double lng) {
+  if (p < 0 || p >= n_polys || !or_valid_point(lat, lng)) return 0;
+  double *bb = or_bboxes(verts, ring_off, poly_ring_off, n_polys);
+  int c = or_covers_sphere(verts, ring_off, poly_ring_off, bb, p, lat, lng);
+  free(bb);
+  return c;
+}
+
+/* The join in the spherical model: outputs as oracle_join. */
+int oracle_join_sphere(const double *verts, const int64_t *ring_off,
+                       const int32_t *poly_ring_off, int32_t n_polys, const double *pts,
+                       int64_t n, int32_t *out, int32_t *cnt, int64_t *pair_pt,
+                       int32_t *pair_poly, int64_t capacity, int64_t *n_pairs, int nthreads) {
+  double *bb = or_bboxes(verts, ring_off, poly_ring_off, n_polys);
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; i++) {
+    double lat = pts[2 * i], lng = pts[2 * i + 1];
+    int32_t first = -1, c = 0;
+    if (or_valid_point(lat, lng))
+      for (int p = 0; p < n_polys; p++)
+        if (or_covers_sphere(verts, ring_off, poly_ring_off, bb, p, lat, lng)) {
+          if (first < 0) first = p;
+          c++;
+        }
+    out[i] = first;
+    cnt[i] = c;
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; i++) {
+    if (cnt[i] < 2) continue;
+    double lat = pts[2 * i], lng = pts[2 * i + 1];
+    for (int p = out[i] + 1; p < n_polys; p++)
+      if (or_covers_sphere(verts, ring_off, poly_ring_off, bb, p, lat, lng)) {
+        if (m < capacity) {
+          pair_pt[m] = i;
+          pair_poly[m] = p;
+        }
+        m++;
+      }
+  }
+  *n_pairs = m;
+  free(bb);
+  return 0;
+}
+
+/* Great-circle distance in metres from (lat, lng) to the boundary (all
+ * edges, as minor arcs) of polygon p: to the arc's great circle where the
+ * point's foot lies between the endpoints, else to the nearer endpoint.
+ * R = 6,371,008.8 m. For checking parity near edges. */
+double oracle_boundary_dist_sphere_m(const double *verts, const int64_t *ring_off,
+                                     const int32_t *poly_ring_off, int32_t p, double lat,
+                                     double lng) {
+  const double R = 6371008.8;
+  double q[3];
+  or_unit(lat, lng, q);
+  double best = INFINITY;
+  for (int r = poly_ring_off[p]; r < poly_ring_off[p + 1]; r++) {
+    int64_t k0 = ring_off[r], k1 = ring_off[r + 1];
+    for (int64_t k = k0; k < k1; k++) {
+      int64_t kn = (k + 1 < k1) ? k + 1 : k0;
+      double a[3], b[3];
+      or_unit(verts[2 * k], verts[2 * k + 1], a);
+      or_unit(verts[2 * kn], verts[2 * kn + 1], b);
+      double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]};
+      double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      double d;
+      /* the foot of q on the great circle lies on the arc iff it is on the
+       * inner side of both planes through n and an endpoint */
+      double an[3] = {n[1] * a[2] - n[2] * a[1], n[2] * a[0] - n[0] * a[2], n[0] * a[1] - n[1] * a[0]};
+      double nb[3] = {b[1] * n[2] - b[2] * n[1], b[2] * n[0] - b[0] * n[2], b[0] * n[1] - b[1] * n[0]};
+      int on_arc = nn > 0 && (q[0] * an[0] + q[1] * an[1] + q[2] * an[2]) >= 0 &&
+                   (q[0] * nb[0] + q[1] * nb[1] + q[2] * nb[2]) >= 0;
+      if (on_arc) {
+        double s = (q[0] * n[0] + q[1] * n[1] + q[2] * n[2]) / nn;
+        d = fabs(asin(fmax(-1.0, fmin(1.0, s))));
+      } else {
+        double da[3] = {q[1] * a[2] - q[2] * a[1], q[2] * a[0] - q[0] * a[2], q[0] * a[1] - q[1] * a[0]};
+        double db[3] = {q[1] * b[2] - q[2] * b[1], q[2] * b[0] - q[0] * b[2], q[0] * b[1] - q[1] * b[0]};
+        double xa = atan2(sqrt(da[0] * da[0] + da[1] * da[1] + da[2] * da[2]),
+                          q[0] * a[0] + q[1] * a[1] + q[2] * a[2]);
+        double xb = atan2(sqrt(db[0] * db[0] + db[1] * db[1] + db[2] * db[2]),
+                          q[0] * b[0] + q[1] * b[1] + q[2] * b[2]);
+        d = fmin(xa, xb);
+      }
+      if (d * R < best) best = d * R;
+    }
+  }
+  return best;
+}
+
+void oracle_boundary_dist_sphere_pairs(const double *verts, const int64_t *ring_off,
+                                       const int32_t *poly_ring_off, const double *pts,
+                                       const int64_t *pair_pt, const int32_t *pair_poly,
+                                       int64_t m, double *dist) {
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < m; i++) {
+    int64_t q = pair_pt[i];
+    dist[i] = oracle_boundary_dist_sphere_m(verts, ring_off, poly_ring_off, pair_poly[i],
+                                            pts[2 * q], pts[2 * q + 1]);
+  }
+}
+
 /*
  * Checker for the approximate join: planar distance in metres from (lat, lng)
  * to the boundary (all ring edges) of polygon p, in the local equirectangular

@@ -275,3 +275,75 @@ def test_boundary_distance_checker():
     assert abs(d - synth.M_PER_DEG) < 1e-6
     d = oracle.boundary_dist_m(sq, 0, lat=0.5, lng=0.5)
     assert abs(d - 0.5 * synth.M_PER_DEG * np.cos(np.radians(0.5))) < 1e-6
+
+
+# ---------------------------------------------------------- spherical model
+
+def _gc_lat(lat_a, lng_a, lat_b, lng_b, lng):
+    """Latitude of the great circle through a and b at longitude lng (closed
+    form: tan(lat) is a combination of the endpoints' tangents weighted by
+    the sines of the longitude differences)."""
+    r = np.radians
+    t = (np.tan(r(lat_a)) * np.sin(r(lng_b - lng)) + np.tan(r(lat_b)) * np.sin(r(lng - lng_a))) \
+        / np.sin(r(lng_b - lng_a))
+    return np.degrees(np.arctan(t))
+
+
+def test_sphere_edges_bulge_poleward_by_the_closed_form():
+    """A lat/lng rectangle whose east-west edges are great-circle arcs: at the
+    middle longitude the southern edge lies north of its chord and the
+    northern edge north of its own, by the closed form of the great circle's
+    latitude. Points just inside and outside of each arc, and between arc
+    and chord (where the planar and spherical models differ)."""
+    sq = [np.array([[40.0, -75.0], [40.0, -73.0], [41.0, -73.0], [41.0, -75.0]])]
+    P = synth.Polygons.from_rings([sq])
+    south = _gc_lat(40.0, -75.0, 40.0, -73.0, -74.0)
+    north = _gc_lat(41.0, -75.0, 41.0, -73.0, -74.0)
+    assert south > 40.004 and north > 41.004
+    eps = 1e-6
+    for lat, want_sphere, want_plane in ((south + eps, True, True), (south - eps, False, True),
+                                         ((40.0 + south) / 2, False, True),
+                                         (north - eps, True, False), (north + eps, False, False),
+                                         ((41.0 + north) / 2, True, False), (40.5, True, True),
+                                         (39.99, False, False)):
+        assert oracle.covers_sphere(P, 0, lat, -74.0) == want_sphere, lat
+        assert oracle.covers(P, 0, lat, -74.0) == want_plane, lat
+    # off the middle longitude the closed form still decides
+    for lng in (-74.9, -74.3, -73.2):
+        g = _gc_lat(40.0, -75.0, 40.0, -73.0, lng)
+        assert oracle.covers_sphere(P, 0, g + eps, lng) and not oracle.covers_sphere(P, 0, g - eps, lng)
+
+
+def test_sphere_vertices_meridians_and_reversal():
+    """Vertices and points on a meridian edge are covered; reversing a ring
+    or rotating its start changes nothing; far from edges the spherical and
+    planar models agree (the arcs and chords differ by centimetres here)."""
+    ring = np.array([[40.6, -74.1], [40.6, -73.9], [40.8, -73.9], [40.8, -74.0], [40.7, -74.1]])
+    P = synth.Polygons.from_rings([[ring]])
+    for lat, lng in ring:
+        assert oracle.covers_sphere(P, 0, lat, lng)
+    assert oracle.covers_sphere(P, 0, 40.7, -73.9)      # on the meridian edge
+    assert not oracle.covers_sphere(P, 0, 40.7, -73.9 + 1e-9)
+    rng = np.random.default_rng(12)
+    pts = np.stack([rng.uniform(40.55, 40.85, 4000), rng.uniform(-74.15, -73.85, 4000)], 1)
+    variants = [ring[::-1], np.roll(ring, 2, 0), np.roll(ring[::-1], 3, 0)]
+    base = oracle.join_sphere(P, pts).out
+    for v in variants:
+        assert np.array_equal(oracle.join_sphere(synth.Polygons.from_rings([[v]]), pts).out, base)
+    plane = oracle.join(P, pts).out
+    far = oracle.boundary_dist_sphere_pairs(P, pts, np.stack([np.arange(len(pts)),
+                                                              np.zeros(len(pts), np.int64)], 1)) > 1.0
+    assert far.sum() > 3500 and np.array_equal(base[far], plane[far])
+
+
+def test_sphere_partition_covers_generic_points_once():
+    """The Voronoi partition's neighbours share identical arcs, so in the
+    spherical model too every in-box point away from edges is covered by
+    exactly one polygon (the holes of C2 excepted: C1 has none)."""
+    P = synth.workload_polygons("c1")
+    pts = synth.workload_points("c1", 0, 20000)
+    res = oracle.join_sphere(P, pts)
+    pairs = np.stack([np.arange(len(pts)), np.maximum(res.out, 0).astype(np.int64)], 1)
+    far = oracle.boundary_dist_sphere_pairs(P, pts, pairs) > 0.01
+    assert far.sum() > 19000
+    assert np.all(res.cnt[far] == 1)
