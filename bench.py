@@ -558,7 +558,16 @@ def run_c2(args, emit=True):
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic["exact"] if traffic and "exact" in traffic else None,
                      "kernel": "probe_kernel (exact mode)", "kernel_ms": probe_ms,
-                     "bytes_per_point": BYTES_PER_POINT, "points_per_launch": n},
+                     "bytes_per_point": BYTES_PER_POINT, "points_per_launch": n,
+                     "measured_GBps": (traffic["exact"] / (probe_ms * 1e-3) / 1e9
+                                       if traffic and "exact" in traffic else None),
+                     "join_frac": BYTES_PER_POINT * n / (float(np.mean(tot)) * 1e-3) / 1e9
+                                  / PEAK_HBM_GBS,
+                     "what": "frac: the probe kernel's algorithmic bytes (20 per point) over "
+                             "its event-timed duration, against 8 TB/s (the 40% target is "
+                             "stated for the probe); join_frac: the same bytes over the whole "
+                             "exact join (probe + resolve); measured_GBps: the kernel's "
+                             "rocprofv3-counted HBM bytes over its duration"},
         "latency_ms": {"p50": percentile(tot, 50), "p99": percentile(tot, 99),
                        "what": "one join of all points (one step), HIP events"},
         "batched_exact": batched,
@@ -978,16 +987,45 @@ def summarize_trace(d):
             name, grid, blk, len(v), v.mean(), v.min(), v.max(), v.sum() / 1e3))
 
 
+def _act_kernel_args(name):
+    m = re.search(r"(probe_kernel|resolve_kernel|resolve_list_kernel)<([^>]*)>", name)
+    if not m:
+        return None, None
+    return m.group(1), [x.strip() for x in m.group(2).split(",")]
+
+
 def _lean_act_kernel(name):
     """This library's kernels without counters and pair output (the FULL
     template argument: third of probe_kernel, second of resolve_kernel,
-    first of resolve_list_kernel)."""
-    m = re.match(r"(probe_kernel|resolve_kernel|resolve_list_kernel)<([^>]*)>", name)
-    if not m:
+    first of resolve_list_kernel; 0 = lean)."""
+    kind, a = _act_kernel_args(name)
+    if kind is None:
         return False
-    a = [x.strip() for x in m.group(2).split(",")]
-    full = {"probe_kernel": 2, "resolve_kernel": 1, "resolve_list_kernel": 0}[m.group(1)]
-    return a[full] == "false"
+    full = {"probe_kernel": 2, "resolve_kernel": 1, "resolve_list_kernel": 0}[kind]
+    return a[full] in ("0", "false")
+
+
+def _kernel_label(name):
+    """Short label of a lean, unbatched kernel of this library (None for the
+    others): probe_kernel<mode, LDS levels, full, points per lane, batched,
+    ids> with mode 0 approximate, 1 exact with the pending mask, 2 exact with
+    the probe's queues, 3 exact with per-wave pending lists (the default),
+    4 and 5 the count joins; resolve_kernel<local, full, batched>;
+    resolve_list_kernel<full, count>."""
+    kind, a = _act_kernel_args(name)
+    if kind is None or not _lean_act_kernel(name):
+        return None
+    if kind == "probe_kernel":
+        if a[4] != "false":
+            return None
+        label = "probe_kernel " + {"0": "approx", "1": "exact-mask", "2": "exact-queue",
+                                   "3": "exact", "4": "count approx", "5": "count exact"}[a[0]]
+        return label + (" ids" if len(a) > 5 and a[5] == "true" else "")
+    if kind == "resolve_kernel":
+        if a[2] != "false":
+            return None
+        return "resolve_kernel %s" % ("local" if a[0] == "true" else "all-edges")
+    return "resolve_list_kernel" + (" count" if len(a) > 1 and a[1] == "true" else "")
 
 
 def summarize_counters(dirs, points_per_launch):
@@ -1063,26 +1101,12 @@ def summarize_pmc(fdir, wdir):
     print("| kernel | HBM bytes per launch | fetch (scaled) | write (scaled) | launches |")
     print("|---|---|---|---|---|")
     for k in sorted(fv):
-        # probe_kernel<mode, lds, count, points per lane, batched>: mode 0
-        # approximate, 1 exact (pending points in a mask for resolve_kernel),
-        # 2 exact (pending points resolved by the probe's queues), 3 exact
-        # (per-wave pending lists for resolve_list_kernel, the default)
-        pm = re.search(r"probe_kernel<(\d), \d+, false, \d+, false>", k)
-        rm = re.search(r"resolve_kernel<(true|false), false, false>", k)
-        lm = re.search(r"resolve_list_kernel<false>", k)
-        if not pm and not rm and not lm:
+        label = _kernel_label(k)
+        if label is None:
             continue  # other kernels, and the counting variants
-        if pm:
-            label = "probe_kernel %s" % {"0": "approx", "1": "exact-mask", "2": "exact-queue",
-                                         "3": "exact"}[pm.group(1)]
-        elif rm:
-            label = "resolve_kernel %s" % ("local" if rm.group(1) == "true" else "all-edges")
-        else:
-            label = "resolve_list_kernel"
         f = float(np.median(fv[k])) * fcal
         wr = float(np.median(wv.get(k, [0.0]))) * wcal
         print("| %s | %.4g | %.4g | %.4g | %d |" % (label, f + wr, f, wr, len(fv[k])))
-
 
 if __name__ == "__main__":
     main()

@@ -62,6 +62,20 @@ enum {
  * index reports the mode it took (act_stats.mode). */
 enum { ACT_EXACT = 0, ACT_APPROX = 1, ACT_AUTO = 2 };
 
+/* Geometry of the polygons' edges. PLANE (default): straight segments in the
+ * plane x = longitude, y = latitude (the ST_Covers reading, exact on the
+ * input coordinates). SPHERE: minor great-circle arcs between the vertices,
+ * as in S2's point-in-polygon test, which the paper uses for refinement
+ * (Section III-A). A point is covered by a spherical polygon when it is a
+ * vertex, lies on an edge, or when the arc from it north along its meridian
+ * to the pole crosses the edges an odd number of times (polygons contain no
+ * pole). Sign tests use fp64 unit vectors, so points within rounding of an
+ * arc (about 1e-9 m) may be decided either way. Cells are classified
+ * against the edges' chords with the cell margin widened by the largest
+ * arc-to-chord distance, so true hits are true for the arcs too; candidates
+ * are refined over all of the polygon's arcs (no cell-local records). */
+enum { ACT_GEOM_PLANE = 0, ACT_GEOM_SPHERE = 1 };
+
 /* Refinement of candidate hits in exact mode. All modes give identical,
  * exact results; they differ in cost. */
 enum {
@@ -114,7 +128,8 @@ typedef struct {
                                  index's limit                             */
   int32_t train_max_level;    /* finest level training splits to (default
                                  30)                                       */
-  int32_t reserved0;
+  int32_t geometry;           /* ACT_GEOM_PLANE (default) or ACT_GEOM_SPHERE
+                                 (exact mode only)                         */
 } act_build_opts;
 
 /* Fills *opts with the defaults (the values act_build uses for NULL). */
@@ -500,8 +515,8 @@ typedef struct {
   int64_t n_edges;
   int64_t n_cells;          /* cells of the super covering                    */
   int64_t n_cells_interior_only; /* cells whose references are all true hits */
-  int64_t n_nodes;          /* trie nodes (256 x 8 B each), node 0 reserved    */
-  int64_t node_bytes;
+  int64_t n_nodes;          /* trie nodes (256 entries each), node 0 reserved */
+  int64_t node_bytes;       /* device bytes of the trie (32-bit entries)      */
   int64_t lut_words;        /* uint32 words of the lookup table               */
   int64_t edge_bytes;       /* device polygon store                           */
   int64_t device_bytes;     /* total HBM held by the index                    */
@@ -521,6 +536,10 @@ typedef struct {
   int64_t image_bytes;      /* device bytes the index's image needs (equal to
                                device_bytes once uploaded; also for
                                host-only builds)                            */
+  double margin_deg;        /* cell margin used (degrees; SPHERE: widened by
+                               the largest arc-to-chord distance)           */
+  int32_t geometry;         /* ACT_GEOM_*                                    */
+  int32_t reserved;
 } act_stats;
 
 int act_index_stats(const act_index *idx, act_stats *out);

@@ -298,9 +298,14 @@ static int or_covers_sphere(const double *verts, const int64_t *ring_off,
       double a[3], b[3];
       or_unit(alat, alng, a);
       or_unit(blat, blng, b);
-      const double n0 = a[1] * b[2] - a[2] * b[1];
-      const double n1 = a[2] * b[0] - a[0] * b[2];
-      const double n2 = a[0] * b[1] - a[1] * b[0];
+      /* the great circle's normal as (b + a) x (b - a) = 2 (a x b): for
+       * nearby endpoints b - a is exact (Sterbenz), so the normal keeps
+       * full relative precision where a x b would cancel */
+      const double s0 = b[0] + a[0], s1 = b[1] + a[1], s2 = b[2] + a[2];
+      const double d0 = b[0] - a[0], d1 = b[1] - a[1], d2 = b[2] - a[2];
+      const double n0 = s1 * d2 - s2 * d1;
+      const double n1 = s2 * d0 - s0 * d2;
+      const double n2 = s0 * d1 - s1 * d0;
       const double det = q[0] * n0 + q[1] * n1 + q[2] * n2;
       if (det == 0.0) return 1; /* on the edge's great circle, inside its range */
       if (lng == hi) continue;  /* half-open longitude range */
@@ -381,8 +386,10 @@ double oracle_boundary_dist_sphere_m(const double *verts, const int64_t *ring_of
       double a[3], b[3];
       or_unit(verts[2 * k], verts[2 * k + 1], a);
       or_unit(verts[2 * kn], verts[2 * kn + 1], b);
-      double n[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
-                     a[0] * b[1] - a[1] * b[0]};
+      const double sa[3] = {b[0] + a[0], b[1] + a[1], b[2] + a[2]};
+      const double da[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      double n[3] = {sa[1] * da[2] - sa[2] * da[1], sa[2] * da[0] - sa[0] * da[2],
+                     sa[0] * da[1] - sa[1] * da[0]};
       double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
       double d;
       /* the foot of q on the great circle lies on the arc iff it is on the
@@ -395,11 +402,11 @@ double oracle_boundary_dist_sphere_m(const double *verts, const int64_t *ring_of
         double s = (q[0] * n[0] + q[1] * n[1] + q[2] * n[2]) / nn;
         d = fabs(asin(fmax(-1.0, fmin(1.0, s))));
       } else {
-        double da[3] = {q[1] * a[2] - q[2] * a[1], q[2] * a[0] - q[0] * a[2], q[0] * a[1] - q[1] * a[0]};
-        double db[3] = {q[1] * b[2] - q[2] * b[1], q[2] * b[0] - q[0] * b[2], q[0] * b[1] - q[1] * b[0]};
-        double xa = atan2(sqrt(da[0] * da[0] + da[1] * da[1] + da[2] * da[2]),
+        double qa[3] = {q[1] * a[2] - q[2] * a[1], q[2] * a[0] - q[0] * a[2], q[0] * a[1] - q[1] * a[0]};
+        double qb[3] = {q[1] * b[2] - q[2] * b[1], q[2] * b[0] - q[0] * b[2], q[0] * b[1] - q[1] * b[0]};
+        double xa = atan2(sqrt(qa[0] * qa[0] + qa[1] * qa[1] + qa[2] * qa[2]),
                           q[0] * a[0] + q[1] * a[1] + q[2] * a[2]);
-        double xb = atan2(sqrt(db[0] * db[0] + db[1] * db[1] + db[2] * db[2]),
+        double xb = atan2(sqrt(qb[0] * qb[0] + qb[1] * qb[1] + qb[2] * qb[2]),
                           q[0] * b[0] + q[1] * b[1] + q[2] * b[2]);
         d = fmin(xa, xb);
       }

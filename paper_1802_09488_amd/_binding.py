@@ -17,6 +17,7 @@ ACT_OK, ACT_E_ARG, ACT_E_POLY, ACT_E_OOM, ACT_E_HIP, ACT_E_OVERFLOW, ACT_E_DEVIC
 ACT_EXACT, ACT_APPROX, ACT_AUTO = 0, 1, 2
 ACT_REFINE_AUTO, ACT_REFINE_LOCAL, ACT_REFINE_FP32_FILTER, ACT_REFINE_FP64 = 0, 1, 2, 3
 ACT_PENDING_AUTO, ACT_PENDING_KERNEL, ACT_PENDING_QUEUE = 0, 1, 2
+ACT_GEOM_PLANE, ACT_GEOM_SPHERE = 0, 1
 ACT_NCOUNTERS = 16
 COUNTER_NAMES = ["points", "invalid", "false_hit", "solely_true", "cand_points", "candidates",
                  "edges", "edge_fp64", "edge_exact", "node_reads", "lut_reads"]
@@ -37,7 +38,7 @@ class BuildOpts(ctypes.Structure):
                 ("threads", ctypes.c_int32), ("prefix_level", ctypes.c_int32),
                 ("margin_deg", ctypes.c_double), ("train_points", ctypes.c_void_p),
                 ("n_train", ctypes.c_int64), ("memory_budget", ctypes.c_int64),
-                ("train_max_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("train_max_level", ctypes.c_int32), ("geometry", ctypes.c_int32)]
 
 
 class JoinArgs(ctypes.Structure):
@@ -89,7 +90,9 @@ class Stats(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("lds_nodes", ctypes.c_int32),
                 ("precision_m", ctypes.c_double), ("build_seconds", ctypes.c_double),
                 ("local_words", ctypes.c_int64), ("train_splits", ctypes.c_int64),
-                ("train_points_used", ctypes.c_int64), ("image_bytes", ctypes.c_int64)]
+                ("train_points_used", ctypes.c_int64), ("image_bytes", ctypes.c_int64),
+                ("margin_deg", ctypes.c_double), ("geometry", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -352,7 +352,7 @@ void emit(Ctx &C, const Work &w, Sink &s) {
   bids.reserve(w.bnd.size());
   for (const Bref &br : w.bnd) bids.push_back(br.poly);
   std::sort(bids.begin(), bids.end());
-  const bool local = C.bp.mode == ACT_EXACT;
+  const bool local = C.bp.mode == ACT_EXACT && C.bp.geometry == ACT_GEOM_PLANE;
   while (a < w.interior.size() || b < bids.size()) {
     if (b >= bids.size() || (a < w.interior.size() && w.interior[a] < bids[b])) {
       s.refs.push_back(((uint32_t)w.interior[a++] << 1) | 1u);
@@ -463,14 +463,14 @@ uint64_t encode_refs_lut(const uint32_t *refs, int n, std::vector<uint32_t> &lut
   return encode_refs_impl(refs, n, lut, dedup, false);
 }
 
-// The top node levels are also kept as 32-bit entries (the GPU stages them
-// in LDS). An entry fits when its high 32 bits are zero: child pointers,
-// lookup-table offsets and single references of polygon ids below 2^29. The
-// others -- two inlined references, or a single reference of a larger id --
-// are rewritten as lookup-table references in those levels.
-static void narrow_top_levels(HostIndex &x, LutDedup *dedup) {
-  const size_t n_top = (size_t)x.n_d0 + (size_t)x.n_d1;
-  for (size_t k = 256; k < (1 + n_top) * 256; k++) {
+// The device keeps every trie entry in 32 bits (1 KiB nodes: half the HBM
+// footprint and twice the entries per cache line; the GPU also stages the
+// top levels in LDS). An entry fits when its high 32 bits are zero: child
+// pointers, lookup-table offsets and single references of polygon ids below
+// 2^29. The others -- two inlined references, or a single reference of a
+// larger id -- are rewritten as (deduplicated) lookup-table references.
+static void narrow_entries(HostIndex &x, LutDedup *dedup) {
+  for (size_t k = 256; k < x.nodes.size(); k++) {
     const uint64_t e = x.nodes[k];
     if ((e >> 32) == 0) continue;
     uint32_t refs[2];
@@ -704,11 +704,12 @@ static uint64_t cell_code(int face, int level, uint32_t i, uint32_t j) {
   return ((uint64_t)face << 61) | (quad_key(i, j) << (sh + 1)) | (1ull << sh);
 }
 
-// Lookup-table words a cell needs at most (deduplication can only save);
-// `top`: the cell lies in the top two node levels, whose 32-bit copy moves
-// inline references to the table.
+// Lookup-table words a cell needs at most (deduplication can only save):
+// with 32-bit trie entries, a cell with two references (or a reference id
+// of 2^29 or more) has a list too. `top` is unused.
 static int64_t cell_lut_words(const Cell &c, const std::vector<uint32_t> &local, bool exact,
                               bool top) {
+  (void)top;  // `exact`: the cell's candidates carry cell-local records
   int nt = 0, nc = 0;
   int64_t rec = 0;
   for (int r = 0; r < c.n; r++) {
@@ -723,7 +724,7 @@ static int64_t cell_lut_words(const Cell &c, const std::vector<uint32_t> &local,
     }
   }
   if (exact && nc > 0) return 2 + nt + 2 * (int64_t)nc + rec;
-  return c.n >= 3 || top ? 2 + c.n : 0;
+  return c.n >= 2 || (c.n == 1 && (c.refs[0] >> 1) >= (1u << 29)) ? 2 + c.n : 0;
 }
 
 // Node level of a cell at level l under prefix level lp.
@@ -816,7 +817,7 @@ static void train_index(Ctx &C, const Prep &P, std::vector<Cell> &cells,
                         std::vector<uint32_t> &local, std::deque<std::vector<uint32_t>> &store,
                         const int lp[6], int64_t fixed_bytes, HostIndex &out) {
   const BuildParams &bp = C.bp;
-  const bool exact = bp.mode == ACT_EXACT;
+  const bool exact = bp.mode == ACT_EXACT && bp.geometry == ACT_GEOM_PLANE;  // with records
   Trainer T(C, P, cells, local, store);
   int64_t lut_words = 10;  // the device copy's padding
   for (int f = 0; f < 6; f++) {
@@ -831,7 +832,8 @@ static void train_index(Ctx &C, const Prep &P, std::vector<Cell> &cells,
     lut_words += cell_lut_words(c, local, exact, node_depth(c.level, T.lp[c.face]) <= 1);
   }
   auto bytes = [&](int64_t n_nodes, int64_t top, int64_t words) {
-    return fixed_bytes + (n_nodes + 1) * 2048 + top * 1024 + 4 * words;
+    (void)top;
+    return fixed_bytes + (n_nodes + 1) * 1024 + 4 * words;
   };
   if (bp.memory_budget > 0 &&
       bytes((int64_t)T.nodes.size(), T.top_nodes, lut_words) > bp.memory_budget)
@@ -946,7 +948,7 @@ static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], co
       bool has_cand = false;
       for (int r = 0; r < c.n; r++) has_cand |= !(c.refs[r] & 1u);
       uint64_t entry;
-      if (has_cand && bp.mode == ACT_EXACT) {
+      if (has_cand && bp.mode == ACT_EXACT && bp.geometry == ACT_GEOM_PLANE) {
         // candidate cell: lookup-table list, the candidates' record offsets,
         // then the records themselves, so that one contiguous read serves a
         // pending point
@@ -999,7 +1001,7 @@ static int build_tries(const std::vector<Cell> &cells, const FaceCells fc[6], co
     }
   }
   renumber_breadth_first(out);
-  narrow_top_levels(out, &dedup);
+  narrow_entries(out, &dedup);
   if (out.lut.size() >= (1ull << 30)) {
     err = "lookup table exceeds 2^30 words";
     return ACT_E_RANGE;
@@ -1019,8 +1021,30 @@ int64_t image_fixed_bytes(int64_t n_polys, int64_t n_edges) {
 
 int64_t image_bytes(const HostIndex &h) {
   return image_fixed_bytes(h.n_polys, (int64_t)h.edges64.size() / 4) +
-         std::max<int64_t>(16, (int64_t)h.nodes.size() * 8) + 4 * ((int64_t)h.lut.size() + 10) +
-         std::max<int64_t>(16, (int64_t)(h.n_d0 + h.n_d1) * 1024);
+         std::max<int64_t>(16, (int64_t)h.nodes.size() * 4) + 4 * ((int64_t)h.lut.size() + 10) +
+         (h.geometry == ACT_GEOM_SPHERE ? std::max<int64_t>(16, 8 * (int64_t)h.normals.size())
+                                        : 0);
+}
+
+// Largest distance, in latitude at equal longitude, between the great-circle
+// arc from (lat_a, lng_a) to (lat_b, lng_b) and the straight chord between
+// them in the lat/lng plane, sampled at 31 interior longitudes (the distance is a
+// smooth bump that vanishes at both ends; the caller pads it). The arc's
+// latitude at longitude l follows from the plane through both endpoints:
+// tan(lat) = (tan(lat_a) sin(lng_b - l) + tan(lat_b) sin(l - lng_a)) /
+// sin(lng_b - lng_a). Edges along a meridian coincide with their chord.
+static double arc_chord_deviation(double lat_a, double lng_a, double lat_b, double lng_b) {
+  if (lng_a == lng_b) return 0.0;
+  const double ta = std::tan(lat_a / kDeg), tb = std::tan(lat_b / kDeg);
+  const double s = std::sin((lng_b - lng_a) / kDeg);
+  double dev = 0;
+  for (int k = 1; k < 32; k++) {
+    const double f = k / 32.0, l = lng_a + f * (lng_b - lng_a);
+    const double t = (ta * std::sin((lng_b - l) / kDeg) + tb * std::sin((l - lng_a) / kDeg)) / s;
+    const double lat_arc = std::atan(t) * kDeg;
+    dev = std::max(dev, std::fabs(lat_arc - (lat_a + f * (lat_b - lat_a))));
+  }
+  return dev;
 }
 
 // ------------------------------------------------------------ index files
@@ -1028,7 +1052,7 @@ int64_t image_bytes(const HostIndex &h) {
 namespace {
 
 constexpr char kFileMagic[8] = {'A', 'C', 'T', 'I', 'D', 'X', '0', '1'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 3;  // 2: 32-bit trie entries; 3: geometry
 
 // Running digest of the bytes written or read (FNV-style mixing).
 struct Digest {
@@ -1105,6 +1129,8 @@ void scalars(IO &io, H &h) {
   io.val(h.build_seconds);
   io.val(h.train_splits);
   io.val(h.train_points_used);
+  io.val(h.geometry);
+  io.val(h.margin_deg);
 }
 
 template <typename IO, typename H>
@@ -1116,6 +1142,7 @@ void arrays(IO &io, H &h) {
   io.vec(h.poly_m);
   io.vec(h.edges32);
   io.vec(h.edges64);
+  io.vec(h.normals);
 }
 
 }  // namespace
@@ -1134,11 +1161,13 @@ static bool image_consistent(const HostIndex &h) {
     if (F.root != -1 && (F.root <= 0 || (uint64_t)F.root >= n_nodes)) return false;
     if (F.plevel < 0 || F.plevel > kMaxLevel) return false;
   }
-  const bool exact = h.mode == ACT_EXACT;
+  const bool exact = h.mode == ACT_EXACT && h.geometry == ACT_GEOM_PLANE;  // lists with records
+  if (h.geometry == ACT_GEOM_SPHERE && h.normals.size() != 3 * (h.edges64.size() / 4)) return false;
   uint64_t last_ok = UINT64_MAX;
   for (uint64_t k = 256; k < h.nodes.size(); k++) {
     const uint64_t e = h.nodes[k];
     if (e == 0) continue;
+    if (e >> 32) return false;  // the device keeps 32-bit entries
     switch (e & kTagMask) {
       case kTagPtr:
         if ((e >> 2) == 0 || (e >> 2) >= n_nodes) return false;
@@ -1237,7 +1266,8 @@ int load_host_index(const char *path, HostIndex &h, void *extra, uint32_t extra_
                         h.nodes.size() % 256 == 0 && h.poly_origin.size() == 2 * (size_t)h.n_polys &&
                         h.poly_m.size() == (size_t)h.n_polys && h.edges64.size() % 4 == 0 &&
                         h.edges32.size() == h.edges64.size() &&
-                        (h.mode == ACT_EXACT || h.mode == ACT_APPROX);
+                        (h.mode == ACT_EXACT || h.mode == ACT_APPROX) &&
+                        (h.geometry == ACT_GEOM_PLANE || h.geometry == ACT_GEOM_SPHERE);
   if (!r.ok || got != want || r.left != 0 || !shape_ok || !image_consistent(h)) {
     h = HostIndex();
     err = std::string(path) + ": truncated or corrupt index file";
@@ -1347,10 +1377,41 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     }
     out.poly_m[p] = m;
   }
+  // ------------------------------------------------------ spherical edges
+  BuildParams bpx = bp;
+  out.geometry = bp.geometry;
+  if (bp.geometry == ACT_GEOM_SPHERE) {
+    // great-circle normals, and the cell margin widened by the largest
+    // distance (in latitude, at equal longitude) between an edge's arc and
+    // its chord, so that chord-based classification holds for the arcs
+    out.normals.resize(3 * n_edges);
+    double dev = 0;
+    for (size_t e = 0; e < n_edges; e++) {
+      const double *q = &P.ex[4 * e];  // ax ay bx by = lng lat lng lat
+      double a[3], b[3];
+      const double ca = std::cos(q[1] / kDeg), cb = std::cos(q[3] / kDeg);
+      a[0] = ca * std::cos(q[0] / kDeg);
+      a[1] = ca * std::sin(q[0] / kDeg);
+      a[2] = std::sin(q[1] / kDeg);
+      b[0] = cb * std::cos(q[2] / kDeg);
+      b[1] = cb * std::sin(q[2] / kDeg);
+      b[2] = std::sin(q[3] / kDeg);
+      // (b + a) x (b - a) = 2 (a x b): b - a of nearby endpoints is exact,
+      // so the normal keeps its relative precision (a x b would cancel)
+      const double s0 = b[0] + a[0], s1 = b[1] + a[1], s2 = b[2] + a[2];
+      const double d0 = b[0] - a[0], d1 = b[1] - a[1], d2 = b[2] - a[2];
+      out.normals[3 * e] = s1 * d2 - s2 * d1;
+      out.normals[3 * e + 1] = s2 * d0 - s0 * d2;
+      out.normals[3 * e + 2] = s0 * d1 - s1 * d0;
+      dev = std::max(dev, arc_chord_deviation(q[1], q[0], q[3], q[2]));
+    }
+    bpx.margin_deg = bp.margin_deg + 1.25 * dev + 1e-12;
+  }
+  out.margin_deg = bpx.margin_deg;
   // --------------------------------------------------------- subdivision
   Ctx C;
   C.P = &P;
-  C.bp = bp;
+  C.bp = bpx;
   int nthreads = bp.threads > 0 ? bp.threads : (int)std::max(1u, std::thread::hardware_concurrency());
 
   std::vector<int32_t> all_polys;

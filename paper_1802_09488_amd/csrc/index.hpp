@@ -74,14 +74,21 @@ struct HostIndex {
   // exact mode: words of cell-local refinement records (stored in `lut`
   // after their cell's list)
   int64_t local_words = 0;
+  // ACT_GEOM_SPHERE: edges are great-circle arcs; the normal a x b of each
+  // edge's great circle (3 doubles per edge, unit vectors of the endpoints)
+  // and the cell margin used (degrees: the build margin plus the largest
+  // arc-to-chord distance)
+  int32_t geometry = ACT_GEOM_PLANE;
+  std::vector<double> normals;
+  double margin_deg = 0;
 
   // statistics
   int64_t n_cells = 0, n_cells_interior_only = 0;
   int32_t max_depth = 0, max_refs = 0, max_cell_level = 0;
   // Nodes are numbered breadth-first: roots occupy indices 1 .. n_d0, the
-  // nodes one level below them n_d0+1 .. n_d0+n_d1. Every entry of these two
-  // levels has its high 32 bits zero, so the GPU stages them in LDS as
-  // 32-bit entries.
+  // nodes one level below them n_d0+1 .. n_d0+n_d1, so the top two levels
+  // are one contiguous run the GPU stages in LDS. Every entry has its high
+  // 32 bits zero: the device image keeps 32-bit entries.
   int32_t n_d0 = 0, n_d1 = 0;
   double build_seconds = 0;
   // training (Section III-D): cells split and training points consumed
@@ -107,11 +114,11 @@ struct BuildParams {
   // stop early (ACT_E_RANGE) once the covering has more cells than this
   // (0 = no limit): a budget check that need not finish the covering
   int64_t cell_limit = 0;
+  int32_t geometry = ACT_GEOM_PLANE;
 };
 
 // Device bytes of an index image besides its trie nodes and lookup table
-// (the polygon store, tables, the LDS copy of the top levels at its largest),
-// as the runtime uploads it: an upper bound used by the training budget.
+// (the polygon store and tables), as the runtime uploads it.
 int64_t image_fixed_bytes(int64_t n_polys, int64_t n_edges);
 
 // Device bytes the runtime uploads for this index.

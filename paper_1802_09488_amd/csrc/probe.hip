@@ -60,7 +60,7 @@ static int fail(int code, const std::string &msg) {
   } while (0)
 
 struct DevImage {
-  uint64_t *nodes = nullptr;
+  uint32_t *nodes = nullptr;  // trie entries, 32 bits each
   uint32_t *lut = nullptr;
   int32_t *eoff = nullptr;
   double2 *origin = nullptr;
@@ -69,9 +69,9 @@ struct DevImage {
   double2 *e64 = nullptr;
   double2 *trig = nullptr;
   struct FaceDev *faces = nullptr;
-  uint32_t *top32 = nullptr;
   uint64_t *sink = nullptr;  // 64 bytes that the probe's idle lanes store to
   uint16_t *hinv = nullptr;  // inverse Hilbert table (joins of precomputed ids)
+  double *normals = nullptr;  // ACT_GEOM_SPHERE: great-circle normal of each edge
   size_t bytes = 0;
 };
 
@@ -144,7 +144,7 @@ struct ProbeParams {
   int64_t cap;
   int64_t *n_pairs;
   unsigned long long *counters;
-  const uint64_t *nodes;
+  const uint32_t *nodes;  // trie entries (32-bit: all fit, see the builder)
   const uint32_t *lut;
   const int32_t *eoff;
   const double2 *origin;
@@ -153,7 +153,7 @@ struct ProbeParams {
   const double2 *e64;
   const double2 *trig;   // kTrigEntries (cos, sin) of whole degrees (device)
   const FaceDev *faces;  // 6 entries (device)
-  const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 as 32-bit entries
+  const uint32_t *top32;  // nodes 1 .. n_d0 + n_d1 (the top levels, staged in LDS)
   int32_t n_lds_nodes;    // trie nodes 1 .. n_lds_nodes staged in LDS
   int32_t refine;
   const uint32_t *local;  // exact mode: base of the cell-local records (the LUT)
@@ -179,6 +179,9 @@ struct ProbeParams {
   // points themselves, pts, are then read only to refine pending ones)
   const uint64_t *ids;
   const uint16_t *hinv;  // inverse Hilbert table, 1024 entries (device)
+  // ACT_GEOM_SPHERE: edges are great-circle arcs with these normals (3
+  // doubles per edge); candidates are refined over all of a polygon's arcs
+  const double *normals;
 };
 
 
@@ -358,6 +361,40 @@ __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px,
   return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
 }
 
+// Unit vector of (lat, lng) degrees (the projection's sin and cos).
+__device__ __forceinline__ void unit_vector(const double2 *trig, double lat, double lng,
+                                            double (&q)[3]) {
+  double sp, cp, sl, cl;
+  sincos_deg(trig, lat, sp, cp);
+  sincos_deg(trig, lng, sl, cl);
+  q[0] = cp * cl;
+  q[1] = cp * sl;
+  q[2] = sp;
+}
+
+// One edge of the spherical crossing test (ACT_GEOM_SPHERE): the arc from the
+// point north along its meridian to the pole. Returns 0 (no effect), 1
+// (toggle) or 2 (the point is a vertex or on the arc). The meridian meets
+// the edge when the point's longitude lies in the edge's half-open range;
+// it crosses it when the point and the pole are on opposite sides of the
+// edge's great circle: det = q . (a x b) has the sign opposite to that of
+// the pole's, which is the sign of lng_b - lng_a. Edges along a meridian are
+// only touched.
+__device__ __forceinline__ int edge_sphere(const ProbeParams &P, int e, double plat, double plng,
+                                           const double (&q)[3]) {
+  const double2 A = P.e64[2 * e], B = P.e64[2 * e + 1];  // (lng, lat)
+  if ((plat == A.y && plng == A.x) || (plat == B.y && plng == B.x)) return 2;
+  if (A.x == B.x)
+    return plng == A.x && plat >= fmin(A.y, B.y) && plat <= fmax(A.y, B.y) ? 2 : 0;
+  const double lo = fmin(A.x, B.x), hi = fmax(A.x, B.x);
+  if (plng < lo || plng > hi) return 0;
+  const double *n = P.normals + 3 * (size_t)e;
+  const double det = q[0] * n[0] + q[1] * n[1] + q[2] * n[2];
+  if (det == 0.0) return 2;
+  if (plng == hi) return 0;
+  return (det > 0.0) != (B.x > A.x) ? 1 : 0;
+}
+
 // Whole-wave point-in-polygon test of one (point, polygon) pair: lane l
 // takes edges e0 + l, e0 + l + 64, ...; crossing parity = parity of the
 // popcounts of the toggle ballots; any lane on an edge decides "covered".
@@ -370,7 +407,16 @@ __device__ bool wave_covers(const ProbeParams &P, int poly, double lat, double l
   const double px = lng, py = lat;
   uint32_t par = 0;
   bool on = false;
-  if (P.refine != ACT_REFINE_FP64) {
+  if (P.normals) {  // spherical edges
+    double q[3];
+    unit_vector(P.trig, lat, lng, q);
+    for (int base = e0; base < e1; base += 64) {
+      const int e = base + lane;
+      const int r = e < e1 ? edge_sphere(P, e, lat, lng, q) : 0;
+      on |= ballot(r == 2) != 0;
+      par ^= (uint32_t)__popcll(ballot(r == 1));
+    }
+  } else if (P.refine != ACT_REFINE_FP64) {
     const double2 o = P.origin[poly];
     const float qx = (float)(px - o.x), qy = (float)(py - o.y);
     const float eta = tier1_eta(fmaxf(P.pm[poly], fmaxf(fabsf(qx), fabsf(qy))));
@@ -418,24 +464,6 @@ struct Hits {
     }
   }
 };
-
-// Slots for k pairs of each lane in the pair list, one atomic per wave:
-// returns the lane's first slot. Must be reached by all 64 lanes.
-__device__ __forceinline__ uint64_t reserve_pairs(const ProbeParams &P, int lane, uint32_t k) {
-  uint32_t incl = k;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint32_t v = __shfl_up(incl, d);
-    if (lane >= d) incl += v;
-  }
-  const uint32_t total = __shfl(incl, 63);
-  unsigned long long base = 0;
-  if (total != 0) {  // wave-uniform
-    if (lane == 0) base = atomicAdd((unsigned long long *)P.n_pairs, (unsigned long long)total);
-    base = __shfl(base, 0);
-  }
-  return base + incl - k;
-}
 
 // One (point, polygon) match of a count join: a histogram bin in LDS, or
 // the polygon's global counter.
@@ -535,7 +563,7 @@ __device__ __forceinline__ void descend_lds(const uint32_t *s_nodes, const FaceD
 
 template <int NP>
 __device__ __forceinline__ void issue_level(const ProbeParams &P, Descent<NP> &D,
-                                            uint64_t (&x)[NP]) {
+                                            uint32_t (&x)[NP]) {
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     D.sh[p] -= 4;
@@ -546,7 +574,7 @@ __device__ __forceinline__ void issue_level(const ProbeParams &P, Descent<NP> &D
 }
 
 template <int NP>
-__device__ __forceinline__ void take_level(Descent<NP> &D, const uint64_t (&x)[NP],
+__device__ __forceinline__ void take_level(Descent<NP> &D, const uint32_t (&x)[NP],
                                            uint32_t &reads) {
 #pragma unroll
   for (int p = 0; p < NP; p++) {
@@ -566,7 +594,7 @@ __device__ __forceinline__ void descend_rest(const ProbeParams &P, Descent<NP> &
 #pragma unroll
     for (int p = 0; p < NP; p++) any |= D.act[p];
     if (!any) break;
-    uint64_t x[NP];
+    uint32_t x[NP];
     issue_level<NP>(P, D, x);
     take_level<NP>(D, x, reads);
   }
@@ -657,32 +685,6 @@ __device__ __forceinline__ RefList lut_refs(const ProbeParams &P, uint32_t off) 
   return L;
 }
 
-// The cell-local record test (local_record_covers) with the header and the
-// first local edge read together (the device copy of the records is padded).
-__device__ __forceinline__ bool local_covers_dev(const uint32_t *rec, double px, double py) {
-  uint32_t w[10];
-#pragma unroll
-  for (int k = 0; k < 10; k++) w[k] = rec[k];
-  const uint32_t n_local = w[0], n_break = w[1] & 0x7fffffffu;
-  uint32_t par = w[1] >> 31;
-  if (n_local > 0) {
-    const int r = edge_test_exact(word_double(w + 2), word_double(w + 4), word_double(w + 6),
-                                  word_double(w + 8), px, py);
-    if (r == 2) return true;
-    par ^= (uint32_t)r;
-  }
-  const uint32_t *d = rec + 10;
-  for (uint32_t k = 1; k < n_local; k++, d += 8) {
-    const int r = edge_test_exact(word_double(d), word_double(d + 2), word_double(d + 4),
-                                  word_double(d + 6), px, py);
-    if (r == 2) return true;
-    par ^= (uint32_t)r;
-  }
-  if (n_local == 0) d = rec + 2;
-  for (uint32_t k = 0; k < n_break; k++, d += 2) par ^= word_double(d) <= py ? 1u : 0u;
-  return par != 0;
-}
-
 // The references of a cell entry (a lookup-table list, or one or two inline
 // references, interior ones first).
 __device__ __forceinline__ RefList entry_refs(const ProbeParams &P, uint64_t e) {
@@ -723,6 +725,16 @@ template <int FULL>
 __device__ bool lane_covers(const ProbeParams &P, int poly, double lat, double lng,
                             uint32_t &c_fp64, uint32_t &c_exact) {
   uint32_t par = 0;
+  if (P.normals) {  // spherical edges
+    double q[3];
+    unit_vector(P.trig, lat, lng, q);
+    for (int e = P.eoff[poly]; e < P.eoff[poly + 1]; e++) {
+      const int r = edge_sphere(P, e, lat, lng, q);
+      if (r == 2) return true;
+      par ^= (uint32_t)r;
+    }
+    return par != 0;
+  }
   for (int e = P.eoff[poly]; e < P.eoff[poly + 1]; e++) {
     const int r = edge_fp64<FULL>(P, e, lng, lat, c_fp64, c_exact);
     if (r == 2) return true;
@@ -1047,6 +1059,20 @@ struct PendingQueue {
   uint2 *list;           // kExactList: this wave's region of the pending list
 };
 
+// Pair output of approximate joins goes through a per-block buffer in LDS:
+// a wave reserves its pairs' slots there with one LDS atomic, and the block
+// moves the buffer to the pair list with one global atomic when it ends
+// (every wave reserving its own slots in the global list instead meets a
+// single, heavily contended counter). A wave whose pairs do not fit writes
+// them to the list directly and marks its slots in the buffer unused.
+constexpr int kPairBuf = 1024;  // pairs (12 KiB), one per probe thread at the flush
+
+struct PairBuf {
+  int64_t *pt;
+  int32_t *poly;
+  uint32_t *count;  // slots reserved so far (may pass kPairBuf)
+};
+
 // Resolves the first n (<= 64) queued points, lane l taking entry l.
 template <int FULL, bool BATCHED>
 __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &Q, uint32_t n,
@@ -1071,7 +1097,8 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
                                             int lane, const uint64_t (&e)[NP],
                                             const bool (&live)[NP], const bool (&valid)[NP],
                                             uint32_t (&c)[8], PendingQueue &Q, uint32_t (&rc)[7],
-                                            uint32_t &c_reads, uint32_t *s_hist) {
+                                            uint32_t &c_reads, uint32_t *s_hist,
+                                            const PairBuf &PB) {
   bool pend[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
@@ -1121,22 +1148,46 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
       }
       if (FULL >= 1 && P.pair_pt) {
         // every other reference is a pair; the wave reserves the slots of
-        // all its lanes' pairs with one atomic
-        const uint32_t total = live[p] ? (uint32_t)n_inl + nt + nc : 0u;
-        uint64_t slot = reserve_pairs(P, lane, total > 0 ? total - 1 : 0u);
-        auto put = [&](int32_t poly) {
-          if (poly == hits.best) return;
-          if ((int64_t)slot < P.cap) {
-            P.pair_pt[slot] = i;
-            P.pair_poly[slot] = poly;
+        // all its lanes' pairs in the block's buffer at once
+        const uint32_t refs = live[p] ? (uint32_t)n_inl + nt + nc : 0u;
+        const uint32_t k = refs > 0 ? refs - 1 : 0u;
+        uint32_t incl = k;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t v = __shfl_up(incl, d);
+          if (lane >= d) incl += v;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        if (total != 0) {  // wave-uniform
+          uint32_t lb = 0;
+          if (lane == 0) lb = atomicAdd(PB.count, total);
+          lb = __shfl(lb, 0);
+          const bool fits = lb + total <= (uint32_t)kPairBuf;
+          unsigned long long gb = 0;
+          if (!fits) {
+            if (lane == 0) gb = atomicAdd((unsigned long long *)P.n_pairs, (unsigned long long)total);
+            gb = __shfl(gb, 0);
+            for (uint32_t q = lb + lane; q < min(lb + total, (uint32_t)kPairBuf); q += 64)
+              PB.poly[q] = -1;  // reserved but unused
           }
-          slot++;
-        };
-        if (live[p]) {
-          if (n_inl > 0) put((int32_t)(r0 >> 1));
-          if (n_inl > 1) put((int32_t)(r1 >> 1));
-          for (uint32_t r = 0; r < nt; r++) put((int32_t)P.lut[off + 1 + r]);
-          for (uint32_t r = 0; r < nc; r++) put((int32_t)P.lut[off + 2 + nt + r]);
+          uint32_t m = incl - k;
+          auto put = [&](int32_t poly) {
+            if (poly == hits.best) return;
+            if (fits) {
+              PB.pt[lb + m] = i;
+              PB.poly[lb + m] = poly;
+            } else if ((int64_t)(gb + m) < P.cap) {
+              P.pair_pt[gb + m] = i;
+              P.pair_poly[gb + m] = poly;
+            }
+            m++;
+          };
+          if (live[p]) {
+            if (n_inl > 0) put((int32_t)(r0 >> 1));
+            if (n_inl > 1) put((int32_t)(r1 >> 1));
+            for (uint32_t r = 0; r < nt; r++) put((int32_t)P.lut[off + 1 + r]);
+            for (uint32_t r = 0; r < nc; r++) put((int32_t)P.lut[off + 2 + nt + r]);
+          }
         }
       }
       if (FULL == 2) c[3] += e[p] != 0;
@@ -1303,6 +1354,13 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   __shared__ FaceDev s_face[6];
   __shared__ double2 s_trig[IDS ? 1 : kTrigEntries];
   __shared__ uint16_t s_hinv[IDS ? 1024 : 1];
+  constexpr bool PAIRBUF = FULL >= 1 && MODE == kApprox;
+  __shared__ int64_t s_ppt[PAIRBUF ? kPairBuf : 1];
+  __shared__ int32_t s_ppo[PAIRBUF ? kPairBuf : 1];
+  __shared__ uint32_t s_pcnt;
+  __shared__ unsigned long long s_pbase;
+  __shared__ uint32_t s_pwave[kProbeWaves];
+  const PairBuf PB{s_ppt, s_ppo, &s_pcnt};
   __shared__ int64_t s_qv[FUSED ? kProbeWaves * kQueueCap : 1];
   __shared__ uint64_t s_qe[FUSED ? kProbeWaves * kQueueCap : 1];
   if (LDS_DEPTH > 0)
@@ -1310,6 +1368,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
   if (threadIdx.x < 6) s_face[threadIdx.x] = P.faces[threadIdx.x];
   if (!IDS && threadIdx.x < kTrigEntries) s_trig[threadIdx.x] = P.trig[threadIdx.x];
   if (IDS) s_hinv[threadIdx.x] = P.hinv[threadIdx.x];  // 1024 threads, 1024 entries
+  if (PAIRBUF && threadIdx.x == 0) s_pcnt = 0;
   // count joins: a per-block histogram of the polygons after the trie levels
   constexpr bool COUNTING = MODE == kApproxCount || MODE == kExactCount;
   uint32_t *s_hist = COUNTING && P.hist_bins > 0 ? s_nodes + P.n_lds_nodes * 256 : nullptr;
@@ -1332,7 +1391,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     // stage B: the tile whose first global level is in flight; nxt: the
     // points of the tile after the one being projected
     Descent<NP> B;
-    uint64_t xB[NP];
+    uint32_t xB[NP];
     bool liveB[NP], validB[NP];
     TileRef TB = tile_ref<BATCHED, NP>(P, first), TN;
     uint32_t tileB = first;
@@ -1363,7 +1422,7 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
       take_level<NP>(B, xB, c_reads);
       descend_rest<NP>(P, B, c_reads);
       finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
-                                            c_reads, s_hist);
+                                            c_reads, s_hist, PB);
       B = A;
       TB = TA;
       tileB = tile;
@@ -1378,10 +1437,36 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     take_level<NP>(B, xB, c_reads);
     descend_rest<NP>(P, B, c_reads);
     finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
-                                          c_reads, s_hist);
+                                          c_reads, s_hist, PB);
   }
   if (MODE == kExactList || MODE == kExactCount)
     P.pcount[blockIdx.x * kProbeWaves + wid] = Q.count;
+  if (PAIRBUF && P.pair_pt) {
+    // move the block's buffered pairs to the pair list: slots in use
+    // (unused ones are marked), compacted with one global reservation
+    __syncthreads();
+    const uint32_t t = threadIdx.x;  // one slot per thread (kPairBuf = block size)
+    const bool use = t < min(s_pcnt, (uint32_t)kPairBuf) && s_ppo[t] >= 0;
+    const uint64_t bal = ballot(use);
+    const uint32_t rank = (uint32_t)lane_rank(bal);
+    if (lane == 0) s_pwave[wid] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < kProbeWaves; w++) {
+      before += w < wid ? s_pwave[w] : 0u;
+      all += s_pwave[w];
+    }
+    if (t == 0 && all)
+      s_pbase = atomicAdd((unsigned long long *)P.n_pairs, (unsigned long long)all);
+    __syncthreads();
+    if (use) {
+      const int64_t slot = (int64_t)(s_pbase + before + rank);
+      if (slot < P.cap) {
+        P.pair_pt[slot] = s_ppt[t];
+        P.pair_poly[slot] = s_ppo[t];
+      }
+    }
+  }
   if (s_hist) {
     __syncthreads();
     for (int k = threadIdx.x; k < P.hist_bins; k += kProbeBlock) {
@@ -1688,7 +1773,7 @@ struct DeviceGuard {
 
 static void free_image(DevImage &d) {
   void *ptrs[] = {d.nodes, d.lut,   d.eoff,  d.origin, d.pm,   d.e32,
-                  d.e64,   d.trig,  d.faces, d.top32, d.sink, d.hinv};
+                  d.e64,   d.trig,  d.faces, d.sink,  d.hinv, d.normals};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   d = DevImage();
@@ -1848,9 +1933,15 @@ static int upload_image(act_index *x) {
   std::vector<double2> trig;
   trig_table(trig);
   int rc;
-  if ((rc = upload(d.nodes, h.nodes.data(), h.nodes.size() * 8, d.bytes))) return rc;
+  {  // the trie with 32-bit entries (the builder narrowed every entry)
+    std::vector<uint32_t> n32(h.nodes.size());
+    for (size_t k = 0; k < n32.size(); k++) n32[k] = (uint32_t)h.nodes[k];
+    if ((rc = upload(d.nodes, n32.data(), n32.size() * 4, d.bytes))) return rc;
+  }
   // the device copy of the lookup table (with the records) carries zero
-  // padding for the resolve kernel's read-ahead (at most 10 words)
+  // padding: lut_refs reads a list's first four words together, and the
+  // approximate probe reads the head of a list's candidate part even when
+  // that part is empty, so reads near the table's end stay in bounds
   std::vector<uint32_t> lut(h.lut);
   lut.resize(lut.size() + 10, 0u);
   if ((rc = upload(d.lut, lut.data(), lut.size() * 4, d.bytes))) return rc;
@@ -1863,11 +1954,6 @@ static int upload_image(act_index *x) {
   FaceDev f[6];
   face_table(h, f);
   if ((rc = upload(d.faces, f, sizeof f, d.bytes))) return rc;
-  // the top two node levels as 32-bit entries (their high halves are zero)
-  const size_t n_top = (size_t)(h.n_d0 + h.n_d1) * 256;
-  std::vector<uint32_t> top(n_top);
-  for (size_t k = 0; k < n_top; k++) top[k] = (uint32_t)h.nodes[256 + k];
-  if ((rc = upload(d.top32, top.data(), top.size() * 4, d.bytes))) return rc;
   const uint64_t zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if ((rc = upload(d.sink, zeros, sizeof zeros, d.bytes))) return rc;
   // the inverse of the 4-level Hilbert table: (state, 8 position bits) ->
@@ -1880,6 +1966,9 @@ static int upload_image(act_index *x) {
       inv[st * 256 + (e & 255)] = (uint16_t)(b | (e & 0x300));
     }
   if ((rc = upload(d.hinv, inv, sizeof inv, d.bytes))) return rc;
+  if (h.geometry == ACT_GEOM_SPHERE &&
+      (rc = upload(d.normals, h.normals.data(), h.normals.size() * 8, d.bytes)))
+    return rc;
   return ACT_OK;
 }
 
@@ -1926,10 +2015,12 @@ static void index_params(const act_index *x, int refine, int n_lds, ProbeParams 
   P.e64 = x->dev.e64;
   P.trig = x->dev.trig;
   P.faces = x->dev.faces;
-  P.top32 = x->dev.top32;
+  P.top32 = x->dev.nodes + 256;  // node 1 onward: the top levels come first
   P.n_lds_nodes = n_lds;
   P.refine = refine == ACT_REFINE_AUTO ? ACT_REFINE_LOCAL : refine;
-  P.local = x->host.mode == ACT_EXACT ? x->dev.lut : nullptr;  // records live in the LUT
+  // records live in the LUT (planar exact indexes; spherical ones have none)
+  P.local = x->host.mode == ACT_EXACT && x->host.geometry == ACT_GEOM_PLANE ? x->dev.lut : nullptr;
+  P.normals = x->host.geometry == ACT_GEOM_SPHERE ? x->dev.normals : nullptr;
   P.sink = x->dev.sink;
   P.hinv = x->dev.hinv;
 }
@@ -2173,6 +2264,7 @@ static uint64_t index_digest(const HostIndex &h) {
   mix(h.lut.data(), h.lut.size() * 4);
   mix(h.edges64.data(), h.edges64.size() * 8);
   mix(&h.precision_m, sizeof h.precision_m);
+  mix(&h.geometry, sizeof h.geometry);
   return d;
 }
 
@@ -2321,7 +2413,7 @@ void act_build_opts_init(act_build_opts *o) {
   o->n_train = 0;
   o->memory_budget = 0;
   o->train_max_level = 30;
-  o->reserved0 = 0;
+  o->geometry = ACT_GEOM_PLANE;
 }
 
 // Builds the host index and, for a device, uploads it. ACT_AUTO follows the
@@ -2389,6 +2481,11 @@ int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t
   bp.n_train = o.n_train;
   bp.memory_budget = o.memory_budget;
   bp.train_max_level = o.train_max_level ? o.train_max_level : 30;
+  bp.geometry = o.geometry;
+  if (bp.geometry != ACT_GEOM_PLANE && bp.geometry != ACT_GEOM_SPHERE)
+    return fail(ACT_E_ARG, "geometry must be ACT_GEOM_PLANE or ACT_GEOM_SPHERE");
+  if (bp.geometry == ACT_GEOM_SPHERE && mode != ACT_EXACT)
+    return fail(ACT_E_ARG, "spherical geometry is supported in exact mode only");
   if (bp.n_train < 0 || (bp.n_train > 0 && !bp.train_points))
     return fail(ACT_E_ARG, "training needs n_train >= 0 points");
   if (bp.memory_budget < 0) return fail(ACT_E_ARG, "memory_budget < 0");
@@ -2659,7 +2756,7 @@ int act_index_stats(const act_index *x, act_stats *o) {
   o->n_cells = h.n_cells;
   o->n_cells_interior_only = h.n_cells_interior_only;
   o->n_nodes = (int64_t)h.nodes.size() / 256;
-  o->node_bytes = (int64_t)h.nodes.size() * 8;
+  o->node_bytes = (int64_t)h.nodes.size() * 4;  // device entries are 32-bit
   o->lut_words = (int64_t)h.lut.size();
   o->edge_bytes = (int64_t)(h.edges32.size() * 4 + h.edges64.size() * 8);
   o->device_bytes = (int64_t)x->dev.bytes;
@@ -2679,6 +2776,8 @@ int act_index_stats(const act_index *x, act_stats *o) {
   o->train_splits = h.train_splits;
   o->train_points_used = h.train_points_used;
   o->image_bytes = image_bytes(h);
+  o->margin_deg = h.margin_deg;
+  o->geometry = h.geometry;
   return ACT_OK;
 }
 

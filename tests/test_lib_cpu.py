@@ -443,16 +443,54 @@ def test_load_refuses_out_of_range_references(act, tmp_path):
     raw = bytearray(path.read_bytes())
     assert _fnv(bytes(raw[:-8])) == struct.unpack("<Q", raw[-8:])[0]  # the documented digest
     assert act.load(path, device=-1).digest() == idx.digest()
-    n_nodes = struct.unpack("<Q", raw[224:232])[0] // 256
-    ent = np.frombuffer(bytes(raw[232:232 + 8 * 256 * n_nodes]), dtype=np.uint64)
+    # magic, version, extra bytes (16), the scalars (220), then the node
+    # array's length and entries
+    at = 16 + 220
+    n_nodes = struct.unpack("<Q", raw[at:at + 8])[0] // 256
+    ent = np.frombuffer(bytes(raw[at + 8:at + 8 + 8 * 256 * n_nodes]), dtype=np.uint64)
     for label, want_tag, value in (("pointer", 0, (n_nodes + 5) << 2),
                                    ("list", 3, ((1 << 29) << 2) | 3)):
         k = int(np.nonzero((ent != 0) & ((ent & np.uint64(3)) == np.uint64(want_tag)))[0][0])
         bad = bytearray(raw)
-        bad[232 + 8 * k:240 + 8 * k] = struct.pack("<Q", value)
+        bad[at + 8 + 8 * k:at + 16 + 8 * k] = struct.pack("<Q", value)
         bad[-8:] = struct.pack("<Q", _fnv(bytes(bad[:-8])))
         p = tmp_path / ("bad_%s.act" % label)
         p.write_bytes(bytes(bad))
         with pytest.raises(act.ActError) as e:
             act.load(p, device=-1)
         assert "corrupt" in str(e.value), label
+
+
+def test_sphere_index_structure(act, tmp_path):
+    """Spherical geometry (great-circle edges): the cell margin grows by the
+    largest arc-to-chord distance, and the index stays conservative for the
+    arcs: every polygon that covers a point in the spherical model (oracle)
+    is referenced by the point's cell and every true hit is a spherical
+    containment; approximate mode refuses it; index files keep it."""
+    P = synth.workload_polygons("c2")
+    idx = act.build(P, "exact", device=-1, geometry="sphere")
+    st = idx.stats()
+    assert st["geometry"] == 1 and st["margin_deg"] > 1e-9
+    assert act.build(P, "exact", device=-1).stats()["margin_deg"] == 1e-9
+    rng = np.random.default_rng(29)
+    v = P.verts[rng.choice(len(P.verts), 3000, replace=False)]
+    pts = np.concatenate([synth.workload_points("c2", 0, 20000), v,
+                          v + rng.integers(-2, 3, v.shape) * np.spacing(v)])
+    face, _, _, s, tt = C.project(pts[:, 0], pts[:, 1])
+    i, j = C.leaf_ij(s, tt)
+    ent = idx.lookup_host(face, i, j)
+    lut = idx.lut_host()
+    truth = _truth(oracle.join_sphere(P, pts))
+    for k in range(len(pts)):
+        refs = _decode(ent[k], lut)
+        ids_k = {p for p, _ in refs}
+        assert truth.get(k, set()) <= ids_k, (k, truth.get(k), refs)
+        for p, interior in refs:
+            if interior:
+                assert p in truth.get(k, set()), (k, p)
+    with pytest.raises(act.ActError):
+        act.build(P, "approx", 4.0, device=-1, geometry="sphere")
+    path = tmp_path / "sphere.act"
+    idx.save(path)
+    got = act.load(path, device=-1)
+    assert got.digest() == idx.digest() and got.stats()["geometry"] == 1
