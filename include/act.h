@@ -130,6 +130,22 @@ typedef struct {
                                  30)                                       */
   int32_t geometry;           /* ACT_GEOM_PLANE (default) or ACT_GEOM_SPHERE
                                  (exact mode only)                         */
+  /* Per-polygon coverings with cell budgets (exact mode), as the paper
+   * configures them (Section V: 128 covering cells up to level 30, 256
+   * interior cells up to level 20, with max_level = 30). 0 (default) builds
+   * the joint subdivision instead, whose cells stop at max_level wherever a
+   * polygon's boundary passes. Each polygon's covering is refined coarsest
+   * cell first while its cell count stays within max_covering_cells (cells
+   * inside the polygon are final); its interior covering keeps cells inside
+   * the polygon, refined while within max_interior_cells and up to
+   * max_interior_level; all coverings are merged without overlap, each cell
+   * keeping the references of every covering cell it lies in (Section
+   * III-B). Training (below) then refines the cells that the training
+   * points find expensive. */
+  int32_t max_covering_cells; /* 0 (default): no budget                   */
+  int32_t max_interior_cells; /* default 256                               */
+  int32_t max_interior_level; /* default 20                                */
+  int32_t reserved1;
 } act_build_opts;
 
 /* Fills *opts with the defaults (the values act_build uses for NULL). */

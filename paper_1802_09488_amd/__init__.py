@@ -277,13 +277,16 @@ class Index:
 def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
           device: int = 0, threads: int = 0, margin_deg: float = 0.0,
           prefix_level: int = -1, train_points=None, memory_budget: int = 0,
-          train_max_level: int = 30, geometry: str = "plane") -> Index:
+          train_max_level: int = 30, geometry: str = "plane", max_covering_cells: int = 0,
+          max_interior_cells: int = 256, max_interior_level: int = 20) -> Index:
     """Build an index (host) and upload it to `device` (-1: host only).
     prefix_level -1 lets the builder choose the trie's prefix level.
     train_points: optional (n, 2) float64 (lat, lng) host array the exact
     index is trained with (Section III-D) within memory_budget bytes of
     device image (0: no limit). geometry "sphere": edges are great-circle
-    arcs (exact mode)."""
+    arcs (exact mode). max_covering_cells > 0: per-polygon coverings with
+    cell budgets (the paper's configuration: 128, 256, 20 with max_level
+    30) instead of the joint subdivision."""
     m = {"exact": ACT_EXACT, "approx": ACT_APPROX, "auto": ACT_AUTO}.get(mode, mode)
     v = np.ascontiguousarray(polys.verts, dtype=np.float64)
     ro = np.ascontiguousarray(polys.ring_off, dtype=np.int64)
@@ -297,7 +300,10 @@ def build(polys, mode="exact", precision_m: float = 0.0, *, max_level: int = 20,
                         n_train=0 if tp is None else tp.shape[0],
                         memory_budget=int(memory_budget), train_max_level=train_max_level,
                         geometry={"plane": _b.ACT_GEOM_PLANE,
-                                  "sphere": _b.ACT_GEOM_SPHERE}.get(geometry, geometry))
+                                  "sphere": _b.ACT_GEOM_SPHERE}.get(geometry, geometry),
+                        max_covering_cells=max_covering_cells,
+                        max_interior_cells=max_interior_cells,
+                        max_interior_level=max_interior_level)
     h = ctypes.c_void_p()
     _b.check(lib.act_build(_np_ptr(v), _np_ptr(ro), _np_ptr(pro), n_polys, m, float(precision_m),
                            ctypes.byref(opts), ctypes.byref(h)))

@@ -38,7 +38,9 @@ class BuildOpts(ctypes.Structure):
                 ("threads", ctypes.c_int32), ("prefix_level", ctypes.c_int32),
                 ("margin_deg", ctypes.c_double), ("train_points", ctypes.c_void_p),
                 ("n_train", ctypes.c_int64), ("memory_budget", ctypes.c_int64),
-                ("train_max_level", ctypes.c_int32), ("geometry", ctypes.c_int32)]
+                ("train_max_level", ctypes.c_int32), ("geometry", ctypes.c_int32),
+                ("max_covering_cells", ctypes.c_int32), ("max_interior_cells", ctypes.c_int32),
+                ("max_interior_level", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class JoinArgs(ctypes.Structure):

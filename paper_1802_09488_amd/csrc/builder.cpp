@@ -415,6 +415,172 @@ void dfs(Ctx &C, const Work &w, Sink &s) {
   }
 }
 
+// ------------------------------------- coverings with per-polygon cell budgets
+//
+// The paper computes a covering and an interior covering of each polygon
+// with S2's region coverer under cell-count budgets (Section V: at most 128
+// covering cells up to level 30, at most 256 interior cells up to level 20)
+// and merges them into a super covering (Section III-B, flavour iii). Here
+// each polygon's coverings are computed greedily, coarsest cells first:
+//   covering: a cell inside the polygon is final; a boundary cell is
+//   replaced by its children that meet the polygon while the cells kept,
+//   queued and the new children stay within the budget (and the level cap),
+//   else it is final. Every cell that meets the polygon stays covered.
+//   interior covering: cells inside the polygon are kept; boundary cells
+//   are expanded while the budget and the level cap allow, else dropped.
+// Cell status is the conservative classification of the joint subdivision
+// (exact tests on the cell's inflated box), for the one polygon.
+
+struct CoverCell {
+  int face, level;
+  uint32_t i, j;
+  bool interior;  // the cell lies inside the polygon
+};
+
+// Key of a cell (coordinates at its level): face, quadtree path (i above j
+// at each level) and a marker bit, laid out like a cell id.
+static uint64_t code_of(int face, int level, uint32_t i, uint32_t j) {
+  uint64_t key = 0;
+  for (int b = level - 1; b >= 0; b--) key = (key << 2) | (((i >> b) & 1u) << 1) | ((j >> b) & 1u);
+  const int sh = 2 * (kMaxLevel - level);
+  return ((uint64_t)face << 61) | (key << (sh + 1)) | (1ull << sh);
+}
+
+// One polygon's covering (interior = false) or interior covering.
+static void cover_polygon(Ctx &C, int p, bool interior_only, int max_cells, int max_level,
+                          std::vector<CoverCell> &out) {
+  const Prep &P = *C.P;
+  std::vector<Bref> bnd{{p, 0, P.e_off[p + 1] - P.e_off[p]}};
+  std::vector<int32_t> edges;
+  for (int e = P.e_off[p]; e < P.e_off[p + 1]; e++) edges.push_back(e);
+  std::vector<int32_t> none;
+  // the queue, coarsest first (ties: face, i, j), as a binary heap
+  std::vector<Work> pool;
+  auto worse = [&pool](size_t a, size_t b) {
+    const Work &x = pool[a], &y = pool[b];
+    if (x.level != y.level) return x.level > y.level;
+    if (x.face != y.face) return x.face > y.face;
+    return x.i != y.i ? x.i > y.i : x.j > y.j;
+  };
+  std::vector<size_t> heap;
+  auto push = [&](Work &&w) {
+    pool.push_back(std::move(w));
+    heap.push_back(pool.size() - 1);
+    std::push_heap(heap.begin(), heap.end(), worse);
+  };
+  auto met = [&](const Work &w) { return !w.interior.empty() || !w.bnd.empty(); };
+  for (int face = 0; face < 6; face++) {
+    Work w;
+    w.face = face;
+    w.level = 0;
+    w.i = w.j = 0;
+    w.box = inflate(cell_bounds(face, 0, 0, 0), C.bp.margin_deg);
+    classify(C, w.box, none, bnd, edges, w);
+    if (met(w)) push(std::move(w));
+  }
+  int kept = 0;
+  while (!heap.empty()) {
+    std::pop_heap(heap.begin(), heap.end(), worse);
+    const size_t k = heap.back();
+    heap.pop_back();
+    const Work w = std::move(pool[k]);
+    if (w.bnd.empty()) {  // inside the polygon
+      out.push_back({w.face, w.level, w.i, w.j, true});
+      kept++;
+      continue;
+    }
+    Work ch[4];
+    int n_ch = 0;
+    if (w.level < max_level)
+      for (int q = 0; q < 4; q++) {
+        make_child(C, w, q, ch[n_ch]);
+        if (met(ch[n_ch])) n_ch++;
+      }
+    const bool expand = w.level < max_level && kept + (int)heap.size() + n_ch <= max_cells;
+    if (expand) {
+      for (int q = 0; q < n_ch; q++) push(std::move(ch[q]));
+    } else if (!interior_only) {
+      out.push_back({w.face, w.level, w.i, w.j, false});
+      kept++;
+    }
+  }
+}
+
+// The super covering of the polygons' budgeted coverings (flavour iii:
+// no overlap, each cell keeps the references of every covering cell it
+// lies in; a polygon is a true hit where one of its interior cells lies).
+// Overlaps are resolved top-down: a cell with indexed descendants hands its
+// references to its four children. Emits the cells into `sink`.
+static void budget_super_covering(Ctx &C, int nthreads, Sink &sink) {
+  const BuildParams &bp = C.bp;
+  const int np = C.P->n_polys;
+  std::vector<std::vector<CoverCell>> cov(np), inn(np);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int p; (p = next.fetch_add(1)) < np;) {
+      cover_polygon(C, p, false, bp.max_covering_cells, bp.max_level, cov[p]);
+      cover_polygon(C, p, true, bp.max_interior_cells, bp.max_interior_level, inn[p]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; t++) pool.emplace_back(work);
+  work();
+  for (auto &th : pool) th.join();
+  // references of every indexed cell, and the set of proper ancestors
+  std::unordered_map<uint64_t, std::vector<uint32_t>> own;
+  std::unordered_set<uint64_t> above;
+  for (int p = 0; p < np; p++)
+    for (const auto *list : {&cov[p], &inn[p]})
+      for (const CoverCell &c : *list) {
+        own[code_of(c.face, c.level, c.i, c.j)].push_back(((uint32_t)p << 1) | (c.interior ? 1u : 0u));
+        for (int l = c.level - 1; l >= 0; l--)
+          if (!above.insert(code_of(c.face, l, c.i >> (c.level - l), c.j >> (c.level - l))).second)
+            break;  // its ancestors are in already
+      }
+  cov.clear();
+  inn.clear();
+  // top-down: references inherited from covering ancestors
+  struct Frame {
+    int face, level;
+    uint32_t i, j;
+    std::vector<uint32_t> refs;
+  };
+  std::vector<Frame> stack;
+  for (int face = 5; face >= 0; face--) stack.push_back({face, 0, 0, 0, {}});
+  while (!stack.empty()) {
+    Frame f = std::move(stack.back());
+    stack.pop_back();
+    const uint64_t code = code_of(f.face, f.level, f.i, f.j);
+    auto it = own.find(code);
+    if (it != own.end()) f.refs.insert(f.refs.end(), it->second.begin(), it->second.end());
+    if (above.count(code)) {
+      for (int q = 3; q >= 0; q--)
+        stack.push_back({f.face, f.level + 1, (f.i << 1) | (uint32_t)(q >> 1),
+                         (f.j << 1) | (uint32_t)(q & 1), f.refs});
+      continue;
+    }
+    if (f.refs.empty()) continue;
+    // per polygon: a true hit if any of its cells here is interior
+    std::sort(f.refs.begin(), f.refs.end());
+    Work w;
+    w.face = f.face;
+    w.level = f.level;
+    w.i = f.i;
+    w.j = f.j;
+    w.box = inflate(cell_bounds(f.face, f.level, f.i, f.j), bp.margin_deg);
+    for (size_t k = 0; k < f.refs.size();) {
+      const uint32_t poly = f.refs[k] >> 1;
+      bool inside = false;
+      for (; k < f.refs.size() && (f.refs[k] >> 1) == poly; k++) inside |= (f.refs[k] & 1u) != 0;
+      if (inside)
+        w.interior.push_back((int32_t)poly);
+      else
+        w.bnd.push_back({(int32_t)poly, 0, 0});
+    }
+    emit(C, w, sink);
+  }
+}
+
 // ------------------------------------------------------------------- LUT
 
 }  // namespace
@@ -703,6 +869,7 @@ static uint64_t cell_code(int face, int level, uint32_t i, uint32_t j) {
   const int sh = 2 * (kMaxLevel - level);
   return ((uint64_t)face << 61) | (quad_key(i, j) << (sh + 1)) | (1ull << sh);
 }
+
 
 // Lookup-table words a cell needs at most (deduplication can only save):
 // with 32-bit trie entries, a cell with two references (or a reference id
@@ -1276,6 +1443,62 @@ int load_host_index(const char *path, HostIndex &h, void *extra, uint32_t extra_
   return ACT_OK;
 }
 
+// The physical index (Section III-C) from the emitted cells: gathered,
+// sorted, trained (exact mode), laid out as tries and lookup table.
+static int finish_build(Ctx &C, const Prep &P, const BuildParams &bp, std::vector<Sink> &sinks,
+                        HostIndex &out, std::string &err,
+                        std::chrono::steady_clock::time_point t0, int32_t n_polys) {
+  // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
+  // shifted to level 30
+  std::vector<Cell> cells;
+  std::vector<uint32_t> local;  // all sinks' records, embedded in the lookup table below
+  auto gather = [&](const Sink &s) {
+    const uint64_t base = local.size();
+    local.insert(local.end(), s.local.begin(), s.local.end());
+    for (const CellOut &c : s.cells)
+      cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
+                       quad_key(c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level)),
+                       &s.refs[c.ref_off], &s.locs[c.ref_off], base, c.ref_cnt});
+  };
+  for (const Sink &s : sinks) gather(s);
+  if (local.size() >= (1ull << 32)) {
+    err = "cell-local refinement records exceed 2^32 words";
+    return ACT_E_RANGE;
+  }
+  auto by_key = [](const Cell &a, const Cell &b) {
+    return a.face != b.face ? a.face < b.face : a.key < b.key;
+  };
+  std::sort(cells.begin(), cells.end(), by_key);
+  // ------------------------------------------------------------- tries
+  FaceCells fc[6];
+  face_ranges(cells, fc);
+  int lp[6];
+  int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
+  std::deque<std::vector<uint32_t>> trained;  // reference arrays of cells made by training
+  if (bp.mode == ACT_EXACT && bp.n_train > 0) {
+    // training keeps the faces' prefix levels: the trie grows only below them
+    train_index(C, P, cells, local, trained, lp,
+                image_fixed_bytes(n_polys, (int64_t)(P.ex.size() / 4)), out);
+    if (local.size() >= (1ull << 32)) {
+      err = "cell-local refinement records exceed 2^32 words";
+      return ACT_E_RANGE;
+    }
+    std::sort(cells.begin(), cells.end(), by_key);
+    face_ranges(cells, fc);
+    n_nodes = 1;
+    for (int f = 0; f < 6; f++) {
+      int64_t d1;
+      if (fc[f].c1 > fc[f].c0) n_nodes += count_nodes(cells, fc[f], lp[f], d1);
+    }
+  }
+  out.n_cells = (int64_t)cells.size();
+  const int rc = build_tries(cells, fc, lp, n_nodes, local, out, bp, err);
+  if (rc) return rc;
+  out.build_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return ACT_OK;
+}
+
 int build_host_index(const double *verts, const int64_t *ring_off, const int32_t *poly_ring_off,
                      int32_t n_polys, const BuildParams &bp, HostIndex &out, std::string &err) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1414,6 +1637,16 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
   C.bp = bpx;
   int nthreads = bp.threads > 0 ? bp.threads : (int)std::max(1u, std::thread::hardware_concurrency());
 
+  if (bpx.max_covering_cells > 0) {
+    // the paper's coverings with cell budgets, merged (exact mode)
+    std::vector<Sink> one(1);
+    budget_super_covering(C, nthreads, one[0]);
+    if (C.failed) {
+      err = C.err;
+      return C.err_code;
+    }
+    return finish_build(C, P, bpx, one, out, err, t0, n_polys);
+  }
   std::vector<int32_t> all_polys;
   std::vector<Bref> all_bnd;
   std::vector<int32_t> all_edges;
@@ -1428,7 +1661,7 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     w.face = face;
     w.level = 0;
     w.i = w.j = 0;
-    w.box = inflate(cell_bounds(face, 0, 0, 0), bp.margin_deg);
+    w.box = inflate(cell_bounds(face, 0, 0, 0), bpx.margin_deg);
     std::vector<int32_t> none;
     classify(C, w.box, none, all_bnd, all_edges, w);
     frontier.push_back(std::move(w));
@@ -1471,56 +1704,11 @@ int build_host_index(const double *verts, const int64_t *ring_off, const int32_t
     err = C.err;
     return C.err_code;
   }
-  // gather cells; a cell is addressed by its first leaf (I, J) = (i, j)
-  // shifted to level 30
-  std::vector<Cell> cells;
-  std::vector<uint32_t> local;  // all sinks' records, embedded in the lookup table below
-  auto gather = [&](const Sink &s) {
-    const uint64_t base = local.size();
-    local.insert(local.end(), s.local.begin(), s.local.end());
-    for (const CellOut &c : s.cells)
-      cells.push_back({c.face, c.level, c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level),
-                       quad_key(c.i << (kMaxLevel - c.level), c.j << (kMaxLevel - c.level)),
-                       &s.refs[c.ref_off], &s.locs[c.ref_off], base, c.ref_cnt});
-  };
-  gather(top);
-  for (const Sink &s : sinks) gather(s);
-  if (local.size() >= (1ull << 32)) {
-    err = "cell-local refinement records exceed 2^32 words";
-    return ACT_E_RANGE;
-  }
-  auto by_key = [](const Cell &a, const Cell &b) {
-    return a.face != b.face ? a.face < b.face : a.key < b.key;
-  };
-  std::sort(cells.begin(), cells.end(), by_key);
-  // ------------------------------------------------------------- tries
-  FaceCells fc[6];
-  face_ranges(cells, fc);
-  int lp[6];
-  int64_t n_nodes = choose_prefix(cells, fc, bp, lp);
-  std::deque<std::vector<uint32_t>> trained;  // reference arrays of cells made by training
-  if (bp.mode == ACT_EXACT && bp.n_train > 0) {
-    // training keeps the faces' prefix levels: the trie grows only below them
-    train_index(C, P, cells, local, trained, lp,
-                image_fixed_bytes(n_polys, (int64_t)(P.ex.size() / 4)), out);
-    if (local.size() >= (1ull << 32)) {
-      err = "cell-local refinement records exceed 2^32 words";
-      return ACT_E_RANGE;
-    }
-    std::sort(cells.begin(), cells.end(), by_key);
-    face_ranges(cells, fc);
-    n_nodes = 1;
-    for (int f = 0; f < 6; f++) {
-      int64_t d1;
-      if (fc[f].c1 > fc[f].c0) n_nodes += count_nodes(cells, fc[f], lp[f], d1);
-    }
-  }
-  out.n_cells = (int64_t)cells.size();
-  const int rc = build_tries(cells, fc, lp, n_nodes, local, out, bp, err);
-  if (rc) return rc;
-  out.build_seconds =
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return ACT_OK;
+  std::vector<Sink> all;
+  all.reserve(sinks.size() + 1);
+  all.push_back(std::move(top));
+  for (Sink &k : sinks) all.push_back(std::move(k));
+  return finish_build(C, P, bpx, all, out, err, t0, n_polys);
 }
 
 }  // namespace act

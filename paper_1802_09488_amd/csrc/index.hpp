@@ -115,6 +115,12 @@ struct BuildParams {
   // (0 = no limit): a budget check that need not finish the covering
   int64_t cell_limit = 0;
   int32_t geometry = ACT_GEOM_PLANE;
+  // per-polygon coverings with cell budgets (exact mode; 0 = the joint
+  // subdivision): covering cells (up to max_level) and interior cells (up
+  // to max_interior_level)
+  int32_t max_covering_cells = 0;
+  int32_t max_interior_cells = 256;
+  int32_t max_interior_level = 20;
 };
 
 // Device bytes of an index image besides its trie nodes and lookup table

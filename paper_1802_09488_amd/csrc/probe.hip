@@ -2414,6 +2414,10 @@ void act_build_opts_init(act_build_opts *o) {
   o->memory_budget = 0;
   o->train_max_level = 30;
   o->geometry = ACT_GEOM_PLANE;
+  o->max_covering_cells = 0;
+  o->max_interior_cells = 256;
+  o->max_interior_level = 20;
+  o->reserved1 = 0;
 }
 
 // Builds the host index and, for a device, uploads it. ACT_AUTO follows the
@@ -2482,6 +2486,14 @@ int act_build(const double *verts_latlng, const int64_t *ring_off, const int32_t
   bp.memory_budget = o.memory_budget;
   bp.train_max_level = o.train_max_level ? o.train_max_level : 30;
   bp.geometry = o.geometry;
+  bp.max_covering_cells = o.max_covering_cells;
+  bp.max_interior_cells = o.max_interior_cells ? o.max_interior_cells : 256;
+  bp.max_interior_level = o.max_interior_level ? o.max_interior_level : 20;
+  if (bp.max_covering_cells < 0 || bp.max_interior_cells < 0 || bp.max_interior_level < 1 ||
+      bp.max_interior_level > kMaxLevel)
+    return fail(ACT_E_ARG, "covering budgets out of range");
+  if (bp.max_covering_cells > 0 && mode != ACT_EXACT)
+    return fail(ACT_E_ARG, "covering budgets apply to exact mode");
   if (bp.geometry != ACT_GEOM_PLANE && bp.geometry != ACT_GEOM_SPHERE)
     return fail(ACT_E_ARG, "geometry must be ACT_GEOM_PLANE or ACT_GEOM_SPHERE");
   if (bp.geometry == ACT_GEOM_SPHERE && mode != ACT_EXACT)

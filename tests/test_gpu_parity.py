@@ -1021,3 +1021,23 @@ def test_saved_and_auto_indexes(act, tmp_path):
     assert small.mode == act.ACT_EXACT and small.stats()["device_bytes"] <= approx - 1
     out, pairs, _ = gpu_join(small, pts)
     assert_exact(P, pts, out, pairs, "c2-auto-exact")
+
+
+@pytest.mark.parametrize("w,n_train", [("c1", 0), ("c2", 0), ("c2", 1_000_000)])
+def test_budgeted_covering_exact(act, w, n_train):
+    """The paper's covering configuration (per-polygon coverings of at most
+    128 cells up to level 30 and 256 interior cells up to level 20, merged),
+    untrained and trained: bit-exact against the oracle in every refinement
+    mode, pairs included."""
+    P = synth.workload_polygons(w)
+    kw = {"train_points": synth.training_points(w, n_train)} if n_train else {}
+    idx = act.build(P, "exact", max_level=30, max_covering_cells=128, **kw)
+    st = idx.stats()
+    assert st["max_cell_level"] > 20
+    rng = np.random.default_rng(95)
+    pts = np.concatenate([synth.workload_points(w, 0, 200_000), edge_case_points(P, rng),
+                          _cell_corner_points(P, rng, 30_000,
+                                              np.arange(8, st["max_cell_level"] + 1))])
+    for mode in REFINE_MODES:
+        out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+        assert_exact(P, pts, out, pairs, "%s-budget-%d-%s" % (w, n_train, mode))

@@ -494,3 +494,30 @@ def test_sphere_index_structure(act, tmp_path):
     idx.save(path)
     got = act.load(path, device=-1)
     assert got.digest() == idx.digest() and got.stats()["geometry"] == 1
+
+
+def test_budgeted_coverings(act):
+    """Per-polygon coverings with the paper's cell budgets (128 covering
+    cells up to level 30, 256 interior cells up to level 20), merged without
+    overlap: the index is conservative against the oracle (every covering
+    polygon referenced, every true hit true), far smaller than the joint
+    subdivision, and training with points of the workload's distribution
+    makes more points solely true hits (the Table IV effect)."""
+    P = synth.workload_polygons("c2")
+    idx = act.build(P, "exact", device=-1, max_level=30, max_covering_cells=128)
+    st = idx.stats()
+    joint = act.build(P, "exact", device=-1).stats()
+    assert st["n_cells"] < joint["n_cells"] / 4 and st["n_nodes"] < joint["n_nodes"] / 4
+    rng = np.random.default_rng(31)
+    v = P.verts[rng.choice(len(P.verts), 2000, replace=False)]
+    pts = np.concatenate([synth.workload_points("c2", 0, 20000), v,
+                          v + rng.integers(-1, 2, v.shape) * np.spacing(v)])
+    _structural_check(act, P, idx, pts)
+    trained = act.build(P, "exact", device=-1, max_level=30, max_covering_cells=128,
+                        train_points=synth.training_points("c2", 300_000))
+    assert trained.stats()["train_splits"] > 1000
+    _structural_check(act, P, trained, pts[:5000])
+    fresh = synth.workload_points("c2", 50_000, 70_000)
+    assert _cand_fraction(trained, fresh) < 0.7 * _cand_fraction(idx, fresh)
+    with pytest.raises(act.ActError):
+        act.build(P, "approx", 4.0, device=-1, max_covering_cells=128)
