@@ -294,6 +294,34 @@ def cpu_baseline_and_parity(P, workload, n_sample, gpu_out, gpu_pairs=None, gpu_
     return base, parity
 
 
+def paper_config_leg(act, P, workload, pts, out, steps, n_train=1_000_000):
+    """The paper's covering configuration (Section V: per-polygon coverings of
+    at most 128 cells up to level 30 and 256 interior cells up to level 20,
+    merged), untrained and trained with n_train points of the workload's
+    distribution (Section III-D): exact-join time on the resident points and
+    the index metrics of the paper's Tables III and IV (tree nodes, false
+    hits, solely true hits, candidates per refined point)."""
+    import numpy as np
+    import synth
+    n = pts.shape[0]
+    res = {"covering": "max covering cells 128, max level 30, max interior cells 256, "
+                       "max interior level 20", "n_train": n_train}
+    for name, tp in (("untrained", None), ("trained", synth.training_points(workload, n_train))):
+        t0 = time.perf_counter()
+        ix = act.build(P, "exact", max_level=30, max_covering_cells=128, train_points=tp)
+        tb = time.perf_counter() - t0
+        ix.reserve(n)
+        wall, tot, _ = time_joins(ix, pts, out, steps, 1)
+        _, _, ctr = ix.join_ex(pts, out, counters=True)
+        st = ix.stats()
+        res[name] = dict(_index_metrics(ctr), tree_nodes=st["n_nodes"], cells=st["n_cells"],
+                         image_bytes=st["image_bytes"], train_splits=st["train_splits"],
+                         build_s=tb, join_ms_mean=float(np.mean(tot)),
+                         points_per_s=n * steps / wall)
+        del ix
+    return res
+
+
 def precomputed_ids_leg(act, indexes, pts, steps, exact_out):
     """Joins of points that arrive with their level-30 cell ids (the paper's
     probe input): the ids are computed once (act_cell_ids, timed too), then
@@ -521,6 +549,8 @@ def run_c2(args, emit=True):
                                                                              exact_out))}
     log("pair output and per-polygon counts")
     pc, pc_keep = pairs_and_counts_leg(act, [("exact", idx), ("approx4m", idx_a)], pts, k)
+    log("the paper's covering configuration, untrained and trained")
+    paper_cfg = paper_config_leg(act, P, "c2", pts, out, k)
     log("joins of precomputed cell ids")
     ids_leg = precomputed_ids_leg(act, [("exact", idx), ("approx4m", idx_a)], pts, k, exact_out)
     log("batched join (graph replay)")
@@ -582,6 +612,7 @@ def run_c2(args, emit=True):
                      "traffic": traffic["approx"] if traffic and "approx" in traffic else None},
         "refine_variants": var,
         "pairs_and_counts": pc,
+        "paper_configuration": paper_cfg,
         "precomputed_ids": ids_leg,
         "counters_exact": ctr,
         "counters_approx4m": ctr_a,
