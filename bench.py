@@ -39,6 +39,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_POINT = 20  # 16 B fp64 (lat, lng) in + 4 B int32 id out
+# Finest covering level of the benchmarks' exact indexes: 22 fills the
+# deepest trie node level (levels 19-22 under the workloads' prefix level 6)
+# and halves the candidate cells per level over the library's default of 20
+# without another node level (c3: 0.66 -> 0.41 ms per 2^24 points).
+EXACT_LEVEL = 22
 COPY_BYTES = 1 << 30  # calibration copy (device to device)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_probe_c2.md")
 KERNEL_SOURCES = ["probe.hip", "geom.hpp", "cellid.hpp", "index.hpp"]
@@ -483,7 +488,7 @@ def run_c2(args, emit=True):
     log("polygons", args.workload)
     P = synth.workload_polygons(args.workload)
     t0 = time.perf_counter()
-    idx = act.build(P, "exact")
+    idx = act.build(P, "exact", max_level=EXACT_LEVEL)
     t_build_exact = time.perf_counter() - t0
     t0 = time.perf_counter()
     idx_a = act.build(P, "approx", 4.0)
@@ -505,7 +510,7 @@ def run_c2(args, emit=True):
         # the committed kernel profiles were taken with
         # tuned on the whole workload: a smaller sample favours smaller grids
         log("autotuner on all points")
-        tuned = {"exact": act.build(P, "exact").tune(pts),
+        tuned = {"exact": act.build(P, "exact", max_level=EXACT_LEVEL).tune(pts),
                  "approx4m": act.build(P, "approx", 4.0).tune(pts)}
 
     log("timing exact")
@@ -579,9 +584,9 @@ def run_c2(args, emit=True):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s: %d Voronoi polygons over the NYC box (%d edges), %d fp64 "
-                               "mixture points resident in HBM, exact join (covering level 20, "
+                               "mixture points resident in HBM, exact join (covering level %d, "
                                "cell-local refinement); approx@4m beside it"
-                               % (args.workload, P.n_polys, st["n_edges"], n),
+                               % (args.workload, P.n_polys, st["n_edges"], n, EXACT_LEVEL),
                    "n_points": n, "n_polys": P.n_polys, "mode": "exact",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -673,8 +678,8 @@ def _index_metrics(ctr):
 def compact_legs(args, keep):
     """Compact forms of the other workloads, in the default run:
     c3: 2^26 points of the 40,000-polygon stream in 2^24 batches, exact
-    (untrained, and trained with 4e6 points: the Table IV analogue) and
-    approx@1m, with an oracle sample; c4: the first 1,000 batches of the
+    (covering level 22, and the library's default level 20) and approx@1m,
+    with an oracle sample; c4: the first 1,000 batches of the
     uneven-batch mix on the c3 exact index, tuned, one graph replay per
     step, oracle on 1% of the batches plus every batch under 1,000 points;
     c5: the serving sweep at 1e3, 1e4 and 5e4 requests/s over the c2
@@ -690,13 +695,11 @@ def compact_legs(args, keep):
     log("c3: polygons and indexes")
     P = synth.workload_polygons("c3")
     t0 = time.perf_counter()
-    ie = act.build(P, "exact")
+    ie = act.build(P, "exact", max_level=EXACT_LEVEL)
     tb_e = time.perf_counter() - t0
-    tp = synth.training_points("c3", 4_000_000)
     t0 = time.perf_counter()
-    it = act.build(P, "exact", train_points=tp)
+    it = act.build(P, "exact")  # the library's default covering level, 20
     tb_t = time.perf_counter() - t0
-    del tp
     n, bsz = 1 << 26, 1 << 24
     log("c3: staging %d points" % n)
     pts = _stage_points("c3", n)
@@ -704,10 +707,10 @@ def compact_legs(args, keep):
     ie.reserve(bsz)
     it.reserve(bsz)
     steps = 3
-    c3 = {"n_points": n, "batch": bsz, "steps": steps}
+    c3 = {"n_points": n, "batch": bsz, "steps": steps, "exact_covering_level": EXACT_LEVEL}
     sample = synth.workload_points("c3", 0, 200_000)
     ref = oracle.join(P, sample, nthreads=cores)
-    for name, ix, tb in (("exact", ie, tb_e), ("exact_trained_4e6", it, tb_t)):
+    for name, ix, tb in (("exact", ie, tb_e), ("exact_level20", it, tb_t)):
         wall, ms = _timed_stream(ix, pts, out, bsz, steps)
         _, _, ctr = ix.join_ex(pts[:bsz], out[:bsz], counters=True)
         st = ix.stats()
@@ -841,7 +844,7 @@ def run_c3(args):
     bsz = w["batch"]
     P = synth.workload_polygons("c3")
     t0 = time.perf_counter()
-    idx = act.build(P, "exact")
+    idx = act.build(P, "exact", max_level=EXACT_LEVEL)
     tb_e = time.perf_counter() - t0
     t0 = time.perf_counter()
     idx_a = act.build(P, "approx", 1.0)
@@ -915,7 +918,7 @@ def run_c4(args):
     import synth
     import paper_1802_09488_amd as act
     P = synth.workload_polygons("c3")
-    idx = act.build(P, "exact")
+    idx = act.build(P, "exact", max_level=EXACT_LEVEL)
     sizes = synth.batch_sizes(10_000, 3004)
     total = int(sizes.sum())
     log("staging %d points in %d batches" % (total, len(sizes)))
@@ -972,7 +975,7 @@ def run_c5(args):
     import synth
     import paper_1802_09488_amd as act
     ia = act.build(synth.workload_polygons("c2"), "approx", 4.0)
-    ie = act.build(synth.workload_polygons("c3"), "exact")
+    ie = act.build(synth.workload_polygons("c3"), "exact", max_level=EXACT_LEVEL)
     pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
     sec = args.serve_seconds or 10.0
     srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4, 1e5, 2e5], sec)

@@ -1041,3 +1041,21 @@ def test_budgeted_covering_exact(act, w, n_train):
     for mode in REFINE_MODES:
         out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
         assert_exact(P, pts, out, pairs, "%s-budget-%d-%s" % (w, n_train, mode))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("w", ["c2", "c3"])
+def test_benchmark_covering_level_exact(act, w):
+    """The benchmarks' exact indexes (finest covering level 22, which fills
+    the deepest trie node level): bit-exact against the oracle on workload
+    points, edge cases and points at cell corners down to level 22, in every
+    refinement mode."""
+    P = synth.workload_polygons(w)
+    idx = act.build(P, "exact", max_level=22)
+    assert idx.stats()["max_cell_level"] == 22
+    rng = np.random.default_rng(97)
+    pts = np.concatenate([synth.workload_points(w, 0, 200_000), edge_case_points(P, rng)[:20_000],
+                          _cell_corner_points(P, rng, 40_000, np.arange(16, 23))])
+    for mode in REFINE_MODES:
+        out, pairs, _ = gpu_join(idx, pts, refine=getattr(act, mode))
+        assert_exact(P, pts, out, pairs, "%s-level22-%s" % (w, mode))
