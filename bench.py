@@ -53,11 +53,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+HOST_SIDE_MARKER = b"// ============================================== host side"
+
+
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the device code: probe.hip up to its
+    host-side marker (kernels and device functions; the launches and the C
+    ABI after it do not change what a kernel does) and the headers the
+    kernels include."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1802_09488_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+            b = fh.read()
+        if f == "probe.hip":
+            k = b.find(HOST_SIDE_MARKER)
+            if k < 0:
+                raise SystemExit("probe.hip has no host-side marker")
+            b = b[:k]
+        h.update(b)
     return h.hexdigest()[:16]
 
 

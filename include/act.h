@@ -232,6 +232,17 @@ int act_join_pairs(const act_index *idx, const double *d_points, int64_t n,
                    int64_t capacity, int64_t *d_n_pairs, void *stream);
 
 /*
+ * act_join_status -- the overflow check of a pair join: waits for `stream`,
+ * reads the device pair counter `d_n_pairs` that act_join_pairs (or
+ * act_join_ex with pair output) added to, and returns ACT_OK when every
+ * pair was stored (counter <= capacity) or ACT_E_OVERFLOW when pairs were
+ * dropped (rerun with a capacity of at least the counter). `n_pairs`
+ * (optional, host) receives the counter. Errors: ACT_E_ARG, ACT_E_HIP.
+ */
+int act_join_status(const int64_t *d_n_pairs, int64_t capacity, void *stream,
+                    int64_t *n_pairs);
+
+/*
  * act_join_ids -- act_join for points that arrive with their level-30 cell
  * ids, as the points of the paper's probe do (Listing 3: each point carries
  * its cell id; the projection is not part of the probe there).
@@ -305,10 +316,23 @@ int act_join_noalloc(const act_index *idx, const double *d_points, int64_t n,
  * points (no allocation). Call this beforehand to size it for `points`
  * points per pass, e.g. before capturing joins into a HIP graph, where
  * allocation is not allowed; enlarging an existing workspace synchronises
- * the stream first. No-op for approximate-mode indexes. Workspaces live
- * until act_free. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_OOM, ACT_E_HIP.
+ * the stream first. No-op for approximate-mode indexes. Workspaces are
+ * keyed by the stream handle and live until act_workspace_release or
+ * act_free. Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_OOM, ACT_E_HIP.
  */
 int act_workspace_reserve(const act_index *idx, void *stream, int64_t points);
+
+/*
+ * act_workspace_release -- free the workspaces (pending mask and lists,
+ * batched-join buffers) that joins on `stream` hold in this index, after
+ * waiting for the work queued on the stream. Call it before destroying a
+ * stream that ran joins: an index used from many short-lived streams
+ * otherwise keeps one workspace per stream handle until act_free. A stream
+ * without a workspace is a no-op; a later join on the stream allocates
+ * again. Not allowed while the stream is being captured (ACT_E_RANGE).
+ * Errors: ACT_E_ARG, ACT_E_DEVICE, ACT_E_RANGE, ACT_E_HIP.
+ */
+int act_workspace_release(const act_index *idx, void *stream);
 
 /* Join counters (uint64 each), accumulated by act_join_ex when asked. */
 enum {

@@ -182,12 +182,15 @@ class Index:
         _b.check(lib.act_join_ex(self._h, ctypes.byref(a), _stream_ptr(stream)))
         pairs = None
         if capacity is not None:
-            m = int(cnt.item())
-            if m > capacity:
-                err = ActError(_b.ACT_E_OVERFLOW, "%d pairs exceed capacity %d" % (m, capacity))
-                err.needed = m
+            m = ctypes.c_int64()
+            rc = lib.act_join_status(ctypes.c_void_p(cnt.data_ptr()), int(capacity),
+                                     _stream_ptr(stream), ctypes.byref(m))
+            if rc == _b.ACT_E_OVERFLOW:
+                err = ActError(rc, lib.act_last_error().decode())
+                err.needed = m.value
                 raise err
-            pairs = torch.stack([pp[:m], pq[:m].to(torch.int64)], 1)
+            _b.check(rc)
+            pairs = torch.stack([pp[:m.value], pq[:m.value].to(torch.int64)], 1)
         cdict = None
         if counters:
             c = ctr.cpu().numpy()
@@ -197,6 +200,11 @@ class Index:
     def reserve(self, points, stream=None):
         """Size the stream's exact-mode workspace for `points` points per pass."""
         _b.check(lib.act_workspace_reserve(self._h, _stream_ptr(stream), int(points)))
+
+    def release(self, stream=None):
+        """Free the workspaces joins on `stream` hold in this index (call
+        before dropping a stream that ran joins)."""
+        _b.check(lib.act_workspace_release(self._h, _stream_ptr(stream)))
 
     def join_batched(self, descriptors, total_points, ticks=None, stream=None):
         """Join many batches at once. `descriptors`: CUDA int64 tensor (nb, 3)

@@ -120,6 +120,8 @@ def _load():
         "act_join_ids": ([p, p, p, i64, p, p], ctypes.c_int),
         "act_join_ex": ([p, p, p], ctypes.c_int),
         "act_workspace_reserve": ([p, p, i64], ctypes.c_int),
+        "act_workspace_release": ([p, p], ctypes.c_int),
+        "act_join_status": ([p, i64, p, p], ctypes.c_int),
         "act_cell_ids": ([p, i64, p, p], ctypes.c_int),
         "act_index_stats": ([p, p], ctypes.c_int),
         "act_lookup_host": ([p, p, p, p, i64, p], ctypes.c_int),

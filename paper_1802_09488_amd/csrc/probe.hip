@@ -1679,6 +1679,8 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
   }
 }
 
+// ============================================== host side: launches and the C ABI
+
 using ProbeFn = void (*)(ProbeParams);
 template <int MODE, int LDS, int FULL>
 static ProbeFn probe_np(int np) {
@@ -2600,6 +2602,37 @@ int act_workspace_reserve(const act_index *x, void *stream, int64_t points) {
   DeviceGuard g(x->device);
   Workspace *w = nullptr;
   return get_workspace(x, stream, std::max<int64_t>(points, 64), true, w);
+}
+
+int act_workspace_release(const act_index *x, void *stream) {
+  if (!x) return fail(ACT_E_ARG, "index is NULL");
+  if (x->device < 0) return fail(ACT_E_DEVICE, "index was built without a device");
+  int rc = check_stream_device(x, stream);
+  if (rc) return rc;
+  DeviceGuard g(x->device);
+  std::lock_guard<std::mutex> lk(x->ws_mu);
+  auto it = x->ws.find(stream);
+  if (it == x->ws.end()) return ACT_OK;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
+      cs != hipStreamCaptureStatusNone)
+    return fail(ACT_E_RANGE, "cannot release a workspace while its stream is being captured");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  free_workspace(it->second);
+  x->ws.erase(it);
+  return ACT_OK;
+}
+
+int act_join_status(const int64_t *d_n_pairs, int64_t capacity, void *stream, int64_t *n_pairs) {
+  if (!d_n_pairs || capacity < 0) return fail(ACT_E_ARG, "bad argument");
+  int64_t m = 0;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(&m, d_n_pairs, sizeof m, hipMemcpyDeviceToHost));
+  if (n_pairs) *n_pairs = m;
+  if (m > capacity)
+    return fail(ACT_E_OVERFLOW, std::to_string(m) + " pairs exceed the capacity of " +
+                                    std::to_string(capacity));
+  return ACT_OK;
 }
 
 int act_join_ex(const act_index *x, const act_join_args *args, void *stream) {

@@ -546,6 +546,9 @@ void act_server_destroy(act_server *s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto &kv : s->all) delete kv.second;
+  // the indexes outlive the server: drop the workspaces its streams hold
+  for (hipStream_t st : s->streams)
+    for (const act_index *x : s->indexes) (void)act_workspace_release(x, st);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : s->events) (void)hipEventDestroy(ev);
   if (s->dev_base) (void)hipFree(s->dev_base);
