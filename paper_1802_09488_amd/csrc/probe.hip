@@ -145,6 +145,7 @@ struct ProbeParams {
   int64_t *n_pairs;
   unsigned long long *counters;
   const uint32_t *nodes;  // trie entries (32-bit: all fit, see the builder)
+  uint32_t node_bytes32;  // the entries' bytes when below 2^32, else 0
   const uint32_t *lut;
   const int32_t *eoff;
   const double2 *origin;
@@ -202,9 +203,15 @@ constexpr int kProbeWaves = kProbeBlock / 64;
 // degree. (cos b, sin b) come from a 361-entry table (b = -180 .. 180,
 // computed on the host with the C library), and sin d, cos d (d = u pi/180)
 // from short Taylor series in u, the degree-to-radian factor folded into
-// the coefficients: the first omitted terms are below 8e-19 and 7e-16. The
-// sum formulas then give sin x and cos x to a few units of 1e-16, with no
-// quadrant logic. x - b is exact (Sterbenz's lemma, or b = 0).
+// the coefficients: cos d to the d^4 term (the first omitted term is below
+// 7e-16), no quadrant logic. The join's sine stops at the d^3 term (the
+// first omitted term is below 4.2e-13): it is the sine of an angle within
+// 4.2e-13 radians (2.5e-11 degrees) of d, so the probe projects a point
+// within 2.5e-11 degrees of the input in latitude and in longitude, which
+// the 1e-9 degree margin of the cell classification covers 40 times, at any
+// latitude. Cell ids (act_cell_ids) take the d^5 term too (first omitted
+// term below 8e-19), so that they match the leaf cell of the point to
+// within rounding. x - b is exact (Sterbenz's lemma, or b = 0).
 constexpr int kTrigEntries = 361;
 constexpr double kRad = 0.017453292519943295;  // pi / 180
 constexpr double kSin3 = -kRad * kRad * kRad / 6.0;
@@ -212,12 +219,13 @@ constexpr double kSin5 = kRad * kRad * kRad * kRad * kRad / 120.0;
 constexpr double kCos2 = -kRad * kRad / 2.0;
 constexpr double kCos4 = kRad * kRad * kRad * kRad / 24.0;
 
+template <bool LEAF_EXACT = false>
 __device__ __forceinline__ void sincos_deg(const double2 *trig, double x, double &s, double &c) {
   const double b = rint(x);
   const double2 t = trig[(int)b + 180];  // (cos b, sin b)
   const double u = x - b;
   const double u2 = u * u;
-  const double sd = u * fma(u2, fma(u2, kSin5, kSin3), kRad);
+  const double sd = u * (LEAF_EXACT ? fma(u2, fma(u2, kSin5, kSin3), kRad) : fma(u2, kSin3, kRad));
   const double cd = fma(u2, fma(u2, kCos4, kCos2), 1.0);
   s = fma(t.y, cd, t.x * sd);
   c = fma(t.x, cd, -(t.y * sd));
@@ -245,12 +253,13 @@ __device__ __forceinline__ uint32_t leaf_coord(double c, double r29) {
 // The face is the axis of the largest |coordinate| (ties go to the lower
 // axis: x before y before z) and its sign; (u, v) are the two other
 // coordinates in cyclic axis order divided by that magnitude.
+template <bool LEAF_EXACT = false>
 __device__ __forceinline__ bool project(const double2 *trig, double lat, double lng,
                                         uint32_t &face, uint32_t &i, uint32_t &j) {
   if (!(fabs(lat) <= 90.0 && fabs(lng) <= 180.0)) return false;
   double sp, cp, sl, cl;
-  sincos_deg(trig, lat, sp, cp);
-  sincos_deg(trig, lng, sl, cl);
+  sincos_deg<LEAF_EXACT>(trig, lat, sp, cp);
+  sincos_deg<LEAF_EXACT>(trig, lng, sl, cl);
   const double x = cp * cl, y = cp * sl, z = sp;
   const bool xmaj = fabs(x) >= fabs(y);
   const double mxy = fmax(fabs(x), fabs(y));
@@ -361,12 +370,14 @@ __device__ __forceinline__ int edge_fp64(const ProbeParams &P, int e, double px,
   return edge_test_exact(A.x, A.y, B.x, B.y, px, py);
 }
 
-// Unit vector of (lat, lng) degrees (the projection's sin and cos).
+// Unit vector of (lat, lng) degrees, with the full sine series: the
+// refinement's sign tests need the point itself, not one within the cell
+// margin.
 __device__ __forceinline__ void unit_vector(const double2 *trig, double lat, double lng,
                                             double (&q)[3]) {
   double sp, cp, sl, cl;
-  sincos_deg(trig, lat, sp, cp);
-  sincos_deg(trig, lng, sl, cl);
+  sincos_deg<true>(trig, lat, sp, cp);
+  sincos_deg<true>(trig, lng, sl, cl);
   q[0] = cp * cl;
   q[1] = cp * sl;
   q[2] = sp;
@@ -512,64 +523,121 @@ constexpr uint32_t kMaxOutLut = 0x7ffffffcu;  // largest offset -3 - off can car
 
 __device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == kTagPtr && e != 0; }
 
+// Streaming accesses: each point is read once and each output written once,
+// so they bypass the caches' retention (nontemporal), leaving L2 to the
+// trie nodes that every point's descent revisits. A tile's points and
+// outputs are accessed through a buffer resource spanning exactly the
+// tile's points (base and size are wave-uniform): the hardware's range
+// check turns the accesses of lanes past the tile's end into reads of zero
+// and dropped stores, so every lane issues them without any address
+// clamping or masking, and the compiler's waits for the loads in flight
+// stay exact. (Raw buffer, stride 0; the third descriptor word is the
+// 32-bit data format the gfx9 family expects; aux 2 = nontemporal.)
+constexpr int kBufferFlags = 0x00020000;
+constexpr int kBufferNT = 2;
+constexpr int kBufferOutOfRange = 0x40000000;  // beyond every buffer made here
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_buffer(const void *base, int32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufferFlags);
+}
+
+typedef int act_int4_v __attribute__((ext_vector_type(4)));
+typedef int act_int2_v __attribute__((ext_vector_type(2)));
+
 // Steps 5-6 for NP points of a lane at once, split into the parts of the
 // probe's pipeline: the prefix check and the LDS-staged levels
 // (descend_lds), one global node level (issue_level / take_level) and the
 // remaining global levels (descend_rest). The descents run side by side,
-// so each step issues up to NP independent loads. Written without branches:
-// a lane whose descent has ended keeps its entry and reads a harmless slot
-// (LDS word 0, or node 0, which the builder reserves), so the wave never
-// splits. Pointer entries hold node indices below 2^30, so their high
-// halves are zero and the tag tests use the low half only.
+// so each step issues up to NP independent loads.
+//
+// Node level d below a face's prefix (d = 0 .. 7; the builder keeps every
+// trie within 8 levels of its prefix) is keyed by the d-th nibbles of i and
+// j under the prefix. Those key bytes are gathered once per point into two
+// words: with a, b = i, j shifted so that their first nibble under the
+// prefix is the top one, `ev` holds the bytes of the even levels (level
+// 2k in byte 3 - k) and `od` those of the odd ones, so a level's key is one
+// bit-field extract at an offset known at compile time. All lanes of a wave
+// walk the levels in step, so the level index is uniform.
+//
+// Written without branches: a lane whose descent has ended keeps its entry
+// and its last node, which it keeps reading harmlessly (a lane that never
+// started reads node 1, the first LDS-staged node, or node 0, which the
+// builder reserves), so the wave never splits. Device entries are 32-bit;
+// a node is carried as its pointer entry (index << 2), so its byte offset
+// is the entry << 8.
 template <int NP>
 struct Descent {
-  uint32_t ci[NP], cj[NP], node[NP];
-  int sh[NP];
+  uint32_t ev[NP], od[NP];
+  uint32_t node[NP];
+  uint32_t e[NP];
   bool act[NP];
-  uint64_t e[NP];
 };
+
+template <int D>
+__device__ __forceinline__ uint32_t level_key(uint32_t ev, uint32_t od) {
+  return ((D & 1 ? od : ev) >> (24 - 8 * (D >> 1))) & 255u;
+}
+
+// One level's entry v of a lane: record it while the descent is live, and
+// follow it if it is a child pointer (tag 00, nonzero).
+template <int NP>
+__device__ __forceinline__ void step_level(Descent<NP> &D, int p, uint32_t v, uint32_t &reads) {
+  reads += D.act[p];
+  D.e[p] = D.act[p] ? v : D.e[p];
+  const bool ptr = D.act[p] & ((v & 3u) == 0u) & (v != 0u);
+  D.node[p] = ptr ? v : D.node[p];
+  D.act[p] = ptr;
+}
 
 template <int LDS_DEPTH, int NP>
 __device__ __forceinline__ void descend_lds(const uint32_t *s_nodes, const FaceDev *s_face,
-                                            const uint32_t (&face)[NP], const bool (&valid)[NP],
+                                            const uint32_t (&face)[NP], const uint32_t (&ci)[NP],
+                                            const uint32_t (&cj)[NP], const bool (&valid)[NP],
                                             Descent<NP> &D, uint32_t &reads) {
-  uint32_t lo[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     const FaceDev F = s_face[face[p]];
-    D.sh[p] = F.sh0;
-    D.node[p] = (uint32_t)F.root;
-    D.act[p] = valid[p] & (F.root >= 0) & ((D.ci[p] >> F.sh0) == F.pi) &
-               ((D.cj[p] >> F.sh0) == F.pj);
-    lo[p] = 0;
+    D.act[p] = valid[p] & (F.root >= 0) & ((ci[p] >> F.sh0) == F.pi) &
+               ((cj[p] >> F.sh0) == F.pj);
+    // i, j << (32 - sh0): the bits under the prefix at the top (0 when the
+    // prefix is the leaf level: such a root's entries are all one cell)
+    const uint32_t a = __builtin_amdgcn_alignbit(ci[p], 0u, (uint32_t)F.sh0);
+    const uint32_t b = __builtin_amdgcn_alignbit(cj[p], 0u, (uint32_t)F.sh0);
+    D.ev[p] = (a & 0xf0f0f0f0u) | ((b >> 4) & 0x0f0f0f0fu);
+    D.od[p] = ((a << 4) & 0xf0f0f0f0u) | (b & 0x0f0f0f0fu);
+    D.node[p] = D.act[p] ? (uint32_t)F.root << 2 : (LDS_DEPTH > 0 ? 1u << 2 : 0u);
+    D.e[p] = 0u;
   }
+  // s_nodes holds nodes 1 .. n_lds_nodes, which include every node of the
+  // LDS-staged levels
+  const uint32_t *s_base = s_nodes - 256;
 #pragma unroll
   for (int d = 0; d < LDS_DEPTH; d++) {
 #pragma unroll
     for (int p = 0; p < NP; p++) {
-      D.sh[p] -= 4;
-      const uint32_t k =
-          D.act[p] ? ((D.node[p] - 1u) << 8) | node_slot(D.ci[p], D.cj[p], D.sh[p]) : 0u;
-      const uint32_t v = s_nodes[k];
-      reads += D.act[p];
-      lo[p] = D.act[p] ? v : lo[p];
-      D.act[p] = D.act[p] & ((v & 3u) == 0u) & (v != 0u);
-      D.node[p] = v >> 2;
+      const uint32_t key = d == 0 ? level_key<0>(D.ev[p], D.od[p]) : level_key<1>(D.ev[p], D.od[p]);
+      step_level<NP>(D, p, s_base[(D.node[p] << 6) | key], reads);
     }
   }
-#pragma unroll
-  for (int p = 0; p < NP; p++) D.e[p] = lo[p];
 }
 
-template <int NP>
-__device__ __forceinline__ void issue_level(const ProbeParams &P, Descent<NP> &D,
+// Global node level D_: a buffer over the trie's entries (32-bit offsets)
+// when they span under 4 GiB, else 64-bit addresses. (The flag is uniform,
+// and both paths issue the same loads, so the waits stay exact.)
+template <int NP, int D_>
+__device__ __forceinline__ void issue_level(const ProbeParams &P, const Descent<NP> &D,
                                             uint32_t (&x)[NP]) {
+  if (P.node_bytes32) {
+    const __amdgpu_buffer_rsrc_t nb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t *>(P.nodes), (short)0, (int)P.node_bytes32, kBufferFlags);
 #pragma unroll
-  for (int p = 0; p < NP; p++) {
-    D.sh[p] -= 4;
-    const uint64_t k =
-        D.act[p] ? ((uint64_t)D.node[p] << 8) | node_slot(D.ci[p], D.cj[p], D.sh[p]) : 0u;
-    x[p] = P.nodes[k];
+    for (int p = 0; p < NP; p++)
+      x[p] = __builtin_amdgcn_raw_buffer_load_b32(
+          nb, (int)((D.node[p] << 8) | (level_key<D_>(D.ev[p], D.od[p]) << 2)), 0, 0);
+  } else {
+#pragma unroll
+    for (int p = 0; p < NP; p++)
+      x[p] = P.nodes[((uint64_t)D.node[p] << 6) | level_key<D_>(D.ev[p], D.od[p])];
   }
 }
 
@@ -577,41 +645,23 @@ template <int NP>
 __device__ __forceinline__ void take_level(Descent<NP> &D, const uint32_t (&x)[NP],
                                            uint32_t &reads) {
 #pragma unroll
-  for (int p = 0; p < NP; p++) {
-    const uint32_t v = (uint32_t)x[p];
-    reads += D.act[p];
-    D.e[p] = D.act[p] ? x[p] : D.e[p];
-    D.act[p] = D.act[p] & ((v & 3u) == 0u) & (v != 0u);
-    D.node[p] = v >> 2;
-  }
+  for (int p = 0; p < NP; p++) step_level<NP>(D, p, x[p], reads);
 }
 
-template <int NP>
+// Levels D_ .. 7, while any of the lane's descents is live.
+template <int NP, int D_>
 __device__ __forceinline__ void descend_rest(const ProbeParams &P, Descent<NP> &D,
                                              uint32_t &reads) {
-  for (;;) {
+  if constexpr (D_ < 8) {
     bool any = false;
 #pragma unroll
     for (int p = 0; p < NP; p++) any |= D.act[p];
-    if (!any) break;
+    if (!any) return;
     uint32_t x[NP];
-    issue_level<NP>(P, D, x);
+    issue_level<NP, D_>(P, D, x);
     take_level<NP>(D, x, reads);
+    descend_rest<NP, D_ + 1>(P, D, reads);
   }
-}
-
-// Streaming accesses: each point is read once and each output written once,
-// so they bypass the caches' retention (nontemporal), leaving L2 to the
-// trie nodes that every point's descent revisits.
-typedef double act_double2_v __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ double2 load_point(const double2 *p) {
-  const act_double2_v v = __builtin_nontemporal_load((const act_double2_v *)p);
-  return make_double2(v.x, v.y);
-}
-
-__device__ __forceinline__ void store_out(int32_t *p, int32_t v) {
-  __builtin_nontemporal_store(v, p);
 }
 
 // Where a tile's points live: its first point, its output, how many of
@@ -1094,12 +1144,13 @@ __device__ __forceinline__ void drain_queue(const ProbeParams &P, PendingQueue &
 // Step 7-9 for the NP points of a lane in tile `tile` (points at T).
 template <int MODE, int FULL, int NP, bool BATCHED>
 __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile, const TileRef &T,
-                                            int lane, const uint64_t (&e)[NP],
+                                            int lane, const uint32_t (&e)[NP],
                                             const bool (&live)[NP], const bool (&valid)[NP],
                                             uint32_t (&c)[8], PendingQueue &Q, uint32_t (&rc)[7],
                                             uint32_t &c_reads, uint32_t *s_hist,
                                             const PairBuf &PB) {
   bool pend[NP];
+  const __amdgpu_buffer_rsrc_t out_buf = tile_buffer(T.out, 4 * T.n);
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     const int k = p * 64 + lane;  // within the tile
@@ -1111,11 +1162,13 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
     }
     // stage 3: the entry's references (Section III-E: one payload, two
     // payloads or a lookup-table offset)
-    const uint32_t tag = (uint32_t)(e[p] & kTagMask);
-    const uint32_t r0 = (uint32_t)((e[p] >> 2) & 0x7fffffffu);
-    const uint32_t r1 = (uint32_t)((e[p] >> 33) & 0x7fffffffu);
+    // (32-bit entries: the builder narrows every two-reference entry whose
+    // second reference is not 0, a candidate, to a lookup-table list)
+    const uint32_t tag = e[p] & (uint32_t)kTagMask;
+    const uint32_t r0 = e[p] >> 2;
+    const uint32_t r1 = 0u;
     const int n_inl = e[p] == 0 || tag == kTagLut ? 0 : (tag == kTagTwo ? 2 : 1);
-    const uint32_t off = (uint32_t)(e[p] >> 2);
+    const uint32_t off = e[p] >> 2;
     if (MODE == kApproxCount) {
       // approximate count join: every reference of the cell is a match
       if (live[p]) {
@@ -1191,9 +1244,9 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         }
       }
       if (FULL == 2) c[3] += e[p] != 0;
-      // every lane stores (lanes without a point to the sink), so the
-      // store is always issued and the compiler's waits stay exact
-      store_out(live[p] ? T.out + k : (int32_t *)P.sink, hits.best);
+      // every lane stores (past the tile's end the range check drops it),
+      // so the store is always issued and the compiler's waits stay exact
+      __builtin_amdgcn_raw_buffer_store_b32((uint32_t)hits.best, out_buf, 4 * k, 0, kBufferNT);
       pend[p] = false;
     } else {
       // exact mode: a point whose cell entry has candidate references or is
@@ -1223,16 +1276,21 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         v = hits.best;
         if (FULL == 2) c[3] += e[p] != 0;
       }
-      // one store from every lane (lanes without a point to the sink); a
-      // count join writes no out[]
-      if (MODE != kExactCount) store_out(live[p] ? T.out + k : (int32_t *)P.sink, v);
+      // one store from every lane (dropped past the tile's end); a count
+      // join writes no out[]
+      if (MODE != kExactCount)
+        __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, out_buf, 4 * k, 0, kBufferNT);
       if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
       if (MODE == kExactList || MODE == kExactCount) {
         // the wave appends its pending points (index in the pass, code) to
-        // its region of the list; other lanes store to the sink
+        // its region of the list, through a buffer over the region's free
+        // part: the other lanes' stores are out of range and dropped
         const uint64_t pm = ballot(pend[p]);
-        uint2 *dst = pend[p] ? Q.list + Q.count + lane_rank(pm) : (uint2 *)(P.sink + 2);
-        *dst = make_uint2(tile * (uint32_t)(64 * NP) + (uint32_t)k, (uint32_t)v);
+        const __amdgpu_buffer_rsrc_t lb =
+            tile_buffer(Q.list + Q.count, 8 * (int32_t)(P.region - Q.count));
+        const act_int2_v w = {(int)(tile * (uint32_t)(64 * NP) + (uint32_t)k), (int)v};
+        __builtin_amdgcn_raw_buffer_store_b64(w, lb, pend[p] ? 8 * lane_rank(pm) : kBufferOutOfRange,
+                                              0, 0);
         Q.count += (uint32_t)__popcll(pm);
       }
     }
@@ -1256,31 +1314,22 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
   if (P.gticks && lane < NP) P.gticks[(int64_t)tile * NP + lane] = wall_clock64();
 }
 
-// Loads the points of tile T into v. Every lane loads, so the load is
-// always issued: lanes past the tile's end load its last point. A batched
-// join's padding tile has no points: it loads those of `alt` instead, or
-// nothing when `alt` has none either (a single join's tiles all have
-// points, and `alt` is then a tile of the same join).
-// IDS: the tile's precomputed cell ids are loaded instead (8 bytes each,
-// carried in the x half).
-template <bool BATCHED, int NP, bool IDS = false>
-__device__ __forceinline__ void load_tile(const TileRef &T, const TileRef &alt, int lane,
-                                          double2 (&v)[NP]) {
-  const TileRef &S = T.n > 0 ? T : alt;
-  if (BATCHED && S.n <= 0) {
-#pragma unroll
-    for (int p = 0; p < NP; p++) v[p] = make_double2(0.0, 0.0);
-    return;
-  }
-  const int kmax = S.n - 1;
+// Loads the points of tile T into v (lanes past its end read zeros, which
+// they do not use). IDS: the tile's precomputed cell ids are loaded instead
+// (8 bytes each, carried in the x half).
+template <int NP, bool IDS = false>
+__device__ __forceinline__ void load_tile(const TileRef &T, int lane, double2 (&v)[NP]) {
+  const __amdgpu_buffer_rsrc_t buf =
+      IDS ? tile_buffer(T.ids, 8 * T.n) : tile_buffer(T.pts, 16 * T.n);
 #pragma unroll
   for (int p = 0; p < NP; p++) {
+    const int k = p * 64 + lane;
     if (IDS) {
-      const unsigned long long id =
-          __builtin_nontemporal_load((const unsigned long long *)S.ids + min(p * 64 + lane, kmax));
-      v[p] = make_double2(__longlong_as_double((long long)id), 0.0);
+      const act_int2_v w = __builtin_amdgcn_raw_buffer_load_b64(buf, 8 * k, 0, kBufferNT);
+      v[p] = make_double2(__hiloint2double(w.y, w.x), 0.0);
     } else {
-      v[p] = load_point(S.pts + min(p * 64 + lane, kmax));
+      const act_int4_v w = __builtin_amdgcn_raw_buffer_load_b128(buf, 16 * k, 0, kBufferNT);
+      v[p] = make_double2(__hiloint2double(w.y, w.x), __hiloint2double(w.w, w.z));
     }
   }
 }
@@ -1314,20 +1363,20 @@ __device__ __forceinline__ void project_tile(const double2 *s_trig, const uint32
                                              const double2 (&pts)[NP], Descent<NP> &D,
                                              bool (&live)[NP], bool (&valid)[NP],
                                              uint32_t &c_reads, const uint16_t *s_hinv) {
-  uint32_t face[NP];
+  uint32_t face[NP], ci[NP], cj[NP];
 #pragma unroll
   for (int p = 0; p < NP; p++) {
     live[p] = p * 64 + lane < T.n;
-    face[p] = D.ci[p] = D.cj[p] = 0;
+    face[p] = ci[p] = cj[p] = 0;
     if (IDS) {
       valid[p] = live[p] && decode_leaf(s_hinv, (uint64_t)__double_as_longlong(pts[p].x), face[p],
-                                        D.ci[p], D.cj[p]);
+                                        ci[p], cj[p]);
       face[p] = valid[p] ? face[p] : 0u;
     } else {
-      valid[p] = live[p] && project(s_trig, pts[p].x, pts[p].y, face[p], D.ci[p], D.cj[p]);
+      valid[p] = live[p] && project(s_trig, pts[p].x, pts[p].y, face[p], ci[p], cj[p]);
     }
   }
-  descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, valid, D, c_reads);
+  descend_lds<LDS_DEPTH, NP>(s_nodes, s_face, face, ci, cj, valid, D, c_reads);
 }
 
 // The probe. Each wavefront walks tiles of 64 * NP consecutive points (NP
@@ -1398,12 +1447,12 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
     double2 nxt[NP];
     {  // prologue: the wave's first tile
       double2 cur[NP];
-      load_tile<BATCHED, NP, IDS>(TB, TB, lane, cur);
+      load_tile<NP, IDS>(TB, lane, cur);
       TN = first + nwaves < ntiles ? tile_ref<BATCHED, NP>(P, first + nwaves) : TB;
-      load_tile<BATCHED, NP, IDS>(TN, TB, lane, nxt);
+      load_tile<NP, IDS>(TN, lane, nxt);
       project_tile<LDS_DEPTH, NP, IDS>(s_trig, s_nodes, s_face, TB, lane, cur, B, liveB, validB,
                                        c_reads, s_hinv);
-      issue_level<NP>(P, B, xB);
+      issue_level<NP, LDS_DEPTH>(P, B, xB);
     }
     // steady state: no wave-uniform branches around memory operations, so
     // the compiler's waits for the node level in flight and for the next
@@ -1414,13 +1463,13 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
       double2 cur[NP];
 #pragma unroll
       for (int p = 0; p < NP; p++) cur[p] = nxt[p];
-      load_tile<BATCHED, NP, IDS>(TN, TA, lane, nxt);
+      load_tile<NP, IDS>(TN, lane, nxt);
       Descent<NP> A;
       bool liveA[NP], validA[NP];
       project_tile<LDS_DEPTH, NP, IDS>(s_trig, s_nodes, s_face, TA, lane, cur, A, liveA, validA,
                                        c_reads, s_hinv);
       take_level<NP>(B, xB, c_reads);
-      descend_rest<NP>(P, B, c_reads);
+      descend_rest<NP, LDS_DEPTH + 1>(P, B, c_reads);
       finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
                                             c_reads, s_hist, PB);
       B = A;
@@ -1431,11 +1480,11 @@ __global__ __launch_bounds__(kProbeBlock, (kProbeWavesPerEU<MODE, NP>)) void pro
         liveB[p] = liveA[p];
         validB[p] = validA[p];
       }
-      issue_level<NP>(P, B, xB);
+      issue_level<NP, LDS_DEPTH>(P, B, xB);
     }
     // epilogue: the wave's last tile
     take_level<NP>(B, xB, c_reads);
-    descend_rest<NP>(P, B, c_reads);
+    descend_rest<NP, LDS_DEPTH + 1>(P, B, c_reads);
     finish_tile<MODE, FULL, NP, BATCHED>(P, tileB, TB, lane, B.e, liveB, validB, c, Q, rc,
                                           c_reads, s_hist, PB);
   }
@@ -1673,7 +1722,7 @@ __global__ __launch_bounds__(256) void cell_id_kernel(const double2 *pts, int64_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     double2 p = pts[i];
     uint32_t face, ci, cj;
-    ids[i] = project(s_trig, p.x, p.y, face, ci, cj)
+    ids[i] = project<true>(s_trig, p.x, p.y, face, ci, cj)
                  ? (((uint64_t)face << 61) | (hilbert60(s_htab, ci, cj) << 1) | 1ull)
                  : 0ull;
   }
@@ -2009,6 +2058,8 @@ static int default_lds_depth(const HostIndex &h) {
 // The index's device image in the kernel parameters.
 static void index_params(const act_index *x, int refine, int n_lds, ProbeParams &P) {
   P.nodes = x->dev.nodes;
+  const uint64_t nb = 4ull * x->host.nodes.size();
+  P.node_bytes32 = nb < (1ull << 32) ? (uint32_t)nb : 0u;
   P.lut = x->dev.lut;
   P.eoff = x->dev.eoff;
   P.origin = x->dev.origin;
