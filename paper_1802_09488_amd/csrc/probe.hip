@@ -145,7 +145,7 @@ struct ProbeParams {
   int64_t *n_pairs;
   unsigned long long *counters;
   const uint32_t *nodes;  // trie entries (32-bit: all fit, see the builder)
-  uint32_t node_bytes32;  // the entries' bytes when below 2^32, else 0
+  uint32_t node_bytes32;  // the entries' bytes when below 2^32 - 4096, else 0
   const uint32_t *lut;
   const int32_t *eoff;
   const double2 *origin;
@@ -535,7 +535,10 @@ __device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == 
 // 32-bit data format the gfx9 family expects; aux 2 = nontemporal.)
 constexpr int kBufferFlags = 0x00020000;
 constexpr int kBufferNT = 2;
-constexpr int kBufferOutOfRange = 0x40000000;  // beyond every buffer made here
+constexpr int kBufferOutOfRange = 0x40000000;  // beyond every tile and list buffer
+// beyond the trie's entries: the buffer path is taken for tries below this
+constexpr uint32_t kNodeBuffer32Max = 0xfffff000u;
+constexpr int kNodeOutOfRange = (int)0xfffff000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_buffer(const void *base, int32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufferFlags);
@@ -623,7 +626,10 @@ __device__ __forceinline__ void descend_lds(const uint32_t *s_nodes, const FaceD
 
 // Global node level D_: a buffer over the trie's entries (32-bit offsets)
 // when they span under 4 GiB, else 64-bit addresses. (The flag is uniform,
-// and both paths issue the same loads, so the waits stay exact.)
+// and both paths issue the same loads, so the waits stay exact.) Lanes
+// whose descent has ended must not each fetch a line of their last node:
+// their buffer offset is out of range (no memory access, zero returned),
+// or their address is node 0's first entry (one line for all of them).
 template <int NP, int D_>
 __device__ __forceinline__ void issue_level(const ProbeParams &P, const Descent<NP> &D,
                                             uint32_t (&x)[NP]) {
@@ -631,13 +637,16 @@ __device__ __forceinline__ void issue_level(const ProbeParams &P, const Descent<
     const __amdgpu_buffer_rsrc_t nb = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<uint32_t *>(P.nodes), (short)0, (int)P.node_bytes32, kBufferFlags);
 #pragma unroll
-    for (int p = 0; p < NP; p++)
-      x[p] = __builtin_amdgcn_raw_buffer_load_b32(
-          nb, (int)((D.node[p] << 8) | (level_key<D_>(D.ev[p], D.od[p]) << 2)), 0, 0);
+    for (int p = 0; p < NP; p++) {
+      const uint32_t off = (D.node[p] << 8) | (level_key<D_>(D.ev[p], D.od[p]) << 2);
+      x[p] = __builtin_amdgcn_raw_buffer_load_b32(nb, D.act[p] ? (int)off : kNodeOutOfRange, 0, 0);
+    }
   } else {
 #pragma unroll
-    for (int p = 0; p < NP; p++)
-      x[p] = P.nodes[((uint64_t)D.node[p] << 6) | level_key<D_>(D.ev[p], D.od[p])];
+    for (int p = 0; p < NP; p++) {
+      const uint64_t k = ((uint64_t)D.node[p] << 6) | level_key<D_>(D.ev[p], D.od[p]);
+      x[p] = P.nodes[D.act[p] ? k : 0u];
+    }
   }
 }
 
@@ -2059,7 +2068,7 @@ static int default_lds_depth(const HostIndex &h) {
 static void index_params(const act_index *x, int refine, int n_lds, ProbeParams &P) {
   P.nodes = x->dev.nodes;
   const uint64_t nb = 4ull * x->host.nodes.size();
-  P.node_bytes32 = nb < (1ull << 32) ? (uint32_t)nb : 0u;
+  P.node_bytes32 = nb <= kNodeBuffer32Max ? (uint32_t)nb : 0u;
   P.lut = x->dev.lut;
   P.eoff = x->dev.eoff;
   P.origin = x->dev.origin;
