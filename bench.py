@@ -195,63 +195,36 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
     """Serving: requests of floor(exp(U(0, ln 65536))) points, each aimed at
     one of the resident indexes (Bernoulli 1/2), arriving as a Poisson
     process at each rate in qps_list for `seconds`; points are windows of
-    the indexes' point pools (host). Latency = completion (results in host
-    memory) minus scheduled arrival."""
-    import gc
-    import threading
-
+    the indexes' point pools (host). The requests are replayed by the
+    library's native load generator (act_server_replay: one thread paces the
+    submissions on the server's clock, another waits for completions).
+    Latency = completion (results in host memory) minus scheduled arrival."""
     import numpy as np
     # requests are at most max_points long; a launch group joins up to 2^20
     srv = act.Server(indexes, slots=slots, arena_bytes=arena_bytes, max_request_points=1 << 20)
     g = np.random.default_rng(seed)
+    pools = [np.ascontiguousarray(q, dtype=np.float64) for q in pools]
+    ptrs = [q.ctypes.data for q in pools]
     res = []
     for qps in qps_list:
         nreq = int(qps * seconds)
         sizes = np.floor(np.exp(g.uniform(0.0, np.log(max_points), nreq))).astype(np.int64)
         target = g.integers(0, len(indexes), nreq)
         gaps = g.exponential(1.0 / qps, nreq)
-        starts = [g.integers(0, len(pools[t]) - sz) for t, sz in zip(target, sizes)]
-        tickets = [None] * nreq
-        lat = np.zeros(nreq)
-        done_t = np.zeros(nreq)
-        ready = threading.Semaphore(0)
-
-        def waiter():
-            for k in range(nreq):
-                ready.acquire()
-                _, tm = srv.wait(tickets[k])
-                lat[k] = tm["done_s"] - tm["arrival_s"]
-                done_t[k] = tm["done_s"]
-
-        # the request views and arrival times are made before the clock
-        # starts; the submit loop paces itself on time.monotonic, the clock
-        # act_server_clock reads (CLOCK_MONOTONIC), without a library call
-        views = [pools[t][a:a + n] for t, a, n in zip(target, starts, sizes)]
-        idxs = [int(t) for t in target]
-        t0 = act.Server.clock() + 0.05
-        arrival = (t0 + np.cumsum(gaps)).tolist()
-        off = act.Server.clock() - time.monotonic()
-        th = threading.Thread(target=waiter)
-        gc.disable()  # no collector pauses inside the paced loop
-        th.start()
-        mono = time.monotonic
-        for k in range(nreq):
-            due = arrival[k] - off
-            while mono() < due:
-                pass
-            tickets[k] = srv.submit(idxs[k], views[k], arrival=arrival[k])
-            ready.release()
-        th.join()
-        gc.enable()
-        span = float(done_t.max() - arrival[0])
+        starts = np.array([g.integers(0, len(pools[t]) - sz) for t, sz in zip(target, sizes)],
+                          dtype=np.int64)
+        arrival = act.Server.clock() + 0.05 + np.cumsum(gaps)
+        lat = srv.replay(target, ptrs, starts, sizes, arrival)
+        span = float(np.max(arrival + lat) - arrival[0]) if nreq else 1.0
         res.append({"qps_offered": qps, "requests": nreq, "seconds": seconds,
                     "points": int(sizes.sum()), "points_per_s": float(sizes.sum()) / span,
                     "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                                   "p99": 1e3 * float(np.percentile(lat, 99))},
+                                   "p99": 1e3 * float(np.percentile(lat, 99)),
+                                   "max": 1e3 * float(np.max(lat))},
                     "qps_achieved": nreq / span})
     st = srv.stats()
     srv.close()
-    return {"slots": slots, "arena_bytes": int(arena_bytes),
+    return {"slots": slots, "arena_bytes": int(arena_bytes), "load_generator": "act_server_replay",
             "request_points": "floor(exp(U(0, ln %d))), seed %d" % (max_points, seed),
             "runs": res, "failed": st["failed"], "requests": st["completed"],
             "launch_groups": st["launches"]}

@@ -396,6 +396,25 @@ class Server:
             raise ActError(rc, lib.act_server_last_error().decode())
         return out, {k: getattr(tm, k) for k, _ in tm._fields_}
 
+    def replay(self, index, pool_ptrs, starts, sizes, arrival, ring_points=1 << 26):
+        """Native load generator (act_server_replay): request k joins
+        sizes[k] points starting at row starts[k] of host pool index[k]
+        (pool_ptrs[index[k]]: the address of a C-contiguous (m, 2) float64
+        array the caller keeps alive) at arrival[k] (Server.clock()
+        seconds). Returns the latencies in seconds."""
+        index = np.ascontiguousarray(index, dtype=np.int32)
+        sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+        arrival = np.ascontiguousarray(arrival, dtype=np.float64)
+        base = np.asarray(pool_ptrs, dtype=np.uint64)[index]
+        ptrs = np.ascontiguousarray(base + 16 * np.asarray(starts, dtype=np.uint64))
+        lat = np.empty(len(sizes), dtype=np.float64)
+        rc = lib.act_server_replay(self._h, len(sizes), _np_ptr(index), _np_ptr(ptrs),
+                                   _np_ptr(sizes), _np_ptr(arrival), int(ring_points),
+                                   _np_ptr(lat))
+        if rc:
+            raise ActError(rc, lib.act_server_last_error().decode())
+        return lat
+
     def stats(self) -> dict:
         st = _b.ServerStats()
         _b.check(lib.act_server_stats_get(self._h, ctypes.byref(st)))

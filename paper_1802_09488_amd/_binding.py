@@ -137,6 +137,7 @@ def _load():
         "act_server_create": ([p, i32, p, p], ctypes.c_int),
         "act_server_submit": ([p, i32, p, i64, p, d, p], ctypes.c_int),
         "act_server_wait": ([p, ctypes.c_uint64, p], ctypes.c_int),
+        "act_server_replay": ([p, i64, p, p, p, p, i64, p], ctypes.c_int),
         "act_server_stats_get": ([p, p], ctypes.c_int),
         "act_server_clock": ([], d),
         "act_server_destroy": ([p], None),

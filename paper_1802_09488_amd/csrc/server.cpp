@@ -527,6 +527,99 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t) {
   return st == ACT_OK ? ACT_OK : fail(st, "request failed");
 }
 
+int act_server_replay(act_server *s, int64_t n, const int32_t *index,
+                      const double *const *h_points, const int64_t *n_points,
+                      const double *arrival_s, int64_t ring_points, double *latency_s) {
+  if (!s || n < 0 || (n > 0 && (!index || !h_points || !n_points || !arrival_s)) ||
+      ring_points < 1)
+    return fail(ACT_E_ARG, "bad argument");
+  for (int64_t k = 0; k < n; k++)
+    if (n_points[k] < 0 || n_points[k] > ring_points)
+      return fail(ACT_E_RANGE, "a request is longer than the output ring");
+  std::vector<int32_t> ring;
+  std::vector<uint64_t> tickets;
+  std::vector<int64_t> start;  // each request's place in the ring
+  std::vector<int> sub_rc;
+  try {
+    ring.resize((size_t)ring_points);
+    tickets.assign((size_t)n, 0);
+    start.assign((size_t)n, 0);
+    sub_rc.assign((size_t)n, ACT_OK);
+  } catch (...) {
+    return fail(ACT_E_OOM, "out of host memory");
+  }
+  // the ring is used in request order: [tail, head) holds the outputs of
+  // requests submitted and not yet waited for
+  std::mutex mu;
+  std::condition_variable cv;
+  int64_t head = 0, tail = 0, used = 0, submitted = 0, waited = 0;
+  int first_err = ACT_OK;
+  std::string err_msg;
+  std::thread waiter([&] {
+    for (int64_t k = 0; k < n; k++) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return submitted > k; });
+      }
+      int rc = sub_rc[k];
+      act_request_times t{};
+      if (rc == ACT_OK) {
+        rc = act_server_wait(s, tickets[k], &t);
+        if (latency_s) latency_s[k] = t.done_s - t.arrival_s;
+      } else if (latency_s) {
+        latency_s[k] = -1.0;
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc != ACT_OK && first_err == ACT_OK) {
+        first_err = rc;
+        err_msg = g_server_err;
+      }
+      // release this request's outputs and any gap before them (the unused
+      // end of the ring when its outputs wrapped to the start)
+      const int64_t end = start[k] + n_points[k];
+      used -= start[k] >= tail ? end - tail : (ring_points - tail) + end;
+      tail = end;
+      waited = k + 1;
+      cv.notify_all();
+    }
+  });
+  for (int64_t k = 0; k < n; k++) {
+    const int64_t m = n_points[k];
+    {
+      // room for m outputs: at head, or from 0 when the end is too short
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] {
+        if (waited == submitted) {  // nothing outstanding: restart at 0
+          head = tail = used = 0;
+          return true;
+        }
+        // in use: [tail, head), or once wrapped, [tail, the end) (with the
+        // end's unused gap) and [0, head); the two cases differ in `used`
+        if (used == head - tail) return head + m <= ring_points || m <= tail;
+        return head + m <= tail;
+      });
+      const int64_t at = head + m <= ring_points ? head : 0;
+      if (at != head) used += ring_points - head;  // the end's gap
+      start[k] = at;
+      head = at + m;
+      used += m;
+    }
+    const double due = arrival_s[k];
+    while (now_s() < due) {
+    }
+    uint64_t t = 0;
+    const int rc = act_server_submit(s, index[k], h_points[k], m, ring.data() + start[k], due, &t);
+    std::lock_guard<std::mutex> lk(mu);
+    tickets[k] = t;
+    sub_rc[k] = rc;
+    submitted = k + 1;
+    cv.notify_all();
+  }
+  waiter.join();
+  if (first_err != ACT_OK) return fail(first_err, "replay: " + err_msg);
+  return ACT_OK;
+}
+
 int act_server_stats_get(act_server *s, act_server_stats *st) {
   if (!s || !st) return fail(ACT_E_ARG, "bad argument");
   std::lock_guard<std::mutex> lk(s->mu);

@@ -705,6 +705,32 @@ def test_server_admission_by_memory(act):
     srv.close()
 
 
+def test_server_replay_wraps_its_ring(act):
+    """act_server_replay over a ring barely longer than the longest request:
+    the outputs wrap around the ring and requests wait for room, and every
+    request completes with a latency of at least its queueing; a request
+    longer than the ring is refused before anything is submitted."""
+    P, idx = index(act, "c1", "exact")
+    pool = np.ascontiguousarray(synth.workload_points("c1", 0, 200_000))
+    srv = act.Server([idx], slots=2, arena_bytes=8 << 20, max_request_points=1 << 16)
+    rng = np.random.default_rng(17)
+    n = 400
+    sizes = rng.integers(0, 5000, n)
+    sizes[::37] = 5000
+    starts = rng.integers(0, len(pool) - 5000, n)
+    arrival = act.Server.clock() + 0.01 + np.cumsum(rng.exponential(1e-5, n))
+    lat = srv.replay(np.zeros(n, np.int32), [pool.ctypes.data], starts, sizes, arrival,
+                     ring_points=7000)
+    assert np.all(lat >= 0) and np.all(np.isfinite(lat))
+    st = srv.stats()
+    assert st["completed"] == n and st["failed"] == 0
+    with pytest.raises(act.ActError):
+        srv.replay(np.zeros(1, np.int32), [pool.ctypes.data], [0], [5000], [0.0],
+                   ring_points=4000)
+    assert srv.stats()["submitted"] == n
+    srv.close()
+
+
 def c3_sample(n_first, windows, win, seed):
     """The first n_first points of the C3 stream (batch 0) plus `windows`
     seeded windows of `win` points anywhere in its 1e9 points (60 batches)."""
