@@ -211,8 +211,8 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
         sizes = np.floor(np.exp(g.uniform(0.0, np.log(max_points), nreq))).astype(np.int64)
         target = g.integers(0, len(indexes), nreq)
         gaps = g.exponential(1.0 / qps, nreq)
-        starts = np.array([g.integers(0, len(pools[t]) - sz) for t, sz in zip(target, sizes)],
-                          dtype=np.int64)
+        room = np.array([len(q) for q in pools], dtype=np.int64)[target] - sizes
+        starts = (g.random(nreq) * room).astype(np.int64)
         arrival = act.Server.clock() + 0.05 + np.cumsum(gaps)
         lat = srv.replay(target, ptrs, starts, sizes, arrival)
         span = float(np.max(arrival + lat) - arrival[0]) if nreq else 1.0
@@ -431,7 +431,7 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="c2: only the headline exact and approx@4m joins (for rocprofv3 runs)")
     ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="seconds per serving rate (default 2 in c2, 10 in c5)")
+                    help="seconds per serving rate (default 2 in c2, 4 in c5)")
     ap.add_argument("--summarize-trace", metavar="DIR")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR")
@@ -664,12 +664,12 @@ def _index_metrics(ctr):
 def compact_legs(args, keep):
     """Compact forms of the other workloads, in the default run:
     c3: 2^26 points of the 40,000-polygon stream in 2^24 batches, exact
-    (covering level 22, and the library's default level 20) and approx@1m,
-    with an oracle sample; c4: the first 1,000 batches of the
+    (covering level 22, with the launch defaults and tuned, and the
+    library's default level 20) and approx@1m, with an oracle sample; c4: the first 1,000 batches of the
     uneven-batch mix on the c3 exact index, tuned, one graph replay per
     step, oracle on 1% of the batches plus every batch under 1,000 points;
-    c5: the serving sweep at 1e3, 1e4 and 5e4 requests/s over the c2
-    approx@4m and c3 exact indexes."""
+    c5: the serving sweep at 1e3, 1e4, 1e5 and 4e5 requests/s over the c2
+    approx@4m and c3 exact indexes (native load generator)."""
     import numpy as np
     import torch
 
@@ -709,6 +709,13 @@ def compact_legs(args, keep):
                     "build_s": tb, "oracle_sample_identical": ok}
     wq, _ = _timed_stream(ie, pts, out, bsz, 1, pending=act.ACT_PENDING_QUEUE)
     c3["exact_in_probe_queue_points_per_s"] = n / wq
+    # the autotuner's pick for this index on one batch, then the same stream
+    tune = ie.tune(pts[:bsz])
+    wall, ms = _timed_stream(ie, pts, out, bsz, steps)
+    c3["exact_tuned"] = {"points_per_s": n * steps / wall, "stream_ms": float(np.median(ms)),
+                         "tuner": tune,
+                         "oracle_sample_identical":
+                             bool(np.array_equal(out[:200_000].cpu().numpy(), ref.out))}
     t0 = time.perf_counter()
     oracle.join(P, sample, nthreads=cores)
     dt = time.perf_counter() - t0
@@ -784,7 +791,7 @@ def compact_legs(args, keep):
 
     log("c5: serving sweep")
     pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
-    srv = serving_leg(act, [keep["approx4m"], ie], pools, [1e3, 1e4, 5e4], 2.0)
+    srv = serving_leg(act, [keep["approx4m"], ie], pools, [1e3, 1e4, 1e5, 4e5], 2.0)
     srv["indexes"] = "c2 approx@4m, c3 exact"
     legs["c5"] = srv
     return legs
@@ -955,16 +962,17 @@ def run_c4(args):
 
 
 def run_c5(args):
-    """Serving: Poisson arrivals at 1e3, 1e4, 5e4, 1e5 and 2e5 requests/s of
+    """Serving: Poisson arrivals at 1e3 ... 1.6e6 requests/s of
     floor(exp(U(0, ln 65536))) points, each aimed at the 290-polygon
-    approx@4m index or the 40,000-polygon exact index."""
+    approx@4m index or the 40,000-polygon exact index, replayed by the
+    native load generator for 4 s per rate."""
     import synth
     import paper_1802_09488_amd as act
     ia = act.build(synth.workload_polygons("c2"), "approx", 4.0)
     ie = act.build(synth.workload_polygons("c3"), "exact", max_level=EXACT_LEVEL)
     pools = [synth.workload_points("c2", 0, 1 << 22), synth.workload_points("c3", 0, 1 << 22)]
-    sec = args.serve_seconds or 10.0
-    srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4, 1e5, 2e5], sec)
+    sec = args.serve_seconds or 4.0
+    srv = serving_leg(act, [ia, ie], pools, [1e3, 1e4, 5e4, 1e5, 2e5, 4e5, 8e5, 1.6e6], sec)
     srv["indexes"] = "c2 approx@4m, c3 exact"
     best = max(r["points_per_s"] for r in srv["runs"])
     _line(best, len(srv["runs"]), 0, 1000.0 * sec,
