@@ -756,8 +756,9 @@ def test_c3_exact_sample_all_refine_modes(act):
 
 @pytest.mark.timeout(900)
 def test_c3_approx_1m_guarantee(act):
-    """40,000 polygons at 1 m precision (a ~7 GB trie): no covering pair
-    missing, every extra pair within 1 m of the polygon's boundary."""
+    """40,000 polygons at 1 m precision (a 3.5 GB trie, node entries read
+    through 32-bit buffer offsets): no covering pair missing, every extra
+    pair within 1 m of the polygon's boundary."""
     P = synth.workload_polygons("c3")
     idx = act.build(P, "approx", 1.0)
     assert idx.stats()["max_cell_level"] >= 23
@@ -765,6 +766,33 @@ def test_c3_approx_1m_guarantee(act):
     out, pairs, _ = gpu_join(idx, pts)
     n_extra, n_pairs = assert_approx(P, pts, out, pairs, 1.0, "c3-approx1m")
     assert n_extra < 0.05 * n_pairs
+    del idx
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.skipif(os.environ.get("ACT_SLOW_TESTS") != "1",
+                    reason="builds a 7 GB trie (about 2 minutes); set ACT_SLOW_TESTS=1")
+def test_c3_approx_trie_over_4gib(act):
+    """40,000 polygons at 0.6 m precision: the trie's entries span more than
+    4 GiB, so the probe reads them with 64-bit addresses; the approximate
+    guarantee holds on the C3 sample, and the join is identical at every
+    LDS depth and both point counts per lane."""
+    P = synth.workload_polygons("c3")
+    idx = act.build(P, "approx", 0.6)
+    assert idx.stats()["node_bytes"] > (1 << 32)
+    pts = c3_sample(40_000, 8, 4096, 53)
+    out, pairs, _ = gpu_join(idx, pts)
+    assert_approx(P, pts, out, pairs, 0.6, "c3-approx0.6")
+    t = torch.from_numpy(pts).cuda()
+    ref = idx.join(t)
+    for lds in (0, 1, 2):
+        for np_ in (1, 2):
+            try:
+                o, _, _ = idx.join_ex(t, lds_levels=lds, points_per_lane=np_)
+            except act.ActError as e:  # top levels larger than the LDS budget
+                assert e.code == -7 and lds > 0
+                continue
+            assert torch.equal(o, ref), (lds, np_)
     del idx
 
 
