@@ -63,6 +63,23 @@ def test_ids_from_the_library_match_join(act, w, mode, prec, n):
         assert np.array_equal(got[:200_000], oracle.join(P, pts[:200_000]).out)
 
 
+@pytest.mark.parametrize("mode,prec", [("exact", 0.0), ("approx", 4.0)])
+def test_ids_ragged_lengths(act, mode, prec):
+    """Lengths that end inside a tile (the probe reads a tile's ids and
+    writes its outputs through buffers sized to the tile): the join of ids
+    equals the join of the points, and nothing past n is written."""
+    P, idx = index(act, "c2", mode, prec)
+    pts = synth.workload_points("c2", 0, 5000)
+    t = torch.from_numpy(pts).cuda()
+    ids = act.cell_ids(t)
+    for n in (1, 2, 63, 64, 65, 127, 129, 255, 257, 4097):
+        out = torch.full((n + 64,), -7, dtype=torch.int32, device="cuda")
+        idx.join_ids(ids[:n], t[:n] if mode == "exact" else None, out=out[:n])
+        want = idx.join(t[:n])
+        assert torch.equal(out[:n], want), n
+        assert bool((out[n:] == -7).all()), n
+
+
 @pytest.mark.parametrize("w", ["c1", "c2"])
 def test_host_ids_give_the_oracle(act, w):
     P, idx = index(act, w, "exact")

@@ -328,9 +328,13 @@ def test_small_and_ragged_lengths(act, mode):
     for n in (1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 4097, 70_001):
         for npl in (1, 2):
             for grid in (1, 3, 0, 4096):
-                lean, _, _ = idx.join_ex(t[:n], points_per_lane=npl, grid=grid)
+                # outputs are written through buffers sized to each tile:
+                # nothing past n may change
+                buf = torch.full((n + 200,), -7, dtype=torch.int32, device="cuda")
+                lean, _, _ = idx.join_ex(t[:n], out=buf[:n], points_per_lane=npl, grid=grid)
                 torch.cuda.synchronize()
                 assert np.array_equal(lean.cpu().numpy(), full[:n]), (n, npl, grid)
+                assert bool((buf[n:] == -7).all()), (n, npl, grid)
             o, pr, _ = gpu_join(idx, pts[:n], points_per_lane=npl)
             assert np.array_equal(o, full[:n]), (n, npl)
             assert np.array_equal(pr, full_pairs[full_pairs[:, 0] < n]), (n, npl)
