@@ -214,13 +214,17 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
         room = np.array([len(q) for q in pools], dtype=np.int64)[target] - sizes
         starts = (g.random(nreq) * room).astype(np.int64)
         arrival = act.Server.clock() + 0.05 + np.cumsum(gaps)
-        lat = srv.replay(target, ptrs, starts, sizes, arrival)
-        span = float(np.max(arrival + lat) - arrival[0]) if nreq else 1.0
+        tm = srv.replay(target, ptrs, starts, sizes, arrival)
+        lat = tm["done_s"] - tm["arrival_s"]
+        queued = tm["admitted_s"] - tm["arrival_s"]  # waiting for a slot and memory
+        span = float(np.max(tm["done_s"]) - arrival[0]) if nreq else 1.0
         res.append({"qps_offered": qps, "requests": nreq, "seconds": seconds,
                     "points": int(sizes.sum()), "points_per_s": float(sizes.sum()) / span,
                     "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
                                    "p99": 1e3 * float(np.percentile(lat, 99)),
                                    "max": 1e3 * float(np.max(lat))},
+                    "queued_ms": {"p50": 1e3 * float(np.percentile(queued, 50)),
+                                  "p99": 1e3 * float(np.percentile(queued, 99))},
                     "qps_achieved": nreq / span})
     st = srv.stats()
     srv.close()

@@ -534,8 +534,10 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t);
  * calling thread spins until it is due, so the pacing does not depend on
  * the caller's runtime), joining n_points[k] points at h_points[k] (host,
  * 2*n_points[k] doubles) with indexes[index[k]]. A second thread waits for
- * the requests in order and writes latency_s[k] = completion - arrival
- * (seconds; -1 for a request that failed; latency_s may be NULL). Results
+ * the requests in order and writes each one's times to times[k] (host, n
+ * entries, may be NULL: arrival, admission and completion on
+ * act_server_clock, so latency = done_s - arrival_s; admitted_s and done_s
+ * are -1 for a request that failed). Results
  * go to an output ring of ring_points int32 that the call allocates and
  * reuses in request order; a request waits for room in it (which then
  * counts in its latency), and none may be longer than the ring
@@ -544,7 +546,7 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t);
  */
 int act_server_replay(act_server *s, int64_t n, const int32_t *index,
                       const double *const *h_points, const int64_t *n_points,
-                      const double *arrival_s, int64_t ring_points, double *latency_s);
+                      const double *arrival_s, int64_t ring_points, act_request_times *times);
 int act_server_stats_get(act_server *s, act_server_stats *stats);
 double act_server_clock(void);
 /* Finish every queued request, then release streams and arenas. */

@@ -401,19 +401,21 @@ class Server:
         sizes[k] points starting at row starts[k] of host pool index[k]
         (pool_ptrs[index[k]]: the address of a C-contiguous (m, 2) float64
         array the caller keeps alive) at arrival[k] (Server.clock()
-        seconds). Returns the latencies in seconds."""
+        seconds). Returns a structured array of each request's arrival_s,
+        admitted_s and done_s (Server.clock() seconds) and n."""
         index = np.ascontiguousarray(index, dtype=np.int32)
         sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         arrival = np.ascontiguousarray(arrival, dtype=np.float64)
         base = np.asarray(pool_ptrs, dtype=np.uint64)[index]
         ptrs = np.ascontiguousarray(base + 16 * np.asarray(starts, dtype=np.uint64))
-        lat = np.empty(len(sizes), dtype=np.float64)
+        times = np.zeros(len(sizes), dtype=[("arrival_s", np.float64), ("admitted_s", np.float64),
+                                            ("done_s", np.float64), ("n", np.int64)])
         rc = lib.act_server_replay(self._h, len(sizes), _np_ptr(index), _np_ptr(ptrs),
                                    _np_ptr(sizes), _np_ptr(arrival), int(ring_points),
-                                   _np_ptr(lat))
+                                   _np_ptr(times))
         if rc:
             raise ActError(rc, lib.act_server_last_error().decode())
-        return lat
+        return times
 
     def stats(self) -> dict:
         st = _b.ServerStats()

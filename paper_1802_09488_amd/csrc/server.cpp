@@ -529,7 +529,7 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t) {
 
 int act_server_replay(act_server *s, int64_t n, const int32_t *index,
                       const double *const *h_points, const int64_t *n_points,
-                      const double *arrival_s, int64_t ring_points, double *latency_s) {
+                      const double *arrival_s, int64_t ring_points, act_request_times *times) {
   if (!s || n < 0 || (n > 0 && (!index || !h_points || !n_points || !arrival_s)) ||
       ring_points < 1)
     return fail(ACT_E_ARG, "bad argument");
@@ -565,10 +565,12 @@ int act_server_replay(act_server *s, int64_t n, const int32_t *index,
       act_request_times t{};
       if (rc == ACT_OK) {
         rc = act_server_wait(s, tickets[k], &t);
-        if (latency_s) latency_s[k] = t.done_s - t.arrival_s;
-      } else if (latency_s) {
-        latency_s[k] = -1.0;
+      } else {
+        t.arrival_s = arrival_s[k];
+        t.n = n_points[k];
       }
+      if (rc != ACT_OK) t.done_s = t.admitted_s = -1.0;
+      if (times) times[k] = t;
       std::lock_guard<std::mutex> lk(mu);
       if (rc != ACT_OK && first_err == ACT_OK) {
         first_err = rc;

@@ -723,9 +723,11 @@ def test_server_replay_wraps_its_ring(act):
     sizes[::37] = 5000
     starts = rng.integers(0, len(pool) - 5000, n)
     arrival = act.Server.clock() + 0.01 + np.cumsum(rng.exponential(1e-5, n))
-    lat = srv.replay(np.zeros(n, np.int32), [pool.ctypes.data], starts, sizes, arrival,
-                     ring_points=7000)
-    assert np.all(lat >= 0) and np.all(np.isfinite(lat))
+    tm = srv.replay(np.zeros(n, np.int32), [pool.ctypes.data], starts, sizes, arrival,
+                    ring_points=7000)
+    assert np.array_equal(tm["n"], sizes)
+    assert np.all(tm["arrival_s"] == arrival)
+    assert np.all(tm["admitted_s"] >= tm["arrival_s"]) and np.all(tm["done_s"] >= tm["admitted_s"])
     st = srv.stats()
     assert st["completed"] == n and st["failed"] == 0
     with pytest.raises(act.ActError):
