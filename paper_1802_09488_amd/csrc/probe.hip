@@ -563,9 +563,10 @@ typedef int act_int2_v __attribute__((ext_vector_type(2)));
 // walk the levels in step, so the level index is uniform.
 //
 // Written without branches: a lane whose descent has ended keeps its entry
-// and its last node, which it keeps reading harmlessly (a lane that never
-// started reads node 1, the first LDS-staged node, or node 0, which the
-// builder reserves), so the wave never splits. Device entries are 32-bit;
+// and its last node, whose LDS copy it keeps reading harmlessly (a lane that
+// never started reads node 1, the first LDS-staged node), and at the global
+// levels it reads nothing (issue_level), so the wave never splits. Device
+// entries are 32-bit;
 // a node is carried as its pointer entry (index << 2), so its byte offset
 // is the entry << 8.
 template <int NP>
@@ -1295,8 +1296,11 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         // its region of the list, through a buffer over the region's free
         // part: the other lanes' stores are out of range and dropped
         const uint64_t pm = ballot(pend[p]);
-        const __amdgpu_buffer_rsrc_t lb =
-            tile_buffer(Q.list + Q.count, 8 * (int32_t)(P.region - Q.count));
+        // (the region's free part, capped below the out-of-range offset:
+        // it always holds the wave's next 64 entries)
+        const __amdgpu_buffer_rsrc_t lb = tile_buffer(
+            Q.list + Q.count,
+            (int32_t)min<uint64_t>(8ull * (P.region - Q.count), (uint64_t)kBufferOutOfRange));
         const act_int2_v w = {(int)(tile * (uint32_t)(64 * NP) + (uint32_t)k), (int)v};
         __builtin_amdgcn_raw_buffer_store_b64(w, lb, pend[p] ? 8 * lane_rank(pm) : kBufferOutOfRange,
                                               0, 0);
