@@ -74,6 +74,31 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "probe_counters_c2.md")
+# VALU issue ceiling: 1024 SIMDs x 2.4 GHz, one 64-lane wave instruction
+# every 4 cycles per SIMD (fp64 FMA at full rate), in lane operations/s
+PEAK_VALU_LANE_OPS = 1024 * 2.4e9 / 4 * 64
+
+
+def measured_valu():
+    """VALU instructions per 64 points of the probe kernels, from the
+    committed counter summary, if it was taken on the current kernel
+    sources (else None)."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    txt = open(COUNTERS_FILE).read()
+    m = re.search(r"kernel sources sha256/16: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    out = {}
+    for mode, label in (("approx", "0"), ("exact", "3")):
+        r = re.search(r"\| probe_kernel<%s, 2, 0, 2, false, false> \| \d+ \| ([0-9.e+]+) \|" % label,
+                      txt)
+        if r:
+            out[mode] = float(r.group(1))
+    return out or None
+
+
 def measured_traffic():
     """Probe HBM bytes per launch from the committed counter summary, if it
     was taken on the current kernel sources (else None)."""
@@ -559,7 +584,19 @@ def run_c2(args, emit=True):
     probe_ms = float(np.mean(prb))
     achieved = BYTES_PER_POINT * n / (probe_ms * 1e-3) / 1e9
     traffic = measured_traffic()
+    valu = measured_valu()
     st, sa = idx.stats(), idx_a.stats()
+    alu = None
+    if valu and "exact" in valu:
+        # lane operations per point = wave instructions per 64 points
+        ops = valu["exact"] * n / (probe_ms * 1e-3)
+        alu = {"bound": "valu", "achieved": ops, "peak": PEAK_VALU_LANE_OPS,
+               "unit": "lane-ops/s", "frac": ops / PEAK_VALU_LANE_OPS,
+               "valu_instr_per_point": valu["exact"],
+               "what": "secondary ceiling: the probe's VALU instructions per point "
+                       "(rocprofv3 SQ_INSTS_VALU, committed summary) over its event-timed "
+                       "duration, against 1024 SIMDs issuing one wave instruction every 4 "
+                       "cycles at 2.4 GHz (fp64 FMA runs at that rate)"}
     res = {
         "metric": "joined points/sec (exact & approx@4m) + HBM roofline %; p50/p99 batch latency",
         "value": value,
@@ -592,15 +629,19 @@ def run_c2(args, emit=True):
                              "its event-timed duration, against 8 TB/s (the 40% target is "
                              "stated for the probe); join_frac: the same bytes over the whole "
                              "exact join (probe + resolve); measured_GBps: the kernel's "
-                             "rocprofv3-counted HBM bytes over its duration"},
+                             "rocprofv3-counted HBM bytes over its duration",
+                     "alu": alu},
         "latency_ms": {"p50": percentile(tot, 50), "p99": percentile(tot, 99),
                        "what": "one join of all points (one step), HIP events"},
         "batched_exact": batched,
         "serving": serving,
-        "exact": {"join_ms_mean": float(np.mean(tot)), "probe_ms_mean": probe_ms,
+        "exact": {"join_ms_mean": float(np.mean(tot)), "join_ms_median": float(np.median(tot)),
+                  "join_ms_min": float(np.min(tot)), "probe_ms_mean": probe_ms,
                   "resolve_ms_mean": float(np.mean(tot) - probe_ms)},
         "approx4m": {"points_per_s": n * args.steps / wall_a,
                      "join_ms_mean": float(np.mean(tot_a)),
+                     "join_ms_median": float(np.median(tot_a)),
+                     "join_ms_min": float(np.min(tot_a)),
                      "latency_ms": {"p50": percentile(tot_a, 50), "p99": percentile(tot_a, 99)},
                      "roofline_frac": BYTES_PER_POINT * n / (np.mean(prb_a) * 1e-3) / 1e9
                      / PEAK_HBM_GBS,
