@@ -516,10 +516,10 @@ __device__ __forceinline__ uint64_t lookup(const ProbeParams &P, const uint32_t 
 }
 
 // out[] of a pending point until the resolve kernel overwrites it: -3 - the
-// offset of the cell's lookup-table list, or kPending when the cell's
-// references are inline (the resolver then repeats the descent).
+// offset of the cell's lookup-table list (offsets stay below 2^30, the
+// builder's bound on the table), or kPending when the cell's references are
+// inline (the resolver then repeats the descent).
 constexpr int32_t kPending = -2;
-constexpr uint32_t kMaxOutLut = 0x7ffffffcu;  // largest offset -3 - off can carry
 
 __device__ __forceinline__ bool is_child(uint64_t e) { return (e & kTagMask) == kTagPtr && e != 0; }
 
@@ -1263,39 +1263,43 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
       // a lookup-table list is pending. Its list offset goes to out[]; then
       // either its bit goes to the pending mask (resolve_kernel finishes
       // it) or the point joins the wave's queue.
-      const bool cand_inl = (n_inl > 0 && !(r0 & 1u)) || (n_inl > 1 && !(r1 & 1u));
-      pend[p] = live[p] && (tag == kTagLut || cand_inl);
-      const uint64_t m = MODE == kExactFused ? ballot(pend[p]) : 0ull;
+      // With 32-bit entries the only entry without candidates that has a
+      // reference is a one-reference entry (tag 01) whose reference is
+      // interior (bit 2): a two-reference entry's second reference is
+      // candidate 0. So a live point is pending exactly when its entry is a
+      // list, a two-reference entry or a one-reference entry with a
+      // candidate, and a point that is not pending has at most one
+      // (interior) reference: no pair beyond out[].
+      (void)r1;
+      const bool one_true = tag == kTagOne && (e[p] & 4u) != 0u;
+      pend[p] = live[p] && (tag == kTagLut || tag == kTagTwo || (tag == kTagOne && !one_true));
+      // the wave's pending lanes, taken once while the predicate is a mask
+      const uint64_t pm = ballot(pend[p]);
       int32_t v;
-      if (pend[p]) {
-        v = tag == kTagLut && off <= kMaxOutLut ? -3 - (int32_t)off : kPending;
-        if (MODE == kExactFused) {
-          const uint32_t slot = (Q.head + Q.count + (uint32_t)lane_rank(m)) & (kQueueCap - 1);
-          Q.v[slot] = (int64_t)tile * (64 * NP) + k;
-          Q.e[slot] = e[p];
-        }
-      } else if (MODE == kExactCount) {
-        // a cell without candidates: its inline references are true hits
-        if (live[p] && n_inl > 0) count_add(P, s_hist, r0 >> 1);
-        if (live[p] && n_inl > 1) count_add(P, s_hist, r1 >> 1);
+      if (MODE == kExactCount) {
+        if (live[p] && one_true) count_add(P, s_hist, e[p] >> 3);
         v = 0;
       } else {
-        Hits<(FULL >= 1)> hits;
-        if (n_inl > 0) hits.add(P, i, (int32_t)(r0 >> 1));
-        if (n_inl > 1) hits.add(P, i, (int32_t)(r1 >> 1));
-        v = hits.best;
-        if (FULL == 2) c[3] += e[p] != 0;
+        v = tag == kTagLut ? -3 - (int32_t)off
+            : pend[p]      ? kPending
+            : one_true     ? (int32_t)(e[p] >> 3)
+                           : -1;
+        if (FULL == 2) c[3] += !pend[p] && live[p] && e[p] != 0;
+      }
+      if (MODE == kExactFused && pend[p]) {
+        const uint32_t slot = (Q.head + Q.count + (uint32_t)lane_rank(pm)) & (kQueueCap - 1);
+        Q.v[slot] = (int64_t)tile * (64 * NP) + k;
+        Q.e[slot] = e[p];
       }
       // one store from every lane (dropped past the tile's end); a count
       // join writes no out[]
       if (MODE != kExactCount)
         __builtin_amdgcn_raw_buffer_store_b32((uint32_t)v, out_buf, 4 * k, 0, kBufferNT);
-      if (MODE == kExactFused) Q.count += (uint32_t)__popcll(m);
+      if (MODE == kExactFused) Q.count += (uint32_t)__popcll(pm);
       if (MODE == kExactList || MODE == kExactCount) {
         // the wave appends its pending points (index in the pass, code) to
         // its region of the list, through a buffer over the region's free
         // part: the other lanes' stores are out of range and dropped
-        const uint64_t pm = ballot(pend[p]);
         // (the region's free part, capped below the out-of-range offset:
         // it always holds the wave's next 64 entries)
         const __amdgpu_buffer_rsrc_t lb = tile_buffer(
