@@ -1214,14 +1214,15 @@ __device__ __forceinline__ void finish_tile(const ProbeParams &P, uint32_t tile,
         // all its lanes' pairs in the block's buffer at once
         const uint32_t refs = live[p] ? (uint32_t)n_inl + nt + nc : 0u;
         const uint32_t k = refs > 0 ? refs - 1 : 0u;
-        uint32_t incl = k;
+        // (most waves have no pair beyond out[]: they skip the scan)
+        if (ballot(k != 0u) != 0ull) {  // wave-uniform
+          uint32_t incl = k;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const uint32_t v = __shfl_up(incl, d);
-          if (lane >= d) incl += v;
-        }
-        const uint32_t total = __shfl(incl, 63);
-        if (total != 0) {  // wave-uniform
+          for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+          }
+          const uint32_t total = __shfl(incl, 63);
           uint32_t lb = 0;
           if (lane == 0) lb = atomicAdd(PB.count, total);
           lb = __shfl(lb, 0);
