@@ -242,6 +242,9 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
         tm = srv.replay(target, ptrs, starts, sizes, arrival)
         lat = tm["done_s"] - tm["arrival_s"]
         queued = tm["admitted_s"] - tm["arrival_s"]  # waiting for a slot and memory
+        phases = {"staging": tm["launched_s"] - tm["admitted_s"],   # points into pinned memory
+                  "gpu": tm["results_s"] - tm["launched_s"],        # copies and join, found done
+                  "copy_out": tm["done_s"] - tm["results_s"]}       # results to the callers
         span = float(np.max(tm["done_s"]) - arrival[0]) if nreq else 1.0
         res.append({"qps_offered": qps, "requests": nreq, "seconds": seconds,
                     "points": int(sizes.sum()), "points_per_s": float(sizes.sum()) / span,
@@ -250,13 +253,20 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
                                    "max": 1e3 * float(np.max(lat))},
                     "queued_ms": {"p50": 1e3 * float(np.percentile(queued, 50)),
                                   "p99": 1e3 * float(np.percentile(queued, 99))},
+                    "service_p99_ms": {k: 1e3 * float(np.percentile(v, 99))
+                                       for k, v in phases.items()},
+                    "slowest_request_ms": {k: 1e3 * float(v[int(np.argmax(lat))])
+                                           for k, v in dict(phases, queued=queued).items()},
                     "qps_achieved": nreq / span})
     st = srv.stats()
     srv.close()
     return {"slots": slots, "arena_bytes": int(arena_bytes), "load_generator": "act_server_replay",
             "request_points": "floor(exp(U(0, ln %d))), seed %d" % (max_points, seed),
             "runs": res, "failed": st["failed"], "requests": st["completed"],
-            "launch_groups": st["launches"]}
+            "launch_groups": st["launches"],
+            "scheduler_max_ms": {"pass": 1e3 * st["max_pass_s"], "launch": 1e3 * st["max_launch_s"],
+                                 "stage": 1e3 * st["max_stage_s"],
+                                 "finish": 1e3 * st["max_finish_s"]}}
 
 
 def cpu_baseline_and_parity(P, workload, n_sample, gpu_out, gpu_pairs=None, gpu_counts=None,

@@ -492,7 +492,10 @@ int act_tune(act_index *idx, const double *d_sample, int64_t n, int32_t *d_out, 
  * result does not depend on the group it ran in.
  * Exact-mode workspaces for every (index, stream) are reserved at creation
  * for max_request_points (longer requests run in passes), so serving
- * allocates nothing. The indexes must outlive the server.
+ * allocates nothing, and every slot is warmed up once (a 64-point join
+ * with each index on its stream, with its copies), so the first requests
+ * do not pay the runtime's first use of a stream. The indexes must outlive
+ * the server.
  */
 typedef struct act_server act_server;
 
@@ -504,8 +507,13 @@ typedef struct {
                                   (default 2^20)                              */
 } act_server_opts;
 
+/* A request's times (act_server_clock() seconds): arrival; admission (its
+ * launch group took a slot and arena memory); launched (the group's points
+ * staged and its copies and join enqueued); results (the group's results
+ * found in pinned host memory); done (the request's results copied to its
+ * h_out). */
 typedef struct {
-  double arrival_s, admitted_s, done_s;  /* act_server_clock() seconds       */
+  double arrival_s, admitted_s, launched_s, results_s, done_s;
   int64_t n;
 } act_request_times;
 
@@ -513,6 +521,11 @@ typedef struct {
   int64_t submitted, admitted, completed, failed, queued, points, arena_bytes;
   int32_t slots, reserved;
   int64_t launches;  /* launch groups (joins) started                        */
+  /* the scheduler thread's longest pass through its loop (idle waits
+   * excluded), and the longest it spent on one group's launch (staging
+   * and enqueuing its copies and join), on the staging copies alone, and
+   * on one group's completion (result copies), in seconds              */
+  double max_pass_s, max_launch_s, max_stage_s, max_finish_s;
 } act_server_stats;
 
 void act_server_opts_init(act_server_opts *opts);
@@ -535,9 +548,8 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t);
  * the caller's runtime), joining n_points[k] points at h_points[k] (host,
  * 2*n_points[k] doubles) with indexes[index[k]]. A second thread waits for
  * the requests in order and writes each one's times to times[k] (host, n
- * entries, may be NULL: arrival, admission and completion on
- * act_server_clock, so latency = done_s - arrival_s; admitted_s and done_s
- * are -1 for a request that failed). Results
+ * entries, may be NULL; latency = done_s - arrival_s; the times after
+ * arrival are -1 for a request that failed). Results
  * go to an output ring of ring_points int32 that the call allocates and
  * reuses in request order; a request waits for room in it (which then
  * counts in its latency), and none may be longer than the ring

@@ -402,13 +402,15 @@ class Server:
         (pool_ptrs[index[k]]: the address of a C-contiguous (m, 2) float64
         array the caller keeps alive) at arrival[k] (Server.clock()
         seconds). Returns a structured array of each request's arrival_s,
-        admitted_s and done_s (Server.clock() seconds) and n."""
+        admitted_s, launched_s, results_s and done_s (Server.clock()
+        seconds) and n."""
         index = np.ascontiguousarray(index, dtype=np.int32)
         sizes = np.ascontiguousarray(sizes, dtype=np.int64)
         arrival = np.ascontiguousarray(arrival, dtype=np.float64)
         base = np.asarray(pool_ptrs, dtype=np.uint64)[index]
         ptrs = np.ascontiguousarray(base + 16 * np.asarray(starts, dtype=np.uint64))
         times = np.zeros(len(sizes), dtype=[("arrival_s", np.float64), ("admitted_s", np.float64),
+                                            ("launched_s", np.float64), ("results_s", np.float64),
                                             ("done_s", np.float64), ("n", np.int64)])
         rc = lib.act_server_replay(self._h, len(sizes), _np_ptr(index), _np_ptr(ptrs),
                                    _np_ptr(sizes), _np_ptr(arrival), int(ring_points),

@@ -70,6 +70,7 @@ class ServerOpts(ctypes.Structure):
 
 class RequestTimes(ctypes.Structure):
     _fields_ = [("arrival_s", ctypes.c_double), ("admitted_s", ctypes.c_double),
+                ("launched_s", ctypes.c_double), ("results_s", ctypes.c_double),
                 ("done_s", ctypes.c_double), ("n", ctypes.c_int64)]
 
 
@@ -78,7 +79,9 @@ class ServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("points", ctypes.c_int64),
                 ("arena_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("launches", ctypes.c_int64)]
+                ("reserved", ctypes.c_int32), ("launches", ctypes.c_int64),
+                ("max_pass_s", ctypes.c_double), ("max_launch_s", ctypes.c_double),
+                ("max_stage_s", ctypes.c_double), ("max_finish_s", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):

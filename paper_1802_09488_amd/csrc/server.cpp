@@ -93,7 +93,7 @@ struct Request {
   const double *h_points;
   int64_t n;
   int32_t *h_out;
-  double arrival, admitted = 0, done = 0;
+  double arrival, admitted = 0, launched = 0, copied = 0, done = 0;
   int64_t offset = 0;  // first point in its launch group
   int status = ACT_OK;
 };
@@ -250,6 +250,12 @@ constexpr size_t kGroupMax = 1024;
 // request's index.
 constexpr size_t kGroupScan = 4096;
 
+// Longest durations, kept by the scheduler thread (under `mu`).
+void note_max(act_server *s, double act_server_stats::*field, double v) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (v > s->stats.*field) s->stats.*field = v;
+}
+
 // Stage a group into pinned memory and start its copies and join on its
 // slot's stream (scheduler thread, `mu` not held).
 int launch(act_server *s, int slot, const Group &g) {
@@ -264,7 +270,9 @@ int launch(act_server *s, int slot, const Group &g) {
   s->copy_work.clear();
   for (const Request *r : g.reqs)
     if (r->n) s->copy_work.push_back({pin_pts + 2 * r->offset, r->h_points, 16 * (size_t)r->n});
+  const double t_stage = now_s();
   group_copies(s->copies, s->copy_work, s->copy_pieces);
+  note_max(s, &act_server_stats::max_stage_s, now_s() - t_stage);
   if (hipMemcpyAsync(dev_pts, pin_pts, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
     return ACT_E_HIP;
   int rc = act_join(s->indexes[g.index], dev_pts, n, dev_out, st);
@@ -272,12 +280,15 @@ int launch(act_server *s, int slot, const Group &g) {
   if (hipMemcpyAsync(pin_out, dev_out, 4 * (size_t)n, hipMemcpyDeviceToHost, st) != hipSuccess)
     return ACT_E_HIP;
   if (hipEventRecord(s->events[slot], st) != hipSuccess) return ACT_E_HIP;
+  const double t = now_s();
+  for (Request *r : g.reqs) r->launched = t;  // written before the group is shared
   return ACT_OK;
 }
 
 // Copy a finished group's results out, free its buffers and complete its
 // requests (scheduler thread, `mu` not held on entry).
 void finish(act_server *s, Group &g, int status) {
+  const double t_gpu = now_s();  // the group's results are in pinned memory
   if (status == ACT_OK) {
     s->copy_work.clear();
     for (const Request *r : g.reqs)
@@ -295,6 +306,7 @@ void finish(act_server *s, Group &g, int status) {
     const double t = now_s();
     for (Request *r : g.reqs) {
       r->status = status;
+      r->copied = t_gpu;
       r->done = t;
       s->stats.completed++;
       s->stats.points += r->n;
@@ -361,7 +373,11 @@ bool take_group(act_server *s, Group &g) {
 
 void worker_loop(act_server *s) {
   (void)hipSetDevice(s->device);
+  double last = now_s();
   for (;;) {
+    const double t_pass = now_s();
+    if (t_pass - last > s->stats.max_pass_s) note_max(s, &act_server_stats::max_pass_s, t_pass - last);
+    last = t_pass;
     bool progress = false;
     // completions
     for (size_t k = 0; k < s->running.size(); k++) {
@@ -369,7 +385,9 @@ void worker_loop(act_server *s) {
       if (!g.busy()) continue;
       const hipError_t q = hipEventQuery(s->events[k]);
       if (q == hipErrorNotReady) continue;
+      const double t0 = now_s();
       finish(s, g, q == hipSuccess ? ACT_OK : ACT_E_HIP);
+      note_max(s, &act_server_stats::max_finish_s, now_s() - t0);
       progress = true;
     }
     // admissions, front of the queue first
@@ -387,7 +405,9 @@ void worker_loop(act_server *s) {
         if (s->queue.empty() || !take_group(s, g)) break;
       }
       progress = true;
+      const double t0 = now_s();
       const int rc = g.n > 0 ? launch(s, slot, g) : ACT_OK;
+      note_max(s, &act_server_stats::max_launch_s, now_s() - t0);
       if (rc != ACT_OK || g.n == 0) {
         // whatever was enqueued must finish before the buffers are reused
         if (rc != ACT_OK) (void)hipStreamSynchronize(s->streams[slot]);
@@ -405,6 +425,7 @@ void worker_loop(act_server *s) {
         std::unique_lock<std::mutex> lk(s->mu);
         if (s->stop && s->queue.empty()) break;
         s->cv_work.wait(lk, [s] { return s->stop || !s->queue.empty(); });
+        last = now_s();  // an idle wait is not a pass
       }
     }
   }
@@ -471,6 +492,30 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
       }
     }
   }
+  // warm every slot up once (a staging copy, a tiny join with each index
+  // and a result copy on its stream): the runtime's first operations on a
+  // stream can take milliseconds, and the first requests would pay them
+  if (!rc && arena >= 20 * 64) {
+    const int64_t n = 64;
+    double *pin_pts = (double *)s->pin_base;
+    std::memset(pin_pts, 0, 16 * (size_t)n);  // (0, 0): a valid point
+    double *dev_pts = (double *)s->dev_base;
+    int32_t *dev_out = (int32_t *)(s->dev_base + 16 * n);
+    int32_t *pin_out = (int32_t *)(s->pin_base + 16 * n);
+    for (size_t k = 0; k < s->streams.size() && !rc; k++) {
+      hipStream_t st = s->streams[k];
+      if (hipMemcpyAsync(dev_pts, pin_pts, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(ACT_E_HIP, "warm-up copy failed");
+      for (const act_index *x : s->indexes)
+        if (!rc && act_join(x, dev_pts, n, dev_out, st) != ACT_OK)
+          rc = fail(ACT_E_HIP, std::string("warm-up join: ") + act_last_error());
+      if (!rc && (hipMemcpyAsync(pin_out, dev_out, 4 * (size_t)n, hipMemcpyDeviceToHost, st) !=
+                      hipSuccess ||
+                  hipEventRecord(s->events[k], st) != hipSuccess ||
+                  hipStreamSynchronize(st) != hipSuccess))
+        rc = fail(ACT_E_HIP, "warm-up failed");
+    }
+  }
   if (rc) {
     act_server_destroy(s);
     return rc;
@@ -518,6 +563,8 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t) {
   if (t) {
     t->arrival_s = r->arrival;
     t->admitted_s = r->admitted;
+    t->launched_s = r->launched > 0 ? r->launched : r->admitted;
+    t->results_s = r->copied;
     t->done_s = r->done;
     t->n = r->n;
   }
@@ -569,7 +616,7 @@ int act_server_replay(act_server *s, int64_t n, const int32_t *index,
         t.arrival_s = arrival_s[k];
         t.n = n_points[k];
       }
-      if (rc != ACT_OK) t.done_s = t.admitted_s = -1.0;
+      if (rc != ACT_OK) t.done_s = t.results_s = t.launched_s = t.admitted_s = -1.0;
       if (times) times[k] = t;
       std::lock_guard<std::mutex> lk(mu);
       if (rc != ACT_OK && first_err == ACT_OK) {

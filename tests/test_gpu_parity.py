@@ -621,7 +621,8 @@ def test_server_results_same_alone_and_in_mix(act):
     tickets = [srv.submit(w, p, arrival=act.Server.clock()) for w, p in reqs]
     for (w, p), t in zip(reqs, tickets):
         out, tm = srv.wait(t)
-        assert tm["arrival_s"] <= tm["admitted_s"] <= tm["done_s"] and tm["n"] == len(p)
+        assert tm["arrival_s"] <= tm["admitted_s"] <= tm["launched_s"] <= tm["results_s"] \
+            <= tm["done_s"] and tm["n"] == len(p)
         if len(p) == 0:
             continue
         alone = (i1 if w == 0 else i2).join(torch.from_numpy(p).cuda()).cpu().numpy()
@@ -727,7 +728,9 @@ def test_server_replay_wraps_its_ring(act):
                     ring_points=7000)
     assert np.array_equal(tm["n"], sizes)
     assert np.all(tm["arrival_s"] == arrival)
-    assert np.all(tm["admitted_s"] >= tm["arrival_s"]) and np.all(tm["done_s"] >= tm["admitted_s"])
+    assert np.all(tm["admitted_s"] >= tm["arrival_s"])
+    assert np.all(tm["launched_s"] >= tm["admitted_s"]) and np.all(tm["results_s"] >= tm["launched_s"])
+    assert np.all(tm["done_s"] >= tm["results_s"])
     st = srv.stats()
     assert st["completed"] == n and st["failed"] == 0
     with pytest.raises(act.ActError):
