@@ -122,22 +122,29 @@ def percentile(v, q):
 
 
 def time_joins(idx, pts, out, steps, warmup, **kw):
-    """Times `steps` joins (after `warmup`): wall clock around all of them,
-    HIP events around each join and after its probe kernel."""
+    """Times `steps` joins (after `warmup`): wall clock around `steps`
+    back-to-back joins with nothing else on the stream; then, in a second
+    pass of `steps` joins outside that window, HIP events around each join
+    and after its probe kernel (event records between the launches would
+    otherwise add their own gaps to the wall-clock figure)."""
     import torch
     for _ in range(warmup):
         idx.join_ex(pts, out, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        idx.join_ex(pts, out, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     ev = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(3)) for _ in range(steps)]
     for _, m, _ in ev:
         m.record()  # creates the event the library records after the probe
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for a, m, b in ev:
         a.record()
         idx.join_ex(pts, out, probe_event=m, **kw)
         b.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     total = [a.elapsed_time(b) for a, _, b in ev]
     probe = [a.elapsed_time(m) for a, m, _ in ev]
     return wall, total, probe
@@ -456,7 +463,7 @@ def pairs_and_counts_leg(act, indexes, pts, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="all", choices=["all", "c2", "c3", "c4", "c5"],
                     help="all (default): the c2 headline (290 polygons, 1e8 points) plus "
@@ -685,7 +692,8 @@ def run_c2(args, emit=True):
 
 def _timed_stream(idx, pts, out, bsz, steps, **kw):
     """Joins of pts in batches of bsz (one step = all batches): wall clock
-    over the steps and HIP-event time of each."""
+    over `steps` back-to-back steps, then the HIP-event time of each step of
+    a second pass outside that window."""
     import torch
     n = pts.shape[0]
 
@@ -694,15 +702,19 @@ def _timed_stream(idx, pts, out, bsz, steps, **kw):
             idx.join_ex(pts[s:s + bsz], out[s:s + bsz], **kw)
     once()
     torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
-    t = time.perf_counter()
     for a, b in ev:
         a.record()
         once()
         b.record()
     torch.cuda.synchronize()
-    return time.perf_counter() - t, [a.elapsed_time(b) for a, b in ev]
+    return wall, [a.elapsed_time(b) for a, b in ev]
 
 
 def _index_metrics(ctr):
@@ -747,7 +759,7 @@ def compact_legs(args, keep):
     out = torch.empty(n, dtype=torch.int32, device="cuda")
     ie.reserve(bsz)
     it.reserve(bsz)
-    steps = 3
+    steps = 5
     c3 = {"n_points": n, "batch": bsz, "steps": steps, "exact_covering_level": EXACT_LEVEL}
     sample = synth.workload_points("c3", 0, 200_000)
     ref = oracle.join(P, sample, nthreads=cores)
