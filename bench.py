@@ -245,7 +245,9 @@ def serving_leg(act, indexes, pools, qps_list, seconds, seed=5005, slots=8,
         gaps = g.exponential(1.0 / qps, nreq)
         room = np.array([len(q) for q in pools], dtype=np.int64)[target] - sizes
         starts = (g.random(nreq) * room).astype(np.int64)
-        arrival = act.Server.clock() + 0.05 + np.cumsum(gaps)
+        # the replay allocates and writes its output ring before its first
+        # submission: the first arrival is far enough ahead for that
+        arrival = act.Server.clock() + 0.25 + np.cumsum(gaps)
         tm = srv.replay(target, ptrs, starts, sizes, arrival)
         lat = tm["done_s"] - tm["arrival_s"]
         queued = tm["admitted_s"] - tm["arrival_s"]  # waiting for a slot and memory

@@ -492,9 +492,12 @@ int act_tune(act_index *idx, const double *d_sample, int64_t n, int32_t *d_out, 
  * result does not depend on the group it ran in.
  * Exact-mode workspaces for every (index, stream) are reserved at creation
  * for max_request_points (longer requests run in passes), so serving
- * allocates nothing, and every slot is warmed up once (a 64-point join
- * with each index on its stream, with its copies), so the first requests
- * do not pay the runtime's first use of a stream. The indexes must outlive
+ * allocates nothing, and the slots are warmed up (per slot, twice, all
+ * slots in flight together: a join of min(max_request_points, 2^20,
+ * arena / (20 * slots)) points at (0, 0) with each index on its stream,
+ * with its copies), so the first requests do not pay the runtime's first
+ * use of a stream. The pinned arena is written once at creation (its
+ * pages are faulted in then, not during staging). The indexes must outlive
  * the server.
  */
 typedef struct act_server act_server;
@@ -553,8 +556,11 @@ int act_server_wait(act_server *s, uint64_t ticket, act_request_times *t);
  * go to an output ring of ring_points int32 that the call allocates and
  * reuses in request order; a request waits for room in it (which then
  * counts in its latency), and none may be longer than the ring
- * (ACT_E_RANGE). Returns once every request has completed: ACT_OK or the
- * first failure.
+ * (ACT_E_RANGE). The ring is allocated and written once before the first
+ * submission (tens of milliseconds for 2^26 points), so the first arrival
+ * should lie that far ahead of the call: a request whose arrival time has
+ * passed is submitted at once, and the delay counts in its latency.
+ * Returns once every request has completed: ACT_OK or the first failure.
  */
 int act_server_replay(act_server *s, int64_t n, const int32_t *index,
                       const double *const *h_points, const int64_t *n_points,

@@ -390,7 +390,10 @@ void worker_loop(act_server *s) {
       note_max(s, &act_server_stats::max_finish_s, now_s() - t0);
       progress = true;
     }
-    // admissions, front of the queue first
+    // admissions, front of the queue first: one launch per pass, so that
+    // the completions are looked at again between launches (a launch's
+    // staging and enqueues can take milliseconds, and groups that finish
+    // meanwhile would otherwise wait for all of the pass's launches)
     for (;;) {
       int slot = -1;
       for (size_t k = 0; k < s->running.size(); k++)
@@ -415,6 +418,7 @@ void worker_loop(act_server *s) {
         continue;
       }
       s->running[slot] = std::move(g);
+      break;
     }
     bool busy = false;
     for (const Group &g : s->running) busy |= g.busy();
@@ -470,6 +474,10 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
   if (hipMalloc((void **)&s->dev_base, (size_t)arena) != hipSuccess ||
       hipHostMalloc((void **)&s->pin_base, (size_t)arena, hipHostMallocDefault) != hipSuccess)
     rc = fail(ACT_E_OOM, "cannot allocate the request arenas");
+  // touch every page of the pinned arena once: the first host writes to
+  // its pages otherwise fault them in during staging, which stretched the
+  // first requests' staging to milliseconds
+  if (!rc) std::memset(s->pin_base, 0, (size_t)arena);
   s->dev_arena.reset(arena);
   s->pin_arena.reset(arena);
   for (int k = 0; k < o.slots && !rc; k++) {
@@ -492,29 +500,40 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
       }
     }
   }
-  // warm every slot up once (a staging copy, a tiny join with each index
-  // and a result copy on its stream): the runtime's first operations on a
-  // stream can take milliseconds, and the first requests would pay them
-  if (!rc && arena >= 20 * 64) {
-    const int64_t n = 64;
-    double *pin_pts = (double *)s->pin_base;
-    std::memset(pin_pts, 0, 16 * (size_t)n);  // (0, 0): a valid point
-    double *dev_pts = (double *)s->dev_base;
-    int32_t *dev_out = (int32_t *)(s->dev_base + 16 * n);
-    int32_t *pin_out = (int32_t *)(s->pin_base + 16 * n);
-    for (size_t k = 0; k < s->streams.size() && !rc; k++) {
-      hipStream_t st = s->streams[k];
-      if (hipMemcpyAsync(dev_pts, pin_pts, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
-        rc = fail(ACT_E_HIP, "warm-up copy failed");
-      for (const act_index *x : s->indexes)
-        if (!rc && act_join(x, dev_pts, n, dev_out, st) != ACT_OK)
-          rc = fail(ACT_E_HIP, std::string("warm-up join: ") + act_last_error());
-      if (!rc && (hipMemcpyAsync(pin_out, dev_out, 4 * (size_t)n, hipMemcpyDeviceToHost, st) !=
-                      hipSuccess ||
-                  hipEventRecord(s->events[k], st) != hipSuccess ||
-                  hipStreamSynchronize(st) != hipSuccess))
-        rc = fail(ACT_E_HIP, "warm-up failed");
+  // warm the slots up (per slot: a staging copy, a join with each index
+  // and a result copy on its stream, all slots in flight together, twice
+  // over): the runtime's first operations on a stream, and its first
+  // stretch with that many operations in flight, can take milliseconds, and
+  // the first requests would pay them. The groups are request-sized
+  // (max_request_points, at most 2^20 points: 16 MiB in, 4 MiB out) and
+  // each slot has its own buffers: after a warm-up with one 64-point join
+  // per slot in turn, launches in the first second of serving still
+  // stalled for several milliseconds
+  const int64_t n_slots = (int64_t)s->streams.size();
+  const int64_t n_warm =
+      std::min<int64_t>({o.max_request_points, 1 << 20, arena / (20 * std::max<int64_t>(n_slots, 1))});
+  if (!rc && n_warm >= 1) {
+    const int64_t n = n_warm;
+    for (int round = 0; round < 2 && !rc; round++) {
+      for (int64_t k = 0; k < n_slots && !rc; k++) {
+        hipStream_t st = s->streams[(size_t)k];
+        char *pin = s->pin_base + 20 * n * k;
+        char *dev = s->dev_base + 20 * n * k;
+        // the pinned arena was zeroed above: n points at (0, 0), valid
+        if (hipMemcpyAsync(dev, pin, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
+          rc = fail(ACT_E_HIP, "warm-up copy failed");
+        for (const act_index *x : s->indexes)
+          if (!rc && act_join(x, (const double *)dev, n, (int32_t *)(dev + 16 * n), st) != ACT_OK)
+            rc = fail(ACT_E_HIP, std::string("warm-up join: ") + act_last_error());
+        if (!rc && (hipMemcpyAsync(pin + 16 * n, dev + 16 * n, 4 * (size_t)n, hipMemcpyDeviceToHost,
+                                   st) != hipSuccess ||
+                    hipEventRecord(s->events[(size_t)k], st) != hipSuccess))
+          rc = fail(ACT_E_HIP, "warm-up failed");
+      }
     }
+    for (int64_t k = 0; k < n_slots; k++)
+      if (hipStreamSynchronize(s->streams[(size_t)k]) != hipSuccess && !rc)
+        rc = fail(ACT_E_HIP, "warm-up failed");
   }
   if (rc) {
     act_server_destroy(s);
