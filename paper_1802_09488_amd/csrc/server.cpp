@@ -508,17 +508,18 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
   // (max_request_points, at most 2^20 points: 16 MiB in, 4 MiB out) and
   // each slot has its own buffers: after a warm-up with one 64-point join
   // per slot in turn, launches in the first second of serving still
-  // stalled for several milliseconds
-  const int64_t n_slots = (int64_t)s->streams.size();
-  const int64_t n_warm =
-      std::min<int64_t>({o.max_request_points, 1 << 20, arena / (20 * std::max<int64_t>(n_slots, 1))});
+  // stalled for several milliseconds. Slot k's buffers start at k * stride,
+  // 256-byte aligned like the arena's own allocations.
+  const int64_t n_slots = std::max<int64_t>((int64_t)s->streams.size(), 1);
+  const int64_t n_warm = std::min<int64_t>({o.max_request_points, 1 << 20, (arena / n_slots - 255) / 20});
+  const int64_t stride = (20 * n_warm + 255) / 256 * 256;
   if (!rc && n_warm >= 1) {
     const int64_t n = n_warm;
     for (int round = 0; round < 2 && !rc; round++) {
-      for (int64_t k = 0; k < n_slots && !rc; k++) {
+      for (int64_t k = 0; k < (int64_t)s->streams.size() && !rc; k++) {
         hipStream_t st = s->streams[(size_t)k];
-        char *pin = s->pin_base + 20 * n * k;
-        char *dev = s->dev_base + 20 * n * k;
+        char *pin = s->pin_base + stride * k;
+        char *dev = s->dev_base + stride * k;
         // the pinned arena was zeroed above: n points at (0, 0), valid
         if (hipMemcpyAsync(dev, pin, 16 * (size_t)n, hipMemcpyHostToDevice, st) != hipSuccess)
           rc = fail(ACT_E_HIP, "warm-up copy failed");
@@ -531,8 +532,8 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
           rc = fail(ACT_E_HIP, "warm-up failed");
       }
     }
-    for (int64_t k = 0; k < n_slots; k++)
-      if (hipStreamSynchronize(s->streams[(size_t)k]) != hipSuccess && !rc)
+    for (size_t k = 0; k < s->streams.size(); k++)
+      if (hipStreamSynchronize(s->streams[k]) != hipSuccess && !rc)
         rc = fail(ACT_E_HIP, "warm-up failed");
   }
   if (rc) {
