@@ -538,7 +538,8 @@ int act_server_create(const act_index *const *indexes, int32_t n_indexes,
  * indexes[index]; results to h_out (host, n int32). Both buffers must stay
  * valid until act_server_wait returns for the ticket. arrival_s (seconds on
  * act_server_clock(), 0 = now) is the request's arrival time for latency.
- * ACT_E_RANGE if the request can never fit the arena. */
+ * ACT_E_RANGE if the request can never fit the arena (20 bytes a point,
+ * rounded up to the arena's 256-byte granules). */
 int act_server_submit(act_server *s, int32_t index, const double *h_points, int64_t n,
                       int32_t *h_out, double arrival_s, uint64_t *ticket);
 /* Block until the request is complete; its times go to *t (may be NULL).

@@ -553,7 +553,10 @@ int act_server_submit(act_server *s, int32_t index, const double *h_points, int6
   if (!s || !ticket || n < 0 || (n > 0 && (!h_points || !h_out)))
     return fail(ACT_E_ARG, "bad argument");
   if (index < 0 || index >= (int32_t)s->indexes.size()) return fail(ACT_E_ARG, "no such index");
-  if (20 * n > s->dev_arena.size()) return fail(ACT_E_RANGE, "request larger than the arena");
+  // (the arenas hand out 256-byte granules: a request whose rounded size
+  // exceeds them could never be admitted, and would block the queue)
+  if ((20 * n + 255) / 256 * 256 > s->dev_arena.size())
+    return fail(ACT_E_RANGE, "request larger than the arena");
   Request *r = new (std::nothrow) Request;
   if (!r) return fail(ACT_E_OOM, "out of host memory");
   r->index = index;

@@ -710,6 +710,31 @@ def test_server_admission_by_memory(act):
     srv.close()
 
 
+def test_server_tiny_arenas(act):
+    """Arenas too small for a warm-up group per slot (the warm-up shrinks
+    to one point per slot, or is left out) still serve every request that
+    fits them, with the oracle's results. The arenas hand out 256-byte
+    granules (20 bytes a point), so a request fits if its rounded size
+    does; one that fits only unrounded is refused at submission (it could
+    never be admitted)."""
+    P, idx = index(act, "c1", "exact")
+    pts = synth.workload_points("c1", 0, 2_000)
+    ref = oracle.join(P, pts).out
+    for arena in (1000, 1100, 4096):
+        srv = act.Server([idx], slots=4, arena_bytes=arena, max_request_points=1 << 16)
+        fit = arena // 256 * 256 // 20  # 38, 51 and 204 points
+        sizes = [0, 1, 5, fit]
+        ts = [(k * 100, m, srv.submit(0, pts[k * 100:k * 100 + m])) for k, m in enumerate(sizes)]
+        for a, m, t in ts:
+            out, _ = srv.wait(t)
+            assert np.array_equal(out, ref[a:a + m]), (arena, m)
+        assert srv.stats()["completed"] == len(sizes)
+        if arena == 1000:  # 50 points: 1000 bytes, 1024 rounded
+            with pytest.raises(act.ActError):
+                srv.submit(0, pts[:50])
+        srv.close()
+
+
 def test_server_replay_wraps_its_ring(act):
     """act_server_replay over a ring barely longer than the longest request:
     the outputs wrap around the ring and requests wait for room, and every
