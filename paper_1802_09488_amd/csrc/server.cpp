@@ -555,7 +555,7 @@ int act_server_submit(act_server *s, int32_t index, const double *h_points, int6
   if (index < 0 || index >= (int32_t)s->indexes.size()) return fail(ACT_E_ARG, "no such index");
   // (the arenas hand out 256-byte granules: a request whose rounded size
   // exceeds them could never be admitted, and would block the queue)
-  if ((20 * n + 255) / 256 * 256 > s->dev_arena.size())
+  if (n > s->dev_arena.size() / 20 || (20 * n + 255) / 256 * 256 > s->dev_arena.size())
     return fail(ACT_E_RANGE, "request larger than the arena");
   Request *r = new (std::nothrow) Request;
   if (!r) return fail(ACT_E_OOM, "out of host memory");
