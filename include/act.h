@@ -486,8 +486,10 @@ int act_tune(act_index *idx, const double *d_sample, int64_t n, int32_t *d_out, 
  * up, the request at the front of the queue is admitted together with the
  * requests for the same index waiting behind it (continuous batching: up to
  * max_request_points points in all, or the front request alone if it is
- * longer; up to 1024 requests). The group is staged into pinned memory,
- * copied to the GPU, joined (one act_join) and copied back on the slot's
+ * longer; up to 1024 requests). The group is staged into pinned memory;
+ * a group of up to 2^16 points is joined (one act_join) straight from it,
+ * the kernels reading the points and writing the results over PCIe, and a
+ * larger one is copied to the GPU, joined and copied back, on the slot's
  * stream; each request's results land in its caller's h_out. A request's
  * result does not depend on the group it ran in.
  * Exact-mode workspaces for every (index, stream) are reserved at creation
