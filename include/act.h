@@ -211,6 +211,11 @@ int act_load(const char *path, int32_t device, act_index **out);
  *           or -1.
  * n == 0 is a no-op. Further matches of a point (overlapping polygons,
  * shared edges and vertices) are not reported here; use act_join_pairs.
+ * "Device" here means an address the kernels can use: device memory, or
+ * pinned host memory at its device address (hipHostGetDevicePointer),
+ * which the kernels then read and write over PCIe (the serving loop does
+ * this for small groups). The results are in place once the stream has
+ * passed the call.
  */
 int act_join(const act_index *idx, const double *d_points, int64_t n,
              int32_t *d_out, void *stream);
